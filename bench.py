@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""Forward + backward throughput of the Gaussian Mesh Renderer hot path on one MI355X.
+
+One step = the whole hot path over one batch: per-face conversion + EWA projection, binning,
+(tile | depth) radix sort, tile ranges, front-to-back compositing, the fused L2-loss backward
+(reverse-order adjoint, projection and conversion backward, vertex gather); the 2M-face torus
+workload also runs the captured Adam step with the lists rebuilt in the backward.  Inputs are
+synthetic and resident in HBM before timing.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--config {1..5}] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+FP32_VECTOR_TFLOPS = 157.3     # MI355X vector FP32 (packed); 78.6 non-packed
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--autotune", action="store_true", help="pick tile shape / raster mode with gmr_autotune")
+    ap.add_argument("--tile", type=str, default=None, help="WxH binning tile, e.g. 16x16")
+    ap.add_argument("--raster-mode", type=int, default=None)
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def stage_profile(r):
+    import ctypes
+    import numpy as np
+    from paper_2602_14493_amd import _lib
+    names = ctypes.create_string_buffer(32 * 16)
+    ms = (ctypes.c_float * 16)()
+    cnt = (ctypes.c_int32 * 16)()
+    n = ctypes.c_int32()
+    _lib.call("gmr_profile_read", r.handle.ptr, 16, names, ms, cnt, ctypes.byref(n))
+    out = {}
+    raw = names.raw
+    for i in range(n.value):
+        nm = raw[32 * i:32 * i + 32].split(b"\0")[0].decode()
+        out[nm] = (float(ms[i]), int(cnt[i]))
+    return out
+
+
+def byte_model(stage, F, FV, V, P, I, tiles):
+    """Algorithmic HBM bytes of one launch group of `stage` (what the stage must move at least)."""
+    return {
+        "project": F * (12 + 36 + 36) + FV * (48 + 16 + 4),
+        "scan_emit": FV * (4 + 4 + 16) + I * 12,
+        "sort_hist": I * 8,
+        "sort_pass": I * 24,
+        "tile_ranges": I * 8 + tiles * 8,
+        "raster_fwd": I * (4 + 48) + tiles * 8 + P * (12 + 4 + 8),
+        "raster_bwd": I * (4 + 48) + tiles * 8 + P * (12 + 12 + 8) + FV * 32,
+        "face_bwd": F * (12 + 36 + 48) + FV * 32,
+        "vertex_gather": V * 4 + 3 * F * (4 + 12 + 12) + V * 24,
+        "fill": FV * 32,
+    }.get(stage, 0)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by view "
+              f"across GPUs as a design, not a run.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2602_14493_amd as gmr
+    import workloads as wl
+
+    torch.cuda.set_device(0)
+    W = wl.make_workload(args.config)
+    batch = gmr.Batch.from_workload(W)
+    kw = {}
+    if args.tile:
+        tw, th = (int(x) for x in args.tile.lower().split("x"))
+        kw.update(tile_w=tw, tile_h=th)
+    if args.raster_mode is not None:
+        kw["raster_mode"] = args.raster_mode
+    r = gmr.Renderer(batch, W.faces, gmr.default_options(**kw))
+    verts = torch.from_numpy(W.verts).cuda()
+    colors = torch.from_numpy(W.colors).cuda()
+    tverts = torch.from_numpy(W.target_verts).cuda()
+    with torch.no_grad():
+        target, _, _, _ = r.forward(tverts, colors, check=True)
+    target = target.clone()
+    if args.autotune:
+        r.autotune(verts, colors, target, iters=3)
+    recompute = args.config in (3, 5)
+    use_graph = args.config == 5
+    P = W.num_pixels
+
+    # ---- batched form ------------------------------------------------------------------------
+    if use_graph:
+        loop = gmr.GraphAdamLoop(r, verts, colors, target, lr=1e-3, recompute=True)
+        loop.capture()
+
+        def step():
+            loop.graph.replay()
+
+        def step_profiled():
+            loop._step_body()
+    else:
+        rgb, alpha, saved, ws = r.forward(verts, colors, check=True)
+        ws_b = r.new_workspace() if recompute else ws
+        dV = torch.empty_like(verts)
+        dC = torch.empty_like(colors)
+
+        def step():
+            r.fwd_raw(verts, colors, rgb, alpha, saved, ws)
+            r.bwd_l2_raw(verts, colors, rgb, target, 1.0, saved, ws_b, 1 if recompute else 0, dV, dC)
+
+        step_profiled = step
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = P / (ms_step * 1e-3) / 1e6
+    ws_ref = loop.ws_fwd if use_graph else ws
+    cnt = r.counters(ws_ref)
+    if cnt.overflow:
+        raise RuntimeError("instance capacity overflowed during the timed steps")
+    I = cnt.instances
+
+    # ---- per-stage timing (HIP events on the library's stream), same steps ----------------------
+    from paper_2602_14493_amd import _lib
+    _lib.call("gmr_profile_enable", r.handle.ptr, 1)
+    for _ in range(args.steps):
+        step_profiled()
+    torch.cuda.synchronize()
+    prof = stage_profile(r)
+    _lib.call("gmr_profile_enable", r.handle.ptr, 0)
+    F, V = batch.num_faces, batch.num_verts
+    FV = int(sum(int(W.face_offsets[m + 1] - W.face_offsets[m]) for m in W.view_mesh))
+    tiles = int(sum(((w + r.opts.tile_w - 1) // r.opts.tile_w) * ((h + r.opts.tile_h - 1) // r.opts.tile_h)
+                    for w, h in batch.sizes))
+    stages = {}
+    for k, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        avg = ms / n
+        b = byte_model(k, F, FV, V, P, I, tiles)
+        stages[k] = {"ms_per_launch": round(avg, 4), "launches_per_step": n / args.steps,
+                     "ms_per_step": round(ms / args.steps, 4), "alg_GBps": round(b / (avg * 1e-3) / 1e9, 1)}
+    dom = max(stages, key=lambda k: stages[k]["ms_per_step"])
+    d = stages[dom]
+    achieved = d["alg_GBps"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+
+    # ---- per-view launches (same work, one launch set per view) -------------------------------
+    per_view = None
+    if not args.no_per_view and W.num_views > 1 and not use_graph:
+        rs = []
+        for v in range(W.num_views):
+            bv = batch.view(v)
+            v0, v1, f0, f1 = bv.mesh_range
+            rv = gmr.Renderer(bv, W.faces[f0:f1] - v0, r.opts, handle=r.handle)
+            vv, cc = verts[v0:v1].contiguous(), colors[v0:v1].contiguous()
+            npx = bv.num_pixels
+            po = int(W.pixel_offsets()[v])
+            tg = target[po:po + npx].contiguous()
+            o_rgb, o_a, o_s, o_ws = rv.forward(vv, cc, check=True)
+            o_wsb = rv.new_workspace() if recompute else o_ws
+            rs.append((rv, vv, cc, tg, o_rgb, o_a, o_s, o_ws, o_wsb, torch.empty_like(vv), torch.empty_like(cc)))
+
+        def step_pv():
+            for (rv, vv, cc, tg, o_rgb, o_a, o_s, o_ws, o_wsb, dv, dc) in rs:
+                rv.fwd_raw(vv, cc, o_rgb, o_a, o_s, o_ws)
+                rv.bwd_l2_raw(vv, cc, o_rgb, tg, 1.0, o_s, o_wsb, 1 if recompute else 0, dv, dc)
+        for _ in range(args.warmup):
+            step_pv()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            step_pv()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_pv = e0.elapsed_time(e1) / args.steps
+        per_view = {"ms_per_step": round(ms_pv, 4), "Mpixel_per_s": round(P / (ms_pv * 1e-3) / 1e6, 2),
+                    "batched_speedup": round(ms_pv / ms_step, 3)}
+
+    # ---- CPU baseline: the FP64 oracle, forward + adjoint -------------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        views = list(range(W.num_views)) if args.config in (1, 2) else [0]
+        sample_px = int(sum(W.cams[v].width * W.cams[v].height for v in views))
+        Wsub = W if args.config in (1, 2) else wl._single(W.name, *W.mesh(int(W.view_mesh[0])), [W.cams[0]])
+        tg_np = target[:sample_px].cpu().numpy().astype(np.float64) if args.config not in (1, 2) else \
+            target.cpu().numpy().astype(np.float64)
+        t_cpu, reps = 0.0, 0
+        while t_cpu < args.cpu_seconds or reps == 0:
+            t1 = time.perf_counter()
+            o_rgb, o_tf, _, _ = oracle.render_workload(Wsub)
+            _, g = oracle.l2_loss(o_rgb, tg_np)
+            oracle.adjoint_workload(Wsub, g)
+            t_cpu += time.perf_counter() - t1
+            reps += 1
+        cpu = {"value": round(sample_px * reps / t_cpu / 1e6, 4), "unit": "Mpixel/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{'all' if args.config in (1, 2) else 'view 0 of'} {W.num_views} views, "
+                         f"{sample_px} px, fwd+adjoint, {reps} reps, {t_cpu:.1f} s"}
+
+    out = {
+        "metric": "fwd+bwd Mpixel/s (batched)",
+        "value": round(value, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": W.name, "faces": F, "verts": V, "views": W.num_views, "pixels": P,
+                   "instances": I, "tile": f"{r.opts.tile_w}x{r.opts.tile_h}", "raster_mode": r.opts.raster_mode,
+                   "recompute_lists": recompute, "adam_graph": use_graph},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_view": per_view,
+        "stages": stages,
+        "wall_s": round(wall, 3),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/* gmr.h -- C ABI of the MI355X (gfx950) Gaussian Mesh Renderer hot path (libgmr.so).
+ *
+ * The renderer turns every triangle of a mesh into one planar 3D Gaussian (Liu & Okura,
+ * "Gaussian Mesh Renderer for Lightweight Differentiable Rendering", Sec. 2.2: local facet frame,
+ * closed-form second moments Eq. 6-9, area-matched covariance Eq. 12-13 or the embedded form
+ * Eq. 15, opacity 1 and the vertex-average colour Eq. 16), splats it with the 3DGS rasteriser the
+ * paper adopts (Sec. 2.1: EWA projection, tile binning on a (tile | depth) key, front-to-back
+ * alpha compositing) and back-propagates image gradients to vertex positions and colours.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named *_dev are DEVICE pointers owned by the caller; pointers named *_host are host
+ *    pointers owned by the caller.  No entry point keeps a pointer after it returns.
+ *  - No entry point allocates or frees device memory, or synchronises the stream, except
+ *    gmr_read_counters (which synchronises) -- so fwd/bwd/adam may be captured in a hipGraph.
+ *  - Work is enqueued on `stream`.  Argument errors are detected on the host BEFORE anything is
+ *    enqueued and return a status; nothing is thrown across the ABI.  gmr_last_error() returns a
+ *    thread-local description of the last failure.
+ *  - Indices are int32 (vertices, faces, face-views and pixels of one batch < 2^31; instances
+ *    < 2^30).  Image sides are <= 32767.
+ *  - Colours are linear RGB floats; images are float32 [pixels][3], pixels of all views back to
+ *    back, each view row-major.  Pixel (i, j) has its centre at (i + 0.5, j + 0.5).
+ *  - Cameras are pinholes with OpenCV axes (+x right, +y down, +z forward): p = R x + t,
+ *    u = fx p.x / p.z + cx, v = fy p.y / p.z + cy.
+ */
+#ifndef GMR_H
+#define GMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gmr_status {
+  GMR_OK = 0,
+  GMR_ERR_INVALID_ARG = 1,   /* a size, pointer or option is out of range                       */
+  GMR_ERR_WORKSPACE = 2,     /* the workspace / saved buffer is smaller than required            */
+  GMR_ERR_CAPACITY = 3,      /* instance count exceeded the workspace's capacity (see counters)  */
+  GMR_ERR_UNSUPPORTED = 4,   /* valid request this build does not support                        */
+  GMR_ERR_HIP = 5            /* a HIP runtime call failed                                        */
+} gmr_status;
+
+/* Pinhole camera (world -> camera p = R x + t, R row-major).  near_plane/far_plane cull
+ * Gaussians whose centre depth p.z is outside (near_plane, far_plane). */
+typedef struct gmr_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float near_plane, far_plane;
+} gmr_camera;
+
+/* Renderer options.  gmr_default_options() fills the defaults given in brackets. */
+typedef struct gmr_options {
+  int32_t cov_mode;          /* [0] 0: area-matched covariance (Eq. 13); 1: embedded Sigma2D (Eq. 15) */
+  float dilation;            /* [0.3] screen-space low-pass added to the 2D covariance, px^2      */
+  float alpha_min;           /* [1/255] Gaussians with alpha below it are skipped at a pixel       */
+  float alpha_max;           /* [0.99] alpha clamp (keeps 1 - alpha >= 0.01)                      */
+  float t_eps;               /* [1e-4] compositing stops before transmittance would fall below it */
+  float bg[3];               /* [0,0,0] background colour                                         */
+  int32_t tile_w, tile_h;    /* [16,16] binning tile in pixels: multiples of 8 in [8, 64]          */
+  int32_t raster_mode;       /* [0] 0: one workgroup per tile group; 1: persistent work queue     */
+  int32_t reserved;          /* must be 0                                                          */
+  int64_t instance_capacity; /* [0] (Gaussian, tile) instances the workspace holds; must be > 0
+                                when sizing a workspace or rendering                               */
+} gmr_options;
+
+/* A batch: M meshes stored back to back (face indices are GLOBAL into the flat vertex array and
+ * the faces of mesh m reference only its vertices), and NV views, each bound to one mesh.
+ * All arrays are HOST arrays.  Global Gaussian id of face f of the flat face array is f. */
+typedef struct gmr_batch {
+  int32_t num_meshes;
+  int32_t num_views;
+  const int64_t* vert_offsets_host;  /* [num_meshes + 1], vert_offsets[0] = 0                  */
+  const int64_t* face_offsets_host;  /* [num_meshes + 1], face_offsets[0] = 0                  */
+  const int32_t* view_mesh_host;     /* [num_views] mesh of each view                          */
+  const gmr_camera* cams_host;       /* [num_views]                                            */
+} gmr_batch;
+
+/* Counters the device keeps in the workspace (read back with gmr_read_counters). */
+typedef struct gmr_counters {
+  int64_t instances;   /* (Gaussian, tile) instances the last pass generated                  */
+  int64_t capacity;    /* capacity of the workspace                                           */
+  int32_t overflow;    /* 1 if instances > capacity (outputs of that pass are incomplete)    */
+  int32_t reserved;
+} gmr_counters;
+
+typedef struct gmr_ctx* gmr_handle;
+
+/* ---------------------------------------------------------------------------------------------
+ * Library / context
+ * ------------------------------------------------------------------------------------------- */
+
+/* Returns the default options (Sec. 2.2 constants are compiled in; see gmr_options). */
+gmr_options gmr_default_options(void);
+
+/* Creates a context bound to HIP device `device` (queries its CU count for persistent launches).
+ * Errors: GMR_ERR_INVALID_ARG (null out / bad device), GMR_ERR_HIP. */
+gmr_status gmr_create(gmr_handle* out, int device);
+gmr_status gmr_destroy(gmr_handle h);
+
+const char* gmr_status_string(gmr_status s);
+const char* gmr_last_error(void);
+
+/* ---------------------------------------------------------------------------------------------
+ * Sizing.  All pure host functions.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Bytes of the device view table for this batch + options (see gmr_view_table_fill). */
+gmr_status gmr_view_table_size(const gmr_batch* batch, const gmr_options* opt, size_t* bytes);
+
+/* Writes the view table (per-view camera, offsets, tile grid; per-mesh face ranges and view
+ * lists) into a HOST buffer; the caller copies it to device memory and passes that device copy as
+ * `table_dev` to the render calls, together with the SAME batch and options.  The table is
+ * immutable across calls, so a captured graph may keep using it. */
+gmr_status gmr_view_table_fill(const gmr_batch* batch, const gmr_options* opt, void* host_dst, size_t bytes);
+
+/* Workspace bytes for one forward+backward of this batch at opt->instance_capacity.  The
+ * workspace holds the per face-view projected records, the instance keys/values (double
+ * buffered), the sort state, the tile ranges and the backward's gradient accumulators.
+ * `saved_bytes` is the per-pixel state render_fwd leaves for render_bwd (8 bytes per pixel). */
+gmr_status gmr_workspace_size(const gmr_batch* batch, const gmr_options* opt, size_t* ws_bytes, size_t* saved_bytes);
+
+/* CSR of (vertex -> face*3 + corner), entries ascending per vertex: the deterministic gather the
+ * backward uses to sum per-corner gradients into vertices.  Host-side; build once per topology.
+ * faces_host [num_faces][3] global indices; off_host [num_verts + 1]; ent_host [3 num_faces].
+ * Errors: GMR_ERR_INVALID_ARG for an index outside [0, num_verts). */
+gmr_status gmr_build_adjacency(const int32_t* faces_host, int64_t num_faces, int64_t num_verts,
+                               int32_t* off_host, int32_t* ent_host);
+
+/* ---------------------------------------------------------------------------------------------
+ * Forward / backward
+ * ------------------------------------------------------------------------------------------- */
+
+/* Forward pass of every view of the batch: per-face conversion (Sec. 2.2) fused with EWA
+ * projection per view, instance emission, (tile | depth) radix sort, tile ranges, and per-tile
+ * front-to-back compositing.
+ *   verts_dev  [V][3] f32, faces_dev [F][3] i32 (global), colors_dev [V][3] f32
+ *   out_rgb_dev   [P][3] f32  composite + T_final * bg
+ *   out_alpha_dev [P]    f32  1 - T_final (may be NULL)
+ *   saved_dev     saved_bytes (T_final and the list position after the last composited
+ *                 Gaussian, per pixel) -- input of gmr_render_bwd
+ *   ws_dev/ws_bytes  workspace of gmr_workspace_size; after the call it holds the sorted
+ *                 lists, which gmr_render_bwd may reuse (recompute_lists = 0).
+ * If the instance count exceeds the capacity, writes are clamped, the overflow counter is set and
+ * the image is incomplete; the call still returns GMR_OK (the count is only known on the device):
+ * check gmr_read_counters and re-run with a larger capacity. */
+gmr_status gmr_render_fwd(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table_dev,
+                          const float* verts_dev, const int32_t* faces_dev, const float* colors_dev,
+                          float* out_rgb_dev, float* out_alpha_dev, void* saved_dev,
+                          void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Backward pass: reverse-order adjoint of the compositing per pixel, chained through the EWA
+ * projection and the conversion to vertex positions and colours.
+ *   d_rgb_dev   [P][3] f32  dL/d rgb;  d_alpha_dev [P] f32 dL/d alpha (may be NULL)
+ *   saved_dev   as written by gmr_render_fwd for the same inputs
+ *   adj_off_dev [V + 1], adj_ent_dev [3F]  from gmr_build_adjacency (device copies)
+ *   recompute_lists  0: ws_dev still holds the forward's lists (same inputs, untouched);
+ *                    1: rebuild them (bit-identical to the forward's) inside ws_dev.
+ *   d_verts_dev [V][3], d_colors_dev [V][3]  OVERWRITTEN with the gradients.
+ * Culled faces (degenerate, behind the camera, off-screen) receive zero gradient. */
+gmr_status gmr_render_bwd(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table_dev,
+                          const float* verts_dev, const int32_t* faces_dev, const float* colors_dev,
+                          const float* d_rgb_dev, const float* d_alpha_dev, const void* saved_dev,
+                          const int32_t* adj_off_dev, const int32_t* adj_ent_dev, int32_t recompute_lists,
+                          float* d_verts_dev, float* d_colors_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Same as gmr_render_bwd for the colour loss of Sec. 3.1 (mean squared error over every channel
+ * of every pixel of every view, times loss_weight): dL/d rgb = loss_weight * 2 (rgb - target) / (3P)
+ * is formed inside the backward kernel from out_rgb_dev (the forward's output) and target_dev.
+ * If loss_dev is not NULL, the loss value (f32) is written there. */
+gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table_dev,
+                             const float* verts_dev, const int32_t* faces_dev, const float* colors_dev,
+                             const float* rgb_dev, const float* target_dev, float loss_weight,
+                             const void* saved_dev, const int32_t* adj_off_dev, const int32_t* adj_ent_dev,
+                             int32_t recompute_lists, float* d_verts_dev, float* d_colors_dev, float* loss_dev,
+                             void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Where the forward's tile lists live inside a workspace laid out for (batch, opt): byte offsets
+ * of the tile ranges (uint32 [tiles][2] = start, end into the sorted instances), the sorted
+ * instance values (uint32 [instance_capacity] face-view indices, sorted by (tile, float32 depth,
+ * face-view)), the projected records (float32 [face-views][12]) and the bin records
+ * (uint32 [face-views][4]: first tile, nx | ny << 16, tiles_x, float32 depth bits).  Tiles of
+ * view v are numbered from the sum of the earlier views' tile counts, row-major.  Face-views of
+ * view v are numbered from the sum of the earlier views' face counts, in face order.  Pure host
+ * arithmetic; the contents are valid after gmr_render_fwd (or a recomputing gmr_render_bwd). */
+gmr_status gmr_workspace_view(const gmr_batch* batch, const gmr_options* opt, size_t* ranges_off, size_t* vals_off,
+                              size_t* rec_off, size_t* bin_off);
+
+/* Reads the workspace's device counters (synchronises `stream`).  Not capturable. */
+gmr_status gmr_read_counters(const void* ws_dev, size_t ws_bytes, gmr_counters* out_host, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Stage timing (tracing).  While enabled, every stage of gmr_render_fwd / gmr_render_bwd* on this
+ * handle is bracketed by a HIP event pair on the call's stream.  For eager calls only: do not
+ * enable it around graph capture.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Turns stage timing on (enable = 1) or off and discards what was recorded. */
+gmr_status gmr_profile_enable(gmr_handle h, int32_t enable);
+
+/* Waits for the recorded events and returns, per stage, its name (names: max_stages x 32 chars),
+ * the summed milliseconds and the number of timed launch groups; then discards the records.
+ * Stages: project, scan_emit, sort_hist, sort_pass (one group per radix pass), tile_ranges,
+ * raster_fwd, fill, raster_bwd, face_bwd, vertex_gather.  max_stages must be >= 10. */
+gmr_status gmr_profile_read(gmr_handle h, int32_t max_stages, char* names, float* ms_total, int32_t* launches,
+                            int32_t* n_stages);
+
+/* ---------------------------------------------------------------------------------------------
+ * Optimiser step (the configuration's Adam on vertex positions)
+ * ------------------------------------------------------------------------------------------- */
+
+/* One Adam step on n floats: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), with t = ++(*step_dev) read and
+ * incremented on the device (so a captured graph advances it on every replay).
+ * step_dev: one int32 on the device, 0 before the first step. */
+gmr_status gmr_adam_step(float* param_dev, const float* grad_dev, float* m_dev, float* v_dev, int64_t n,
+                         float lr, float beta1, float beta2, float eps, int32_t* step_dev, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Autotuning (tile shape and raster mode).  Allocates its own scratch and synchronises: call it
+ * outside graph capture.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Times forward + L2 backward for each candidate tile shape and raster mode on the given inputs
+ * (iters timed launches each, after one warm-up) and writes the fastest options to best_out
+ * (instance_capacity set with 25% headroom over the measured count).  Results are cached in the
+ * handle per (image sizes, face count, views); a cached entry is returned without timing.
+ * ms_out (may be NULL) receives the best time per forward+backward. */
+gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options* base,
+                        const float* verts_dev, const int32_t* faces_dev, const float* colors_dev,
+                        const float* target_dev, const int32_t* adj_off_dev, const int32_t* adj_ent_dev,
+                        int32_t iters, gmr_options* best_out, float* ms_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMR_H */

@@ -1,0 +1,718 @@
+// C ABI of libgmr: argument validation, the device view table, workspace layout, stage
+// orchestration on the caller's stream, and the tile-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gmr_common.h"
+#include "gmr_launch.h"
+
+using namespace gmr;
+
+// Stages timed by gmr_profile_* (HIP events around each launch group on the call's stream).
+enum Stage { kStProject, kStScanEmit, kStSortHist, kStSortPass, kStRanges, kStRasterFwd, kStFill, kStRasterBwd,
+             kStFaceBwd, kStGather, kNumStages };
+static const char* kStageNames[kNumStages] = {"project",     "scan_emit",  "sort_hist", "sort_pass",
+                                              "tile_ranges", "raster_fwd", "fill",      "raster_bwd",
+                                              "face_bwd",    "vertex_gather"};
+
+struct gmr_ctx {
+  int device = 0;
+  int num_cus = 256;
+  std::map<std::string, std::pair<gmr_options, float>> tune_cache;
+  bool prof = false;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+gmr_status fail(gmr_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define GMR_CHECK_HIP(expr)                                                                     \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) return fail(GMR_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Plan {
+  int32_t nm = 0, nv = 0;
+  int64_t v_total = 0, f_total = 0, fv_total = 0, p_total = 0;
+  int32_t tiles_total = 0, items_total = 0, sub_x = 0, sub_y = 0;
+  int32_t tile_w = 16, tile_h = 16;
+  std::vector<ViewDev> views;
+  std::vector<int32_t> mfo, mvo, mvs;
+  Layout L{};
+  size_t table_bytes = 0;
+};
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.f; }
+
+gmr_status validate_options(const gmr_options* o) {
+  if (!o) return fail(GMR_ERR_INVALID_ARG, "options is NULL");
+  if (o->cov_mode != 0 && o->cov_mode != 1) return fail(GMR_ERR_INVALID_ARG, "cov_mode must be 0 or 1");
+  if (!(std::isfinite(o->dilation) && o->dilation >= 0.f)) return fail(GMR_ERR_INVALID_ARG, "dilation must be finite and >= 0");
+  if (!(o->alpha_min > 0.f && o->alpha_min < 1.f)) return fail(GMR_ERR_INVALID_ARG, "alpha_min must be in (0, 1)");
+  if (!(o->alpha_max >= o->alpha_min && o->alpha_max < 1.f)) return fail(GMR_ERR_INVALID_ARG, "alpha_max must be in [alpha_min, 1)");
+  if (!(o->t_eps > 0.f && o->t_eps < 1.f)) return fail(GMR_ERR_INVALID_ARG, "t_eps must be in (0, 1)");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(o->bg[i])) return fail(GMR_ERR_INVALID_ARG, "bg must be finite");
+  auto tile_ok = [](int32_t t) { return t >= 8 && t <= 64 && t % 8 == 0; };
+  if (!tile_ok(o->tile_w) || !tile_ok(o->tile_h)) return fail(GMR_ERR_INVALID_ARG, "tile_w/tile_h must be multiples of 8 in [8, 64]");
+  if (o->raster_mode != 0 && o->raster_mode != 1) return fail(GMR_ERR_INVALID_ARG, "raster_mode must be 0 or 1");
+  if (o->reserved != 0) return fail(GMR_ERR_INVALID_ARG, "reserved must be 0");
+  return GMR_OK;
+}
+
+gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacity, Plan& p) {
+  gmr_status st = validate_options(o);
+  if (st != GMR_OK) return st;
+  if (!b) return fail(GMR_ERR_INVALID_ARG, "batch is NULL");
+  if (b->num_meshes < 1) return fail(GMR_ERR_INVALID_ARG, "num_meshes must be >= 1");
+  if (b->num_views < 1) return fail(GMR_ERR_INVALID_ARG, "num_views must be >= 1");
+  if (!b->vert_offsets_host || !b->face_offsets_host || !b->view_mesh_host || !b->cams_host)
+    return fail(GMR_ERR_INVALID_ARG, "batch arrays must not be NULL");
+  p.nm = b->num_meshes;
+  p.nv = b->num_views;
+  const int64_t* vo = b->vert_offsets_host;
+  const int64_t* fo = b->face_offsets_host;
+  if (vo[0] != 0 || fo[0] != 0) return fail(GMR_ERR_INVALID_ARG, "vert_offsets[0] and face_offsets[0] must be 0");
+  for (int m = 0; m < p.nm; ++m)
+    if (vo[m + 1] < vo[m] || fo[m + 1] < fo[m]) return fail(GMR_ERR_INVALID_ARG, "offsets must be non-decreasing");
+  p.v_total = vo[p.nm];
+  p.f_total = fo[p.nm];
+  if (p.v_total >= (1ll << 31) || p.f_total >= (1ll << 31)) return fail(GMR_ERR_INVALID_ARG, "too many vertices or faces (>= 2^31)");
+  p.tile_w = o->tile_w;
+  p.tile_h = o->tile_h;
+  p.sub_x = o->tile_w / kSub;
+  p.sub_y = o->tile_h / kSub;
+  p.views.assign(p.nv, ViewDev{});
+  std::vector<std::vector<int32_t>> per_mesh(p.nm);
+  int64_t fv = 0, px = 0, tiles = 0;
+  for (int v = 0; v < p.nv; ++v) {
+    const int32_t m = b->view_mesh_host[v];
+    if (m < 0 || m >= p.nm) return fail(GMR_ERR_INVALID_ARG, "view_mesh out of range");
+    const gmr_camera& c = b->cams_host[v];
+    if (c.width < 1 || c.height < 1 || c.width > 32767 || c.height > 32767)
+      return fail(GMR_ERR_INVALID_ARG, "camera width/height must be in [1, 32767]");
+    if (!finite_pos(c.fx) || !finite_pos(c.fy) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+      return fail(GMR_ERR_INVALID_ARG, "camera intrinsics must be finite with fx, fy > 0");
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(c.R[i])) return fail(GMR_ERR_INVALID_ARG, "camera R must be finite");
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(c.t[i])) return fail(GMR_ERR_INVALID_ARG, "camera t must be finite");
+    if (!(c.near_plane > 0.f) || !(c.far_plane > c.near_plane)) return fail(GMR_ERR_INVALID_ARG, "need 0 < near_plane < far_plane");
+    ViewDev& V = p.views[v];
+    std::memcpy(V.R, c.R, sizeof V.R);
+    std::memcpy(V.t, c.t, sizeof V.t);
+    V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy;
+    V.W = c.width; V.H = c.height;
+    V.tiles_x = (c.width + p.tile_w - 1) / p.tile_w;
+    V.tiles_y = (c.height + p.tile_h - 1) / p.tile_h;
+    V.fv_offset = fv;
+    V.pixel_offset = px;
+    V.tile_base = (int32_t)tiles;
+    V.mesh = m;
+    V.face_begin = (int32_t)fo[m];
+    V.face_end = (int32_t)fo[m + 1];
+    V.znear = c.near_plane;
+    V.zfar = c.far_plane;
+    fv += fo[m + 1] - fo[m];
+    px += (int64_t)c.width * c.height;
+    tiles += (int64_t)V.tiles_x * V.tiles_y;
+    per_mesh[m].push_back(v);
+    if (fv >= (1ll << 31) || px >= (1ll << 31) || tiles * p.sub_x * p.sub_y >= (1ll << 31))
+      return fail(GMR_ERR_INVALID_ARG, "batch too large (face-views, pixels or raster items >= 2^31)");
+  }
+  p.fv_total = fv;
+  p.p_total = px;
+  p.tiles_total = (int32_t)tiles;
+  p.items_total = (int32_t)(tiles * p.sub_x * p.sub_y);
+  p.mfo.assign(fo, fo + p.nm + 1);
+  p.mvo.assign(p.nm + 1, 0);
+  p.mvs.clear();
+  for (int m = 0; m < p.nm; ++m) {
+    p.mvo[m + 1] = p.mvo[m] + (int32_t)per_mesh[m].size();
+    for (int32_t v : per_mesh[m]) p.mvs.push_back(v);
+  }
+  p.table_bytes = sizeof(TableHdr) + sizeof(ViewDev) * p.nv + sizeof(int32_t) * (2 * (p.nm + 1) + p.nv);
+
+  // workspace layout
+  int64_t cap = o->instance_capacity;
+  if (need_capacity && (cap <= 0 || cap >= (1ll << 30)))
+    return fail(GMR_ERR_INVALID_ARG, "instance_capacity must be in [1, 2^30)");
+  if (cap <= 0) cap = 1;
+  Layout& L = p.L;
+  L.fv_total = p.fv_total;
+  L.faces_total = p.f_total;
+  L.pixels_total = p.p_total;
+  L.capacity = cap;
+  L.tiles_total = p.tiles_total;
+  L.items_total = p.items_total;
+  int tile_bits = 0;
+  while ((1ll << tile_bits) < p.tiles_total) ++tile_bits;
+  L.key_bits = 32 + tile_bits;
+  L.passes = (L.key_bits + 7) / 8;
+  L.scan_blocks = (int32_t)((p.fv_total + kScanTile - 1) / kScanTile);
+  if (L.scan_blocks > 65536) return fail(GMR_ERR_INVALID_ARG, "too many face-views for the single-level scan");
+  L.sort_parts = (int32_t)((cap + kSortPart - 1) / kSortPart);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t r = off; off = align_up(off + bytes); return r; };
+  L.hdr = take(sizeof(WsHdr));
+  L.rec = take((size_t)p.fv_total * kRecF4 * 16);
+  L.bin = take((size_t)p.fv_total * 16);
+  L.cnt = take((size_t)p.fv_total * 4);
+  L.bsum = take((size_t)std::max(L.scan_blocks, 1) * 4);
+  L.boff = take((size_t)std::max(L.scan_blocks, 1) * 8);
+  L.keys0 = take((size_t)cap * 8);
+  L.keys1 = take((size_t)cap * 8);
+  L.vals0 = take((size_t)cap * 4);
+  L.vals1 = take((size_t)cap * 4);
+  L.hist = take(kMaxPasses * 256 * 4);
+  L.dig = take(kMaxPasses * 256 * 4);
+  L.desc0 = take((size_t)L.sort_parts * 256 * 4);
+  L.desc1 = take((size_t)L.sort_parts * 256 * 4);
+  L.ranges = take((size_t)p.tiles_total * 8);
+  L.dfv = take((size_t)p.fv_total * 32);
+  L.fgrad = take((size_t)p.f_total * 48);
+  L.total = off;
+  return GMR_OK;
+}
+
+void write_table(const Plan& p, void* dst) {
+  char* base = static_cast<char*>(dst);
+  TableHdr h{};
+  h.num_views = p.nv;
+  h.num_meshes = p.nm;
+  h.tile_w = p.tile_w;
+  h.tile_h = p.tile_h;
+  h.tiles_total = p.tiles_total;
+  h.sub_x = p.sub_x;
+  h.sub_y = p.sub_y;
+  h.items_total = p.items_total;
+  h.fv_total = p.fv_total;
+  h.pixels_total = p.p_total;
+  h.faces_total = p.f_total;
+  h.views_off = sizeof(TableHdr);
+  h.mesh_face_off = h.views_off + (int32_t)(sizeof(ViewDev) * p.nv);
+  h.mesh_view_off = h.mesh_face_off + (int32_t)(sizeof(int32_t) * (p.nm + 1));
+  h.mesh_views_off = h.mesh_view_off + (int32_t)(sizeof(int32_t) * (p.nm + 1));
+  std::memcpy(base, &h, sizeof h);
+  std::memcpy(base + h.views_off, p.views.data(), sizeof(ViewDev) * p.nv);
+  std::memcpy(base + h.mesh_face_off, p.mfo.data(), sizeof(int32_t) * (p.nm + 1));
+  std::memcpy(base + h.mesh_view_off, p.mvo.data(), sizeof(int32_t) * (p.nm + 1));
+  std::memcpy(base + h.mesh_views_off, p.mvs.data(), sizeof(int32_t) * p.nv);
+}
+
+KOpts kopts(const gmr_options* o) {
+  KOpts k;
+  k.cov_mode = o->cov_mode;
+  k.dilation = o->dilation;
+  k.alpha_min = o->alpha_min;
+  k.alpha_max = o->alpha_max;
+  k.t_eps = o->t_eps;
+  k.bg0 = o->bg[0];
+  k.bg1 = o->bg[1];
+  k.bg2 = o->bg[2];
+  return k;
+}
+
+struct WsPtrs {
+  WsHdr* hdr;
+  float4* rec;
+  uint4* bin;
+  uint32_t* cnt;
+  uint32_t* bsum;
+  uint64_t* boff;
+  uint64_t* keys0;
+  uint64_t* keys1;
+  uint32_t* vals0;
+  uint32_t* vals1;
+  uint32_t* hist;
+  uint32_t* dig;
+  uint32_t* desc0;
+  uint32_t* desc1;
+  uint32_t* ranges;
+  float* dfv;
+  float4* fgrad;
+  uint32_t* sorted_vals;
+};
+
+WsPtrs ws_ptrs(const Layout& L, void* ws) {
+  char* b = static_cast<char*>(ws);
+  WsPtrs w;
+  w.hdr = reinterpret_cast<WsHdr*>(b + L.hdr);
+  w.rec = reinterpret_cast<float4*>(b + L.rec);
+  w.bin = reinterpret_cast<uint4*>(b + L.bin);
+  w.cnt = reinterpret_cast<uint32_t*>(b + L.cnt);
+  w.bsum = reinterpret_cast<uint32_t*>(b + L.bsum);
+  w.boff = reinterpret_cast<uint64_t*>(b + L.boff);
+  w.keys0 = reinterpret_cast<uint64_t*>(b + L.keys0);
+  w.keys1 = reinterpret_cast<uint64_t*>(b + L.keys1);
+  w.vals0 = reinterpret_cast<uint32_t*>(b + L.vals0);
+  w.vals1 = reinterpret_cast<uint32_t*>(b + L.vals1);
+  w.hist = reinterpret_cast<uint32_t*>(b + L.hist);
+  w.dig = reinterpret_cast<uint32_t*>(b + L.dig);
+  w.desc0 = reinterpret_cast<uint32_t*>(b + L.desc0);
+  w.desc1 = reinterpret_cast<uint32_t*>(b + L.desc1);
+  w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
+  w.dfv = reinterpret_cast<float*>(b + L.dfv);
+  w.fgrad = reinterpret_cast<float4*>(b + L.fgrad);
+  w.sorted_vals = (L.passes & 1) ? w.vals1 : w.vals0;
+  return w;
+}
+
+int hist_blocks(const gmr_ctx* h) { return std::max(1, h->num_cus) * 4; }
+
+// Records a HIP event pair around the enclosed launches when profiling is on.
+struct StageTimer {
+  gmr_ctx* h;
+  hipStream_t s;
+  gmr_ctx::Rec r;
+  bool on;
+  StageTimer(gmr_ctx* h_, hipStream_t s_, int stage) : h(h_), s(s_), on(h_ && h_->prof) {
+    r.stage = stage;
+    if (on) {
+      on = hipEventCreate(&r.a) == hipSuccess && hipEventCreate(&r.b) == hipSuccess;
+      if (on) (void)hipEventRecord(r.a, s);
+    }
+  }
+  ~StageTimer() {
+    if (on) {
+      (void)hipEventRecord(r.b, s);
+      h->recs.push_back(r);
+    }
+  }
+};
+
+// Conversion + projection + binning + sort (+ optionally zeroing the face-view gradients).
+void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* table, const float* verts,
+                 const int32_t* faces, const float* colors, const WsPtrs& w, bool zero_dfv, hipStream_t s) {
+  const KOpts ko = kopts(o);
+  {
+    StageTimer t(h, s, kStProject);
+    launch_project(table, p.f_total, verts, faces, colors, ko, w.rec, w.bin, w.cnt,
+                   zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, s);
+  }
+  {
+    StageTimer t(h, s, kStScanEmit);
+    launch_bin(w.cnt, w.bin, p.fv_total, w.bsum, w.boff, p.L.scan_blocks, w.hdr, w.hist, kMaxPasses * 256,
+               (uint32_t)p.L.capacity, (uint32_t)p.L.passes, w.keys0, w.vals0, s);
+  }
+  {
+    StageTimer t(h, s, kStSortHist);
+    launch_sort_hist(w.keys0, w.hdr, w.hist, w.dig, w.desc0, p.L.sort_parts, p.L.passes, hist_blocks(h), s);
+  }
+  for (int pass = 0; pass < p.L.passes; ++pass) {
+    StageTimer t(h, s, kStSortPass);
+    launch_sort_pass(w.keys0, w.vals0, w.keys1, w.vals1, w.hdr, w.dig, w.desc0, w.desc1, p.L.sort_parts, pass, s);
+  }
+  {
+    StageTimer t(h, s, kStRanges);
+    launch_tile_ranges((p.L.passes & 1) ? w.keys1 : w.keys0, w.hdr, w.ranges, p.tiles_total, hist_blocks(h), s);
+  }
+}
+
+int persistent_blocks(const gmr_ctx* h, const gmr_options* o) { return o->raster_mode == 1 ? h->num_cus * 8 : 0; }
+
+gmr_status check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GMR_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return GMR_OK;
+}
+
+gmr_status common_checks(gmr_handle h, const void* table, const void* ws, size_t ws_bytes, const Plan& p) {
+  if (!h) return fail(GMR_ERR_INVALID_ARG, "handle is NULL");
+  if (!table) return fail(GMR_ERR_INVALID_ARG, "table_dev is NULL");
+  if (!ws) return fail(GMR_ERR_INVALID_ARG, "ws_dev is NULL");
+  if (ws_bytes < p.L.total) return fail(GMR_ERR_WORKSPACE, "workspace smaller than gmr_workspace_size");
+  return GMR_OK;
+}
+
+gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table, const float* verts,
+                    const int32_t* faces, const float* colors, const float* d_rgb, const float* d_alpha, const float* rgb,
+                    const float* target, float loss_weight, const void* saved, const int32_t* adj_off,
+                    const int32_t* adj_ent, int32_t recompute, float* d_verts, float* d_colors, float* loss_dev, void* ws,
+                    size_t ws_bytes, void* stream) {
+  Plan p;
+  gmr_status st = make_plan(batch, opt, true, p);
+  if (st != GMR_OK) return st;
+  st = common_checks(h, table, ws, ws_bytes, p);
+  if (st != GMR_OK) return st;
+  if (!verts || !faces || !colors || !saved || !adj_off || !adj_ent || !d_verts || !d_colors)
+    return fail(GMR_ERR_INVALID_ARG, "a required device pointer is NULL");
+  if (target ? !rgb : !d_rgb) return fail(GMR_ERR_INVALID_ARG, "need d_rgb, or rgb and target for the L2 form");
+  if (recompute != 0 && recompute != 1) return fail(GMR_ERR_INVALID_ARG, "recompute_lists must be 0 or 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const WsPtrs w = ws_ptrs(p.L, ws);
+  const KOpts ko = kopts(opt);
+  if (recompute) {
+    build_lists(h, p, opt, table, verts, faces, colors, w, true, s);
+  } else {
+    StageTimer t(h, s, kStFill);
+    launch_fill_f32(w.dfv, p.fv_total * 8, 0.f, s);
+  }
+  {
+    StageTimer t(h, s, kStFill);
+    launch_fill_u32(&w.hdr->work_bwd, 1, 0u, s);
+    launch_fill_f32(&w.hdr->loss, 1, 0.f, s);
+  }
+  const float* saved_T = static_cast<const float*>(saved);
+  const uint32_t* saved_n = reinterpret_cast<const uint32_t*>(saved_T + p.p_total);
+  const double n3 = 3.0 * (double)p.p_total;
+  {
+    StageTimer t(h, s, kStRasterBwd);
+    launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), w.ranges, w.sorted_vals, w.rec, ko, saved_T,
+                      saved_n, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
+                      w.dfv, w.hdr, s);
+  }
+  {
+    StageTimer t(h, s, kStFaceBwd);
+    launch_face_bwd(table, p.f_total, verts, faces, ko, reinterpret_cast<const float4*>(w.dfv), w.fgrad, s);
+  }
+  {
+    StageTimer t(h, s, kStGather);
+    launch_vertex_gather(adj_off, adj_ent, reinterpret_cast<const float*>(w.fgrad), p.v_total, d_verts, d_colors, s);
+  }
+  if (loss_dev) GMR_CHECK_HIP(hipMemcpyAsync(loss_dev, &w.hdr->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
+  return check_launch();
+}
+
+std::string tune_key(const Plan& p, const gmr_options* o) {
+  std::string k = std::to_string(p.nv) + ":" + std::to_string(p.f_total) + ":" + std::to_string(o->cov_mode);
+  for (const ViewDev& v : p.views) k += ":" + std::to_string(v.W) + "x" + std::to_string(v.H);
+  return k;
+}
+
+}  // namespace
+
+// ================================================================================================
+extern "C" {
+
+gmr_options gmr_default_options(void) {
+  gmr_options o;
+  std::memset(&o, 0, sizeof o);
+  o.cov_mode = 0;
+  o.dilation = 0.3f;
+  o.alpha_min = 1.0f / 255.0f;
+  o.alpha_max = 0.99f;
+  o.t_eps = 1e-4f;
+  o.bg[0] = o.bg[1] = o.bg[2] = 0.f;
+  o.tile_w = 16;
+  o.tile_h = 16;
+  o.raster_mode = 0;
+  o.reserved = 0;
+  o.instance_capacity = 0;
+  return o;
+}
+
+const char* gmr_status_string(gmr_status s) {
+  switch (s) {
+    case GMR_OK: return "ok";
+    case GMR_ERR_INVALID_ARG: return "invalid argument";
+    case GMR_ERR_WORKSPACE: return "workspace too small";
+    case GMR_ERR_CAPACITY: return "instance capacity exceeded";
+    case GMR_ERR_UNSUPPORTED: return "unsupported";
+    case GMR_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* gmr_last_error(void) { return g_err.c_str(); }
+
+gmr_status gmr_create(gmr_handle* out, int device) {
+  if (!out) return fail(GMR_ERR_INVALID_ARG, "out is NULL");
+  int n = 0;
+  GMR_CHECK_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(GMR_ERR_INVALID_ARG, "device out of range");
+  hipDeviceProp_t prop;
+  GMR_CHECK_HIP(hipGetDeviceProperties(&prop, device));
+  gmr_ctx* c = new gmr_ctx;
+  c->device = device;
+  c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  *out = c;
+  return GMR_OK;
+}
+
+gmr_status gmr_destroy(gmr_handle h) {
+  delete h;
+  return GMR_OK;
+}
+
+gmr_status gmr_view_table_size(const gmr_batch* batch, const gmr_options* opt, size_t* bytes) {
+  if (!bytes) return fail(GMR_ERR_INVALID_ARG, "bytes is NULL");
+  Plan p;
+  gmr_status st = make_plan(batch, opt, false, p);
+  if (st != GMR_OK) return st;
+  *bytes = p.table_bytes;
+  return GMR_OK;
+}
+
+gmr_status gmr_view_table_fill(const gmr_batch* batch, const gmr_options* opt, void* host_dst, size_t bytes) {
+  if (!host_dst) return fail(GMR_ERR_INVALID_ARG, "host_dst is NULL");
+  Plan p;
+  gmr_status st = make_plan(batch, opt, false, p);
+  if (st != GMR_OK) return st;
+  if (bytes < p.table_bytes) return fail(GMR_ERR_INVALID_ARG, "view table buffer too small");
+  write_table(p, host_dst);
+  return GMR_OK;
+}
+
+gmr_status gmr_workspace_size(const gmr_batch* batch, const gmr_options* opt, size_t* ws_bytes, size_t* saved_bytes) {
+  if (!ws_bytes || !saved_bytes) return fail(GMR_ERR_INVALID_ARG, "output pointer is NULL");
+  Plan p;
+  gmr_status st = make_plan(batch, opt, true, p);
+  if (st != GMR_OK) return st;
+  *ws_bytes = p.L.total;
+  *saved_bytes = (size_t)p.p_total * 8;
+  return GMR_OK;
+}
+
+gmr_status gmr_build_adjacency(const int32_t* faces, int64_t nf, int64_t nv, int32_t* off, int32_t* ent) {
+  if (!faces || !off || !ent || nf < 0 || nv < 0) return fail(GMR_ERR_INVALID_ARG, "bad adjacency arguments");
+  if (3 * nf >= (1ll << 31)) return fail(GMR_ERR_INVALID_ARG, "too many faces");
+  std::vector<int32_t> cnt(nv + 1, 0);
+  for (int64_t i = 0; i < 3 * nf; ++i) {
+    const int32_t v = faces[i];
+    if (v < 0 || v >= nv) return fail(GMR_ERR_INVALID_ARG, "face index out of range");
+    cnt[v + 1]++;
+  }
+  off[0] = 0;
+  for (int64_t v = 0; v < nv; ++v) off[v + 1] = off[v] + cnt[v + 1];
+  std::vector<int32_t> cur(off, off + nv);
+  for (int64_t i = 0; i < 3 * nf; ++i) ent[cur[faces[i]]++] = (int32_t)i;  // i = face * 3 + corner, ascending
+  return GMR_OK;
+}
+
+gmr_status gmr_render_fwd(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
+                          const float* verts, const int32_t* faces, const float* colors, float* out_rgb, float* out_alpha,
+                          void* saved, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  gmr_status st = make_plan(batch, opt, true, p);
+  if (st != GMR_OK) return st;
+  st = common_checks(h, table, ws, ws_bytes, p);
+  if (st != GMR_OK) return st;
+  if (!verts || !faces || !colors || !out_rgb || !saved) return fail(GMR_ERR_INVALID_ARG, "a required device pointer is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const WsPtrs w = ws_ptrs(p.L, ws);
+  build_lists(h, p, opt, table, verts, faces, colors, w, false, s);
+  float* saved_T = static_cast<float*>(saved);
+  uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
+  {
+    StageTimer t(h, s, kStRasterFwd);
+    launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), w.ranges, w.sorted_vals, w.rec, kopts(opt),
+                      out_rgb, out_alpha, saved_T, saved_n, w.hdr, s);
+  }
+  return check_launch();
+}
+
+gmr_status gmr_profile_enable(gmr_handle h, int32_t enable) {
+  if (!h) return fail(GMR_ERR_INVALID_ARG, "handle is NULL");
+  for (auto& r : h->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  h->recs.clear();
+  h->prof = enable != 0;
+  return GMR_OK;
+}
+
+gmr_status gmr_profile_read(gmr_handle h, int32_t max_stages, char* names, float* ms_total, int32_t* launches,
+                            int32_t* n_stages) {
+  if (!h || !names || !ms_total || !launches || !n_stages || max_stages < kNumStages)
+    return fail(GMR_ERR_INVALID_ARG, "bad profile arguments");
+  for (int i = 0; i < kNumStages; ++i) {
+    std::memset(names + 32 * i, 0, 32);
+    std::strncpy(names + 32 * i, kStageNames[i], 31);
+    ms_total[i] = 0.f;
+    launches[i] = 0;
+  }
+  for (auto& r : h->recs) {
+    GMR_CHECK_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    GMR_CHECK_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    ms_total[r.stage] += ms;
+    launches[r.stage] += 1;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  h->recs.clear();
+  *n_stages = kNumStages;
+  return GMR_OK;
+}
+
+gmr_status gmr_render_bwd(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
+                          const float* verts, const int32_t* faces, const float* colors, const float* d_rgb,
+                          const float* d_alpha, const void* saved, const int32_t* adj_off, const int32_t* adj_ent,
+                          int32_t recompute, float* d_verts, float* d_colors, void* ws, size_t ws_bytes, void* stream) {
+  return bwd_impl(h, batch, opt, table, verts, faces, colors, d_rgb, d_alpha, nullptr, nullptr, 0.f, saved, adj_off,
+                  adj_ent, recompute, d_verts, d_colors, nullptr, ws, ws_bytes, stream);
+}
+
+gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
+                             const float* verts, const int32_t* faces, const float* colors, const float* rgb,
+                             const float* target, float loss_weight, const void* saved, const int32_t* adj_off,
+                             const int32_t* adj_ent, int32_t recompute, float* d_verts, float* d_colors, float* loss_dev,
+                             void* ws, size_t ws_bytes, void* stream) {
+  if (!rgb || !target) return fail(GMR_ERR_INVALID_ARG, "rgb and target must not be NULL");
+  if (!std::isfinite(loss_weight)) return fail(GMR_ERR_INVALID_ARG, "loss_weight must be finite");
+  return bwd_impl(h, batch, opt, table, verts, faces, colors, nullptr, nullptr, rgb, target, loss_weight, saved, adj_off,
+                  adj_ent, recompute, d_verts, d_colors, loss_dev, ws, ws_bytes, stream);
+}
+
+gmr_status gmr_workspace_view(const gmr_batch* batch, const gmr_options* opt, size_t* ranges_off, size_t* vals_off,
+                              size_t* rec_off, size_t* bin_off) {
+  if (!ranges_off || !vals_off || !rec_off || !bin_off) return fail(GMR_ERR_INVALID_ARG, "output pointer is NULL");
+  Plan p;
+  gmr_status st = make_plan(batch, opt, true, p);
+  if (st != GMR_OK) return st;
+  *ranges_off = p.L.ranges;
+  *vals_off = (p.L.passes & 1) ? p.L.vals1 : p.L.vals0;
+  *rec_off = p.L.rec;
+  *bin_off = p.L.bin;
+  return GMR_OK;
+}
+
+gmr_status gmr_read_counters(const void* ws, size_t ws_bytes, gmr_counters* out, void* stream) {
+  if (!ws || !out || ws_bytes < sizeof(WsHdr)) return fail(GMR_ERR_INVALID_ARG, "bad arguments");
+  WsHdr hdr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GMR_CHECK_HIP(hipMemcpyAsync(&hdr, ws, sizeof hdr, hipMemcpyDeviceToHost, s));
+  GMR_CHECK_HIP(hipStreamSynchronize(s));
+  out->instances = hdr.count;
+  out->capacity = hdr.capacity;
+  out->overflow = (int32_t)hdr.overflow;
+  out->reserved = 0;
+  return GMR_OK;
+}
+
+gmr_status gmr_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                         int32_t* step, void* stream) {
+  if (!p || !g || !m || !v || !step || n < 0) return fail(GMR_ERR_INVALID_ARG, "bad Adam arguments");
+  if (!(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps > 0.f && std::isfinite(lr)))
+    return fail(GMR_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  launch_adam(p, g, m, v, n, lr, b1, b2, eps, step, static_cast<hipStream_t>(stream));
+  return check_launch();
+}
+
+gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options* base, const float* verts,
+                        const int32_t* faces, const float* colors, const float* target, const int32_t* adj_off,
+                        const int32_t* adj_ent, int32_t iters, gmr_options* best_out, float* ms_out, void* stream) {
+  if (!h || !best_out || !verts || !faces || !colors || !target || !adj_off || !adj_ent || iters < 1)
+    return fail(GMR_ERR_INVALID_ARG, "bad autotune arguments");
+  Plan p0;
+  gmr_options b = *base;
+  if (b.instance_capacity <= 0) b.instance_capacity = 1;
+  gmr_status st = make_plan(batch, &b, true, p0);
+  if (st != GMR_OK) return st;
+  const std::string key = tune_key(p0, &b);
+  auto it = h->tune_cache.find(key);
+  if (it != h->tune_cache.end()) {
+    *best_out = it->second.first;
+    if (ms_out) *ms_out = it->second.second;
+    return GMR_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int shapes[][2] = {{8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}};
+  float best_ms = 1e30f;
+  gmr_options best = b;
+  float *rgb = nullptr, *dv = nullptr, *dc = nullptr;
+  void *saved = nullptr, *ws = nullptr, *table = nullptr;
+  size_t ws_cap = 0, table_cap = 0;
+  GMR_CHECK_HIP(hipMalloc(&rgb, sizeof(float) * 3 * p0.p_total));
+  GMR_CHECK_HIP(hipMalloc(&saved, 8 * p0.p_total));
+  GMR_CHECK_HIP(hipMalloc(&dv, sizeof(float) * 3 * p0.v_total));
+  GMR_CHECK_HIP(hipMalloc(&dc, sizeof(float) * 3 * p0.v_total));
+  hipEvent_t e0, e1;
+  GMR_CHECK_HIP(hipEventCreate(&e0));
+  GMR_CHECK_HIP(hipEventCreate(&e1));
+  gmr_status result = GMR_OK;
+  for (const auto& sh : shapes) {
+    for (int mode = 0; mode < 2 && result == GMR_OK; ++mode) {
+      gmr_options o = b;
+      o.tile_w = sh[0];
+      o.tile_h = sh[1];
+      o.raster_mode = mode;
+      o.instance_capacity = std::max<int64_t>(b.instance_capacity, 1 << 20);
+      for (int attempt = 0; attempt < 3 && result == GMR_OK; ++attempt) {
+        Plan p;
+        if ((result = make_plan(batch, &o, true, p)) != GMR_OK) break;
+        if (p.table_bytes > table_cap) {
+          if (table) (void)hipFree(table);
+          table_cap = p.table_bytes;
+          if (hipMalloc(&table, table_cap) != hipSuccess) { result = fail(GMR_ERR_HIP, "autotune: hipMalloc"); break; }
+        }
+        std::vector<char> tb(p.table_bytes);
+        write_table(p, tb.data());
+        if (hipMemcpy(table, tb.data(), p.table_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+          result = fail(GMR_ERR_HIP, "autotune: hipMemcpy");
+          break;
+        }
+        if (p.L.total > ws_cap) {
+          if (ws) (void)hipFree(ws);
+          ws_cap = p.L.total;
+          if (hipMalloc(&ws, ws_cap) != hipSuccess) { result = fail(GMR_ERR_HIP, "autotune: hipMalloc workspace"); break; }
+        }
+        if ((result = gmr_render_fwd(h, batch, &o, table, verts, faces, colors, rgb, nullptr, saved, ws, ws_cap, s)) != GMR_OK) break;
+        gmr_counters c;
+        if ((result = gmr_read_counters(ws, ws_cap, &c, s)) != GMR_OK) break;
+        if (c.overflow) {
+          o.instance_capacity = std::min<int64_t>((1ll << 30) - 1, (int64_t)(c.instances * 1.25) + 1024);
+          continue;
+        }
+        // warm-up + timed iterations of forward + fused L2 backward (lists reused)
+        if ((result = gmr_render_bwd_l2(h, batch, &o, table, verts, faces, colors, rgb, target, 1.f, saved, adj_off,
+                                        adj_ent, 0, dv, dc, nullptr, ws, ws_cap, s)) != GMR_OK)
+          break;
+        (void)hipEventRecord(e0, s);
+        for (int i = 0; i < iters && result == GMR_OK; ++i) {
+          result = gmr_render_fwd(h, batch, &o, table, verts, faces, colors, rgb, nullptr, saved, ws, ws_cap, s);
+          if (result == GMR_OK)
+            result = gmr_render_bwd_l2(h, batch, &o, table, verts, faces, colors, rgb, target, 1.f, saved, adj_off, adj_ent,
+                                       0, dv, dc, nullptr, ws, ws_cap, s);
+        }
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) { result = fail(GMR_ERR_HIP, "autotune: event sync"); break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)iters;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = o;
+          best.instance_capacity = std::min<int64_t>((1ll << 30) - 1, (int64_t)(c.instances * 1.25) + 1024);
+        }
+        break;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(rgb);
+  (void)hipFree(saved);
+  (void)hipFree(dv);
+  (void)hipFree(dc);
+  if (ws) (void)hipFree(ws);
+  if (table) (void)hipFree(table);
+  if (result != GMR_OK) return result;
+  h->tune_cache[key] = {best, best_ms};
+  *best_out = best;
+  if (ms_out) *ms_out = best_ms;
+  return GMR_OK;
+}
+
+}  // extern "C"

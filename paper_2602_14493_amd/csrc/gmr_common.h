@@ -1,0 +1,228 @@
+// Internal layouts and device helpers of libgmr (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gmr.h"
+
+namespace gmr {
+
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kSub = 8;              // raster sub-block side: one 8x8 pixel block per wavefront
+constexpr int kRecF4 = 3;            // projected record = 3 x float4 = 48 B per face-view
+constexpr int kSortBlock = 256;      // onesweep workgroup (4 wavefronts)
+constexpr int kSortItems = 16;       // keys per thread
+constexpr int kSortPart = kSortBlock * kSortItems;  // keys per partition
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanBlock * kScanItems;  // face-views per scan block
+constexpr int kMaxPasses = 8;
+constexpr uint32_t kFlagAgg = 1u << 30;   // onesweep partition descriptor: aggregate published
+constexpr uint32_t kFlagInc = 2u << 30;   // inclusive prefix published
+constexpr uint32_t kValMask = (1u << 30) - 1u;
+
+// Device view table --------------------------------------------------------------------------
+struct TableHdr {          // 80 B
+  int32_t num_views, num_meshes, tile_w, tile_h;
+  int32_t tiles_total, sub_x, sub_y, items_total;   // sub_x/y: 8x8 blocks per tile; items = tiles*sub
+  int64_t fv_total, pixels_total, faces_total;
+  int32_t views_off, mesh_face_off, mesh_view_off, mesh_views_off;  // byte offsets in the table
+  int32_t pad[2];
+};
+struct ViewDev {           // 128 B
+  float R[9], t[3];
+  float fx, fy, cx, cy;
+  int32_t W, H, tiles_x, tiles_y;
+  int64_t fv_offset, pixel_offset;
+  int32_t tile_base, mesh, face_begin, face_end;
+  float znear, zfar;
+  int32_t pad[2];
+};
+static_assert(sizeof(TableHdr) == 80, "table header");
+static_assert(sizeof(ViewDev) == 128, "view record");
+
+__host__ __device__ inline const ViewDev* table_views(const void* t) {
+  return reinterpret_cast<const ViewDev*>(static_cast<const char*>(t) + static_cast<const TableHdr*>(t)->views_off);
+}
+__host__ __device__ inline const int32_t* table_i32(const void* t, int32_t off) {
+  return reinterpret_cast<const int32_t*>(static_cast<const char*>(t) + off);
+}
+
+// Workspace header (device counters) ------------------------------------------------------------
+struct WsHdr {                 // 256 B at the start of the workspace
+  uint32_t count;              // instances generated (may exceed capacity)
+  uint32_t overflow;
+  uint32_t capacity;
+  uint32_t passes;
+  uint32_t part_ctr[kMaxPasses];   // onesweep partition tickets, one per pass
+  uint32_t work_fwd, work_bwd;     // persistent raster queues
+  uint32_t pad0[2];
+  float loss;                      // L2 loss value of the last fused backward
+  uint32_t pad1[47];
+};
+static_assert(sizeof(WsHdr) == 256, "ws header");
+
+// Kernel-side options (plain values) ---------------------------------------------------------------
+struct KOpts {
+  int32_t cov_mode;
+  float dilation, alpha_min, alpha_max, t_eps;
+  float bg0, bg1, bg2;
+};
+
+// Workspace layout, computed on the host (byte offsets) -------------------------------------------
+struct Layout {
+  size_t hdr, rec, bin, cnt, bsum, boff, keys0, keys1, vals0, vals1, hist, dig, desc0, desc1, ranges,
+      dfv, fgrad, total;
+  int64_t fv_total, faces_total, pixels_total, capacity;
+  int32_t tiles_total, items_total, passes, key_bits, scan_blocks, sort_parts;
+};
+
+// Small device helpers -------------------------------------------------------------------------------
+__device__ inline float u2f(uint32_t x) { return __uint_as_float(x); }
+__device__ inline uint32_t f2u(float x) { return __float_as_uint(x); }
+
+__device__ inline uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ inline void wave_lds_sync() {
+  // LDS requests of one wavefront complete in order; this keeps the compiler from reordering an
+  // LDS store of one lane past a later LDS load of another lane.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Mesh containing global face f (face offsets are ascending).
+__device__ inline int find_mesh(const int32_t* mesh_face_off, int num_meshes, int32_t f) {
+  int lo = 0, hi = num_meshes - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (mesh_face_off[mid] <= f) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// View containing global tile t (tile bases are ascending).
+__device__ inline int find_view_by_tile(const ViewDev* views, int nv, int32_t t) {
+  int lo = 0, hi = nv - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (views[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Conversion of one face (Sec. 2.2) in closed form, double precision.  The uniform triangle's
+// covariance sum_q (q - mu)(q - mu)^T / 12 written with the edges e1 = v_j - v_i, e2 = v_k - v_i
+// is (2 e1 e1^T + 2 e2 e2^T - e1 e2^T - e2 e1^T) / 36: the embedded 2D covariance of Eq. 15.
+// Eq. 13 scales it by kappa = |A| / (pi sqrt(max(lambda1 lambda2, eps))) with lambda1 lambda2 =
+// |A|^2 / 108 and adds s_z^2 n n^T.
+struct FaceGeo {
+  double e1[3], e2[3], m[3];   // edges and their cross product
+  double mm, area, kappa;      // |m|, |A|, kappa (1 in the embedded form)
+  bool clamped;                // kappa from the epsilon branch of Eq. 12
+  double mu[3];
+  double S[6];                 // xx xy xz yy yz zz
+};
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kEpsL = 1e-14;   // Eq. 12
+constexpr double kSz2 = 1e-12;    // s_z^2, s_z = 1e-6
+
+__device__ inline bool face_convert(const double* vi, const double* vj, const double* vk, int cov_mode, FaceGeo& g) {
+  for (int a = 0; a < 3; ++a) { g.e1[a] = vj[a] - vi[a]; g.e2[a] = vk[a] - vi[a]; }
+  g.m[0] = g.e1[1] * g.e2[2] - g.e1[2] * g.e2[1];
+  g.m[1] = g.e1[2] * g.e2[0] - g.e1[0] * g.e2[2];
+  g.m[2] = g.e1[0] * g.e2[1] - g.e1[1] * g.e2[0];
+  double mm2 = g.m[0] * g.m[0] + g.m[1] * g.m[1] + g.m[2] * g.m[2];
+  if (!(mm2 > 0.0) || !(mm2 < 1e300)) return false;
+  g.mm = sqrt(mm2);
+  g.area = 0.5 * g.mm;
+  for (int a = 0; a < 3; ++a) g.mu[a] = (vi[a] + vj[a] + vk[a]) * (1.0 / 3.0);
+  const double* e1 = g.e1;
+  const double* e2 = g.e2;
+  double M[6];
+  M[0] = 2.0 * e1[0] * e1[0] + 2.0 * e2[0] * e2[0] - 2.0 * e1[0] * e2[0];
+  M[1] = 2.0 * e1[0] * e1[1] + 2.0 * e2[0] * e2[1] - e1[0] * e2[1] - e2[0] * e1[1];
+  M[2] = 2.0 * e1[0] * e1[2] + 2.0 * e2[0] * e2[2] - e1[0] * e2[2] - e2[0] * e1[2];
+  M[3] = 2.0 * e1[1] * e1[1] + 2.0 * e2[1] * e2[1] - 2.0 * e1[1] * e2[1];
+  M[4] = 2.0 * e1[1] * e1[2] + 2.0 * e2[1] * e2[2] - e1[1] * e2[2] - e2[1] * e1[2];
+  M[5] = 2.0 * e1[2] * e1[2] + 2.0 * e2[2] * e2[2] - 2.0 * e1[2] * e2[2];
+  if (cov_mode == 1) {
+    g.kappa = 1.0;
+    g.clamped = false;
+    for (int a = 0; a < 6; ++a) g.S[a] = M[a] * (1.0 / 36.0);
+    return true;
+  }
+  double det2 = g.area * g.area * (1.0 / 108.0);
+  g.clamped = !(det2 >= kEpsL);
+  g.kappa = g.area / (kPi * sqrt(g.clamped ? kEpsL : det2));
+  double inv = 1.0 / g.mm;
+  double n0 = g.m[0] * inv, n1 = g.m[1] * inv, n2 = g.m[2] * inv;
+  double k36 = g.kappa * (1.0 / 36.0);
+  g.S[0] = k36 * M[0] + kSz2 * n0 * n0;
+  g.S[1] = k36 * M[1] + kSz2 * n0 * n1;
+  g.S[2] = k36 * M[2] + kSz2 * n0 * n2;
+  g.S[3] = k36 * M[3] + kSz2 * n1 * n1;
+  g.S[4] = k36 * M[4] + kSz2 * n1 * n2;
+  g.S[5] = k36 * M[5] + kSz2 * n2 * n2;
+  return true;
+}
+
+// EWA projection of (mu, S) through view V, double precision (Sec. 2.1's splatting: first-order
+// Jacobian of the pinhole at the mean; a `dilation` px^2 low-pass on the screen covariance).
+struct ProjGeo {
+  double p[3];         // camera-space mean
+  double J[6];         // 2x3 Jacobian of (u, v) w.r.t. p
+  double W[6];         // R S R^T (xx xy xz yy yz zz)
+  double sxx, sxy, syy, det;
+  double a, b, c;      // conic = inverse screen covariance
+  double u, v;
+};
+
+__device__ inline bool view_project(const ViewDev& V, const double* mu, const double* S, double dilation, ProjGeo& q) {
+  for (int r = 0; r < 3; ++r)
+    q.p[r] = (double)V.R[3 * r] * mu[0] + (double)V.R[3 * r + 1] * mu[1] + (double)V.R[3 * r + 2] * mu[2] + (double)V.t[r];
+  if (!(q.p[2] > (double)V.znear) || !(q.p[2] < (double)V.zfar)) return false;
+  double iz = 1.0 / q.p[2];
+  double fx = V.fx, fy = V.fy;
+  q.J[0] = fx * iz; q.J[1] = 0.0; q.J[2] = -fx * q.p[0] * iz * iz;
+  q.J[3] = 0.0; q.J[4] = fy * iz; q.J[5] = -fy * q.p[1] * iz * iz;
+  // W = R S R^T with S symmetric (xx xy xz yy yz zz)
+  double Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+  double RS[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      RS[3 * r + c] = (double)V.R[3 * r] * Sf[c] + (double)V.R[3 * r + 1] * Sf[3 + c] + (double)V.R[3 * r + 2] * Sf[6 + c];
+  double Wf[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = r; c < 3; ++c)
+      Wf[3 * r + c] = RS[3 * r] * (double)V.R[3 * c] + RS[3 * r + 1] * (double)V.R[3 * c + 1] + RS[3 * r + 2] * (double)V.R[3 * c + 2];
+  q.W[0] = Wf[0]; q.W[1] = Wf[1]; q.W[2] = Wf[2]; q.W[3] = Wf[4]; q.W[4] = Wf[5]; q.W[5] = Wf[8];
+  // J W J^T with J = [[j0 0 j2],[0 j4 j5]]
+  double w00 = q.W[0], w01 = q.W[1], w02 = q.W[2], w11 = q.W[3], w12 = q.W[4], w22 = q.W[5];
+  double j0 = q.J[0], j2 = q.J[2], j4 = q.J[4], j5 = q.J[5];
+  double t0 = j0 * w00 + j2 * w02, t1 = j0 * w01 + j2 * w12, t2 = j0 * w02 + j2 * w22;   // row 0 of J W
+  double s1 = j4 * w11 + j5 * w12, s2 = j4 * w12 + j5 * w22;                               // row 1 (cols 1,2)
+  q.sxx = t0 * j0 + t2 * j2 + dilation;
+  q.sxy = t1 * j4 + t2 * j5;
+  q.syy = s1 * j4 + s2 * j5 + dilation;
+  q.det = q.sxx * q.syy - q.sxy * q.sxy;
+  if (!(q.det > 0.0)) return false;
+  double id = 1.0 / q.det;
+  q.a = q.syy * id;
+  q.b = -q.sxy * id;
+  q.c = q.sxx * id;
+  q.u = fx * q.p[0] * iz + (double)V.cx;
+  q.v = fy * q.p[1] * iz + (double)V.cy;
+  return true;
+}
+
+// exp(power) = exp2(-(k w)^2) with w = L (dx, dy), L^T L = conic, k^2 = log2(e) / 2.
+constexpr double kHalfLog2e = 0.72134752044448170368;   // log2(e) / 2
+constexpr float kTwoLn2 = 1.3862943611198906f;           // 1 / k^2
+
+// Pixel-centre predicate of the 3-sigma extent, per axis: the pixels i with |i + 0.5 - u| <= r
+// are ceil(u - r - 0.5) .. floor(u + r - 0.5) (computed in double by the projection).
+
+}  // namespace gmr

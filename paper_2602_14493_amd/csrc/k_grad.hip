@@ -1,0 +1,240 @@
+// Backward of the EWA projection and of the conversion, then the per-vertex gather.
+//
+// k_face_bwd: one thread per face (double precision).  For every view of the face's mesh it reads
+// the face-view's screen-space gradient {du, dv, da, db, dc, dr, dg, db}, re-derives the
+// projection and accumulates dL/dmu and dL/dSigma over views (gradients as full symmetric
+// matrices: dL = tr(G dX)):
+//   conic Q = Sigma'^-1:           G_Sigma' = -Q Gq Q, Gq = [[da, db/2], [db/2, dc]]
+//   Sigma' = J W J^T + d I:        G_W = J^T G_Sigma' J,  G_J = 2 G_Sigma' J W
+//   W = R Sigma R^T:               G_Sigma = R^T G_W R
+//   J(p), (u, v)(p), p = R mu + t: G_mu = R^T G_p
+// then differentiates the closed-form conversion (same expressions as the forward):
+//   Sigma = kappa/36 M + s_z^2 n n^T, M = 2 e1 e1^T + 2 e2 e2^T - e1 e2^T - e2 e1^T
+//   dM: G_e1 = G (4 e1 - 2 e2), G_e2 = G (4 e2 - 2 e1)
+//   n = m/|m|, m = e1 x e2: G_n = 2 s_z^2 G n, G_m = (I - n n^T) G_n / |m|
+//   clamped kappa = |A| / (pi sqrt(eps)), |A| = |m|/2: G_m += tr(G M)/36 / (pi sqrt(eps)) n / 2
+//   m = e1 x e2: G_e1 += e2 x G_m, G_e2 += G_m x e1; mu = (v_i + v_j + v_k)/3
+// and writes per-corner vertex gradients and the face's colour gradient (12 floats per face).
+// k_vertex_gather: one thread per vertex sums its corners through the (vertex -> face, corner)
+// CSR in a fixed order, so the vertex gradients do not depend on atomic ordering.
+#include "gmr_common.h"
+#include "gmr_launch.h"
+
+namespace gmr {
+
+__device__ inline void sym3_from6(const double* s, double (&M)[3][3]) {
+  M[0][0] = s[0]; M[0][1] = s[1]; M[0][2] = s[2];
+  M[1][0] = s[1]; M[1][1] = s[3]; M[1][2] = s[4];
+  M[2][0] = s[2]; M[2][1] = s[4]; M[2][2] = s[5];
+}
+
+__global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table, const float* __restrict__ verts,
+                                                  const int32_t* __restrict__ faces, KOpts o,
+                                                  const float4* __restrict__ dfv, float4* __restrict__ fgrad) {
+  const TableHdr* th = static_cast<const TableHdr*>(table);
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= th->faces_total) return;
+  const int32_t* mfo = table_i32(table, th->mesh_face_off);
+  const int32_t* mvo = table_i32(table, th->mesh_view_off);
+  const int32_t* mvs = table_i32(table, th->mesh_views_off);
+  const ViewDev* views = table_views(table);
+  const int m = find_mesh(mfo, th->num_meshes, (int32_t)f);
+  const int32_t i0 = faces[3 * f], i1 = faces[3 * f + 1], i2 = faces[3 * f + 2];
+  double vi[3], vj[3], vk[3];
+  for (int a = 0; a < 3; ++a) {
+    vi[a] = verts[3 * (int64_t)i0 + a];
+    vj[a] = verts[3 * (int64_t)i1 + a];
+    vk[a] = verts[3 * (int64_t)i2 + a];
+  }
+  FaceGeo g;
+  float4* out = fgrad + 3 * f;
+  if (!face_convert(vi, vj, vk, o.cov_mode, g)) {
+    out[0] = out[1] = out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  double Gmu[3] = {0.0, 0.0, 0.0};
+  double GS[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  float gcol[3] = {0.f, 0.f, 0.f};
+  for (int k = mvo[m]; k < mvo[m + 1]; ++k) {
+    const ViewDev& V = views[mvs[k]];
+    const int64_t fv = V.fv_offset + (f - V.face_begin);
+    const float4 d0 = dfv[2 * fv], d1 = dfv[2 * fv + 1];
+    if (d0.x == 0.f && d0.y == 0.f && d0.z == 0.f && d0.w == 0.f && d1.x == 0.f && d1.y == 0.f && d1.z == 0.f &&
+        d1.w == 0.f)
+      continue;
+    gcol[0] += d1.y; gcol[1] += d1.z; gcol[2] += d1.w;
+    ProjGeo q;
+    if (!view_project(V, g.mu, g.S, (double)o.dilation, q)) continue;
+    const double du = d0.x, dv = d0.y, da = d0.z, db = d0.w, dc = d1.x;
+    // G_Sigma' = -Q Gq Q
+    const double a = q.a, b = q.b, c = q.c;
+    const double m00 = a * da + b * 0.5 * db, m01 = a * 0.5 * db + b * dc;
+    const double m10 = b * da + c * 0.5 * db, m11 = b * 0.5 * db + c * dc;
+    const double gxx = -(m00 * a + m01 * b), gxy = -(m00 * b + m01 * c), gyy = -(m10 * b + m11 * c);
+    const double j0 = q.J[0], j2 = q.J[2], j4 = q.J[4], j5 = q.J[5];
+    // G J (2x3)
+    const double GJ[2][3] = {{gxx * j0, gxy * j4, gxx * j2 + gxy * j5}, {gxy * j0, gyy * j4, gxy * j2 + gyy * j5}};
+    // G_W = J^T (G J); J^T rows: (j0, 0), (0, j4), (j2, j5)
+    double GW[3][3];
+    for (int cc = 0; cc < 3; ++cc) {
+      GW[0][cc] = j0 * GJ[0][cc];
+      GW[1][cc] = j4 * GJ[1][cc];
+      GW[2][cc] = j2 * GJ[0][cc] + j5 * GJ[1][cc];
+    }
+    // G_J = 2 (G J) W
+    double Wm[3][3];
+    sym3_from6(q.W, Wm);
+    double GJm[2][3];
+    for (int r = 0; r < 2; ++r)
+      for (int cc = 0; cc < 3; ++cc)
+        GJm[r][cc] = 2.0 * (GJ[r][0] * Wm[0][cc] + GJ[r][1] * Wm[1][cc] + GJ[r][2] * Wm[2][cc]);
+    // G_Sigma += R^T G_W R
+    double R[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) R[r][cc] = (double)V.R[3 * r + cc];
+    double GWR[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) GWR[r][cc] = GW[r][0] * R[0][cc] + GW[r][1] * R[1][cc] + GW[r][2] * R[2][cc];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) GS[r][cc] += R[0][r] * GWR[0][cc] + R[1][r] * GWR[1][cc] + R[2][r] * GWR[2][cc];
+    // G_p from J(p) and (u, v)(p)
+    const double x = q.p[0], y = q.p[1], iz = 1.0 / q.p[2];
+    const double fx = V.fx, fy = V.fy;
+    double Gp[3];
+    Gp[0] = GJm[0][2] * (-fx * iz * iz) + du * fx * iz;
+    Gp[1] = GJm[1][2] * (-fy * iz * iz) + dv * fy * iz;
+    Gp[2] = GJm[0][0] * (-fx * iz * iz) + GJm[0][2] * (2.0 * fx * x * iz * iz * iz) + GJm[1][1] * (-fy * iz * iz) +
+            GJm[1][2] * (2.0 * fy * y * iz * iz * iz) - du * fx * x * iz * iz - dv * fy * y * iz * iz;
+    for (int r = 0; r < 3; ++r) Gmu[r] += R[0][r] * Gp[0] + R[1][r] * Gp[1] + R[2][r] * Gp[2];
+  }
+  // symmetrise (G_Sigma is symmetric up to rounding)
+  for (int r = 0; r < 3; ++r)
+    for (int cc = r + 1; cc < 3; ++cc) {
+      const double s = 0.5 * (GS[r][cc] + GS[cc][r]);
+      GS[r][cc] = GS[cc][r] = s;
+    }
+  const double* e1 = g.e1;
+  const double* e2 = g.e2;
+  const double scale = (o.cov_mode == 1 ? 1.0 : g.kappa) / 36.0;
+  double Ge1[3], Ge2[3];
+  for (int r = 0; r < 3; ++r) {
+    const double G1 = GS[r][0] * e1[0] + GS[r][1] * e1[1] + GS[r][2] * e1[2];
+    const double G2 = GS[r][0] * e2[0] + GS[r][1] * e2[1] + GS[r][2] * e2[2];
+    Ge1[r] = scale * (4.0 * G1 - 2.0 * G2);
+    Ge2[r] = scale * (4.0 * G2 - 2.0 * G1);
+  }
+  if (o.cov_mode == 0) {
+    const double inv = 1.0 / g.mm;
+    const double n[3] = {g.m[0] * inv, g.m[1] * inv, g.m[2] * inv};
+    double Gn[3];
+    for (int r = 0; r < 3; ++r) Gn[r] = 2.0 * kSz2 * (GS[r][0] * n[0] + GS[r][1] * n[1] + GS[r][2] * n[2]);
+    const double nGn = n[0] * Gn[0] + n[1] * Gn[1] + n[2] * Gn[2];
+    double Gm[3];
+    for (int r = 0; r < 3; ++r) Gm[r] = (Gn[r] - n[r] * nGn) * inv;
+    if (g.clamped) {
+      double M[6];
+      M[0] = 2.0 * e1[0] * e1[0] + 2.0 * e2[0] * e2[0] - 2.0 * e1[0] * e2[0];
+      M[1] = 2.0 * e1[0] * e1[1] + 2.0 * e2[0] * e2[1] - e1[0] * e2[1] - e2[0] * e1[1];
+      M[2] = 2.0 * e1[0] * e1[2] + 2.0 * e2[0] * e2[2] - e1[0] * e2[2] - e2[0] * e1[2];
+      M[3] = 2.0 * e1[1] * e1[1] + 2.0 * e2[1] * e2[1] - 2.0 * e1[1] * e2[1];
+      M[4] = 2.0 * e1[1] * e1[2] + 2.0 * e2[1] * e2[2] - e1[1] * e2[2] - e2[1] * e1[2];
+      M[5] = 2.0 * e1[2] * e1[2] + 2.0 * e2[2] * e2[2] - 2.0 * e1[2] * e2[2];
+      const double trGM = GS[0][0] * M[0] + GS[1][1] * M[3] + GS[2][2] * M[5] +
+                          2.0 * (GS[0][1] * M[1] + GS[0][2] * M[2] + GS[1][2] * M[4]);
+      const double gA = trGM / 36.0 / (kPi * sqrt(kEpsL));
+      for (int r = 0; r < 3; ++r) Gm[r] += 0.5 * gA * n[r];
+    }
+    // m = e1 x e2
+    Ge1[0] += e2[1] * Gm[2] - e2[2] * Gm[1];
+    Ge1[1] += e2[2] * Gm[0] - e2[0] * Gm[2];
+    Ge1[2] += e2[0] * Gm[1] - e2[1] * Gm[0];
+    Ge2[0] += Gm[1] * e1[2] - Gm[2] * e1[1];
+    Ge2[1] += Gm[2] * e1[0] - Gm[0] * e1[2];
+    Ge2[2] += Gm[0] * e1[1] - Gm[1] * e1[0];
+  }
+  float gv[9];
+  for (int r = 0; r < 3; ++r) {
+    const double gm3 = Gmu[r] * (1.0 / 3.0);
+    gv[r] = (float)(-Ge1[r] - Ge2[r] + gm3);
+    gv[3 + r] = (float)(Ge1[r] + gm3);
+    gv[6 + r] = (float)(Ge2[r] + gm3);
+  }
+  out[0] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+  out[1] = make_float4(gv[4], gv[5], gv[6], gv[7]);
+  out[2] = make_float4(gv[8], gcol[0], gcol[1], gcol[2]);
+}
+
+__global__ __launch_bounds__(256) void k_vertex_gather(const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
+                                                       const float* __restrict__ fgrad, int64_t nv,
+                                                       float* __restrict__ dV, float* __restrict__ dC) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  float gx = 0.f, gy = 0.f, gz = 0.f, cr = 0.f, cg = 0.f, cb = 0.f;
+  for (int32_t e = off[v]; e < off[v + 1]; ++e) {
+    const int32_t fc = ent[e];
+    const int32_t f = fc / 3, corner = fc - 3 * f;
+    const float* p = fgrad + 12 * (int64_t)f;
+    gx += p[3 * corner];
+    gy += p[3 * corner + 1];
+    gz += p[3 * corner + 2];
+    cr += p[9];
+    cg += p[10];
+    cb += p[11];
+  }
+  const float third = 1.f / 3.f;
+  dV[3 * v] = gx; dV[3 * v + 1] = gy; dV[3 * v + 2] = gz;
+  dC[3 * v] = cr * third; dC[3 * v + 1] = cg * third; dC[3 * v + 2] = cb * third;
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t n, float val) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = val;
+}
+
+// Adam with bias correction; t = step + 1 is read from the device (advanced by k_adam_tick).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                                              const int32_t* __restrict__ step) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float t = (float)(*step + 1);
+  const float c1 = 1.f - powf(b1, t), c2 = 1.f - powf(b2, t);
+  const float gi = g[i];
+  const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+  const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_adam_tick(int32_t* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
+void launch_face_bwd(const void* table, int64_t faces_total, const float* verts, const int32_t* faces, const KOpts& o,
+                     const float4* dfv, float4* fgrad, hipStream_t s) {
+  if (faces_total <= 0) return;
+  hipLaunchKernelGGL(k_face_bwd, dim3((unsigned)((faces_total + 255) / 256)), dim3(256), 0, s, table, verts, faces, o, dfv,
+                     fgrad);
+}
+
+void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* fgrad, int64_t nv, float* dV, float* dC,
+                          hipStream_t s) {
+  if (nv <= 0) return;
+  hipLaunchKernelGGL(k_vertex_gather, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, off, ent, fgrad, nv, dV, dC);
+}
+
+void launch_fill_f32(float* p, int64_t n, float val, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)nb), dim3(256), 0, s, p, n, val);
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                 int32_t* step, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, step);
+  hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(64), 0, s, step);
+}
+
+}  // namespace gmr

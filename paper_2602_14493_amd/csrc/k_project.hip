@@ -1,0 +1,95 @@
+// Conversion (Sec. 2.2) fused with the EWA projection (Sec. 2.1), one thread per face.
+//
+// A face is converted once, in double precision, and projected into every view of its mesh.  Per
+// face-view it writes, view-major (coalesced across consecutive faces):
+//   rec[fv]  3 x float4 = 48 B  {u_hi, v_hi, u_lo, v_lo}  mean as float pairs (u = u_hi + u_lo)
+//                              {k l11, k l12, k l22, x-rect}  scaled Cholesky factor of the conic
+//                              {r, g, b, y-rect}              Eq. 16 colour; rects pack lo | hi << 16
+//   bin[fv]  uint4 = 16 B      {first tile, nx | ny << 16, tiles_x of the view, float32 depth bits}
+//   cnt[fv]  tiles touched (0 when culled)
+// The mean stays in double until it is split into two floats: a float32 pixel coordinate near
+// x = 1920 carries ~1e-4 px of rounding, which alone would move alpha by ~1e-4.
+#include "gmr_common.h"
+#include "gmr_launch.h"
+
+namespace gmr {
+
+__global__ __launch_bounds__(256) void k_project(const void* __restrict__ table, const float* __restrict__ verts,
+                                                 const int32_t* __restrict__ faces, const float* __restrict__ colors,
+                                                 KOpts o, float4* __restrict__ rec, uint4* __restrict__ bin,
+                                                 uint32_t* __restrict__ cnt, float4* __restrict__ dfv_zero) {
+  const TableHdr* th = static_cast<const TableHdr*>(table);
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= th->faces_total) return;
+  const int32_t* mfo = table_i32(table, th->mesh_face_off);
+  const int32_t* mvo = table_i32(table, th->mesh_view_off);
+  const int32_t* mvs = table_i32(table, th->mesh_views_off);
+  const ViewDev* views = table_views(table);
+  const int m = find_mesh(mfo, th->num_meshes, (int32_t)f);
+  const int tw = th->tile_w, tht = th->tile_h;
+
+  const int32_t i0 = faces[3 * f], i1 = faces[3 * f + 1], i2 = faces[3 * f + 2];
+  double vi[3], vj[3], vk[3];
+  for (int a = 0; a < 3; ++a) {
+    vi[a] = verts[3 * (int64_t)i0 + a];
+    vj[a] = verts[3 * (int64_t)i1 + a];
+    vk[a] = verts[3 * (int64_t)i2 + a];
+  }
+  FaceGeo g;
+  const bool ok = face_convert(vi, vj, vk, o.cov_mode, g);
+  float col[3];
+  for (int a = 0; a < 3; ++a)
+    col[a] = (float)(((double)colors[3 * (int64_t)i0 + a] + (double)colors[3 * (int64_t)i1 + a] +
+                      (double)colors[3 * (int64_t)i2 + a]) * (1.0 / 3.0));
+  const double kscale = sqrt(kHalfLog2e);
+
+  for (int k = mvo[m]; k < mvo[m + 1]; ++k) {
+    const ViewDev& V = views[mvs[k]];
+    const int64_t fv = V.fv_offset + (f - V.face_begin);
+    uint32_t count = 0;
+    ProjGeo q;
+    if (ok && view_project(V, g.mu, g.S, (double)o.dilation, q)) {
+      const double rx = 3.0 * sqrt(q.sxx), ry = 3.0 * sqrt(q.syy);
+      double x0 = ceil(q.u - rx - 0.5), x1 = floor(q.u + rx - 0.5);
+      double y0 = ceil(q.v - ry - 0.5), y1 = floor(q.v + ry - 0.5);
+      x0 = fmax(x0, 0.0); x1 = fmin(x1, (double)(V.W - 1));
+      y0 = fmax(y0, 0.0); y1 = fmin(y1, (double)(V.H - 1));
+      if (x0 <= x1 && y0 <= y1) {
+        const int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
+        const int tx0 = ix0 / tw, tx1 = ix1 / tw, ty0 = iy0 / tht, ty1 = iy1 / tht;
+        const int nx = tx1 - tx0 + 1, ny = ty1 - ty0 + 1;
+        count = (uint32_t)(nx * ny);
+        const float uh = (float)q.u, vh = (float)q.v;
+        const float ul = (float)(q.u - (double)uh), vl = (float)(q.v - (double)vh);
+        // conic = L^T L, L = [[l11, l12], [0, l22]]; l22 = sqrt(det conic) / l11 = 1 / (l11 sqrt(det))
+        const double l11 = sqrt(q.a);
+        const double l12 = q.b / l11;
+        const double l22 = 1.0 / (l11 * sqrt(q.det));
+        float4* r = rec + kRecF4 * fv;
+        r[0] = make_float4(uh, vh, ul, vl);
+        r[1] = make_float4((float)(kscale * l11), (float)(kscale * l12), (float)(kscale * l22),
+                           u2f((uint32_t)ix0 | ((uint32_t)ix1 << 16)));
+        r[2] = make_float4(col[0], col[1], col[2], u2f((uint32_t)iy0 | ((uint32_t)iy1 << 16)));
+        bin[fv] = make_uint4((uint32_t)(V.tile_base + ty0 * V.tiles_x + tx0), (uint32_t)nx | ((uint32_t)ny << 16),
+                             (uint32_t)V.tiles_x, f2u((float)q.p[2]));
+      }
+    }
+    cnt[fv] = count;
+    if (dfv_zero) {
+      dfv_zero[2 * fv] = make_float4(0.f, 0.f, 0.f, 0.f);
+      dfv_zero[2 * fv + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+}
+
+void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
+                    const float* colors, const KOpts& o, float4* rec, uint4* bin, uint32_t* cnt, float4* dfv_zero,
+                    hipStream_t s) {
+  if (faces_total <= 0) return;
+  const int bs = 256;
+  const int64_t nb = (faces_total + bs - 1) / bs;
+  hipLaunchKernelGGL(k_project, dim3((unsigned)nb), dim3(bs), 0, s, table, verts, faces, colors, o, rec, bin, cnt,
+                     dfv_zero);
+}
+
+}  // namespace gmr

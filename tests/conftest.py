@@ -11,6 +11,11 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+    # load what is built; build only when nothing is (hipcc cross-compiles gfx950 without a GPU)
+    lib = os.path.join(ROOT, "paper_2602_14493_amd", "libgmr.so")
+    if not os.path.exists(lib):
+        from paper_2602_14493_amd import build as _build
+        _build.build()
 
 
 def gpu_available() -> bool:

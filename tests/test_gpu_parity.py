@@ -1,0 +1,320 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle, plus the GPU-side
+invariants: bit-exact tile lists, determinism, recompute == saved lists, batched == per-view,
+tile-shape / raster-mode independence, the capacity-overflow protocol and edge cases.
+
+Tolerances (written here, from the spec bar): images 1e-5 absolute on pixels the oracle does
+not flag as near a decision threshold (flagged fraction <= 1e-3); gradients ||d||/||g|| <= 1e-3
+and per element |d| <= 1e-3 |g| + 1e-5 max|g|; tile lists and their order bit-exact outside the
+oracle's ambiguity set."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gmr_testutil import (compare_grads, compare_images, fv_to_face, gpu_setup, to_np, workspace_lists)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_params(**kw):
+    return oracle.Params(**kw)
+
+
+# ------------------------------------------------------------------------------------------------
+# images and gradients vs the oracle
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cov_mode", [0, 1])
+def test_cfg1_image_and_grads(gpu, cov_mode):
+    say(f"cfg1 icosphere s2 128^2 cov_mode={cov_mode}")
+    W = wl.make_workload(1)
+    r, verts, colors = gpu_setup(W, cov_mode=cov_mode)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    P = oracle_params(cov_mode=cov_mode)
+    o_rgb, o_tf, o_nc, o_mask = oracle.render_workload(W, P)
+    compare_images(rgb, alpha, o_rgb, o_tf, o_mask, label=f"cfg1 mode{cov_mode}")
+    rng = np.random.default_rng(101)
+    g_rgb = rng.normal(size=(W.num_pixels, 3)) * (~o_mask)[:, None]
+    g_a = rng.normal(size=W.num_pixels) * (~o_mask)
+    import torch
+    dV, dC = r.backward(verts, colors, torch.from_numpy(g_rgb.astype(np.float32)).cuda(),
+                        torch.from_numpy(g_a.astype(np.float32)).cuda(), saved, ws)
+    oV, oC = oracle.adjoint_workload(W, g_rgb, g_a, P)
+    compare_grads(dV, oV, f"cfg1 mode{cov_mode} dV")
+    compare_grads(dC, oC, f"cfg1 mode{cov_mode} dC")
+
+
+def test_cfg1_fused_l2_matches_explicit_upstream(gpu):
+    """The fused L2 backward equals the explicit backward fed dL/drgb = 2 (rgb - t) / 3P; and
+    with a target the oracle renders from the unjittered mesh it matches the oracle's adjoint."""
+    import torch
+    say("cfg1 fused L2")
+    W = wl.make_workload(1)
+    r, verts, colors = gpu_setup(W)
+    tgt_rgb, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    target = torch.from_numpy(tgt_rgb.astype(np.float32)).cuda()
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    dV1, dC1, loss = r.backward_l2(verts, colors, rgb, target, saved, ws, want_loss=True)
+    g = 2.0 * (rgb - target) / rgb.numel()
+    dV2, dC2 = r.backward(verts, colors, g, None, saved, ws)
+    compare_grads(dV1, to_np(dV2), "fused vs explicit dV", rel=1e-5)
+    compare_grads(dC1, to_np(dC2), "fused vs explicit dC", rel=1e-5)
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W)
+    L, g_o = oracle.l2_loss(o_rgb, tgt_rgb)
+    assert abs(float(loss.item()) - L) <= 1e-5 * L + 1e-9
+    if not o_mask.any():
+        oV, oC = oracle.adjoint_workload(W, g_o)
+        compare_grads(dV1, oV, "cfg1 L2 dV vs oracle")
+        compare_grads(dC1, oC, "cfg1 L2 dC vs oracle")
+    else:
+        g_o = g_o * (~o_mask)[:, None]
+        dV3, dC3 = r.backward(verts, colors, torch.from_numpy(g_o.astype(np.float32)).cuda(), None, saved, ws)
+        oV, oC = oracle.adjoint_workload(W, g_o)
+        compare_grads(dV3, oV, "cfg1 L2 (masked) dV vs oracle")
+        compare_grads(dC3, oC, "cfg1 L2 (masked) dC vs oracle")
+
+
+def test_cfg2_images_and_crop_loss_grads(gpu):
+    """Icosphere subdiv 5, 8 views 512^2: all images vs the oracle; vertex and colour gradients
+    of the L2 loss restricted to the centre crop [224, 288)^2 of every view."""
+    import torch
+    say("cfg2 icosphere s5 8x512^2")
+    W = wl.make_workload(2)
+    r, verts, colors = gpu_setup(W)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W)
+    compare_images(rgb, alpha, o_rgb, o_tf, o_mask, label="cfg2")
+    tgt, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    crop = np.zeros((W.num_views, 512, 512), bool)
+    crop[:, 224:288, 224:288] = True
+    crop = crop.reshape(-1) & ~o_mask
+    n = 3 * int(crop.sum())
+    g = np.where(crop[:, None], 2.0 * (o_rgb - tgt) / n, 0.0)
+    dV, dC = r.backward(verts, colors, torch.from_numpy(g.astype(np.float32)).cuda(), None, saved, ws)
+    oV, oC = oracle.adjoint_workload(W, g)
+    compare_grads(dV, oV, "cfg2 crop dV")
+    compare_grads(dC, oC, "cfg2 crop dC")
+
+
+def test_cfg5_view0_image_full_size(gpu):
+    """2M-face torus at 1920x1080: the batched 32-view forward's first view vs the oracle."""
+    say("cfg5 torus 2M, view 0 of 32 at 1920x1080")
+    W = wl.make_workload(5)
+    r, verts, colors = gpu_setup(W)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    npx = 1920 * 1080
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W, views=[0])
+    compare_images(to_np(rgb)[:npx], to_np(alpha)[:npx], o_rgb, o_tf, o_mask, label="cfg5 view0")
+
+
+# ------------------------------------------------------------------------------------------------
+# tile lists
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+def test_tile_lists_bit_exact(gpu, tile):
+    """Every tile's list (membership and order) equals the oracle's tile list built from per-pixel
+    extents and sorted by (float32 depth, id), except entries the oracle flags as ambiguous."""
+    tw, th = tile
+    say(f"tile lists cfg2 tile {tw}x{th}")
+    W = wl.make_workload(2)
+    r, verts, colors = gpu_setup(W, tile_w=tw, tile_h=th)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    ranges, vals = workspace_lists(r, ws)
+    conv = fv_to_face(W)
+    cams = W.cam_array()
+    tbase = 0
+    checked = 0
+    for v in range(W.num_views):
+        off, ids, amb = oracle.tile_lists_view(W.verts, W.faces, W.colors, cams[v], tw, th)
+        nt = len(off) - 1
+        for t in range(nt):
+            s, e = ranges[tbase + t]
+            vv, gl = conv(vals[s:e])
+            assert (vv == v).all()
+            o_ids = ids[off[t]:off[t + 1]]
+            o_amb = amb[off[t]:off[t + 1]]
+            ambiguous = set(o_ids[o_amb != 0].tolist())
+            want = [i for i, a in zip(o_ids.tolist(), o_amb.tolist()) if a == 0]
+            got = [i for i in gl.tolist() if i not in ambiguous]
+            assert got == want, f"view {v} tile {t}"
+            assert set(gl.tolist()) <= set(o_ids.tolist())
+            checked += len(want)
+        tbase += nt
+    say(f"checked {checked} list entries")
+    assert checked > 100000
+
+
+# ------------------------------------------------------------------------------------------------
+# GPU invariants
+# ------------------------------------------------------------------------------------------------
+
+def test_determinism_and_recompute_lists(gpu):
+    import torch
+    say("determinism cfg2")
+    W = wl.make_workload(2)
+    r, verts, colors = gpu_setup(W)
+    rgb1, a1, s1, ws1 = r.forward(verts, colors)
+    rgb2, a2, s2, ws2 = r.forward(verts, colors)
+    assert torch.equal(rgb1, rgb2) and torch.equal(a1, a2) and torch.equal(s1, s2)
+    l1 = workspace_lists(r, ws1)
+    l2 = workspace_lists(r, ws2)
+    n = int(l1[0][:, 1].max())
+    assert np.array_equal(l1[0], l2[0]) and np.array_equal(l1[1][:n], l2[1][:n])
+    # backward with recompute rebuilds bit-identical lists in a fresh workspace
+    ws3 = r.new_workspace()
+    g = torch.randn_like(rgb1)
+    dV3, dC3 = r.backward(verts, colors, g, None, s1, ws3, recompute=True)
+    l3 = workspace_lists(r, ws3)
+    assert np.array_equal(l1[0], l3[0]) and np.array_equal(l1[1][:n], l3[1][:n])
+    dV1, dC1 = r.backward(verts, colors, g, None, s1, ws1, recompute=False)
+    compare_grads(dV3, to_np(dV1), "recompute vs saved dV", rel=1e-5)
+    compare_grads(dC3, to_np(dC1), "recompute vs saved dC", rel=1e-5)
+
+
+def test_batched_equals_per_view(gpu):
+    """The batched launch and one launch per view give bit-identical images; gradients agree."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("batched vs per-view cfg2")
+    W = wl.make_workload(2)
+    r, verts, colors = gpu_setup(W)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    g = torch.randn_like(rgb)
+    dV, dC = r.backward(verts, colors, g, None, saved, ws)
+    npx = 512 * 512
+    dVs = torch.zeros_like(dV)
+    dCs = torch.zeros_like(dC)
+    for v in range(W.num_views):
+        bv = r.batch.view(v)
+        rv = gmr.Renderer(bv, W.faces, r.opts, handle=r.handle)
+        rgb_v, a_v, s_v, ws_v = rv.forward(verts, colors)
+        assert torch.equal(rgb_v, rgb[v * npx:(v + 1) * npx]), v
+        assert torch.equal(a_v, alpha[v * npx:(v + 1) * npx]), v
+        dv, dc = rv.backward(verts, colors, g[v * npx:(v + 1) * npx], None, s_v, ws_v)
+        dVs += dv
+        dCs += dc
+    compare_grads(dVs, to_np(dV), "per-view sum vs batched dV", rel=1e-5)
+    compare_grads(dCs, to_np(dC), "per-view sum vs batched dC", rel=1e-5)
+
+
+def test_tile_shape_and_raster_mode_invariance(gpu):
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("tile shape / persistent invariance cfg2")
+    W = wl.make_workload(2)
+    r, verts, colors = gpu_setup(W)
+    base, base_a, _, _ = r.forward(verts, colors)
+    for tw, th, mode in [(8, 8, 0), (32, 16, 0), (16, 16, 1), (64, 64, 1), (8, 24, 1)]:
+        r2 = gmr.Renderer(r.batch, W.faces, gmr.default_options(tile_w=tw, tile_h=th, raster_mode=mode),
+                          handle=r.handle)
+        rgb, a, _, _ = r2.forward(verts, colors)
+        assert torch.equal(rgb, base), (tw, th, mode)
+        assert torch.equal(a, base_a), (tw, th, mode)
+
+
+def test_overflow_protocol(gpu):
+    """A workspace too small for the instances sets the overflow counter (writes are clamped);
+    the managed forward then grows the capacity and reproduces the full-capacity image."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("overflow cfg1")
+    W = wl.make_workload(1)
+    r, verts, colors = gpu_setup(W, instance_capacity=64)
+    rgb, alpha, saved = r._alloc_outputs()
+    ws = r.new_workspace()
+    r.fwd_raw(verts, colors, rgb, alpha, saved, ws)
+    c = r.counters(ws)
+    assert c.overflow and c.instances > 64 and c.capacity == 64
+    r2, _, _ = gpu_setup(W, instance_capacity=1 << 20)
+    ref, _, _, _ = r2.forward(verts, colors)
+    out, _, _, ws_b = r.forward(verts, colors, check=True)
+    assert not r.counters(ws_b).overflow and r.opts.instance_capacity > 64
+    assert torch.equal(out, ref)
+
+
+def test_edge_cases(gpu):
+    """Camera looking away (no instances), odd image sizes, 1x1 image, a degenerate face (zero
+    gradient), a mesh partly behind the camera."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("edge cases")
+    rng = np.random.default_rng(7)
+    V, F = wl.random_mesh(rng, 30, spread=0.4, size=0.12)
+    V = V.astype(np.float32)
+    V[3:6] = V[3]  # face 1 collapsed to a point: culled
+    C = rng.uniform(size=V.shape).astype(np.float32)
+    cams = [wl.look_at_camera((0.2, 0.1, 2.0), width=37, height=23),
+            wl.look_at_camera((0.0, 0.0, 2.0), target=(0.0, 0.0, 5.0), width=16, height=16),  # looks away
+            wl.look_at_camera((0.1, 0.0, 2.2), width=1, height=1),
+            wl.look_at_camera((0.0, 0.0, 0.05), width=40, height=40)]  # inside the cloud
+    for k, cam in enumerate(cams):
+        say(f"edge view {k} {cam.width}x{cam.height}")
+        Wk = wl._single("edge", V, F, C, [cam])
+        r, verts, colors = gpu_setup(Wk)
+        rgb, alpha, saved, ws = r.forward(verts, colors)
+        o_rgb, o_tf, _, o_mask = oracle.render_workload(Wk)
+        if o_mask.mean() <= 1e-3:
+            compare_images(rgb, alpha, o_rgb, o_tf, o_mask, label=f"edge{k}")
+        g = rng.normal(size=(Wk.num_pixels, 3)) * (~o_mask)[:, None]
+        dV, dC = r.backward(verts, colors, torch.from_numpy(g.astype(np.float32)).cuda(), None, saved, ws)
+        d = to_np(dV)
+        assert np.isfinite(d).all()
+        assert (d[3:6] == 0).all() or k == 1
+        if k == 1:
+            assert (to_np(rgb) == 0).all() and (d == 0).all()
+        oV, oC = oracle.adjoint_workload(Wk, g)
+        if np.abs(oV).max() > 0:
+            compare_grads(dV, oV, f"edge{k} dV")
+
+
+def test_autograd_recompute_equals_saved(gpu):
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("autograd save vs recompute cfg2")
+    W = wl.make_workload(2)
+    r, verts, colors = gpu_setup(W)
+    tgt = torch.rand((W.num_pixels, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    grads = []
+    for save in (True, False):
+        v = verts.clone().requires_grad_(True)
+        c = colors.clone().requires_grad_(True)
+        rgb, alpha = gmr.render(v, c, r, save_lists=save)
+        loss = ((rgb - tgt) ** 2).mean() + 0.1 * alpha.mean()
+        loss.backward()
+        grads.append((v.grad.clone(), c.grad.clone()))
+    compare_grads(grads[1][0], to_np(grads[0][0]), "autograd recompute vs saved dV", rel=1e-5)
+    compare_grads(grads[1][1], to_np(grads[0][1]), "autograd recompute vs saved dC", rel=1e-5)
+
+
+def test_graph_adam_replays_match_eager(gpu):
+    """The captured step (forward, fused L2 backward with recomputed lists, Adam) replayed several
+    times tracks the same steps run eagerly; every replay is checked."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("graph adam cfg1")
+    W = wl.make_workload(1)
+    r, verts, colors = gpu_setup(W)
+    tgt_rgb, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    target = torch.from_numpy(tgt_rgb.astype(np.float32)).cuda()
+    eager = gmr.GraphAdamLoop(r, verts, colors, target, lr=1e-3)
+    graph = gmr.GraphAdamLoop(r, verts, colors, target, lr=1e-3)
+    graph.capture()
+    graph.verts.copy_(verts)
+    graph.m.zero_(); graph.v.zero_(); graph.step_count.zero_()
+    for k in range(5):
+        eager.run_eager(1)
+        graph.graph.replay()
+        torch.cuda.synchronize()
+        d = (eager.verts - graph.verts).abs().max().item()
+        say(f"replay {k}: max |dverts| = {d:.3e}  loss eager {eager.loss.item():.6e} graph {graph.loss.item():.6e}")
+        assert d <= 1e-5
+        assert abs(eager.loss.item() - graph.loss.item()) <= 1e-4 * eager.loss.item()
+    assert int(graph.step_count.item()) == 5
+    assert not graph.overflow()
+    moved = (graph.verts - verts).abs().max().item()
+    assert 1e-4 < moved < 1e-2
