@@ -59,11 +59,11 @@ def stage_profile(r):
 def byte_model(stage, F, FV, V, P, I, tiles):
     """Algorithmic HBM bytes of one launch group of `stage` (what the stage must move at least)."""
     return {
-        "project": F * (12 + 36 + 36) + FV * (48 + 16 + 4),
-        "scan_emit": FV * (4 + 4 + 16) + I * 12,
-        "sort_hist": I * 8,
-        "sort_pass": I * 24,
-        "tile_ranges": I * 8 + tiles * 8,
+        "project": F * (12 + 36 + 36) + FV * (48 + 16),        # gathers; records + sort elements
+        "sort_fv_pass": FV * 32,                                # 16 B element read + written
+        "scan_emit": FV * 32 + I * 8,                           # elements read twice; instances written
+        "sort_pass": I * 16,                                    # {tile, face-view} read + written
+        "tile_ranges": I * 4 + tiles * 8,
         "raster_fwd": I * (4 + 48) + tiles * 8 + P * (12 + 4 + 8),
         "raster_bwd": I * (4 + 48) + tiles * 8 + P * (12 + 12 + 8) + FV * 32,
         "face_bwd": F * (12 + 36 + 48) + FV * 32,

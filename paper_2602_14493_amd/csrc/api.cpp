@@ -17,11 +17,11 @@
 using namespace gmr;
 
 // Stages timed by gmr_profile_* (HIP events around each launch group on the call's stream).
-enum Stage { kStProject, kStScanEmit, kStSortHist, kStSortPass, kStRanges, kStRasterFwd, kStFill, kStRasterBwd,
-             kStFaceBwd, kStGather, kNumStages };
-static const char* kStageNames[kNumStages] = {"project",     "scan_emit",  "sort_hist", "sort_pass",
-                                              "tile_ranges", "raster_fwd", "fill",      "raster_bwd",
-                                              "face_bwd",    "vertex_gather"};
+enum Stage { kStProject, kStScanEmit, kStSortHist, kStSortFv, kStSortPass, kStRanges, kStRasterFwd, kStFill,
+             kStRasterBwd, kStFaceBwd, kStGather, kNumStages };
+static const char* kStageNames[kNumStages] = {"project",    "scan_emit",   "sort_digits", "sort_fv_pass",
+                                              "sort_pass",  "tile_ranges", "raster_fwd",  "fill",
+                                              "raster_bwd", "face_bwd",    "vertex_gather"};
 
 struct gmr_ctx {
   int device = 0;
@@ -164,29 +164,40 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   L.capacity = cap;
   L.tiles_total = p.tiles_total;
   L.items_total = p.items_total;
+  // tile digits: ceil(bits / 9) passes of at most 9 bits (512 bins), widths as even as possible
   int tile_bits = 0;
   while ((1ll << tile_bits) < p.tiles_total) ++tile_bits;
-  L.key_bits = 32 + tile_bits;
-  L.passes = (L.key_bits + 7) / 8;
+  L.tile_bits = tile_bits;
+  L.tile_passes = std::max(1, (tile_bits + 8) / 9);
+  if (L.tile_passes > kMaxPasses - kTileRow0) return fail(GMR_ERR_INVALID_ARG, "too many tiles");
+  for (int j = 0, sh = 0; j < L.tile_passes; ++j) {
+    const int wbits = (tile_bits - sh + (L.tile_passes - j) - 1) / (L.tile_passes - j);
+    L.tile_shift[j] = sh;
+    L.tile_mask[j] = (int32_t)((1u << wbits) - 1u);
+    sh += wbits;
+  }
   L.scan_blocks = (int32_t)((p.fv_total + kScanTile - 1) / kScanTile);
   if (L.scan_blocks > 65536) return fail(GMR_ERR_INVALID_ARG, "too many face-views for the single-level scan");
-  L.sort_parts = (int32_t)((cap + kSortPart - 1) / kSortPart);
+  L.parts_fv = (int32_t)((p.fv_total + kSortPart - 1) / kSortPart);
+  L.parts_inst = (int32_t)((cap + kSortPart - 1) / kSortPart);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t r = off; off = align_up(off + bytes); return r; };
   L.hdr = take(sizeof(WsHdr));
   L.rec = take((size_t)p.fv_total * kRecF4 * 16);
-  L.bin = take((size_t)p.fv_total * 16);
-  L.cnt = take((size_t)p.fv_total * 4);
+  L.elA = take((size_t)p.fv_total * 16);
+  L.elB = take((size_t)p.fv_total * 16);
   L.bsum = take((size_t)std::max(L.scan_blocks, 1) * 4);
   L.boff = take((size_t)std::max(L.scan_blocks, 1) * 8);
-  L.keys0 = take((size_t)cap * 8);
-  L.keys1 = take((size_t)cap * 8);
-  L.vals0 = take((size_t)cap * 4);
-  L.vals1 = take((size_t)cap * 4);
-  L.hist = take(kMaxPasses * 256 * 4);
-  L.dig = take(kMaxPasses * 256 * 4);
-  L.desc0 = take((size_t)L.sort_parts * 256 * 4);
-  L.desc1 = take((size_t)L.sort_parts * 256 * 4);
+  L.instA = take((size_t)cap * 8);
+  L.instB = take((size_t)cap * 8);
+  L.keysF = take((size_t)cap * 4);
+  L.valsF = take((size_t)cap * 4);
+  L.hist = take(kMaxPasses * kHistStride * 4);
+  L.dig = take(kMaxPasses * kHistStride * 4);
+  L.descF0 = take((size_t)std::max(L.parts_fv, 1) * 256 * 4);
+  L.descF1 = take((size_t)std::max(L.parts_fv, 1) * 256 * 4);
+  L.descI0 = take((size_t)L.parts_inst * 512 * 4);
+  L.descI1 = take((size_t)L.parts_inst * 512 * 4);
   L.ranges = take((size_t)p.tiles_total * 8);
   L.dfv = take((size_t)p.fv_total * 32);
   L.fgrad = take((size_t)p.f_total * 48);
@@ -235,18 +246,20 @@ KOpts kopts(const gmr_options* o) {
 struct WsPtrs {
   WsHdr* hdr;
   float4* rec;
-  uint4* bin;
-  uint32_t* cnt;
+  uint4* elA;
+  uint4* elB;
   uint32_t* bsum;
   uint64_t* boff;
-  uint64_t* keys0;
-  uint64_t* keys1;
-  uint32_t* vals0;
-  uint32_t* vals1;
+  uint2* instA;
+  uint2* instB;
+  uint32_t* keysF;
+  uint32_t* valsF;
   uint32_t* hist;
   uint32_t* dig;
-  uint32_t* desc0;
-  uint32_t* desc1;
+  uint32_t* descF0;
+  uint32_t* descF1;
+  uint32_t* descI0;
+  uint32_t* descI1;
   uint32_t* ranges;
   float* dfv;
   float4* fgrad;
@@ -258,22 +271,24 @@ WsPtrs ws_ptrs(const Layout& L, void* ws) {
   WsPtrs w;
   w.hdr = reinterpret_cast<WsHdr*>(b + L.hdr);
   w.rec = reinterpret_cast<float4*>(b + L.rec);
-  w.bin = reinterpret_cast<uint4*>(b + L.bin);
-  w.cnt = reinterpret_cast<uint32_t*>(b + L.cnt);
+  w.elA = reinterpret_cast<uint4*>(b + L.elA);
+  w.elB = reinterpret_cast<uint4*>(b + L.elB);
   w.bsum = reinterpret_cast<uint32_t*>(b + L.bsum);
   w.boff = reinterpret_cast<uint64_t*>(b + L.boff);
-  w.keys0 = reinterpret_cast<uint64_t*>(b + L.keys0);
-  w.keys1 = reinterpret_cast<uint64_t*>(b + L.keys1);
-  w.vals0 = reinterpret_cast<uint32_t*>(b + L.vals0);
-  w.vals1 = reinterpret_cast<uint32_t*>(b + L.vals1);
+  w.instA = reinterpret_cast<uint2*>(b + L.instA);
+  w.instB = reinterpret_cast<uint2*>(b + L.instB);
+  w.keysF = reinterpret_cast<uint32_t*>(b + L.keysF);
+  w.valsF = reinterpret_cast<uint32_t*>(b + L.valsF);
   w.hist = reinterpret_cast<uint32_t*>(b + L.hist);
   w.dig = reinterpret_cast<uint32_t*>(b + L.dig);
-  w.desc0 = reinterpret_cast<uint32_t*>(b + L.desc0);
-  w.desc1 = reinterpret_cast<uint32_t*>(b + L.desc1);
+  w.descF0 = reinterpret_cast<uint32_t*>(b + L.descF0);
+  w.descF1 = reinterpret_cast<uint32_t*>(b + L.descF1);
+  w.descI0 = reinterpret_cast<uint32_t*>(b + L.descI0);
+  w.descI1 = reinterpret_cast<uint32_t*>(b + L.descI1);
   w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
   w.dfv = reinterpret_cast<float*>(b + L.dfv);
   w.fgrad = reinterpret_cast<float4*>(b + L.fgrad);
-  w.sorted_vals = (L.passes & 1) ? w.vals1 : w.vals0;
+  w.sorted_vals = w.valsF;
   return w;
 }
 
@@ -304,27 +319,50 @@ struct StageTimer {
 void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* table, const float* verts,
                  const int32_t* faces, const float* colors, const WsPtrs& w, bool zero_dfv, hipStream_t s) {
   const KOpts ko = kopts(o);
+  const Layout& L = p.L;
+  const uint32_t fv_words = (uint32_t)std::max(L.parts_fv, 1) * 256u;
+  const uint32_t inst_words = (uint32_t)L.parts_inst * 512u;
   {
     StageTimer t(h, s, kStProject);
-    launch_project(table, p.f_total, verts, faces, colors, ko, w.rec, w.bin, w.cnt,
-                   zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, s);
+    launch_project(table, p.f_total, verts, faces, colors, ko, w.rec, w.elA, w.hist,
+                   zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.hdr, w.descF0, fv_words, s);
+  }
+  // depth digits on the face-view elements: 4 passes, A -> B -> A -> B -> A
+  {
+    StageTimer t(h, s, kStSortHist);
+    launch_sort_digits(w.hist, w.dig, 0, kDepthPasses, 256, s);
+  }
+  for (int pass = 0; pass < kDepthPasses; ++pass) {
+    StageTimer t(h, s, kStSortFv);
+    const bool odd = pass & 1;
+    launch_sort_fv_pass(odd ? w.elB : w.elA, odd ? w.elA : w.elB, (uint32_t)p.fv_total, w.dig + pass * kHistStride,
+                        odd ? w.descF1 : w.descF0, odd ? w.descF0 : w.descF1, fv_words, &w.hdr->part_ctr[pass], 8 * pass,
+                        s);
+  }
+  TilePasses tp;
+  tp.n = L.tile_passes;
+  for (int j = 0; j < kMaxPasses - kTileRow0; ++j) {
+    tp.shift[j] = j < tp.n ? L.tile_shift[j] : 0;
+    tp.mask[j] = j < tp.n ? (uint32_t)L.tile_mask[j] : 0u;
   }
   {
     StageTimer t(h, s, kStScanEmit);
-    launch_bin(w.cnt, w.bin, p.fv_total, w.bsum, w.boff, p.L.scan_blocks, w.hdr, w.hist, kMaxPasses * 256,
-               (uint32_t)p.L.capacity, (uint32_t)p.L.passes, w.keys0, w.vals0, s);
+    launch_bin(table, w.elA, p.fv_total, w.bsum, w.boff, L.scan_blocks, w.hdr, (uint32_t)L.capacity, w.instA, w.hist, tp,
+               w.descI0, inst_words, s);
+    launch_sort_digits(w.hist, w.dig, kTileRow0, tp.n, 512, s);
   }
-  {
-    StageTimer t(h, s, kStSortHist);
-    launch_sort_hist(w.keys0, w.hdr, w.hist, w.dig, w.desc0, p.L.sort_parts, p.L.passes, hist_blocks(h), s);
-  }
-  for (int pass = 0; pass < p.L.passes; ++pass) {
+  // tile digits on the instances: A -> B -> A ..., the last pass writes keysF / valsF
+  for (int j = 0; j < tp.n; ++j) {
     StageTimer t(h, s, kStSortPass);
-    launch_sort_pass(w.keys0, w.vals0, w.keys1, w.vals1, w.hdr, w.dig, w.desc0, w.desc1, p.L.sort_parts, pass, s);
+    const bool odd = j & 1, last = j + 1 == tp.n;
+    launch_sort_inst_pass(odd ? w.instB : w.instA, odd ? w.instA : w.instB, last ? w.keysF : nullptr,
+                          last ? w.valsF : nullptr, &w.hdr->count, (uint32_t)L.capacity,
+                          w.dig + (kTileRow0 + j) * kHistStride, odd ? w.descI1 : w.descI0, odd ? w.descI0 : w.descI1,
+                          last ? 0u : inst_words, &w.hdr->part_ctr[kTileRow0 + j], tp.shift[j], tp.mask[j], s);
   }
   {
     StageTimer t(h, s, kStRanges);
-    launch_tile_ranges((p.L.passes & 1) ? w.keys1 : w.keys0, w.hdr, w.ranges, p.tiles_total, hist_blocks(h), s);
+    launch_tile_ranges(w.keysF, w.hdr, w.ranges, p.tiles_total, hist_blocks(h), s);
   }
 }
 
@@ -582,9 +620,9 @@ gmr_status gmr_workspace_view(const gmr_batch* batch, const gmr_options* opt, si
   gmr_status st = make_plan(batch, opt, true, p);
   if (st != GMR_OK) return st;
   *ranges_off = p.L.ranges;
-  *vals_off = (p.L.passes & 1) ? p.L.vals1 : p.L.vals0;
+  *vals_off = p.L.valsF;
   *rec_off = p.L.rec;
-  *bin_off = p.L.bin;
+  *bin_off = p.L.elA;
   return GMR_OK;
 }
 

@@ -11,13 +11,16 @@ namespace gmr {
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kSub = 8;              // raster sub-block side: one 8x8 pixel block per wavefront
 constexpr int kRecF4 = 3;            // projected record = 3 x float4 = 48 B per face-view
-constexpr int kSortBlock = 256;      // onesweep workgroup (4 wavefronts)
-constexpr int kSortItems = 16;       // keys per thread
-constexpr int kSortPart = kSortBlock * kSortItems;  // keys per partition
+constexpr int kSortBlock = 512;      // onesweep workgroup (8 wavefronts)
+constexpr int kSortItems = 8;        // elements per thread
+constexpr int kSortPart = kSortBlock * kSortItems;  // elements per partition
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;  // face-views per scan block
-constexpr int kMaxPasses = 8;
+constexpr int kMaxPasses = 8;        // histogram rows: 0..3 depth digits (face-views), 4..7 tile digits
+constexpr int kDepthPasses = 4;      // 32 depth bits in 8-bit digits
+constexpr int kTileRow0 = 4;
+constexpr int kHistStride = 512;     // one histogram row holds up to 512 bins
 constexpr uint32_t kFlagAgg = 1u << 30;   // onesweep partition descriptor: aggregate published
 constexpr uint32_t kFlagInc = 2u << 30;   // inclusive prefix published
 constexpr uint32_t kValMask = (1u << 30) - 1u;
@@ -55,7 +58,7 @@ struct WsHdr {                 // 256 B at the start of the workspace
   uint32_t overflow;
   uint32_t capacity;
   uint32_t passes;
-  uint32_t part_ctr[kMaxPasses];   // onesweep partition tickets, one per pass
+  uint32_t part_ctr[kMaxPasses];   // onesweep partition tickets, one per pass (same rows as the histograms)
   uint32_t work_fwd, work_bwd;     // persistent raster queues
   uint32_t pad0[2];
   float loss;                      // L2 loss value of the last fused backward
@@ -72,10 +75,11 @@ struct KOpts {
 
 // Workspace layout, computed on the host (byte offsets) -------------------------------------------
 struct Layout {
-  size_t hdr, rec, bin, cnt, bsum, boff, keys0, keys1, vals0, vals1, hist, dig, desc0, desc1, ranges,
-      dfv, fgrad, total;
+  size_t hdr, rec, elA, elB, bsum, boff, instA, instB, keysF, valsF, hist, dig, descF0, descF1, descI0, descI1,
+      ranges, dfv, fgrad, total;
   int64_t fv_total, faces_total, pixels_total, capacity;
-  int32_t tiles_total, items_total, passes, key_bits, scan_blocks, sort_parts;
+  int32_t tiles_total, items_total, tile_bits, tile_passes, scan_blocks, parts_fv, parts_inst;
+  int32_t tile_shift[kMaxPasses - kTileRow0], tile_mask[kMaxPasses - kTileRow0];
 };
 
 // Small device helpers -------------------------------------------------------------------------------
@@ -98,6 +102,23 @@ __device__ inline int find_mesh(const int32_t* mesh_face_off, int num_meshes, in
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if (mesh_face_off[mid] <= f) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Digit layout of the instance (tile-id) passes: pass p sorts (tile >> shift[p]) & mask[p].
+struct TilePasses {
+  int n;
+  int shift[kMaxPasses - kTileRow0];
+  uint32_t mask[kMaxPasses - kTileRow0];
+};
+
+// View containing face-view fv (face-view offsets are ascending).
+__device__ inline int find_view_by_fv(const ViewDev* views, int nv, int64_t fv) {
+  int lo = 0, hi = nv - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (views[mid].fv_offset <= fv) lo = mid; else hi = mid - 1;
   }
   return lo;
 }

@@ -8,19 +8,23 @@
 
 namespace gmr {
 
+// Clears the per-build counters, histograms and first depth-pass descriptors, then converts and
+// projects every face into every view of its mesh.
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
-                    const float* colors, const KOpts& o, float4* rec, uint4* bin, uint32_t* cnt, float4* dfv_zero,
-                    hipStream_t s);
+                    const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
+                    WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, hipStream_t s);
 
-void launch_bin(const uint32_t* cnt, const uint4* bin, int64_t n, uint32_t* bsum, uint64_t* boff, int nb, WsHdr* hdr,
-                uint32_t* hist, int hist_n, uint32_t cap, uint32_t passes, uint64_t* keys, uint32_t* vals,
+void launch_bin(const void* table, const uint4* el, int64_t n, uint32_t* bsum, uint64_t* boff, int nb, WsHdr* hdr,
+                uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0, uint32_t desc0_words,
                 hipStream_t s);
 
-void launch_sort_hist(const uint64_t* keys0, const WsHdr* hdr, uint32_t* hist, uint32_t* dig, uint32_t* desc0,
-                      int64_t parts_max, int passes, int hist_blocks, hipStream_t s);
-void launch_sort_pass(uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, WsHdr* hdr, const uint32_t* dig,
-                      uint32_t* desc0, uint32_t* desc1, int64_t parts_max, int p, hipStream_t s);
-void launch_tile_ranges(const uint64_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int64_t tiles_total,
+void launch_sort_digits(const uint32_t* hist, uint32_t* dig, int row0, int rows, int radix, hipStream_t s);
+void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* dig, uint32_t* desc_cur,
+                         uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int shift, hipStream_t s);
+void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
+                           uint32_t cap, const uint32_t* dig, uint32_t* desc_cur, uint32_t* desc_next,
+                           uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, hipStream_t s);
+void launch_tile_ranges(const uint32_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int64_t tiles_total,
                         int blocks, hipStream_t s);
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s);

@@ -1,15 +1,18 @@
-// Tile binning: exclusive scan of tiles-touched over face-views, then emission of one
-// (key, value) instance per (face-view, tile): key = global tile << 32 | float32 depth bits,
-// value = face-view index.  Emission order is face-view order, so a stable sort on the key breaks
-// depth ties by ascending global id.
+// Tile binning over the depth-sorted face-view elements: exclusive scan of tiles-touched, then
+// emission of one instance {tile, face-view} per (face-view, tile) in that order.  Emission order
+// is (float32 depth, face-view), so a stable sort on the tile id alone completes the
+// (tile, depth, id) order.  The emitter also accumulates the histograms of the tile digits and
+// clears the first tile pass's descriptors.
 //
-// Scan: reduce (per 4096 face-views) -> single-block scan of the block sums -> emit, which redoes
-// the block-local scan on wavefront shuffles.  Face-view t of block b, wave w, round i, lane l is
+// Scan: reduce (per 4096 elements) -> single-block scan of the block sums -> emit, which redoes the
+// block-local scan on wavefront shuffles.  Element t of block b, wave w, round i, lane l is
 // b*4096 + w*1024 + i*64 + l: every load is a coalesced 64-wide run.
 #include "gmr_common.h"
 #include "gmr_launch.h"
 
 namespace gmr {
+
+__device__ inline uint32_t el_count(const uint4& e) { return (e.w & 0xffffu) * (e.w >> 16); }
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
 #pragma unroll
@@ -26,7 +29,7 @@ __device__ inline uint32_t wave_sum(uint32_t x) {
   return x;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint32_t* __restrict__ cnt, int64_t n,
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint4* __restrict__ el, int64_t n,
                                                             uint32_t* __restrict__ bsum) {
   __shared__ uint32_t s_w[kScanBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -35,7 +38,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint32_t* __re
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t idx = base + (int64_t)i * kWave;
-    if (idx < n) acc += cnt[idx];
+    if (idx < n) acc += el_count(el[idx]);
   }
   acc = wave_sum(acc);
   if (lane == 0) s_w[w] = acc;
@@ -47,15 +50,12 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint32_t* __re
   }
 }
 
-// Single workgroup: exclusive scan of the block sums (64-bit), instance total and overflow flag;
-// also clears the sort histograms and the per-pass partition tickets for this pass of the pipeline.
+// Single workgroup: exclusive scan of the block sums (64-bit), instance total and overflow flag.
 __global__ __launch_bounds__(1024) void k_scan_top(const uint32_t* __restrict__ bsum, int nb, uint64_t* __restrict__ boff,
-                                                   WsHdr* hdr, uint32_t* __restrict__ hist, int hist_n, uint32_t cap,
-                                                   uint32_t passes) {
+                                                   WsHdr* hdr, uint32_t cap) {
   __shared__ uint64_t s_part[1024 / kWave];
   __shared__ uint64_t s_carry;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  for (int i = threadIdx.x; i < hist_n; i += blockDim.x) hist[i] = 0;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
   for (int base = 0; base < nb; base += 1024) {
@@ -83,27 +83,34 @@ __global__ __launch_bounds__(1024) void k_scan_top(const uint32_t* __restrict__ 
   if (threadIdx.x == 0) {
     const uint64_t total = s_carry;
     hdr->capacity = cap;
-    hdr->passes = passes;
     hdr->count = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
     hdr->overflow = total > cap ? 1u : 0u;
-    for (int p = 0; p < kMaxPasses; ++p) hdr->part_ctr[p] = 0;
-    hdr->work_fwd = 0;
-    hdr->work_bwd = 0;
   }
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_emit(const uint32_t* __restrict__ cnt, const uint4* __restrict__ bin,
-                                                     int64_t n, const uint64_t* __restrict__ boff, const WsHdr* __restrict__ hdr,
-                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+__global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ table, const uint4* __restrict__ el, int64_t n,
+                                                     const uint64_t* __restrict__ boff, const WsHdr* __restrict__ hdr,
+                                                     uint2* __restrict__ inst, uint32_t* __restrict__ hist, TilePasses tp,
+                                                     uint32_t* __restrict__ desc0, uint32_t desc0_words) {
   __shared__ uint32_t s_w[kScanBlock / kWave];
+  __shared__ uint32_t s_h[kMaxPasses - kTileRow0][kHistStride];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const ViewDev* views = table_views(table);
+  const int nv = static_cast<const TableHdr*>(table)->num_views;
+  for (int i = threadIdx.x; i < tp.n * kHistStride; i += kScanBlock) (&s_h[0][0])[i] = 0u;
+  {  // this workgroup's slice of the first tile pass's descriptors
+    const uint32_t chunk = (desc0_words + gridDim.x - 1) / gridDim.x;
+    const uint32_t b0 = blockIdx.x * chunk;
+    const uint32_t b1 = min(desc0_words, b0 + chunk);
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += kScanBlock) desc0[i] = 0u;
+  }
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)w * (kScanItems * kWave) + lane;
   uint32_t c[kScanItems];
   uint32_t wtot = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t idx = base + (int64_t)i * kWave;
-    c[i] = idx < n ? cnt[idx] : 0u;
+    c[i] = idx < n ? el_count(el[idx]) : 0u;
     wtot += c[i];
   }
   wtot = wave_sum(wtot);
@@ -118,28 +125,33 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const uint32_t* __restrict_
     const uint64_t my = off + inc - c[i];
     off += __shfl(inc, kWave - 1, kWave);
     if (c[i] == 0) continue;
-    const int64_t fv = base + (int64_t)i * kWave;
-    const uint4 b = bin[fv];
-    const uint32_t nx = b.y & 0xffffu, ny = b.y >> 16;
+    const uint4 e = el[base + (int64_t)i * kWave];
+    const uint32_t nx = e.w & 0xffffu, ny = e.w >> 16;
+    const uint32_t tiles_x = (uint32_t)views[find_view_by_fv(views, nv, (int64_t)e.y)].tiles_x;
     uint64_t pos = my;
     for (uint32_t ty = 0; ty < ny; ++ty) {
       for (uint32_t tx = 0; tx < nx; ++tx, ++pos) {
         if (pos < cap) {
-          const uint32_t tile = b.x + ty * b.z + tx;
-          keys[pos] = ((uint64_t)tile << 32) | (uint64_t)b.w;
-          vals[pos] = (uint32_t)fv;
+          const uint32_t tile = e.z + ty * tiles_x + tx;
+          inst[pos] = make_uint2(tile, e.y);
+          for (int p = 0; p < tp.n; ++p) atomicAdd(&s_h[p][(tile >> tp.shift[p]) & tp.mask[p]], 1u);
         }
       }
     }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < tp.n * kHistStride; i += kScanBlock)
+    if ((&s_h[0][0])[i]) atomicAdd(&hist[kTileRow0 * kHistStride + i], (&s_h[0][0])[i]);
 }
 
-void launch_bin(const uint32_t* cnt, const uint4* bin, int64_t n, uint32_t* bsum, uint64_t* boff, int nb, WsHdr* hdr,
-                uint32_t* hist, int hist_n, uint32_t cap, uint32_t passes, uint64_t* keys, uint32_t* vals,
+void launch_bin(const void* table, const uint4* el, int64_t n, uint32_t* bsum, uint64_t* boff, int nb, WsHdr* hdr,
+                uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0, uint32_t desc0_words,
                 hipStream_t s) {
-  if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, s, cnt, n, bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, boff, hdr, hist, hist_n, cap, passes);
-  if (nb > 0) hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kScanBlock), 0, s, cnt, bin, n, boff, hdr, keys, vals);
+  if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, s, el, n, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, boff, hdr, cap);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kScanBlock), 0, s, table, el, n, boff, hdr, inst, hist, tp, desc0,
+                       desc0_words);
 }
 
 }  // namespace gmr

@@ -5,8 +5,10 @@
 //   rec[fv]  3 x float4 = 48 B  {u_hi, v_hi, u_lo, v_lo}  mean as float pairs (u = u_hi + u_lo)
 //                              {k l11, k l12, k l22, x-rect}  scaled Cholesky factor of the conic
 //                              {r, g, b, y-rect}              Eq. 16 colour; rects pack lo | hi << 16
-//   bin[fv]  uint4 = 16 B      {first tile, nx | ny << 16, tiles_x of the view, float32 depth bits}
-//   cnt[fv]  tiles touched (0 when culled)
+//   el[fv]   uint4 = 16 B      {float32 depth bits, fv, first tile, nx | ny << 16}: the element the
+//                              depth passes of the radix sort move (culled: nx = ny = 0)
+// and adds each element's four 8-bit depth digits to the sort's histograms (LDS, then one global
+// atomic per bin and workgroup).
 // The mean stays in double until it is split into two floats: a float32 pixel coordinate near
 // x = 1920 carries ~1e-4 px of rounding, which alone would move alpha by ~1e-4.
 #include "gmr_common.h"
@@ -14,13 +16,10 @@
 
 namespace gmr {
 
-__global__ __launch_bounds__(256) void k_project(const void* __restrict__ table, const float* __restrict__ verts,
-                                                 const int32_t* __restrict__ faces, const float* __restrict__ colors,
-                                                 KOpts o, float4* __restrict__ rec, uint4* __restrict__ bin,
-                                                 uint32_t* __restrict__ cnt, float4* __restrict__ dfv_zero) {
-  const TableHdr* th = static_cast<const TableHdr*>(table);
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= th->faces_total) return;
+__device__ inline void project_face(const TableHdr* th, const void* __restrict__ table, const float* __restrict__ verts,
+                                    const int32_t* __restrict__ faces, const float* __restrict__ colors, const KOpts& o,
+                                    float4* __restrict__ rec, uint4* __restrict__ el, uint32_t* s_h,
+                                    float4* __restrict__ dfv_zero, int64_t f) {
   const int32_t* mfo = table_i32(table, th->mesh_face_off);
   const int32_t* mvo = table_i32(table, th->mesh_view_off);
   const int32_t* mvs = table_i32(table, th->mesh_views_off);
@@ -46,7 +45,7 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
   for (int k = mvo[m]; k < mvo[m + 1]; ++k) {
     const ViewDev& V = views[mvs[k]];
     const int64_t fv = V.fv_offset + (f - V.face_begin);
-    uint32_t count = 0;
+    uint4 e = make_uint4(0xffffffffu, (uint32_t)fv, 0u, 0u);
     ProjGeo q;
     if (ok && view_project(V, g.mu, g.S, (double)o.dilation, q)) {
       const double rx = 3.0 * sqrt(q.sxx), ry = 3.0 * sqrt(q.syy);
@@ -58,7 +57,6 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
         const int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
         const int tx0 = ix0 / tw, tx1 = ix1 / tw, ty0 = iy0 / tht, ty1 = iy1 / tht;
         const int nx = tx1 - tx0 + 1, ny = ty1 - ty0 + 1;
-        count = (uint32_t)(nx * ny);
         const float uh = (float)q.u, vh = (float)q.v;
         const float ul = (float)(q.u - (double)uh), vl = (float)(q.v - (double)vh);
         // conic = L^T L, L = [[l11, l12], [0, l22]]; l22 = sqrt(det conic) / l11 = 1 / (l11 sqrt(det))
@@ -70,11 +68,13 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
         r[1] = make_float4((float)(kscale * l11), (float)(kscale * l12), (float)(kscale * l22),
                            u2f((uint32_t)ix0 | ((uint32_t)ix1 << 16)));
         r[2] = make_float4(col[0], col[1], col[2], u2f((uint32_t)iy0 | ((uint32_t)iy1 << 16)));
-        bin[fv] = make_uint4((uint32_t)(V.tile_base + ty0 * V.tiles_x + tx0), (uint32_t)nx | ((uint32_t)ny << 16),
-                             (uint32_t)V.tiles_x, f2u((float)q.p[2]));
+        e = make_uint4(f2u((float)q.p[2]), (uint32_t)fv, (uint32_t)(V.tile_base + ty0 * V.tiles_x + tx0),
+                       (uint32_t)nx | ((uint32_t)ny << 16));
       }
     }
-    cnt[fv] = count;
+    el[fv] = e;
+#pragma unroll
+    for (int p = 0; p < kDepthPasses; ++p) atomicAdd(&s_h[p * 256 + ((e.x >> (8 * p)) & 255u)], 1u);
     if (dfv_zero) {
       dfv_zero[2 * fv] = make_float4(0.f, 0.f, 0.f, 0.f);
       dfv_zero[2 * fv + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -82,13 +82,45 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
   }
 }
 
+__global__ __launch_bounds__(256) void k_project(const void* __restrict__ table, const float* __restrict__ verts,
+                                                 const int32_t* __restrict__ faces, const float* __restrict__ colors,
+                                                 KOpts o, float4* __restrict__ rec, uint4* __restrict__ el,
+                                                 uint32_t* __restrict__ hist, float4* __restrict__ dfv_zero) {
+  __shared__ uint32_t s_h[kDepthPasses * 256];
+  for (int i = threadIdx.x; i < kDepthPasses * 256; i += blockDim.x) s_h[i] = 0u;
+  __syncthreads();
+  const TableHdr* th = static_cast<const TableHdr*>(table);
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < th->faces_total) project_face(th, table, verts, faces, colors, o, rec, el, s_h, dfv_zero, f);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kDepthPasses * 256; i += blockDim.x)
+    if (s_h[i]) atomicAdd(&hist[(i >> 8) * kHistStride + (i & 255)], s_h[i]);
+}
+
+// Clears the per-build counters, every histogram row and the first depth pass's descriptors.
+__global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ desc0, int64_t desc0_words) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t; i < desc0_words; i += stride) desc0[i] = 0u;
+  for (int64_t i = t; i < kMaxPasses * kHistStride; i += stride) hist[i] = 0u;
+  if (t == 0) {
+    for (int p = 0; p < kMaxPasses; ++p) hdr->part_ctr[p] = 0u;
+    hdr->work_fwd = 0u;
+    hdr->work_bwd = 0u;
+  }
+}
+
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
-                    const float* colors, const KOpts& o, float4* rec, uint4* bin, uint32_t* cnt, float4* dfv_zero,
-                    hipStream_t s) {
+                    const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
+                    WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, hipStream_t s) {
+  int64_t pb = (desc0_words + 255) / 256;
+  pb = pb < 1 ? 1 : (pb > 4096 ? 4096 : pb);
+  hipLaunchKernelGGL(k_prologue, dim3((unsigned)pb), dim3(256), 0, s, hdr, hist, desc0, desc0_words);
   if (faces_total <= 0) return;
   const int bs = 256;
   const int64_t nb = (faces_total + bs - 1) / bs;
-  hipLaunchKernelGGL(k_project, dim3((unsigned)nb), dim3(bs), 0, s, table, verts, faces, colors, o, rec, bin, cnt,
+  hipLaunchKernelGGL(k_project, dim3((unsigned)nb), dim3(bs), 0, s, table, verts, faces, colors, o, rec, el, hist,
                      dfv_zero);
 }
 

@@ -1,59 +1,28 @@
-// LSD onesweep radix sort of the (tile << 32 | depth) instance keys with their face-view values,
-// 8-bit digits over the low `key_bits` bits (32 depth bits + enough bits for the batch's tiles),
-// then the per-tile [start, end) ranges.
+// LSD onesweep radix sort and tile ranges.
 //
-//  k_sort_hist    one read of the keys builds the digit histograms of every pass at once
-//  k_sort_digits  exclusive scan of each pass's 256-bin histogram -> global digit offsets
-//  k_sort_pass    per pass: each workgroup takes a partition ticket (so every earlier partition
-//                 already runs), ranks its 4096 keys stably in LDS with wavefront ballots (8
-//                 ballots per 64 keys match equal digits), publishes its digit counts, resolves
-//                 its global offsets by decoupled look-back over earlier partitions' descriptors,
-//                 stages the keys in LDS in digit order and writes them out in coalesced runs.
+// The (tile | depth) key of an instance is sorted least significant digit first.  The depth digits
+// are identical for every instance of a face-view, so their passes run on the face-views, before
+// instances are emitted (4 passes of 8 bits over 16 B face-view elements {depth bits, face-view,
+// first tile, nx | ny << 16}); emission then walks face-views in depth order, and the tile digits
+// are sorted on the instances (uint2 {tile, face-view}, passes of up to 9 bits).  The result is the
+// stable sort of the instances by (tile, float32 depth, face-view), i.e. ties in depth broken by
+// ascending global id, with far fewer bytes moved than sorting 64-bit keys per instance.
+//
+// k_onesweep (one launch per pass): each workgroup takes a partition ticket, so every earlier
+// partition is already resident; it loads its 4096 elements, ranks them stably in LDS with
+// wavefront ballots (one ballot per digit bit matches equal digits among 64 lanes), publishes its
+// digit counts, resolves its global offsets by decoupled look-back over the earlier partitions'
+// descriptors, stages the elements in LDS in digit order and writes them out in coalesced runs.
 // Descriptor word: bits 31..30 = {0 empty, 1 aggregate, 2 inclusive prefix}, bits 29..0 = count,
-// so one 32-bit atomic load observes flag and value together.  Two descriptor buffers alternate:
-// each pass clears, for its own partitions, the buffer the next pass will use.
+// so a single 32-bit atomic load observes flag and value together.  Each pass also clears its
+// share of the descriptor buffer the next pass will use.
 #include "gmr_common.h"
 #include "gmr_launch.h"
 
 namespace gmr {
 
-__global__ __launch_bounds__(256) void k_sort_hist(const uint64_t* __restrict__ keys, const WsHdr* __restrict__ hdr,
-                                                   uint32_t* __restrict__ hist, int passes,
-                                                   uint32_t* __restrict__ desc0, int64_t desc_words) {
-  __shared__ uint32_t s_h[kMaxPasses * 256];
-  for (int i = threadIdx.x; i < kMaxPasses * 256; i += blockDim.x) s_h[i] = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < desc_words; i += (int64_t)gridDim.x * blockDim.x)
-    desc0[i] = 0;
-  __syncthreads();
-  const uint32_t n = min(hdr->count, hdr->capacity);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint64_t k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p * 256 + ((k >> (8 * p)) & 255u)], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < passes * 256; i += blockDim.x)
-    if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
-}
-
-__global__ __launch_bounds__(256) void k_sort_digits(const uint32_t* __restrict__ hist, uint32_t* __restrict__ dig,
-                                                     int passes) {
-  __shared__ uint32_t s_w[4];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int p = 0; p < passes; ++p) {
-    const uint32_t x = hist[p * 256 + threadIdx.x];
-    uint32_t inc = x;
-    for (int d = 1; d < 64; d <<= 1) {
-      uint32_t y = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += y;
-    }
-    if (lane == 63) s_w[w] = inc;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int k = 0; k < w; ++k) before += s_w[k];
-    dig[p * 256 + threadIdx.x] = before + inc - x;
-    __syncthreads();
-  }
-}
+__device__ inline uint32_t elem_key(const uint4& e) { return e.x; }
+__device__ inline uint32_t elem_key(const uint2& e) { return e.x; }
 
 __device__ inline uint32_t desc_load(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -62,44 +31,59 @@ __device__ inline void desc_store(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kSortBlock) void k_sort_pass(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                          uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                          WsHdr* hdr, const uint32_t* __restrict__ dig,
-                                                          uint32_t* desc_cur, uint32_t* desc_next, int pass) {
-  __shared__ uint64_t s_keys[kSortPart];
-  __shared__ uint32_t s_vals[kSortPart];
-  __shared__ uint32_t s_wcnt[kSortBlock / kWave][256];
-  __shared__ uint32_t s_bstart[256];
-  __shared__ uint32_t s_gbase[256];
-  __shared__ uint32_t s_wsum[kSortBlock / kWave];
+// kSplit: write keys and values to separate uint32 arrays (the last instance pass).
+template <typename E, int kRadix, bool kSplit>
+__global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ in, E* __restrict__ out,
+                                                         uint32_t* __restrict__ out_k, uint32_t* __restrict__ out_v,
+                                                         const uint32_t* __restrict__ n_dev, uint32_t n_max,
+                                                         const uint32_t* __restrict__ dig, uint32_t* desc_cur,
+                                                         uint32_t* desc_next, uint32_t next_words, uint32_t* ticket,
+                                                         int shift, uint32_t mask) {
+  constexpr int kNW = kSortBlock / kWave;
+  constexpr int kBits = kRadix == 256 ? 8 : 9;
+  __shared__ E s_el[kSortPart];
+  __shared__ uint32_t s_wcnt[kNW][kRadix];
+  __shared__ uint32_t s_bstart[kRadix];
+  __shared__ uint32_t s_gbase[kRadix];
+  __shared__ uint32_t s_wsum[kNW];
   __shared__ uint32_t s_part;
 
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int shift = 8 * pass;
-  if (threadIdx.x == 0) s_part = atomicAdd(&hdr->part_ctr[pass], 1u);
-  for (int i = threadIdx.x; i < (kSortBlock / kWave) * 256; i += kSortBlock) (&s_wcnt[0][0])[i] = 0;
+  // clear this workgroup's slice of the next pass's descriptors (every workgroup, before any exit)
+  {
+    const uint32_t chunk = (next_words + gridDim.x - 1) / gridDim.x;
+    const uint32_t b0 = blockIdx.x * chunk;
+    const uint32_t b1 = min(next_words, b0 + chunk);
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += kSortBlock) desc_next[i] = 0u;
+  }
+  if (threadIdx.x == 0) s_part = atomicAdd(ticket, 1u);
+  for (int i = threadIdx.x; i < kNW * kRadix; i += kSortBlock) (&s_wcnt[0][0])[i] = 0u;
   __syncthreads();
-  const uint32_t n = min(hdr->count, hdr->capacity);
+  const uint32_t n = n_dev ? min(*n_dev, n_max) : n_max;
   const uint32_t part = s_part;
   const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
   if (part >= nparts) return;  // uniform across the workgroup
   const uint32_t base = part * kSortPart;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  uint64_t k[kSortItems];
-  uint32_t v[kSortItems];
+  // ---- load every element first (all loads in flight together)
+  E e[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint32_t idx = base + (uint32_t)w * (kSortItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
+    if (idx < n) e[i] = in[idx];
+    else e[i] = E{};
+  }
+  // ---- stable ranking: wavefront w owns elements [w*ITEMS*64, (w+1)*ITEMS*64), 64 at a time
   uint32_t rank[kSortItems];
-  // ---- stable ranking inside the partition: wavefront w owns keys [w*1024, (w+1)*1024), 64 at a time
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
     const uint32_t idx = base + (uint32_t)w * (kSortItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
     const bool have = idx < n;
-    k[i] = have ? kin[idx] : 0ull;
-    v[i] = have ? vin[idx] : 0u;
-    const uint32_t d = (uint32_t)(k[i] >> shift) & 255u;
+    const uint32_t d = (elem_key(e[i]) >> shift) & mask;
     uint64_t peers = __ballot(have);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < kBits; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
@@ -114,36 +98,38 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const uint64_t* __rest
   }
   __syncthreads();
 
-  // ---- per digit (thread = digit): wavefront-exclusive offsets, publish, look back
-  const int d = threadIdx.x;
+  // ---- per digit: wavefront-exclusive offsets, publish, look back
   uint32_t tot = 0;
-  for (int ww = 0; ww < kSortBlock / kWave; ++ww) {
-    const uint32_t c = s_wcnt[ww][d];
-    s_wcnt[ww][d] = tot;
-    tot += c;
-  }
-  uint32_t* my = desc_cur + (size_t)part * 256 + d;
-  desc_store(my, (part == 0 ? kFlagInc : kFlagAgg) | tot);
-  desc_next[(size_t)part * 256 + d] = 0u;
-  uint32_t excl = 0;
-  if (part > 0) {
-    int j = (int)part - 1;
-    while (true) {
-      const uint32_t x = desc_load(desc_cur + (size_t)j * 256 + d);
-      if ((x & ~kValMask) == 0u) {
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      excl += x & kValMask;
-      if (x & kFlagInc) break;
-      --j;
+  const int d = threadIdx.x;
+  if (d < kRadix) {
+    for (int ww = 0; ww < kNW; ++ww) {
+      const uint32_t c = s_wcnt[ww][d];
+      s_wcnt[ww][d] = tot;
+      tot += c;
     }
-    desc_store(my, kFlagInc | (excl + tot));
+    uint32_t* my = desc_cur + (size_t)part * kRadix + d;
+    desc_store(my, (part == 0 ? kFlagInc : kFlagAgg) | tot);
+    uint32_t excl = 0;
+    if (part > 0) {
+      int j = (int)part - 1;
+      while (true) {
+        const uint32_t x = desc_load(desc_cur + (size_t)j * kRadix + d);
+        if ((x & ~kValMask) == 0u) {
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += x & kValMask;
+        if (x & kFlagInc) break;
+        --j;
+      }
+      desc_store(my, kFlagInc | (excl + tot));
+    }
+    s_gbase[d] = dig[d] + excl;
   }
-  s_gbase[d] = dig[pass * 256 + d] + excl;
-  // block-local exclusive scan over digits -> s_bstart
+  // block-local exclusive scan of the digit totals (threads >= kRadix contribute 0)
   {
     uint32_t inc = tot;
+#pragma unroll
     for (int s = 1; s < kWave; s <<= 1) {
       const uint32_t y = __shfl_up(inc, s, kWave);
       if (lane >= s) inc += y;
@@ -152,7 +138,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const uint64_t* __rest
     __syncthreads();
     uint32_t before = 0;
     for (int ww = 0; ww < w; ++ww) before += s_wsum[ww];
-    s_bstart[d] = before + inc - tot;
+    if (d < kRadix) s_bstart[d] = before + inc - tot;
   }
   __syncthreads();
 
@@ -161,20 +147,43 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const uint64_t* __rest
   for (int i = 0; i < kSortItems; ++i) {
     const uint32_t idx = base + (uint32_t)w * (kSortItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
     if (idx < n) {
-      const uint32_t dd = (uint32_t)(k[i] >> shift) & 255u;
-      const uint32_t pos = s_bstart[dd] + s_wcnt[w][dd] + rank[i];
-      s_keys[pos] = k[i];
-      s_vals[pos] = v[i];
+      const uint32_t dd = (elem_key(e[i]) >> shift) & mask;
+      s_el[s_bstart[dd] + s_wcnt[w][dd] + rank[i]] = e[i];
     }
   }
   __syncthreads();
   const uint32_t nb = min((uint32_t)kSortPart, n - base);
   for (uint32_t s = threadIdx.x; s < nb; s += kSortBlock) {
-    const uint64_t key = s_keys[s];
-    const uint32_t dd = (uint32_t)(key >> shift) & 255u;
+    const E x = s_el[s];
+    const uint32_t dd = (elem_key(x) >> shift) & mask;
     const uint32_t g = s_gbase[dd] + (s - s_bstart[dd]);
-    kout[g] = key;
-    vout[g] = s_vals[s];
+    if constexpr (kSplit) {
+      out_k[g] = elem_key(x);
+      out_v[g] = reinterpret_cast<const uint32_t*>(&x)[1];
+    } else {
+      out[g] = x;
+    }
+  }
+}
+
+// Exclusive scan of `rows` histograms of `radix` bins: dig[r][b] = sum of hist[r][< b].
+__global__ __launch_bounds__(512) void k_sort_digits(const uint32_t* __restrict__ hist, uint32_t* __restrict__ dig,
+                                                     int row0, int rows, int radix) {
+  __shared__ uint32_t s_w[512 / kWave];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int r = row0; r < row0 + rows; ++r) {
+    const uint32_t x = threadIdx.x < radix ? hist[r * kHistStride + threadIdx.x] : 0u;
+    uint32_t inc = x;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t y = __shfl_up(inc, d, kWave);
+      if (lane >= d) inc += y;
+    }
+    if (lane == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before += s_w[k];
+    if (threadIdx.x < radix) dig[r * kHistStride + threadIdx.x] = before + inc - x;
+    __syncthreads();
   }
 }
 
@@ -182,13 +191,13 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = val;
 }
 
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys, const WsHdr* __restrict__ hdr,
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ keys, const WsHdr* __restrict__ hdr,
                                                      uint32_t* __restrict__ ranges) {
   const uint32_t n = min(hdr->count, hdr->capacity);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t t = (uint32_t)(keys[i] >> 32);
-    if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[2 * (size_t)t] = i;
-    if (i + 1 == n || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * (size_t)t + 1] = i + 1;
+    const uint32_t t = keys[i];
+    if (i == 0 || keys[i - 1] != t) ranges[2 * (size_t)t] = i;
+    if (i + 1 == n || keys[i + 1] != t) ranges[2 * (size_t)t + 1] = i + 1;
   }
 }
 
@@ -199,24 +208,33 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)nb), dim3(256), 0, s, p, n, val);
 }
 
-void launch_sort_hist(const uint64_t* keys0, const WsHdr* hdr, uint32_t* hist, uint32_t* dig, uint32_t* desc0,
-                      int64_t parts_max, int passes, int hist_blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_hist, dim3(hist_blocks), dim3(256), 0, s, keys0, hdr, hist, passes, desc0, parts_max * 256);
-  hipLaunchKernelGGL(k_sort_digits, dim3(1), dim3(256), 0, s, hist, dig, passes);
+void launch_sort_digits(const uint32_t* hist, uint32_t* dig, int row0, int rows, int radix, hipStream_t s) {
+  if (rows > 0) hipLaunchKernelGGL(k_sort_digits, dim3(1), dim3(512), 0, s, hist, dig, row0, rows, radix);
 }
 
-// One onesweep pass p: reads buffer (p & 1), writes buffer (p & 1) ^ 1.
-void launch_sort_pass(uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, WsHdr* hdr, const uint32_t* dig,
-                      uint32_t* desc0, uint32_t* desc1, int64_t parts_max, int p, hipStream_t s) {
-  if (parts_max <= 0) return;
-  const bool odd = p & 1;
-  hipLaunchKernelGGL(k_sort_pass, dim3((unsigned)parts_max), dim3(kSortBlock), 0, s, odd ? keys1 : keys0,
-                     odd ? vals1 : vals0, odd ? keys0 : keys1, odd ? vals0 : vals1, hdr, dig, odd ? desc1 : desc0,
-                     odd ? desc0 : desc1, p);
+void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* dig, uint32_t* desc_cur,
+                         uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int shift, hipStream_t s) {
+  const uint32_t parts = (n + kSortPart - 1) / kSortPart;
+  if (parts == 0) return;
+  hipLaunchKernelGGL((k_onesweep<uint4, 256, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, nullptr, nullptr,
+                     nullptr, n, dig, desc_cur, desc_next, next_words, ticket, shift, 255u);
 }
 
-void launch_tile_ranges(const uint64_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int64_t tiles_total,
-                        int blocks, hipStream_t s) {
+void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
+                           uint32_t cap, const uint32_t* dig, uint32_t* desc_cur, uint32_t* desc_next,
+                           uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, hipStream_t s) {
+  const uint32_t parts = (cap + kSortPart - 1) / kSortPart;
+  if (parts == 0) return;
+  if (out_k)
+    hipLaunchKernelGGL((k_onesweep<uint2, 512, true>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v, n_dev,
+                       cap, dig, desc_cur, desc_next, next_words, ticket, shift, mask);
+  else
+    hipLaunchKernelGGL((k_onesweep<uint2, 512, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
+                       n_dev, cap, dig, desc_cur, desc_next, next_words, ticket, shift, mask);
+}
+
+void launch_tile_ranges(const uint32_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int64_t tiles_total, int blocks,
+                        hipStream_t s) {
   launch_fill_u32(ranges, 2 * tiles_total, 0u, s);
   hipLaunchKernelGGL(k_tile_ranges, dim3(blocks), dim3(256), 0, s, sorted_keys, hdr, ranges);
 }
