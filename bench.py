@@ -21,7 +21,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
-FP32_VECTOR_TFLOPS = 157.3     # MI355X vector FP32 (packed); 78.6 non-packed
+FP32_VECTOR_TFLOPS = 157.3     # MI355X vector FP32, published (packed FP32; the build disables packed ops)
+# Arithmetic per (pixel, Gaussian) pair, counting an FMA as 2: forward = offsets 4, w1/w2 4,
+# squared radius 3, exp2 2, clamp/cutoff 2, transmittance 3, weight 1, colour 6 -> 25;
+# backward = the forward's 19 up to the cutoff + rcp, T_k, c.g (5), dL/dalpha (4), weight, S (2),
+# clamp test, dL/dpower, 5 geometry partials (16), 3 colour partials (6) -> 52.
+FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 
 
 def parse():
@@ -30,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
-    ap.add_argument("--autotune", action="store_true", help="pick tile shape / raster mode with gmr_autotune")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile / block shape")
     ap.add_argument("--tile", type=str, default=None, help="WxH binning tile, e.g. 16x16")
     ap.add_argument("--raster-mode", type=int, default=None)
     ap.add_argument("--no-per-view", action="store_true")
@@ -100,8 +105,9 @@ def main():
     with torch.no_grad():
         target, _, _, _ = r.forward(tverts, colors, check=True)
     target = target.clone()
-    if args.autotune:
-        r.autotune(verts, colors, target, iters=3)
+    tuned_ms = None
+    if not args.no_autotune and not args.tile and args.raster_mode is None:
+        _, tuned_ms = r.autotune(verts, colors, target, iters=3)
     recompute = args.config in (3, 5)
     use_graph = args.config == 5
     P = W.num_pixels
@@ -142,9 +148,11 @@ def main():
     value = P / (ms_step * 1e-3) / 1e6
     ws_ref = loop.ws_fwd if use_graph else ws
     cnt = r.counters(ws_ref)
-    if cnt.overflow:
+    cnt_b = r.counters(loop.ws_bwd if use_graph else ws_b)
+    if cnt.overflow or cnt_b.overflow:
         raise RuntimeError("instance capacity overflowed during the timed steps")
     I = cnt.instances
+    pairs = {"raster_fwd": cnt.pairs_fwd, "raster_bwd": cnt_b.pairs_bwd}
 
     # ---- per-stage timing (HIP events on the library's stream), same steps ----------------------
     from paper_2602_14493_amd import _lib
@@ -166,15 +174,24 @@ def main():
         b = byte_model(k, F, FV, V, P, I, tiles)
         stages[k] = {"ms_per_launch": round(avg, 4), "launches_per_step": n / args.steps,
                      "ms_per_step": round(ms / args.steps, 4), "alg_GBps": round(b / (avg * 1e-3) / 1e9, 1)}
+        if k in FLOPS_PER_PAIR:
+            stages[k]["pairs"] = pairs[k]
+            stages[k]["alg_TFLOPs"] = round(pairs[k] * FLOPS_PER_PAIR[k] / (avg * 1e-3) / 1e12, 2)
     dom = max(stages, key=lambda k: stages[k]["ms_per_step"])
     d = stages[dom]
-    achieved = d["alg_GBps"]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    if dom in FLOPS_PER_PAIR:   # compositing kernels: VALU-bound on LDS-broadcast data
+        achieved = d["alg_TFLOPs"]
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_VECTOR_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                    "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": pairs[dom]}
+    else:
+        achieved = d["alg_GBps"]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
 
     # ---- per-view launches (same work, one launch set per view) -------------------------------
     per_view = None
-    if not args.no_per_view and W.num_views > 1 and not use_graph:
+    if not args.no_per_view and W.num_views > 1:
         rs = []
         for v in range(W.num_views):
             bv = batch.view(v)
@@ -240,7 +257,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": W.name, "faces": F, "verts": V, "views": W.num_views, "pixels": P,
-                   "instances": I, "tile": f"{r.opts.tile_w}x{r.opts.tile_h}", "raster_mode": r.opts.raster_mode,
+                   "instances": I, "tile": f"{r.opts.tile_w}x{r.opts.tile_h}", "px_per_lane": r.opts.px_per_lane,
+                   "raster_mode": r.opts.raster_mode, "autotune_ms": tuned_ms,
                    "recompute_lists": recompute, "adam_graph": use_graph},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -61,7 +61,8 @@ typedef struct gmr_options {
   float bg[3];               /* [0,0,0] background colour                                         */
   int32_t tile_w, tile_h;    /* [16,16] binning tile in pixels: multiples of 8 in [8, 64]          */
   int32_t raster_mode;       /* [0] 0: one workgroup per tile group; 1: persistent work queue     */
-  int32_t reserved;          /* must be 0                                                          */
+  int32_t px_per_lane;       /* [1] pixels per lane in the rasteriser: 1, 2 or 4 (a wavefront then
+                                covers an 8 x 8*px_per_lane block); tile_h % (8*px_per_lane) == 0   */
   int64_t instance_capacity; /* [0] (Gaussian, tile) instances the workspace holds; must be > 0
                                 when sizing a workspace or rendering                               */
 } gmr_options;
@@ -84,6 +85,10 @@ typedef struct gmr_counters {
   int64_t capacity;    /* capacity of the workspace                                           */
   int32_t overflow;    /* 1 if instances > capacity (outputs of that pass are incomplete)    */
   int32_t reserved;
+  int64_t pairs_fwd;   /* (pixel, Gaussian) pairs the last forward evaluated inside extents   */
+  int64_t pairs_bwd;   /* pairs the last backward differentiated (composited ones)           */
+  float loss;          /* loss value of the last fused L2 backward                           */
+  int32_t reserved2;
 } gmr_counters;
 
 typedef struct gmr_ctx* gmr_handle;

@@ -75,7 +75,9 @@ gmr_status validate_options(const gmr_options* o) {
   auto tile_ok = [](int32_t t) { return t >= 8 && t <= 64 && t % 8 == 0; };
   if (!tile_ok(o->tile_w) || !tile_ok(o->tile_h)) return fail(GMR_ERR_INVALID_ARG, "tile_w/tile_h must be multiples of 8 in [8, 64]");
   if (o->raster_mode != 0 && o->raster_mode != 1) return fail(GMR_ERR_INVALID_ARG, "raster_mode must be 0 or 1");
-  if (o->reserved != 0) return fail(GMR_ERR_INVALID_ARG, "reserved must be 0");
+  if (o->px_per_lane != 1 && o->px_per_lane != 2 && o->px_per_lane != 4)
+    return fail(GMR_ERR_INVALID_ARG, "px_per_lane must be 1, 2 or 4");
+  if (o->tile_h % (kSub * o->px_per_lane) != 0) return fail(GMR_ERR_INVALID_ARG, "tile_h must be a multiple of 8*px_per_lane");
   return GMR_OK;
 }
 
@@ -100,7 +102,7 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   p.tile_w = o->tile_w;
   p.tile_h = o->tile_h;
   p.sub_x = o->tile_w / kSub;
-  p.sub_y = o->tile_h / kSub;
+  p.sub_y = o->tile_h / (kSub * o->px_per_lane);
   p.views.assign(p.nv, ViewDev{});
   std::vector<std::vector<int32_t>> per_mesh(p.nm);
   int64_t fv = 0, px = 0, tiles = 0;
@@ -409,13 +411,14 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
     StageTimer t(h, s, kStFill);
     launch_fill_u32(&w.hdr->work_bwd, 1, 0u, s);
     launch_fill_f32(&w.hdr->loss, 1, 0.f, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(&w.hdr->pairs_bwd), 2, 0u, s);
   }
   const float* saved_T = static_cast<const float*>(saved);
   const uint32_t* saved_n = reinterpret_cast<const uint32_t*>(saved_T + p.p_total);
   const double n3 = 3.0 * (double)p.p_total;
   {
     StageTimer t(h, s, kStRasterBwd);
-    launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), w.ranges, w.sorted_vals, w.rec, ko, saved_T,
+    launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals, w.rec, ko, saved_T,
                       saved_n, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
                       w.dfv, w.hdr, s);
   }
@@ -454,7 +457,7 @@ gmr_options gmr_default_options(void) {
   o.tile_w = 16;
   o.tile_h = 16;
   o.raster_mode = 0;
-  o.reserved = 0;
+  o.px_per_lane = 1;
   o.instance_capacity = 0;
   return o;
 }
@@ -553,7 +556,7 @@ gmr_status gmr_render_fwd(gmr_handle h, const gmr_batch* batch, const gmr_option
   uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
   {
     StageTimer t(h, s, kStRasterFwd);
-    launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), w.ranges, w.sorted_vals, w.rec, kopts(opt),
+    launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals, w.rec, kopts(opt),
                       out_rgb, out_alpha, saved_T, saved_n, w.hdr, s);
   }
   return check_launch();
@@ -636,6 +639,10 @@ gmr_status gmr_read_counters(const void* ws, size_t ws_bytes, gmr_counters* out,
   out->capacity = hdr.capacity;
   out->overflow = (int32_t)hdr.overflow;
   out->reserved = 0;
+  out->pairs_fwd = (int64_t)hdr.pairs_fwd;
+  out->pairs_bwd = (int64_t)hdr.pairs_bwd;
+  out->loss = hdr.loss;
+  out->reserved2 = 0;
   return GMR_OK;
 }
 
@@ -666,7 +673,14 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
     return GMR_OK;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int shapes[][2] = {{8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}};
+  // candidates: binning tile, pixels per lane (block shape), raster mode
+  struct Cand { int tw, th, px, mode; };
+  std::vector<Cand> cands;
+  const int shapes[][2] = {{8, 8}, {16, 16}, {32, 16}, {32, 32}, {64, 32}};
+  for (const auto& sh : shapes)
+    for (int px : {1, 2, 4})
+      if (sh[1] % (kSub * px) == 0)
+        for (int mode = 0; mode < 2; ++mode) cands.push_back({sh[0], sh[1], px, mode});
   float best_ms = 1e30f;
   gmr_options best = b;
   float *rgb = nullptr, *dv = nullptr, *dc = nullptr;
@@ -680,12 +694,14 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
   GMR_CHECK_HIP(hipEventCreate(&e0));
   GMR_CHECK_HIP(hipEventCreate(&e1));
   gmr_status result = GMR_OK;
-  for (const auto& sh : shapes) {
-    for (int mode = 0; mode < 2 && result == GMR_OK; ++mode) {
+  for (const Cand& cd : cands) {
+    if (result != GMR_OK) break;
+    {
       gmr_options o = b;
-      o.tile_w = sh[0];
-      o.tile_h = sh[1];
-      o.raster_mode = mode;
+      o.tile_w = cd.tw;
+      o.tile_h = cd.th;
+      o.px_per_lane = cd.px;
+      o.raster_mode = cd.mode;
       o.instance_capacity = std::max<int64_t>(b.instance_capacity, 1 << 20);
       for (int attempt = 0; attempt < 3 && result == GMR_OK; ++attempt) {
         Plan p;

@@ -60,9 +60,11 @@ struct WsHdr {                 // 256 B at the start of the workspace
   uint32_t passes;
   uint32_t part_ctr[kMaxPasses];   // onesweep partition tickets, one per pass (same rows as the histograms)
   uint32_t work_fwd, work_bwd;     // persistent raster queues
-  uint32_t pad0[2];
+  unsigned long long pairs_fwd;    // (pixel, Gaussian) pairs the forward evaluated
   float loss;                      // L2 loss value of the last fused backward
-  uint32_t pad1[47];
+  uint32_t pad0;
+  unsigned long long pairs_bwd;    // (pixel, Gaussian) pairs the backward differentiated
+  uint32_t pad1[44];
 };
 static_assert(sizeof(WsHdr) == 256, "ws header");
 

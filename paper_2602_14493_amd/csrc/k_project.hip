@@ -108,6 +108,7 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
     for (int p = 0; p < kMaxPasses; ++p) hdr->part_ctr[p] = 0u;
     hdr->work_fwd = 0u;
     hdr->work_bwd = 0u;
+    hdr->pairs_fwd = 0ull;
   }
 }
 

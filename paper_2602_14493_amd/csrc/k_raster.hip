@@ -1,11 +1,12 @@
 // Per-tile front-to-back alpha compositing and its reverse-order adjoint (the 3DGS rasteriser of
 // Sec. 2.1, with opacity 1 per Sec. 2.2's colour assignment).
 //
-// Work item = one 8x8 pixel block of a tile, handled by one wavefront (one pixel per lane).  A
-// wavefront walks its tile's depth-sorted list 64 instances at a time: each lane gathers one 48 B
-// record, the records whose integer pixel rectangle meets the 8x8 block are kept (ballot), staged
-// in the wavefront's LDS slots and consumed in list order as wave-uniform broadcasts.  The
-// wavefront leaves as soon as every lane has stopped.  Wavefronts never synchronise with each
+// Work item = one 8 x (8 PX) pixel block of a tile, handled by one wavefront: lane (lx, ly) owns the
+// PX pixels (lx, ly + 8k), k < PX.  A wavefront walks its tile's depth-sorted list 64 instances at
+// a time: each lane gathers one 48 B record, the records whose integer pixel rectangle meets the
+// block are kept (ballot), staged in the wavefront's LDS slots and consumed in list order as
+// wave-uniform broadcasts; the x offset and x extent test of a lane are shared by its PX pixels.
+// The wavefront leaves as soon as every pixel has stopped.  Wavefronts never synchronise with each
 // other, so a tile's blocks finish independently.
 //
 // Per pixel and Gaussian (exp(power) = exp2(-(w1^2 + w2^2)), w = k L (dx, dy), L^T L = conic):
@@ -21,9 +22,9 @@
 //   dL/dpower = alpha dL/dalpha when unclamped, else 0
 //   (du, dv) = -dL/dpower (conic (dx, dy));  (da, db, dc) = -dL/dpower (dx^2/2, dx dy, dy^2/2)
 //   dL/dc_k = alpha_k T_k g_C
-// The 8 per-Gaussian partials are summed over the wavefront with a butterfly that halves the
-// values carried per lane at each of the first three steps (10 shuffles for 8 sums), then 8 lanes
-// issue one float atomic each into the face-view's gradient record.
+// A lane first sums its PX pixels' partials; the 8 sums are then reduced over the wavefront with a
+// butterfly that halves the values carried per lane at each of the first three steps (10 shuffles
+// for 8 sums), and 8 lanes issue one float atomic each into the face-view's gradient record.
 #include "gmr_common.h"
 #include "gmr_launch.h"
 
@@ -37,11 +38,12 @@ __device__ inline int xcd_remap(int b, int nb) {
 }
 
 struct ItemGeo {
-  int tile, x, y, bx0, by0;
-  bool valid, any;
-  int64_t pix;
+  int tile, x, bx0, by0, W, H;
+  bool any;
+  int64_t row0;  // pixel index of (0, by0 + ly) in the flat image
 };
 
+template <int PX>
 __device__ inline ItemGeo item_geometry(const TableHdr* th, const ViewDev* views, int item, int lane) {
   ItemGeo g;
   const int spt = th->sub_x * th->sub_y;
@@ -53,33 +55,36 @@ __device__ inline ItemGeo item_geometry(const TableHdr* th, const ViewDev* views
   const int tyi = lt / V.tiles_x, txi = lt - tyi * V.tiles_x;
   const int sy = sub / th->sub_x, sx = sub - sy * th->sub_x;
   g.bx0 = txi * th->tile_w + sx * kSub;
-  g.by0 = tyi * th->tile_h + sy * kSub;
+  g.by0 = tyi * th->tile_h + sy * (kSub * PX);
+  g.W = V.W;
+  g.H = V.H;
   g.any = g.bx0 < V.W && g.by0 < V.H;
   g.x = g.bx0 + (lane & 7);
-  g.y = g.by0 + (lane >> 3);
-  g.valid = g.any && g.x < V.W && g.y < V.H;
-  g.pix = V.pixel_offset + (int64_t)g.y * V.W + g.x;
+  g.row0 = V.pixel_offset + (int64_t)(g.by0 + (lane >> 3)) * V.W;
   return g;
 }
 
-__device__ inline bool rect_meets_block(uint32_t rx, uint32_t ry, int bx0, int by0) {
+__device__ inline bool rect_meets_block(uint32_t rx, uint32_t ry, int bx0, int by0, int bh) {
   const int ix0 = (int)(rx & 0xffffu), ix1 = (int)(rx >> 16), iy0 = (int)(ry & 0xffffu), iy1 = (int)(ry >> 16);
-  return ix0 <= bx0 + kSub - 1 && ix1 >= bx0 && iy0 <= by0 + kSub - 1 && iy1 >= by0;
+  return ix0 <= bx0 + kSub - 1 && ix1 >= bx0 && iy0 <= by0 + bh - 1 && iy1 >= by0;
 }
 
-__device__ inline bool pixel_in_rect(uint32_t rx, uint32_t ry, int x, int y) {
-  const int ix0 = (int)(rx & 0xffffu), ix1 = (int)(rx >> 16), iy0 = (int)(ry & 0xffffu), iy1 = (int)(ry >> 16);
-  return (uint32_t)(x - ix0) <= (uint32_t)(ix1 - ix0) && (uint32_t)(y - iy0) <= (uint32_t)(iy1 - iy0);
+__device__ inline bool in_range(uint32_t r, int x) {
+  const int lo = (int)(r & 0xffffu), hi = (int)(r >> 16);
+  return (uint32_t)(x - lo) <= (uint32_t)(hi - lo);
 }
 
 // Shared by forward and backward so both take bit-identical decisions.
-__device__ inline float gauss_exp(const float4& r0, const float4& r1, float px, float py, float& dx, float& dy,
-                                  float& w1, float& w2) {
-  dx = (r0.x - px) + r0.z;
-  dy = (r0.y - py) + r0.w;
+__device__ inline float gauss_exp(const float4& r1, float dx, float dy, float& w1, float& w2) {
   w1 = fmaf(r1.x, dx, r1.y * dy);
   w2 = r1.z * dy;
   return __builtin_amdgcn_exp2f(-fmaf(w1, w1, w2 * w2));
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -98,18 +103,32 @@ struct FwdArgs {
   WsHdr* hdr;
 };
 
+template <int PX>
 __device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
                                        float4 (*s)[kWave]) {
-  const ItemGeo g = item_geometry(th, views, item, lane);
+  const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return;
-  const float px = (float)g.x + 0.5f, py = (float)g.y + 0.5f;
+  const int ly = lane >> 3;
+  const float px = (float)g.x + 0.5f;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  uint32_t last = 0;
-  bool done = !g.valid;
+  float T[PX], C0[PX], C1[PX], C2[PX];
+  uint32_t last[PX];
+  bool done[PX];
+  int y[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    y[k] = g.by0 + ly + kSub * k;
+    T[k] = 1.f; C0[k] = 0.f; C1[k] = 0.f; C2[k] = 0.f;
+    last[k] = 0;
+    done[k] = !(g.x < g.W && y[k] < g.H);
+  }
+  unsigned long long pairs = 0;
   for (uint32_t cb = start; cb < end; cb += kWave) {
-    if (__ballot(!done) == 0ull) break;
+    bool live = false;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) live |= !done[k];
+    if (__ballot(live) == 0ull) break;
     const uint32_t pos = cb + (uint32_t)lane;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
     bool ov = false;
@@ -117,7 +136,7 @@ __device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, con
       const uint32_t id = a.vals[pos];
       const float4* rp = a.rec + (size_t)kRecF4 * id;
       r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
-      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0);
+      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX);
     }
     uint64_t m = __ballot(ov);
     if (m == 0ull) continue;
@@ -127,40 +146,58 @@ __device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, con
       const int j = __builtin_ctzll(m);
       m &= m - 1;
       const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
-      if (!done && pixel_in_rect(f2u(a1.w), f2u(a2.w), g.x, g.y)) {
-        float dx, dy, w1, w2;
-        const float e = gauss_exp(a0, a1, px, py, dx, dy, w1, w2);
-        const float al = fminf(amax, e);
-        if (al >= amin) {
-          const float Tn = T * (1.f - al);
-          if (Tn < teps) {
-            done = true;
-          } else {
-            const float wt = al * T;
-            C0 = fmaf(a2.x, wt, C0);
-            C1 = fmaf(a2.y, wt, C1);
-            C2 = fmaf(a2.z, wt, C2);
-            T = Tn;
-            last = cb + (uint32_t)j - start + 1u;
+      if (in_range(f2u(a1.w), g.x)) {
+        const float dx = (a0.x - px) + a0.z;
+        const uint32_t ry = f2u(a2.w);
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+          if (!done[k] && in_range(ry, y[k])) {
+            ++pairs;
+            const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
+            float w1, w2;
+            const float e = gauss_exp(a1, dx, dy, w1, w2);
+            const float al = fminf(amax, e);
+            if (al >= amin) {
+              const float Tn = T[k] * (1.f - al);
+              if (Tn < teps) {
+                done[k] = true;
+              } else {
+                const float wt = al * T[k];
+                C0[k] = fmaf(a2.x, wt, C0[k]);
+                C1[k] = fmaf(a2.y, wt, C1[k]);
+                C2[k] = fmaf(a2.z, wt, C2[k]);
+                T[k] = Tn;
+                last[k] = cb + (uint32_t)j - start + 1u;
+              }
+            }
           }
         }
       }
-      if (__ballot(!done) == 0ull) break;
+      bool live2 = false;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) live2 |= !done[k];
+      if (__ballot(live2) == 0ull) break;
     }
     wave_lds_sync();
   }
-  if (g.valid) {
-    float* o = a.out_rgb + 3 * g.pix;
-    o[0] = fmaf(T, a.o.bg0, C0);
-    o[1] = fmaf(T, a.o.bg1, C1);
-    o[2] = fmaf(T, a.o.bg2, C2);
-    if (a.out_alpha) a.out_alpha[g.pix] = 1.f - T;
-    a.saved_T[g.pix] = T;
-    a.saved_n[g.pix] = last;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    if (g.x < g.W && y[k] < g.H) {
+      const int64_t p = g.row0 + (int64_t)(kSub * k) * g.W + g.x;
+      float* o = a.out_rgb + 3 * p;
+      o[0] = fmaf(T[k], a.o.bg0, C0[k]);
+      o[1] = fmaf(T[k], a.o.bg1, C1[k]);
+      o[2] = fmaf(T[k], a.o.bg2, C2[k]);
+      if (a.out_alpha) a.out_alpha[p] = 1.f - T[k];
+      a.saved_T[p] = T[k];
+      a.saved_n[p] = last[k];
+    }
   }
+  pairs = wave_sum_u64(pairs);
+  if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_fwd, pairs);
 }
 
-template <bool kPersistent>
+template <int PX, bool kPersistent>
 __global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
   __shared__ float4 s_rec[256 / kWave][kRecF4][kWave];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
@@ -173,11 +210,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
       if (lane == 0) item = (int)atomicAdd(&a.hdr->work_fwd, 1u);
       item = __shfl(item, 0, kWave);
       if (item >= items) break;
-      raster_fwd_item(a, th, views, item, lane, s_rec[w]);
+      raster_fwd_item<PX>(a, th, views, item, lane, s_rec[w]);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
-    if (item < items) raster_fwd_item(a, th, views, item, lane, s_rec[w]);
+    if (item < items) raster_fwd_item<PX>(a, th, views, item, lane, s_rec[w]);
   }
 }
 
@@ -227,47 +264,58 @@ __device__ inline float wave_reduce8_transpose(const float (&g)[8], int lane) {
   return r;  // lanes with (lane & 7) == 0 hold the sum of g[lane >> 3]
 }
 
-template <bool kL2>
+template <int PX, bool kL2>
 __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
                                        float4 (*s)[kWave], uint32_t* s_id) {
-  const ItemGeo g = item_geometry(th, views, item, lane);
+  const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return;
-  float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, ga = 0.f, Tf = 1.f;
-  uint32_t last = 0;
-  if (g.valid) {
-    Tf = a.saved_T[g.pix];
-    last = a.saved_n[g.pix];
-    if (kL2) {
-      const float* rp = a.rgb + 3 * g.pix;
-      const float* tp = a.target + 3 * g.pix;
-      const float e0 = rp[0] - tp[0], e1 = rp[1] - tp[1], e2 = rp[2] - tp[2];
-      gc0 = a.l2_grad_scale * e0;
-      gc1 = a.l2_grad_scale * e1;
-      gc2 = a.l2_grad_scale * e2;
-      ga = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));  // reused below as the loss term
-    } else {
-      const float* dp = a.d_rgb + 3 * g.pix;
-      gc0 = dp[0]; gc1 = dp[1]; gc2 = dp[2];
-      ga = a.d_alpha ? a.d_alpha[g.pix] : 0.f;
+  const int ly = lane >> 3;
+  const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
+  float gc0[PX], gc1[PX], gc2[PX], K[PX], T[PX], S[PX];
+  uint32_t last[PX];
+  int y[PX];
+  float loss = 0.f;
+  uint32_t mx = 0;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    y[k] = g.by0 + ly + kSub * k;
+    gc0[k] = gc1[k] = gc2[k] = 0.f;
+    float ga = 0.f, Tf = 1.f;
+    last[k] = 0;
+    if (g.x < g.W && y[k] < g.H) {
+      const int64_t p = g.row0 + (int64_t)(kSub * k) * g.W + g.x;
+      Tf = a.saved_T[p];
+      last[k] = min(a.saved_n[p], end - start);  // a saved state from other inputs must not index past the list
+      if (kL2) {
+        const float* rp = a.rgb + 3 * p;
+        const float* tp = a.target + 3 * p;
+        const float e0 = rp[0] - tp[0], e1 = rp[1] - tp[1], e2 = rp[2] - tp[2];
+        gc0[k] = a.l2_grad_scale * e0;
+        gc1[k] = a.l2_grad_scale * e1;
+        gc2[k] = a.l2_grad_scale * e2;
+        loss += fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+      } else {
+        const float* dp = a.d_rgb + 3 * p;
+        gc0[k] = dp[0]; gc1[k] = dp[1]; gc2[k] = dp[2];
+        ga = a.d_alpha ? a.d_alpha[p] : 0.f;
+      }
     }
+    K[k] = Tf * (fmaf(a.o.bg0, gc0[k], fmaf(a.o.bg1, gc1[k], a.o.bg2 * gc2[k])) - ga);
+    T[k] = Tf;
+    S[k] = 0.f;
+    mx = max(mx, last[k]);
   }
   if (kL2) {
-    float l = ga;
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) l += __shfl_xor(l, d, kWave);
-    if (lane == 0 && l != 0.f) atomicAdd(&a.hdr->loss, l * a.l2_loss_scale);
-    ga = 0.f;
+    for (int d = kWave / 2; d > 0; d >>= 1) loss += __shfl_xor(loss, d, kWave);
+    if (lane == 0 && loss != 0.f) atomicAdd(&a.hdr->loss, loss * a.l2_loss_scale);
   }
-  const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
-  last = min(last, end - start);  // a saved state from other inputs must not index past the list
-  uint32_t mx = last;
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
   if (mx == 0) return;
-  const float px = (float)g.x + 0.5f, py = (float)g.y + 0.5f;
+  const float px = (float)g.x + 0.5f;
   const float amin = a.o.alpha_min, amax = a.o.alpha_max;
-  const float K = Tf * (fmaf(a.o.bg0, gc0, fmaf(a.o.bg1, gc1, a.o.bg2 * gc2)) - ga);
-  float T = Tf, S = 0.f;
+  unsigned long long pairs = 0;
   for (int64_t hi = (int64_t)start + mx; hi > (int64_t)start; hi -= kWave) {
     const int64_t pos = hi - 1 - lane;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
@@ -277,7 +325,7 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
       id = a.vals[pos];
       const float4* rp = a.rec + (size_t)kRecF4 * id;
       r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
-      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0);
+      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX);
     }
     uint64_t m = __ballot(ov);
     if (m == 0ull) continue;
@@ -289,32 +337,41 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
       m &= m - 1;
       const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
       const uint32_t idj = s_id[j];
-      const int64_t prel = hi - 1 - j - (int64_t)start;
+      const uint32_t prel = (uint32_t)(hi - 1 - j - (int64_t)start);
       float gr[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       bool contrib = false;
-      if (prel < (int64_t)last && pixel_in_rect(f2u(a1.w), f2u(a2.w), g.x, g.y)) {
-        float dx, dy, w1, w2;
-        const float e = gauss_exp(a0, a1, px, py, dx, dy, w1, w2);
-        const float al = fminf(amax, e);
-        if (al >= amin) {
-          contrib = true;
-          const float rom = __builtin_amdgcn_rcpf(1.f - al);
-          const float Tk = T * rom;
-          const float cg = fmaf(a2.x, gc0, fmaf(a2.y, gc1, a2.z * gc2));
-          const float dal = Tk * cg - (S + K) * rom;
-          const float wt = al * Tk;
-          S = fmaf(wt, cg, S);
-          T = Tk;
-          const float dpow = (e < amax) ? e * dal : 0.f;
-          const float q = dpow * kTwoLn2;
-          gr[0] = -q * a1.x * w1;
-          gr[1] = -q * fmaf(a1.y, w1, a1.z * w2);
-          gr[2] = -0.5f * dpow * dx * dx;
-          gr[3] = -dpow * dx * dy;
-          gr[4] = -0.5f * dpow * dy * dy;
-          gr[5] = wt * gc0;
-          gr[6] = wt * gc1;
-          gr[7] = wt * gc2;
+      if (in_range(f2u(a1.w), g.x)) {
+        const float dx = (a0.x - px) + a0.z;
+        const uint32_t ry = f2u(a2.w);
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+          if (prel < last[k] && in_range(ry, y[k])) {
+            const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
+            float w1, w2;
+            const float e = gauss_exp(a1, dx, dy, w1, w2);
+            const float al = fminf(amax, e);
+            if (al >= amin) {
+              contrib = true;
+              ++pairs;
+              const float rom = __builtin_amdgcn_rcpf(1.f - al);
+              const float Tk = T[k] * rom;
+              const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
+              const float dal = Tk * cg - (S[k] + K[k]) * rom;
+              const float wt = al * Tk;
+              S[k] = fmaf(wt, cg, S[k]);
+              T[k] = Tk;
+              const float dpow = (e < amax) ? e * dal : 0.f;
+              const float q = dpow * kTwoLn2;
+              gr[0] -= q * a1.x * w1;
+              gr[1] -= q * fmaf(a1.y, w1, a1.z * w2);
+              gr[2] -= 0.5f * dpow * dx * dx;
+              gr[3] -= dpow * dx * dy;
+              gr[4] -= 0.5f * dpow * dy * dy;
+              gr[5] = fmaf(wt, gc0[k], gr[5]);
+              gr[6] = fmaf(wt, gc1[k], gr[6]);
+              gr[7] = fmaf(wt, gc2[k], gr[7]);
+            }
+          }
         }
       }
       if (__ballot(contrib) != 0ull) {
@@ -324,9 +381,11 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
     }
     wave_lds_sync();
   }
+  pairs = wave_sum_u64(pairs);
+  if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_bwd, pairs);
 }
 
-template <bool kPersistent, bool kL2>
+template <int PX, bool kPersistent, bool kL2>
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   __shared__ float4 s_rec[256 / kWave][kRecF4][kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
@@ -340,40 +399,55 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
       if (lane == 0) item = (int)atomicAdd(&a.hdr->work_bwd, 1u);
       item = __shfl(item, 0, kWave);
       if (item >= items) break;
-      raster_bwd_item<kL2>(a, th, views, item, lane, s_rec[w], s_id[w]);
+      raster_bwd_item<PX, kL2>(a, th, views, item, lane, s_rec[w], s_id[w]);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
-    if (item < items) raster_bwd_item<kL2>(a, th, views, item, lane, s_rec[w], s_id[w]);
+    if (item < items) raster_bwd_item<PX, kL2>(a, th, views, item, lane, s_rec[w], s_id[w]);
   }
 }
 
-void launch_raster_fwd(const void* table, int items, int persistent_blocks, const uint32_t* ranges, const uint32_t* vals,
-                       const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
-                       uint32_t* saved_n, WsHdr* hdr, hipStream_t s) {
-  FwdArgs a{table, ranges, vals, rec, o, out_rgb, out_alpha, saved_T, saved_n, hdr};
-  if (items <= 0) return;
+template <int PX>
+static void fwd_dispatch(const FwdArgs& a, int items, int persistent_blocks, hipStream_t s) {
   if (persistent_blocks > 0)
-    hipLaunchKernelGGL(k_raster_fwd<true>, dim3(persistent_blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_raster_fwd<PX, true>), dim3(persistent_blocks), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(k_raster_fwd<false>, dim3((items + 3) / 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_raster_fwd<PX, false>), dim3((items + 3) / 4), dim3(256), 0, s, a);
 }
 
-void launch_raster_bwd(const void* table, int items, int persistent_blocks, const uint32_t* ranges, const uint32_t* vals,
-                       const float4* rec, const KOpts& o, const float* saved_T, const uint32_t* saved_n,
-                       const float* d_rgb, const float* d_alpha, const float* rgb, const float* target, float l2_grad_scale,
-                       float l2_loss_scale, float* dfv, WsHdr* hdr, hipStream_t s) {
+template <int PX>
+static void bwd_dispatch(const BwdArgs& a, bool l2, int items, int persistent_blocks, hipStream_t s) {
+  const dim3 grid(persistent_blocks > 0 ? (unsigned)persistent_blocks : (unsigned)((items + 3) / 4));
+  if (persistent_blocks > 0) {
+    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, true, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_raster_bwd<PX, true, false>), grid, dim3(256), 0, s, a);
+  } else {
+    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, false, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_raster_bwd<PX, false, false>), grid, dim3(256), 0, s, a);
+  }
+}
+
+void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges,
+                       const uint32_t* vals, const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha,
+                       float* saved_T, uint32_t* saved_n, WsHdr* hdr, hipStream_t s) {
+  FwdArgs a{table, ranges, vals, rec, o, out_rgb, out_alpha, saved_T, saved_n, hdr};
+  if (items <= 0) return;
+  if (px == 4) fwd_dispatch<4>(a, items, persistent_blocks, s);
+  else if (px == 2) fwd_dispatch<2>(a, items, persistent_blocks, s);
+  else fwd_dispatch<1>(a, items, persistent_blocks, s);
+}
+
+void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges,
+                       const uint32_t* vals, const float4* rec, const KOpts& o, const float* saved_T,
+                       const uint32_t* saved_n, const float* d_rgb, const float* d_alpha, const float* rgb,
+                       const float* target, float l2_grad_scale, float l2_loss_scale, float* dfv, WsHdr* hdr,
+                       hipStream_t s) {
   BwdArgs a{table, ranges, vals, rec, o, saved_T, saved_n, d_rgb, d_alpha, rgb, target, l2_grad_scale, l2_loss_scale, dfv, hdr};
   if (items <= 0) return;
   const bool l2 = target != nullptr;
-  const dim3 grid(persistent_blocks > 0 ? (unsigned)persistent_blocks : (unsigned)((items + 3) / 4));
-  if (persistent_blocks > 0) {
-    if (l2) hipLaunchKernelGGL((k_raster_bwd<true, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_raster_bwd<true, false>), grid, dim3(256), 0, s, a);
-  } else {
-    if (l2) hipLaunchKernelGGL((k_raster_bwd<false, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_raster_bwd<false, false>), grid, dim3(256), 0, s, a);
-  }
+  if (px == 4) bwd_dispatch<4>(a, l2, items, persistent_blocks, s);
+  else if (px == 2) bwd_dispatch<2>(a, l2, items, persistent_blocks, s);
+  else bwd_dispatch<1>(a, l2, items, persistent_blocks, s);
 }
 
 }  // namespace gmr

@@ -125,6 +125,9 @@ class Counters:
     instances: int
     capacity: int
     overflow: bool
+    pairs_fwd: int = 0
+    pairs_bwd: int = 0
+    loss: float = 0.0
 
 
 class Renderer:
@@ -193,7 +196,8 @@ class Renderer:
     def counters(self, ws: torch.Tensor) -> Counters:
         c = gmr_counters()
         call("gmr_read_counters", _ptr(ws), ws.numel(), ctypes.byref(c), _stream(self.device))
-        return Counters(int(c.instances), int(c.capacity), bool(c.overflow))
+        return Counters(int(c.instances), int(c.capacity), bool(c.overflow), int(c.pairs_fwd), int(c.pairs_bwd),
+                        float(c.loss))
 
     # -- raw calls (no capacity management) --------------------------------------------------------
     def fwd_raw(self, verts, colors, rgb, alpha, saved, ws):

@@ -1,0 +1,182 @@
+"""GPU checks at the full sizes of the larger workloads, plus the rasteriser's block-shape
+invariance and the autotuner.
+
+  * UV sphere (399k faces, 4 views 1024^2): gradients through the torch.autograd.Function with the
+    sorted lists rebuilt in the backward, against FP64 central differences of the oracle's loss on
+    32 seeded random vertices and one pole vertex (whose fan faces fall under Eq. 12's epsilon
+    clamp).  Each difference re-renders only the pixel window the vertex's faces cover, with the
+    faces whose extents meet that window -- every other pixel's value is unchanged by the move.
+  * 16-mesh batch (64 views of 256/512/800 px): one batched launch set equals the per-view
+    launches bit for bit; sampled views match the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gmr_testutil import compare_grads, compare_images, gpu_setup, to_np
+
+pytestmark = pytest.mark.gpu
+f32 = np.float32
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_block_shape_invariance(gpu):
+    """1, 2 or 4 pixels per lane (8x8, 8x16, 8x32 blocks per wavefront) give bit-identical images;
+    gradients agree to float rounding (atomic order)."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("pixels-per-lane invariance cfg2")
+    W = wl.make_workload(2)
+    r, verts, colors = gpu_setup(W)
+    base, base_a, s0, ws0 = r.forward(verts, colors)
+    g = torch.randn_like(base)
+    dV0, dC0 = r.backward(verts, colors, g, None, s0, ws0)
+    for tw, th, px, mode in [(16, 16, 2, 0), (32, 32, 4, 0), (8, 32, 4, 1), (16, 16, 2, 1), (64, 32, 4, 0)]:
+        r2 = gmr.Renderer(r.batch, W.faces, gmr.default_options(tile_w=tw, tile_h=th, px_per_lane=px,
+                                                                raster_mode=mode), handle=r.handle)
+        rgb, a, s2, ws2 = r2.forward(verts, colors)
+        assert torch.equal(rgb, base), (tw, th, px, mode)
+        assert torch.equal(a, base_a), (tw, th, px, mode)
+        dV, dC = r2.backward(verts, colors, g, None, s2, ws2)
+        compare_grads(dV, to_np(dV0), f"px{px} {tw}x{th} m{mode} dV", rel=1e-5)
+        compare_grads(dC, to_np(dC0), f"px{px} {tw}x{th} m{mode} dC", rel=1e-5)
+
+
+def test_autotune(gpu):
+    """The autotuner returns a valid configuration whose image equals the default's bit for bit."""
+    import torch
+    say("autotune cfg2")
+    W = wl.make_workload(2)
+    r, verts, colors = gpu_setup(W)
+    base, _, _, _ = r.forward(verts, colors)
+    target = torch.zeros_like(base)
+    best, ms = r.autotune(verts, colors, target, iters=2)
+    say(f"best tile {best.tile_w}x{best.tile_h} px {best.px_per_lane} mode {best.raster_mode}: {ms:.3f} ms")
+    assert ms > 0 and best.instance_capacity > 0
+    rgb, _, _, ws = r.forward(verts, colors, check=True)
+    assert torch.equal(rgb, base)
+    best2, ms2 = r.autotune(verts, colors, target, iters=2)  # cached
+    assert (best2.tile_w, best2.tile_h, best2.px_per_lane, best2.raster_mode) == \
+           (best.tile_w, best.tile_h, best.px_per_lane, best.raster_mode)
+
+
+def _window_submesh(G, faces_of, W, H, margin=2.0):
+    """Pixel window covered by the faces in faces_of (from per-face screen records G) and the faces
+    whose extents meet it."""
+    ok = G[faces_of, 0] > 0
+    if not ok.any():
+        return None, None
+    f = np.asarray(faces_of)[ok]
+    u, v, rx, ry = G[f, 1], G[f, 2], G[f, 6], G[f, 7]
+    x0 = int(np.floor((u - rx).min() - margin)); x1 = int(np.ceil((u + rx).max() + margin)) + 1
+    y0 = int(np.floor((v - ry).min() - margin)); y1 = int(np.ceil((v + ry).max() + margin)) + 1
+    x0, y0, x1, y1 = max(0, x0), max(0, y0), min(W, x1), min(H, y1)
+    if x0 >= x1 or y0 >= y1:
+        return None, None
+    allok = G[:, 0] > 0
+    meet = allok & (G[:, 1] + G[:, 6] + margin >= x0) & (G[:, 1] - G[:, 6] - margin <= x1) & \
+        (G[:, 2] + G[:, 7] + margin >= y0) & (G[:, 2] - G[:, 7] - margin <= y1)
+    return (x0, y0, x1, y1), np.nonzero(meet)[0]
+
+
+def test_cfg3_autograd_recompute_vs_finite_differences(gpu):
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("cfg3 UV sphere 399k faces, 4x1024^2: autograd (recompute lists) vs FP64 FD")
+    W = wl.make_workload(3)
+    r, verts, colors = gpu_setup(W)
+    P = W.num_pixels
+    cams = W.cam_array()
+    tgt, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W)
+    say(f"oracle masked fraction {o_mask.mean():.2e}")
+    weight = (~o_mask).astype(np.float64)
+    target = torch.from_numpy(tgt.astype(f32)).cuda()
+    wt = torch.from_numpy(weight.astype(f32)).cuda()
+    v = verts.clone().requires_grad_(True)
+    c = colors.clone().requires_grad_(True)
+    rgb, alpha = gmr.render(v, c, r, save_lists=False)
+    compare_images(rgb.detach(), alpha.detach(), o_rgb, o_tf, o_mask, label="cfg3")
+    loss = (((rgb - target) ** 2) * wt[:, None]).sum() / (3 * P)
+    loss.backward()
+    dV = to_np(v.grad).astype(np.float64)
+    scale = np.abs(dV).max()
+    rng = np.random.default_rng(33)
+    faces = W.faces
+    vids = list(rng.choice(len(W.verts), 32, replace=False)) + [1]   # vertex 1: first ring, pole fan
+    inc = {int(vid): np.nonzero((faces == vid).any(1))[0] for vid in vids}
+    pole_faces = inc[1]
+    areas = 0.5 * np.linalg.norm(np.cross(W.verts[faces[pole_faces, 1]].astype(float) - W.verts[faces[pole_faces, 0]],
+                                          W.verts[faces[pole_faces, 2]].astype(float) - W.verts[faces[pole_faces, 0]]), axis=1)
+    assert (areas < 1.0392e-6).any(), "the pole vertex should touch clamped faces"
+    Gs = [oracle.gaussians(W.verts, faces, W.colors, cams[k]) for k in range(W.num_views)]
+    po = W.pixel_offsets()
+    checked, worst = 0, 0.0
+    for vid in vids:
+        vid = int(vid)
+        views = []
+        for k in range(W.num_views):
+            win, sub = _window_submesh(Gs[k], inc[vid], W.cams[k].width, W.cams[k].height)
+            if win is not None:
+                views.append((k, win, sub))
+        if not views:
+            continue
+
+        def local(k, win, sub, Vx):
+            x0, y0, x1, y1 = win
+            Wk = W.cams[k].width
+            idx = (po[k] + (np.arange(y0, y1)[:, None] * Wk + np.arange(x0, x1)[None, :])).reshape(-1)
+            return idx
+
+        def loss_fn(Vx):
+            tot = 0.0
+            for k, win, sub in views:
+                rgbw, _, _, _ = oracle.render_view(Vx, faces[sub], W.colors, cams[k], window=win)
+                idx = local(k, win, sub, Vx)
+                d = rgbw.reshape(-1, 3) - tgt[idx]
+                tot += float((weight[idx][:, None] * d * d).sum())
+            return tot / (3 * P)
+
+        def decisions(Vx):
+            return b"".join(oracle.render_view(Vx, faces[sub], W.colors, cams[k], window=win, want_hash=True)[4].tobytes()
+                            for k, win, sub in views)
+
+        fd = oracle.fd_vertex_grad(loss_fn, W.verts, vid, h=1e-6, decision_fn=decisions)
+        for a in range(3):
+            if fd[a] is None:
+                continue
+            err = abs(dV[vid, a] - fd[a])
+            bound = 1e-3 * abs(fd[a]) + 1e-5 * scale
+            worst = max(worst, err / bound)
+            checked += 1
+            assert err <= bound, (vid, a, dV[vid, a], fd[a])
+    say(f"checked {checked} coordinates, worst err/bound {worst:.3f}")
+    assert checked >= 60
+
+
+def test_cfg4_batched_equals_per_view_and_oracle(gpu):
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("cfg4 16 meshes / 64 views: batched vs per-view")
+    W = wl.make_workload(4)
+    r, verts, colors = gpu_setup(W)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    po = W.pixel_offsets()
+    for v in range(W.num_views):
+        bv = r.batch.view(v)
+        v0, v1, f0, f1 = bv.mesh_range
+        rv = gmr.Renderer(bv, W.faces[f0:f1] - v0, r.opts, handle=r.handle)
+        rgb_v, a_v, _, _ = rv.forward(verts[v0:v1].contiguous(), colors[v0:v1].contiguous())
+        assert torch.equal(rgb_v, rgb[po[v]:po[v + 1]]), v
+        assert torch.equal(a_v, alpha[po[v]:po[v + 1]]), v
+    cams = W.cam_array()
+    for v in [0, 17, 40, W.num_views - 1]:
+        m = int(W.view_mesh[v])
+        mv, mf, mc = W.mesh(m)
+        o_rgb, o_tf, _, o_mask = oracle.render_view(mv, mf, mc, cams[v], gid_base=int(W.face_offsets[m]))
+        compare_images(to_np(rgb)[po[v]:po[v + 1]], to_np(alpha)[po[v]:po[v + 1]], o_rgb.reshape(-1, 3),
+                       o_tf.reshape(-1), o_mask.reshape(-1), label=f"cfg4 view {v}")
