@@ -240,12 +240,13 @@ class Renderer:
             if not check:
                 break
             c = self.counters(ws)
-            if not c.overflow:
+            need = min((1 << 30) - 1, int(c.instances * self.headroom) + 1024)
+            if not c.overflow and c.instances * self.headroom <= self.opts.instance_capacity:
                 self.capacity_checked = True
-                if c.instances * self.headroom > self.opts.instance_capacity:
-                    self.opts.instance_capacity = int(c.instances * self.headroom) + 1024
                 break
-            self.opts.instance_capacity = min((1 << 30) - 1, int(c.instances * self.headroom) + 1024)
+            # overflowed, or fits with too little headroom for the next calls: grow the capacity and
+            # redo the pass in a workspace of the new layout (the returned one must match self.opts)
+            self.opts.instance_capacity = max(need, int(self.opts.instance_capacity))
             ws = self.new_workspace()
         else:
             raise RuntimeError("instance capacity did not converge")
