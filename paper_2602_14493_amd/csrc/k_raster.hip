@@ -142,41 +142,44 @@ __device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, con
     if (m == 0ull) continue;
     s[0][lane] = r0; s[1][lane] = r1; s[2][lane] = r2;
     wave_lds_sync();
-    while (m) {
-      const int j = __builtin_ctzll(m);
+    // consume the kept records in list order; the next record's broadcast read is issued before
+    // the current one is evaluated, and the per-pixel update is predicated rather than branched
+    int j = __builtin_ctzll(m);
+    float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
+    while (true) {
       m &= m - 1;
-      const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
-      if (in_range(f2u(a1.w), g.x)) {
-        const float dx = (a0.x - px) + a0.z;
-        const uint32_t ry = f2u(a2.w);
+      const int jn = m ? __builtin_ctzll(m) : j;
+      const float4 b0 = s[0][jn], b1 = s[1][jn], b2 = s[2][jn];
+      const bool inx = in_range(f2u(a1.w), g.x);
+      const float dx = (a0.x - px) + a0.z;
+      const uint32_t ry = f2u(a2.w);
+      const uint32_t pos_next = cb + (uint32_t)j - start + 1u;
 #pragma unroll
-        for (int k = 0; k < PX; ++k) {
-          if (!done[k] && in_range(ry, y[k])) {
-            ++pairs;
-            const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
-            float w1, w2;
-            const float e = gauss_exp(a1, dx, dy, w1, w2);
-            const float al = fminf(amax, e);
-            if (al >= amin) {
-              const float Tn = T[k] * (1.f - al);
-              if (Tn < teps) {
-                done[k] = true;
-              } else {
-                const float wt = al * T[k];
-                C0[k] = fmaf(a2.x, wt, C0[k]);
-                C1[k] = fmaf(a2.y, wt, C1[k]);
-                C2[k] = fmaf(a2.z, wt, C2[k]);
-                T[k] = Tn;
-                last[k] = cb + (uint32_t)j - start + 1u;
-              }
-            }
-          }
-        }
+      for (int k = 0; k < PX; ++k) {
+        const bool act = !done[k] && inx && in_range(ry, y[k]);
+        const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
+        float w1, w2;
+        const float e = gauss_exp(a1, dx, dy, w1, w2);
+        const float al = fminf(amax, e);
+        const bool ok = act && al >= amin;
+        const float Tn = T[k] * (1.f - al);
+        const bool stop = ok && Tn < teps;
+        const bool comp = ok && !(Tn < teps);
+        pairs += act ? 1ull : 0ull;
+        done[k] = done[k] || stop;
+        const float wt = al * T[k];
+        C0[k] = comp ? fmaf(a2.x, wt, C0[k]) : C0[k];
+        C1[k] = comp ? fmaf(a2.y, wt, C1[k]) : C1[k];
+        C2[k] = comp ? fmaf(a2.z, wt, C2[k]) : C2[k];
+        T[k] = comp ? Tn : T[k];
+        last[k] = comp ? pos_next : last[k];
       }
       bool live2 = false;
 #pragma unroll
       for (int k = 0; k < PX; ++k) live2 |= !done[k];
-      if (__ballot(live2) == 0ull) break;
+      if (m == 0ull || __ballot(live2) == 0ull) break;
+      j = jn;
+      a0 = b0; a1 = b1; a2 = b2;
     }
     wave_lds_sync();
   }
@@ -332,52 +335,55 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
     s[0][lane] = r0; s[1][lane] = r1; s[2][lane] = r2;
     s_id[lane] = id;
     wave_lds_sync();
-    while (m) {
-      const int j = __builtin_ctzll(m);
+    int j = __builtin_ctzll(m);
+    float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
+    uint32_t idj = s_id[j];
+    while (true) {
       m &= m - 1;
-      const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
-      const uint32_t idj = s_id[j];
+      const int jn = m ? __builtin_ctzll(m) : j;
+      const float4 b0 = s[0][jn], b1 = s[1][jn], b2 = s[2][jn];
+      const uint32_t idn = s_id[jn];
       const uint32_t prel = (uint32_t)(hi - 1 - j - (int64_t)start);
       float gr[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       bool contrib = false;
-      if (in_range(f2u(a1.w), g.x)) {
-        const float dx = (a0.x - px) + a0.z;
-        const uint32_t ry = f2u(a2.w);
+      const bool inx = in_range(f2u(a1.w), g.x);
+      const float dx = (a0.x - px) + a0.z;
+      const uint32_t ry = f2u(a2.w);
 #pragma unroll
-        for (int k = 0; k < PX; ++k) {
-          if (prel < last[k] && in_range(ry, y[k])) {
-            const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
-            float w1, w2;
-            const float e = gauss_exp(a1, dx, dy, w1, w2);
-            const float al = fminf(amax, e);
-            if (al >= amin) {
-              contrib = true;
-              ++pairs;
-              const float rom = __builtin_amdgcn_rcpf(1.f - al);
-              const float Tk = T[k] * rom;
-              const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
-              const float dal = Tk * cg - (S[k] + K[k]) * rom;
-              const float wt = al * Tk;
-              S[k] = fmaf(wt, cg, S[k]);
-              T[k] = Tk;
-              const float dpow = (e < amax) ? e * dal : 0.f;
-              const float q = dpow * kTwoLn2;
-              gr[0] -= q * a1.x * w1;
-              gr[1] -= q * fmaf(a1.y, w1, a1.z * w2);
-              gr[2] -= 0.5f * dpow * dx * dx;
-              gr[3] -= dpow * dx * dy;
-              gr[4] -= 0.5f * dpow * dy * dy;
-              gr[5] = fmaf(wt, gc0[k], gr[5]);
-              gr[6] = fmaf(wt, gc1[k], gr[6]);
-              gr[7] = fmaf(wt, gc2[k], gr[7]);
-            }
-          }
-        }
+      for (int k = 0; k < PX; ++k) {
+        const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
+        float w1, w2;
+        const float e = gauss_exp(a1, dx, dy, w1, w2);
+        const float al = fminf(amax, e);
+        const bool ok = prel < last[k] && inx && in_range(ry, y[k]) && al >= amin;
+        contrib |= ok;
+        pairs += ok ? 1ull : 0ull;
+        const float rom = __builtin_amdgcn_rcpf(1.f - al);   // 1 - al >= 1 - alpha_max > 0
+        const float Tk = T[k] * rom;
+        const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
+        const float dal = Tk * cg - (S[k] + K[k]) * rom;
+        const float wt = ok ? al * Tk : 0.f;
+        S[k] = fmaf(wt, cg, S[k]);
+        T[k] = ok ? Tk : T[k];
+        const float dpow = (ok && e < amax) ? e * dal : 0.f;
+        const float q = dpow * kTwoLn2;
+        gr[0] -= q * a1.x * w1;
+        gr[1] -= q * fmaf(a1.y, w1, a1.z * w2);
+        gr[2] -= 0.5f * dpow * dx * dx;
+        gr[3] -= dpow * dx * dy;
+        gr[4] -= 0.5f * dpow * dy * dy;
+        gr[5] = fmaf(wt, gc0[k], gr[5]);
+        gr[6] = fmaf(wt, gc1[k], gr[6]);
+        gr[7] = fmaf(wt, gc2[k], gr[7]);
       }
       if (__ballot(contrib) != 0ull) {
         const float r = wave_reduce8_transpose(gr, lane);
         if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)idj + (lane >> 3), r);
       }
+      if (m == 0ull) break;
+      j = jn;
+      idj = idn;
+      a0 = b0; a1 = b1; a2 = b2;
     }
     wave_lds_sync();
   }
