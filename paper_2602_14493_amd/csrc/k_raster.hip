@@ -103,6 +103,38 @@ struct FwdArgs {
   WsHdr* hdr;
 };
 
+// One record against a lane's PX pixels; `valid` = false makes it a no-op (predicated).
+template <int PX>
+__device__ __forceinline__ void fwd_eval(const float4& a0, const float4& a1, const float4& a2, bool valid,
+                                         uint32_t pos_next, int x, float px, const int (&y)[PX], float amin,
+                                         float amax, float teps, float (&T)[PX], float (&C0)[PX], float (&C1)[PX],
+                                         float (&C2)[PX], uint32_t (&last)[PX], bool (&done)[PX],
+                                         unsigned long long& pairs) {
+  const bool inx = valid && in_range(f2u(a1.w), x);
+  const float dx = (a0.x - px) + a0.z;
+  const uint32_t ry = f2u(a2.w);
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    const bool act = !done[k] && inx && in_range(ry, y[k]);
+    const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
+    float w1, w2;
+    const float e = gauss_exp(a1, dx, dy, w1, w2);
+    const float al = fminf(amax, e);
+    const bool ok = act && al >= amin;
+    const float Tn = T[k] * (1.f - al);
+    const bool stop = ok && Tn < teps;
+    const bool comp = ok && !(Tn < teps);
+    pairs += act ? 1ull : 0ull;
+    done[k] = done[k] || stop;
+    const float wt = al * T[k];
+    C0[k] = comp ? fmaf(a2.x, wt, C0[k]) : C0[k];
+    C1[k] = comp ? fmaf(a2.y, wt, C1[k]) : C1[k];
+    C2[k] = comp ? fmaf(a2.z, wt, C2[k]) : C2[k];
+    T[k] = comp ? Tn : T[k];
+    last[k] = comp ? pos_next : last[k];
+  }
+}
+
 template <int PX>
 __device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
                                        float4 (*s)[kWave]) {
@@ -142,44 +174,25 @@ __device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, con
     if (m == 0ull) continue;
     s[0][lane] = r0; s[1][lane] = r1; s[2][lane] = r2;
     wave_lds_sync();
-    // consume the kept records in list order; the next record's broadcast read is issued before
-    // the current one is evaluated, and the per-pixel update is predicated rather than branched
-    int j = __builtin_ctzll(m);
-    float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
-    while (true) {
+    // consume the kept records in list order, two per round: both broadcast reads are issued
+    // before either is evaluated, and the second evaluation is predicated (not branched) when the
+    // round has a single record, so loads and arithmetic share one basic block
+    while (m) {
+      const int j1 = __builtin_ctzll(m);
       m &= m - 1;
-      const int jn = m ? __builtin_ctzll(m) : j;
-      const float4 b0 = s[0][jn], b1 = s[1][jn], b2 = s[2][jn];
-      const bool inx = in_range(f2u(a1.w), g.x);
-      const float dx = (a0.x - px) + a0.z;
-      const uint32_t ry = f2u(a2.w);
-      const uint32_t pos_next = cb + (uint32_t)j - start + 1u;
-#pragma unroll
-      for (int k = 0; k < PX; ++k) {
-        const bool act = !done[k] && inx && in_range(ry, y[k]);
-        const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
-        float w1, w2;
-        const float e = gauss_exp(a1, dx, dy, w1, w2);
-        const float al = fminf(amax, e);
-        const bool ok = act && al >= amin;
-        const float Tn = T[k] * (1.f - al);
-        const bool stop = ok && Tn < teps;
-        const bool comp = ok && !(Tn < teps);
-        pairs += act ? 1ull : 0ull;
-        done[k] = done[k] || stop;
-        const float wt = al * T[k];
-        C0[k] = comp ? fmaf(a2.x, wt, C0[k]) : C0[k];
-        C1[k] = comp ? fmaf(a2.y, wt, C1[k]) : C1[k];
-        C2[k] = comp ? fmaf(a2.z, wt, C2[k]) : C2[k];
-        T[k] = comp ? Tn : T[k];
-        last[k] = comp ? pos_next : last[k];
-      }
+      const bool has2 = m != 0ull;
+      const int j2 = has2 ? __builtin_ctzll(m) : j1;
+      m &= m - (has2 ? 1ull : 0ull);
+      const float4 a0 = s[0][j1], a1 = s[1][j1], a2 = s[2][j1];
+      const float4 b0 = s[0][j2], b1 = s[1][j2], b2 = s[2][j2];
+      fwd_eval<PX>(a0, a1, a2, true, cb + (uint32_t)j1 - start + 1u, g.x, px, y, amin, amax, teps, T, C0, C1, C2,
+                   last, done, pairs);
+      fwd_eval<PX>(b0, b1, b2, has2, cb + (uint32_t)j2 - start + 1u, g.x, px, y, amin, amax, teps, T, C0, C1, C2,
+                   last, done, pairs);
       bool live2 = false;
 #pragma unroll
       for (int k = 0; k < PX; ++k) live2 |= !done[k];
-      if (m == 0ull || __ballot(live2) == 0ull) break;
-      j = jn;
-      a0 = b0; a1 = b1; a2 = b2;
+      if (__ballot(live2) == 0ull) break;
     }
     wave_lds_sync();
   }
@@ -267,6 +280,50 @@ __device__ inline float wave_reduce8_transpose(const float (&g)[8], int lane) {
   return r;  // lanes with (lane & 7) == 0 hold the sum of g[lane >> 3]
 }
 
+// One record's adjoint over a lane's PX pixels (summed into gr); `valid` = false is a no-op.
+// Returns whether any of the lane's pixels composited it.
+template <int PX>
+__device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, const float4& a2, bool valid,
+                                         uint32_t prel, int x, float px, const int (&y)[PX], float amin, float amax,
+                                         const float (&gc0)[PX], const float (&gc1)[PX], const float (&gc2)[PX],
+                                         const float (&K)[PX], const uint32_t (&last)[PX], float (&T)[PX],
+                                         float (&S)[PX], float (&gr)[8], unsigned long long& pairs) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) gr[i] = 0.f;
+  bool contrib = false;
+  const bool inx = valid && in_range(f2u(a1.w), x);
+  const float dx = (a0.x - px) + a0.z;
+  const uint32_t ry = f2u(a2.w);
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
+    float w1, w2;
+    const float e = gauss_exp(a1, dx, dy, w1, w2);
+    const float al = fminf(amax, e);
+    const bool ok = prel < last[k] && inx && in_range(ry, y[k]) && al >= amin;
+    contrib |= ok;
+    pairs += ok ? 1ull : 0ull;
+    const float rom = __builtin_amdgcn_rcpf(1.f - al);  // 1 - al >= 1 - alpha_max > 0
+    const float Tk = T[k] * rom;
+    const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
+    const float dal = Tk * cg - (S[k] + K[k]) * rom;
+    const float wt = ok ? al * Tk : 0.f;
+    S[k] = fmaf(wt, cg, S[k]);
+    T[k] = ok ? Tk : T[k];
+    const float dpow = (ok && e < amax) ? e * dal : 0.f;
+    const float q = dpow * kTwoLn2;
+    gr[0] -= q * a1.x * w1;
+    gr[1] -= q * fmaf(a1.y, w1, a1.z * w2);
+    gr[2] -= 0.5f * dpow * dx * dx;
+    gr[3] -= dpow * dx * dy;
+    gr[4] -= 0.5f * dpow * dy * dy;
+    gr[5] = fmaf(wt, gc0[k], gr[5]);
+    gr[6] = fmaf(wt, gc1[k], gr[6]);
+    gr[7] = fmaf(wt, gc2[k], gr[7]);
+  }
+  return contrib;
+}
+
 template <int PX, bool kL2>
 __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
                                        float4 (*s)[kWave], uint32_t* s_id) {
@@ -335,55 +392,29 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
     s[0][lane] = r0; s[1][lane] = r1; s[2][lane] = r2;
     s_id[lane] = id;
     wave_lds_sync();
-    int j = __builtin_ctzll(m);
-    float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
-    uint32_t idj = s_id[j];
-    while (true) {
+    // two records per round (list positions decreasing), both reads issued first; see forward
+    while (m) {
+      const int j1 = __builtin_ctzll(m);
       m &= m - 1;
-      const int jn = m ? __builtin_ctzll(m) : j;
-      const float4 b0 = s[0][jn], b1 = s[1][jn], b2 = s[2][jn];
-      const uint32_t idn = s_id[jn];
-      const uint32_t prel = (uint32_t)(hi - 1 - j - (int64_t)start);
-      float gr[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      bool contrib = false;
-      const bool inx = in_range(f2u(a1.w), g.x);
-      const float dx = (a0.x - px) + a0.z;
-      const uint32_t ry = f2u(a2.w);
-#pragma unroll
-      for (int k = 0; k < PX; ++k) {
-        const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
-        float w1, w2;
-        const float e = gauss_exp(a1, dx, dy, w1, w2);
-        const float al = fminf(amax, e);
-        const bool ok = prel < last[k] && inx && in_range(ry, y[k]) && al >= amin;
-        contrib |= ok;
-        pairs += ok ? 1ull : 0ull;
-        const float rom = __builtin_amdgcn_rcpf(1.f - al);   // 1 - al >= 1 - alpha_max > 0
-        const float Tk = T[k] * rom;
-        const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
-        const float dal = Tk * cg - (S[k] + K[k]) * rom;
-        const float wt = ok ? al * Tk : 0.f;
-        S[k] = fmaf(wt, cg, S[k]);
-        T[k] = ok ? Tk : T[k];
-        const float dpow = (ok && e < amax) ? e * dal : 0.f;
-        const float q = dpow * kTwoLn2;
-        gr[0] -= q * a1.x * w1;
-        gr[1] -= q * fmaf(a1.y, w1, a1.z * w2);
-        gr[2] -= 0.5f * dpow * dx * dx;
-        gr[3] -= dpow * dx * dy;
-        gr[4] -= 0.5f * dpow * dy * dy;
-        gr[5] = fmaf(wt, gc0[k], gr[5]);
-        gr[6] = fmaf(wt, gc1[k], gr[6]);
-        gr[7] = fmaf(wt, gc2[k], gr[7]);
-      }
-      if (__ballot(contrib) != 0ull) {
+      const bool has2 = m != 0ull;
+      const int j2 = has2 ? __builtin_ctzll(m) : j1;
+      m &= m - (has2 ? 1ull : 0ull);
+      const float4 a0 = s[0][j1], a1 = s[1][j1], a2 = s[2][j1];
+      const float4 b0 = s[0][j2], b1 = s[1][j2], b2 = s[2][j2];
+      const uint32_t id1 = s_id[j1], id2 = s_id[j2];
+      float gr[8], gq[8];
+      const bool c1 = bwd_eval<PX>(a0, a1, a2, true, (uint32_t)(hi - 1 - j1 - (int64_t)start), g.x, px, y, amin, amax,
+                                   gc0, gc1, gc2, K, last, T, S, gr, pairs);
+      const bool c2 = bwd_eval<PX>(b0, b1, b2, has2, (uint32_t)(hi - 1 - j2 - (int64_t)start), g.x, px, y, amin,
+                                   amax, gc0, gc1, gc2, K, last, T, S, gq, pairs);
+      if (__ballot(c1) != 0ull) {
         const float r = wave_reduce8_transpose(gr, lane);
-        if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)idj + (lane >> 3), r);
+        if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id1 + (lane >> 3), r);
       }
-      if (m == 0ull) break;
-      j = jn;
-      idj = idn;
-      a0 = b0; a1 = b1; a2 = b2;
+      if (__ballot(c2) != 0ull) {
+        const float r = wave_reduce8_transpose(gq, lane);
+        if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id2 + (lane >> 3), r);
+      }
     }
     wave_lds_sync();
   }
