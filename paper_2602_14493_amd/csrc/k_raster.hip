@@ -116,6 +116,7 @@ __device__ __forceinline__ void fwd_eval(const float4& a0, const float4& a1, con
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     const bool act = !done[k] && inx && in_range(ry, y[k]);
+    if (PX > 1 && __ballot(act) == 0ull) continue;  // wave-uniform: no lane's row k meets it
     const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
     float w1, w2;
     const float e = gauss_exp(a1, dx, dy, w1, w2);
@@ -296,11 +297,13 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
   const uint32_t ry = f2u(a2.w);
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
+    const bool act = prel < last[k] && inx && in_range(ry, y[k]);
+    if (PX > 1 && __ballot(act) == 0ull) continue;  // wave-uniform skip, as in the forward
     const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
     float w1, w2;
     const float e = gauss_exp(a1, dx, dy, w1, w2);
     const float al = fminf(amax, e);
-    const bool ok = prel < last[k] && inx && in_range(ry, y[k]) && al >= amin;
+    const bool ok = act && al >= amin;
     contrib |= ok;
     pairs += ok ? 1ull : 0ull;
     const float rom = __builtin_amdgcn_rcpf(1.f - al);  // 1 - al >= 1 - alpha_max > 0
