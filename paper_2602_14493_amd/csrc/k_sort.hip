@@ -225,6 +225,16 @@ void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_
                            uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, hipStream_t s) {
   const uint32_t parts = (cap + kSortPart - 1) / kSortPart;
   if (parts == 0) return;
+  // digits of <= 8 bits use the 256-bin variant (fewer ballots, half the descriptors)
+  if (mask <= 255u) {
+    if (out_k)
+      hipLaunchKernelGGL((k_onesweep<uint2, 256, true>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
+                         n_dev, cap, dig, desc_cur, desc_next, next_words, ticket, shift, mask);
+    else
+      hipLaunchKernelGGL((k_onesweep<uint2, 256, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
+                         n_dev, cap, dig, desc_cur, desc_next, next_words, ticket, shift, mask);
+    return;
+  }
   if (out_k)
     hipLaunchKernelGGL((k_onesweep<uint2, 512, true>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v, n_dev,
                        cap, dig, desc_cur, desc_next, next_words, ticket, shift, mask);
