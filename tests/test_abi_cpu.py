@@ -120,6 +120,23 @@ def test_build_adjacency_matches_numpy():
     assert st == _lib.GMR_ERR_INVALID_ARG
 
 
+def test_product_path_never_touches_the_oracle():
+    """Nothing in the package (Python or HIP/C++ sources) imports, links or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_2602_14493_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"\boracle\b|gmr_oracle|gmro_", txt), os.path.join(dirpath, fn)
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
+    assert r.returncode != 0 and "one GPU" in r.stderr
+
+
 def test_status_strings():
     from paper_2602_14493_amd import _lib
     L = _lib.load()
