@@ -196,7 +196,8 @@ def main():
         for v in range(W.num_views):
             bv = batch.view(v)
             v0, v1, f0, f1 = bv.mesh_range
-            rv = gmr.Renderer(bv, W.faces[f0:f1] - v0, r.opts, handle=r.handle)
+            rv = gmr.Renderer(bv, W.faces[f0:f1] - v0, gmr.copy_options(r.opts, instance_capacity=0),
+                              handle=r.handle)
             vv, cc = verts[v0:v1].contiguous(), colors[v0:v1].contiguous()
             npx = bv.num_pixels
             po = int(W.pixel_offsets()[v])

@@ -191,7 +191,7 @@ def test_batched_equals_per_view(gpu):
     dCs = torch.zeros_like(dC)
     for v in range(W.num_views):
         bv = r.batch.view(v)
-        rv = gmr.Renderer(bv, W.faces, r.opts, handle=r.handle)
+        rv = gmr.Renderer(bv, W.faces, gmr.copy_options(r.opts, instance_capacity=0), handle=r.handle)
         rgb_v, a_v, s_v, ws_v = rv.forward(verts, colors)
         assert torch.equal(rgb_v, rgb[v * npx:(v + 1) * npx]), v
         assert torch.equal(a_v, alpha[v * npx:(v + 1) * npx]), v

@@ -169,7 +169,8 @@ def test_cfg4_batched_equals_per_view_and_oracle(gpu):
     for v in range(W.num_views):
         bv = r.batch.view(v)
         v0, v1, f0, f1 = bv.mesh_range
-        rv = gmr.Renderer(bv, W.faces[f0:f1] - v0, r.opts, handle=r.handle)
+        rv = gmr.Renderer(bv, W.faces[f0:f1] - v0, gmr.copy_options(r.opts, instance_capacity=0),
+                          handle=r.handle)
         rgb_v, a_v, _, _ = rv.forward(verts[v0:v1].contiguous(), colors[v0:v1].contiguous())
         assert torch.equal(rgb_v, rgb[po[v]:po[v + 1]]), v
         assert torch.equal(a_v, alpha[po[v]:po[v + 1]]), v
