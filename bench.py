@@ -29,6 +29,50 @@ FP32_VECTOR_TFLOPS = 157.3     # MI355X vector FP32, published (packed FP32; the
 FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 
 
+# Measured HBM bytes per launch of the dominant kernels: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (KiB per dispatch, averaged over the dispatches of one run), each scaled by what the same counter
+# reads for the plain copy of --copy-probe.  Keyed by workload, kernel and launch configuration
+# (tile, pixels per lane, raster mode, lane lists); `src` is the hash of the kernel's sources when the counters
+# were taken, and a changed source reports null.
+TRAFFIC = {}
+STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
+                "sort_pass": "k_sort.hip", "sort_digits": "k_sort.hip", "tile_ranges": "k_sort.hip",
+                "project": "k_project.hip", "scan_emit": "k_bin.hip", "face_bwd": "k_grad.hip",
+                "vertex_gather": "k_grad.hip", "fill": "k_grad.hip"}
+
+
+def source_hash(stage):
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2602_14493_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (STAGE_SOURCE[stage], "gmr_common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, stage, tile, px, mode, lanes):
+    e = TRAFFIC.get((workload, stage, tile, px, mode, lanes))
+    if e is None or e["src"] != source_hash(stage):
+        return None
+    return e["fetch"] + e["write"]
+
+
+def copy_probe():
+    """A plain device-to-device copy of 256 MiB, three launches: FETCH_SIZE / WRITE_SIZE of this copy
+    against its known 2^28 bytes each way give the counters' scale."""
+    import torch
+    n = 64 << 20
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read_per_launch": 4 * n, "copy_probe_bytes_written_per_launch": 4 * n,
+                      "launches": 3}))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -38,6 +82,11 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile / block shape")
     ap.add_argument("--tile", type=str, default=None, help="WxH binning tile, e.g. 16x16")
     ap.add_argument("--raster-mode", type=int, default=None)
+    ap.add_argument("--px-per-lane", type=int, default=None, choices=[1, 2, 4])
+    ap.add_argument("--lane-lists", type=int, default=None, choices=[0, 1])
+    ap.add_argument("--no-graph", action="store_true", help="run the Adam loop eagerly (no HIP graph replay)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -85,6 +134,9 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.copy_probe:
+        copy_probe()
+        return
 
     import paper_2602_14493_amd as gmr
     import workloads as wl
@@ -98,6 +150,10 @@ def main():
         kw.update(tile_w=tw, tile_h=th)
     if args.raster_mode is not None:
         kw["raster_mode"] = args.raster_mode
+    if args.px_per_lane is not None:
+        kw["px_per_lane"] = args.px_per_lane
+    if args.lane_lists is not None:
+        kw["lane_lists"] = args.lane_lists
     r = gmr.Renderer(batch, W.faces, gmr.default_options(**kw))
     verts = torch.from_numpy(W.verts).cuda()
     colors = torch.from_numpy(W.colors).cuda()
@@ -106,7 +162,7 @@ def main():
         target, _, _, _ = r.forward(tverts, colors, check=True)
     target = target.clone()
     tuned_ms = None
-    if not args.no_autotune and not args.tile and args.raster_mode is None:
+    if not args.no_autotune and not kw:
         _, tuned_ms = r.autotune(verts, colors, target, iters=3)
     recompute = args.config in (3, 5)
     use_graph = args.config == 5
@@ -115,10 +171,16 @@ def main():
     # ---- batched form ------------------------------------------------------------------------
     if use_graph:
         loop = gmr.GraphAdamLoop(r, verts, colors, target, lr=1e-3, recompute=True)
-        loop.capture()
+        if args.no_graph:
+            loop._step_body()
+        else:
+            loop.capture()
 
         def step():
-            loop.graph.replay()
+            if args.no_graph:
+                loop._step_body()
+            else:
+                loop.graph.replay()
 
         def step_profiled():
             loop._step_body()
@@ -179,15 +241,17 @@ def main():
             stages[k]["alg_TFLOPs"] = round(pairs[k] * FLOPS_PER_PAIR[k] / (avg * 1e-3) / 1e12, 2)
     dom = max(stages, key=lambda k: stages[k]["ms_per_step"])
     d = stages[dom]
+    traffic = measured_traffic(W.name, dom, f"{r.opts.tile_w}x{r.opts.tile_h}", r.opts.px_per_lane,
+                               r.opts.raster_mode, r.opts.lane_lists)
     if dom in FLOPS_PER_PAIR:   # compositing kernels: VALU-bound on LDS-broadcast data
         achieved = d["alg_TFLOPs"]
         roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_VECTOR_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
                     "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": pairs[dom]}
     else:
         achieved = d["alg_GBps"]
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
 
     # ---- per-view launches (same work, one launch set per view) -------------------------------
     per_view = None
@@ -259,6 +323,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": W.name, "faces": F, "verts": V, "views": W.num_views, "pixels": P,
                    "instances": I, "tile": f"{r.opts.tile_w}x{r.opts.tile_h}", "px_per_lane": r.opts.px_per_lane,
+                   "lane_lists": r.opts.lane_lists,
                    "raster_mode": r.opts.raster_mode, "autotune_ms": tuned_ms,
                    "recompute_lists": recompute, "adam_graph": use_graph},
         "roofline": roofline,

@@ -78,6 +78,8 @@ gmr_status validate_options(const gmr_options* o) {
   if (o->px_per_lane != 1 && o->px_per_lane != 2 && o->px_per_lane != 4)
     return fail(GMR_ERR_INVALID_ARG, "px_per_lane must be 1, 2 or 4");
   if (o->tile_h % (kSub * o->px_per_lane) != 0) return fail(GMR_ERR_INVALID_ARG, "tile_h must be a multiple of 8*px_per_lane");
+  if (o->lane_lists != 0 && o->lane_lists != 1) return fail(GMR_ERR_INVALID_ARG, "lane_lists must be 0 or 1");
+  if (o->reserved_opt != 0) return fail(GMR_ERR_INVALID_ARG, "reserved_opt must be 0");
   return GMR_OK;
 }
 
@@ -418,7 +420,8 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   const double n3 = 3.0 * (double)p.p_total;
   {
     StageTimer t(h, s, kStRasterBwd);
-    launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals, w.rec, ko, saved_T,
+    launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0,
+                      w.ranges, w.sorted_vals, w.rec, ko, saved_T,
                       saved_n, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
                       w.dfv, w.hdr, s);
   }
@@ -458,6 +461,8 @@ gmr_options gmr_default_options(void) {
   o.tile_h = 16;
   o.raster_mode = 0;
   o.px_per_lane = 1;
+  o.lane_lists = 0;
+  o.reserved_opt = 0;
   o.instance_capacity = 0;
   return o;
 }
@@ -556,7 +561,8 @@ gmr_status gmr_render_fwd(gmr_handle h, const gmr_batch* batch, const gmr_option
   uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
   {
     StageTimer t(h, s, kStRasterFwd);
-    launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals, w.rec, kopts(opt),
+    launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0, w.ranges,
+                      w.sorted_vals, w.rec, kopts(opt),
                       out_rgb, out_alpha, saved_T, saved_n, w.hdr, s);
   }
   return check_launch();
@@ -674,13 +680,14 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   // candidates: binning tile, pixels per lane (block shape), raster mode
-  struct Cand { int tw, th, px, mode; };
+  struct Cand { int tw, th, px, mode, lanes; };
   std::vector<Cand> cands;
   const int shapes[][2] = {{8, 8}, {16, 16}, {32, 16}, {32, 32}, {64, 32}};
   for (const auto& sh : shapes)
     for (int px : {1, 2, 4})
       if (sh[1] % (kSub * px) == 0)
-        for (int mode = 0; mode < 2; ++mode) cands.push_back({sh[0], sh[1], px, mode});
+        for (int mode = 0; mode < 2; ++mode)
+          for (int lanes = 0; lanes < 2; ++lanes) cands.push_back({sh[0], sh[1], px, mode, lanes});
   float best_ms = 1e30f;
   gmr_options best = b;
   float *rgb = nullptr, *dv = nullptr, *dc = nullptr;
@@ -702,6 +709,7 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
       o.tile_h = cd.th;
       o.px_per_lane = cd.px;
       o.raster_mode = cd.mode;
+      o.lane_lists = cd.lanes;
       o.instance_capacity = std::max<int64_t>(b.instance_capacity, 1 << 20);
       for (int attempt = 0; attempt < 3 && result == GMR_OK; ++attempt) {
         Plan p;

@@ -81,11 +81,78 @@ __device__ inline float gauss_exp(const float4& r1, float dx, float dy, float& w
   return __builtin_amdgcn_exp2f(-fmaf(w1, w1, w2 * w2));
 }
 
-__device__ inline unsigned long long wave_sum_u64(unsigned long long x) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
-  return x;
+// DPP controls (GFX9 encoding): quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror, row_ror:8,
+// row_shl:4 (lane i reads i + 4 of its 16-lane row), row_shr:4 (reads i - 4).
+constexpr int kDppXor1 = 0xB1;
+constexpr int kDppXor2 = 0x4E;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowShl4 = 0x104;
+constexpr int kDppRowShr4 = 0x114;
+
+// v + (v read from the lane that DPP control kCtrl selects inside its 16-lane row); the
+// permute folds into the add as a DPP operand modifier
+template <int kCtrl>
+__device__ __forceinline__ float add_dpp(float acc, float v) {
+  return acc + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, true));
 }
+
+// The value lane ^ B holds, B in {1, 2, 4, 8, 16}.  All lanes must be active.
+template <int B>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
+  if constexpr (B == 1) return __builtin_amdgcn_update_dpp(0u, v, kDppXor1, 0xF, 0xF, true);
+  else if constexpr (B == 2) return __builtin_amdgcn_update_dpp(0u, v, kDppXor2, 0xF, 0xF, true);
+  else if constexpr (B == 4) {
+    // banks 0 and 2 of each row (lane bit 2 clear) read lane + 4, banks 1 and 3 read lane - 4
+    const uint32_t t = __builtin_amdgcn_update_dpp(0u, v, kDppRowShl4, 0xF, 0x5, true);
+    return __builtin_amdgcn_update_dpp(t, v, kDppRowShr4, 0xF, 0xA, false);
+  } else if constexpr (B == 8) return __builtin_amdgcn_update_dpp(0u, v, kDppRowRor8, 0xF, 0xF, true);
+  else {
+    static_assert(B == 16, "lane_xor: B in {1, 2, 4, 8, 16}");
+    // swapping the odd rows of one copy with the even rows of another leaves row r's partner row
+    // in the first copy for odd r and in the second for even r
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) ? r[0] : r[1];
+  }
+}
+
+// One step of the 64 x 64 bit transpose on one 32-bit word: rows (lanes) r and r ^ B exchange the
+// off-diagonal B x B blocks; m selects the bit positions p with (p & B) == 0.
+template <int B>
+__device__ __forceinline__ uint32_t transpose_step(uint32_t w, int lane, uint32_t m) {
+  const uint32_t y = lane_xor<B>(w, lane);
+  return (lane & B) ? ((w & ~m) | ((y & ~m) >> B)) : ((w & m) | ((y & m) << B));
+}
+
+// Lane r holds row r of a 64 x 64 bit matrix (bit c = entry (r, c)); returns column `lane`.
+__device__ inline uint64_t transpose64(uint64_t x, int lane) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  // B = 32: lanes 0-31 keep their low words and take the partner's low word as the high word;
+  // lanes 32-63 keep their high words and take the partner's high word as the low word -- one
+  // half-wave swap of the low words of the upper half with the high words of the lower half
+  const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+  lo = r[0];
+  hi = r[1];
+  lo = transpose_step<16>(lo, lane, 0x0000FFFFu); hi = transpose_step<16>(hi, lane, 0x0000FFFFu);
+  lo = transpose_step<8>(lo, lane, 0x00FF00FFu);  hi = transpose_step<8>(hi, lane, 0x00FF00FFu);
+  lo = transpose_step<4>(lo, lane, 0x0F0F0F0Fu);  hi = transpose_step<4>(hi, lane, 0x0F0F0F0Fu);
+  lo = transpose_step<2>(lo, lane, 0x33333333u);  hi = transpose_step<2>(hi, lane, 0x33333333u);
+  lo = transpose_step<1>(lo, lane, 0x55555555u);  hi = transpose_step<1>(hi, lane, 0x55555555u);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Pixels of the 8 x 8 block at (bx0, yb) inside the integer rectangle (rx, ry): bit 8 * row + col.
+__device__ inline uint64_t block_coverage(uint32_t rx, uint32_t ry, int bx0, int yb) {
+  const int c0 = max((int)(rx & 0xffffu) - bx0, 0), c1 = min((int)(rx >> 16) - bx0, kSub - 1);
+  const int r0 = max((int)(ry & 0xffffu) - yb, 0), r1 = min((int)(ry >> 16) - yb, kSub - 1);
+  if (c0 > c1 || r0 > r1) return 0ull;
+  const uint32_t cols = (0xFFu << c0) & (0xFFu >> (kSub - 1 - c1));
+  const uint32_t rep = cols * 0x01010101u;
+  const uint64_t rows = (~0ull << (8 * r0)) & (~0ull >> (8 * (kSub - 1 - r1)));
+  return (((uint64_t)rep << 32) | rep) & rows;
+}
+
+__device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
 
 // ------------------------------------------------------------------------------------------------
 // forward
@@ -125,7 +192,7 @@ __device__ __forceinline__ void fwd_eval(const float4& a0, const float4& a1, con
     const float Tn = T[k] * (1.f - al);
     const bool stop = ok && Tn < teps;
     const bool comp = ok && !(Tn < teps);
-    pairs += act ? 1ull : 0ull;
+    pairs += (unsigned long long)__popcll(__ballot(act));  // wave-uniform, scalar unit
     done[k] = done[k] || stop;
     const float wt = al * T[k];
     C0[k] = comp ? fmaf(a2.x, wt, C0[k]) : C0[k];
@@ -210,11 +277,120 @@ __device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, con
       a.saved_n[p] = last[k];
     }
   }
-  pairs = wave_sum_u64(pairs);
   if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_fwd, pairs);
 }
 
-template <int PX, bool kPersistent>
+// Same compositing with per-lane lists: each staged batch's pixel-rectangle coverage of the block
+// (one 64-bit row per Gaussian) is transposed so that every lane holds the batch positions of the
+// Gaussians that contain its pixel, and walks only those, in list order.  Every (pixel, Gaussian)
+// pair takes the same arithmetic as in raster_fwd_item, so images are bit-identical; a lane costs
+// one iteration per Gaussian over its pixel instead of one per Gaussian meeting the block.
+template <int PX>
+__device__ inline void raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
+                                             int lane, float4 (*s)[kWave]) {
+  const ItemGeo g = item_geometry<PX>(th, views, item, lane);
+  if (!g.any) return;
+  const int ly = lane >> 3;
+  const float px = (float)g.x + 0.5f;
+  const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
+  const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
+  float T[PX], C0[PX], C1[PX], C2[PX];
+  uint32_t last[PX];
+  bool done[PX];
+  int y[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    y[k] = g.by0 + ly + kSub * k;
+    T[k] = 1.f; C0[k] = 0.f; C1[k] = 0.f; C2[k] = 0.f;
+    last[k] = 0;
+    done[k] = !(g.x < g.W && y[k] < g.H);
+  }
+  uint32_t pairs = 0;
+  for (uint32_t cb = start; cb < end; cb += kWave) {
+    bool live = false;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) live |= !done[k];
+    if (__ballot(live) == 0ull) break;
+    const uint32_t pos = cb + (uint32_t)lane;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    uint32_t rx = 0, ry = 0;
+    bool ov = false;
+    if (pos < end) {
+      const uint32_t id = a.vals[pos];
+      const float4* rp = a.rec + (size_t)kRecF4 * id;
+      r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
+      rx = f2u(r1.w);
+      ry = f2u(r2.w);
+      ov = rect_meets_block(rx, ry, g.bx0, g.by0, kSub * PX);
+    }
+    if (__ballot(ov) == 0ull) continue;
+    s[0][lane] = r0; s[1][lane] = r1; s[2][lane] = r2;
+    uint64_t mine[PX];
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      const uint64_t cov = ov ? block_coverage(rx, ry, g.bx0, g.by0 + kSub * k) : 0ull;
+      mine[k] = transpose64(cov, lane);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      uint64_t m = done[k] ? 0ull : mine[k];
+      const float py = (float)y[k] + 0.5f;
+      while (m) {
+        const int j = ctz64(m);
+        m &= m - 1;
+        const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
+        const float dx = (a0.x - px) + a0.z;
+        const float dy = (a0.y - py) + a0.w;
+        float w1, w2;
+        const float e = gauss_exp(a1, dx, dy, w1, w2);
+        const float al = fminf(amax, e);
+        ++pairs;
+        if (al >= amin) {
+          const float Tn = T[k] * (1.f - al);
+          if (Tn < teps) {
+            done[k] = true;
+            m = 0ull;
+          } else {
+            const float wt = al * T[k];
+            C0[k] = fmaf(a2.x, wt, C0[k]);
+            C1[k] = fmaf(a2.y, wt, C1[k]);
+            C2[k] = fmaf(a2.z, wt, C2[k]);
+            T[k] = Tn;
+            last[k] = cb + (uint32_t)j - start + 1u;
+          }
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    if (g.x < g.W && y[k] < g.H) {
+      const int64_t p = g.row0 + (int64_t)(kSub * k) * g.W + g.x;
+      float* o = a.out_rgb + 3 * p;
+      o[0] = fmaf(T[k], a.o.bg0, C0[k]);
+      o[1] = fmaf(T[k], a.o.bg1, C1[k]);
+      o[2] = fmaf(T[k], a.o.bg2, C2[k]);
+      if (a.out_alpha) a.out_alpha[p] = 1.f - T[k];
+      a.saved_T[p] = T[k];
+      a.saved_n[p] = last[k];
+    }
+  }
+  // wave sum of the per-lane pair counts
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) pairs += (uint32_t)__shfl_xor((int)pairs, d, kWave);
+  if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_fwd, (unsigned long long)pairs);
+}
+
+template <int PX, bool kPersistent, bool kLanes>
+__device__ __forceinline__ void raster_fwd_any(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
+                                               int lane, float4 (*s)[kWave]) {
+  if constexpr (kLanes) raster_fwd_item_lanes<PX>(a, th, views, item, lane, s);
+  else raster_fwd_item<PX>(a, th, views, item, lane, s);
+}
+
+template <int PX, bool kPersistent, bool kLanes>
 __global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
   __shared__ float4 s_rec[256 / kWave][kRecF4][kWave];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
@@ -227,11 +403,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
       if (lane == 0) item = (int)atomicAdd(&a.hdr->work_fwd, 1u);
       item = __shfl(item, 0, kWave);
       if (item >= items) break;
-      raster_fwd_item<PX>(a, th, views, item, lane, s_rec[w]);
+      raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w]);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
-    if (item < items) raster_fwd_item<PX>(a, th, views, item, lane, s_rec[w]);
+    if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w]);
   }
 }
 
@@ -256,28 +432,33 @@ struct BwdArgs {
   WsHdr* hdr;
 };
 
+// gfx950 half-wave / row swaps: after the swap, adding the two registers leaves in lanes 0-31
+// (rows 0 and 2) the pairwise sum of a and in lanes 32-63 (rows 1 and 3) that of b.
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Wave sum of eight per-lane values, transposed: value i ends in lanes 8i..8i+7.  Each halving
+// step sends one of two values across and keeps the other, so 8 values cost 4 + 2 + 1 exchanges.
 __device__ inline float wave_reduce8_transpose(const float (&g)[8], int lane) {
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
   float h[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const float send = b5 ? g[k] : g[k + 4];
-    const float keep = b5 ? g[k + 4] : g[k];
-    h[k] = keep + __shfl_xor(send, 32, kWave);
-  }
+  for (int k = 0; k < 4; ++k) h[k] = swap32_sum(g[k], g[k + 4]);   // lanes 32-63 now hold g[k + 4]
   float q[2];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const float send = b4 ? h[k] : h[k + 2];
-    const float keep = b4 ? h[k + 2] : h[k];
-    q[k] = keep + __shfl_xor(send, 16, kWave);
-  }
+  for (int k = 0; k < 2; ++k) q[k] = swap16_sum(h[k], h[k + 2]);   // odd rows now hold h[k + 2]
+  const bool b3 = lane & 8;
   const float send = b3 ? q[0] : q[1];
   const float keep = b3 ? q[1] : q[0];
-  float r = keep + __shfl_xor(send, 8, kWave);
-  r += __shfl_xor(r, 4, kWave);
-  r += __shfl_xor(r, 2, kWave);
-  r += __shfl_xor(r, 1, kWave);
+  float r = add_dpp<kDppRowRor8>(keep, send);   // lane ^ 8
+  r = add_dpp<kDppXor1>(r, r);                   // lane ^ 1
+  r = add_dpp<kDppXor2>(r, r);                   // lane ^ 2
+  r = add_dpp<kDppHalfMirror>(r, r);             // lane i <-> 7 - i inside each 8: adds the other quad
   return r;  // lanes with (lane & 7) == 0 hold the sum of g[lane >> 3]
 }
 
@@ -305,7 +486,7 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
     const float al = fminf(amax, e);
     const bool ok = act && al >= amin;
     contrib |= ok;
-    pairs += ok ? 1ull : 0ull;
+    pairs += (unsigned long long)__popcll(__ballot(ok));  // wave-uniform, scalar unit
     const float rom = __builtin_amdgcn_rcpf(1.f - al);  // 1 - al >= 1 - alpha_max > 0
     const float Tk = T[k] * rom;
     const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
@@ -327,9 +508,151 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
   return contrib;
 }
 
-template <int PX, bool kL2>
+// Pairs a wavefront's per-lane backward can hold for one staged batch (8 B each in LDS); a batch
+// whose pixel-rectangle coverage exceeds it takes the block-uniform walk.
+constexpr int kLaneTab = 1024;
+
+struct BwdLds {
+  float4 (*rec)[kWave];  // [3 + PX][64]: records; with lane lists also {coverage lo, hi, table offset} per row group
+  uint32_t* id;          // [64]
+  float4* px;            // [64] per pixel {g_C, list bound} (lane lists)
+  float2* tab;           // [kLaneTab] per pair {dL/dpower, alpha T} (lane lists)
+};
+
+// Block-uniform walk of one staged batch: every record is evaluated by the whole wavefront, two
+// per round, and its 8 partial sums are reduced across the wavefront.
+template <int PX>
+__device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds& L, uint64_t m, int64_t hi,
+                                                  uint32_t start, const ItemGeo& g, float px, const int (&y)[PX],
+                                                  float amin, float amax, const float (&gc0)[PX],
+                                                  const float (&gc1)[PX], const float (&gc2)[PX], const float (&K)[PX],
+                                                  const uint32_t (&last)[PX], float (&T)[PX], float (&S)[PX],
+                                                  unsigned long long& pairs, int lane) {
+  float4 (*s)[kWave] = L.rec;
+  while (m) {
+    const int j1 = __builtin_ctzll(m);
+    m &= m - 1;
+    const bool has2 = m != 0ull;
+    const int j2 = has2 ? __builtin_ctzll(m) : j1;
+    m &= m - (has2 ? 1ull : 0ull);
+    const float4 a0 = s[0][j1], a1 = s[1][j1], a2 = s[2][j1];
+    const float4 b0 = s[0][j2], b1 = s[1][j2], b2 = s[2][j2];
+    const uint32_t id1 = L.id[j1], id2 = L.id[j2];
+    float gr[8], gq[8];
+    const bool c1 = bwd_eval<PX>(a0, a1, a2, true, (uint32_t)(hi - 1 - j1 - (int64_t)start), g.x, px, y, amin, amax,
+                                 gc0, gc1, gc2, K, last, T, S, gr, pairs);
+    const bool c2 = bwd_eval<PX>(b0, b1, b2, has2, (uint32_t)(hi - 1 - j2 - (int64_t)start), g.x, px, y, amin, amax,
+                                 gc0, gc1, gc2, K, last, T, S, gq, pairs);
+    if (__ballot(c1) != 0ull) {
+      const float r = wave_reduce8_transpose(gr, lane);
+      if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id1 + (lane >> 3), r);
+    }
+    if (__ballot(c2) != 0ull) {
+      const float r = wave_reduce8_transpose(gq, lane);
+      if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id2 + (lane >> 3), r);
+    }
+  }
+}
+
+// Per-lane walk of one staged batch, in two phases per pixel row group.
+//  A (lane = pixel): walk the lane's own Gaussians back to front (transposed coverage), update T
+//    and S exactly as the block-uniform walk does, and store each pair's {dL/dpower, alpha T} in
+//    the batch's pair table, grouped by Gaussian (offset = the Gaussian's table offset + the rank
+//    of the pixel among the pixels its rectangle covers).
+//  B (lane = Gaussian): walk the pixels the lane's own rectangle covers, read the pairs that
+//    phase A wrote, and sum the geometry and colour partials in registers.
+// The lane then issues its Gaussian's 8 float atomics.  No cross-lane reduction is needed.
+template <int PX>
+__device__ __forceinline__ void bwd_batch_lanes(const BwdArgs& a, const BwdLds& L, const uint64_t (&cov)[PX],
+                                                uint32_t tab_off, int64_t hi, uint32_t start, uint32_t id,
+                                                const float4& r0, const float4& r1, const ItemGeo& g, float px,
+                                                const int (&y)[PX], float amin, float amax, const float (&gc0)[PX],
+                                                const float (&gc1)[PX], const float (&gc2)[PX], const float (&K)[PX],
+                                                const uint32_t (&last)[PX], float (&T)[PX], float (&S)[PX],
+                                                uint32_t& pairs, int lane) {
+  float4 (*s)[kWave] = L.rec;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
+  const int64_t hs = hi - (int64_t)start;                                // list position of batch slot j: hs - 1 - j
+  const uint32_t prel_own = (uint32_t)(hs - 1 - lane);                   // this lane's Gaussian (valid when cov != 0)
+  float gr[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) gr[i] = 0.f;
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    // slots j with list position < last: j > hs - 1 - last
+    const int64_t jmin = hs - (int64_t)last[k];
+    uint64_t mine = transpose64(cov[k], lane);
+    mine = jmin <= 0 ? mine : (jmin >= 64 ? 0ull : (mine & (~0ull << jmin)));
+    L.px[lane] = make_float4(gc0[k], gc1[k], gc2[k], u2f(last[k]));
+    wave_lds_sync();
+    // ---- phase A: lane = pixel
+    const float py = (float)y[k] + 0.5f;
+    while (mine) {
+      const int j = ctz64(mine);
+      mine &= mine - 1;
+      const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j], c = s[3 + k][j];
+      const uint64_t cj = (uint64_t)f2u(c.x) | ((uint64_t)f2u(c.y) << 32);
+      const uint32_t slot = f2u(c.z) + (uint32_t)__popcll(cj & below);
+      const float dx = (a0.x - px) + a0.z;
+      const float dy = (a0.y - py) + a0.w;
+      float w1, w2;
+      const float e = gauss_exp(a1, dx, dy, w1, w2);
+      const float al = fminf(amax, e);
+      const bool ok = al >= amin;
+      pairs += ok ? 1u : 0u;
+      const float rom = __builtin_amdgcn_rcpf(1.f - al);
+      const float Tk = T[k] * rom;
+      const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
+      const float dal = Tk * cg - (S[k] + K[k]) * rom;
+      const float wt = ok ? al * Tk : 0.f;
+      S[k] = fmaf(wt, cg, S[k]);
+      T[k] = ok ? Tk : T[k];
+      const float dpow = (ok && e < amax) ? e * dal : 0.f;
+      L.tab[slot] = make_float2(dpow, wt);
+    }
+    wave_lds_sync();
+    // ---- phase B: lane = Gaussian
+    uint64_t cm = cov[k];
+    uint32_t slot = f2u(s[3 + k][lane].z);
+    const int yb = g.by0 + kSub * k;
+    while (cm) {
+      const int i = ctz64(cm);
+      cm &= cm - 1;
+      const float4 pd = L.px[i];
+      const float2 t = L.tab[slot];
+      ++slot;
+      if (prel_own >= f2u(pd.w)) continue;  // the pixel stopped before reaching this Gaussian
+      const float pxi = (float)(g.bx0 + (i & 7)) + 0.5f;
+      const float pyi = (float)(yb + (i >> 3)) + 0.5f;
+      const float dx = (r0.x - pxi) + r0.z;
+      const float dy = (r0.y - pyi) + r0.w;
+      const float w1 = fmaf(r1.x, dx, r1.y * dy);
+      const float w2 = r1.z * dy;
+      const float dpow = t.x, wt = t.y;
+      const float q = dpow * kTwoLn2;
+      gr[0] -= q * r1.x * w1;
+      gr[1] -= q * fmaf(r1.y, w1, r1.z * w2);
+      gr[2] -= 0.5f * dpow * dx * dx;
+      gr[3] -= dpow * dx * dy;
+      gr[4] -= 0.5f * dpow * dy * dy;
+      gr[5] = fmaf(wt, pd.x, gr[5]);
+      gr[6] = fmaf(wt, pd.y, gr[6]);
+      gr[7] = fmaf(wt, pd.z, gr[7]);
+      any |= (dpow != 0.f) || (wt != 0.f);
+    }
+    wave_lds_sync();
+  }
+  if (any) {
+    float* d = a.dfv + 8 * (size_t)id;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) atomicAdd(d + i, gr[i]);
+  }
+}
+
+template <int PX, bool kL2, bool kLanes>
 __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
-                                       float4 (*s)[kWave], uint32_t* s_id) {
+                                       const BwdLds& L) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return;
   const int ly = lane >> 3;
@@ -378,60 +701,77 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
   if (mx == 0) return;
   const float px = (float)g.x + 0.5f;
   const float amin = a.o.alpha_min, amax = a.o.alpha_max;
-  unsigned long long pairs = 0;
+  unsigned long long pairs = 0;   // block-uniform walk: wave-uniform count
+  uint32_t lpairs = 0;            // per-lane walk: per-lane count
   for (int64_t hi = (int64_t)start + mx; hi > (int64_t)start; hi -= kWave) {
     const int64_t pos = hi - 1 - lane;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-    uint32_t id = 0;
+    uint32_t id = 0, rx = 0, ry = 0;
     bool ov = false;
     if (pos >= (int64_t)start) {
       id = a.vals[pos];
       const float4* rp = a.rec + (size_t)kRecF4 * id;
       r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
-      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX);
+      rx = f2u(r1.w);
+      ry = f2u(r2.w);
+      ov = rect_meets_block(rx, ry, g.bx0, g.by0, kSub * PX);
     }
-    uint64_t m = __ballot(ov);
+    const uint64_t m = __ballot(ov);
     if (m == 0ull) continue;
-    s[0][lane] = r0; s[1][lane] = r1; s[2][lane] = r2;
-    s_id[lane] = id;
-    wave_lds_sync();
-    // two records per round (list positions decreasing), both reads issued first; see forward
-    while (m) {
-      const int j1 = __builtin_ctzll(m);
-      m &= m - 1;
-      const bool has2 = m != 0ull;
-      const int j2 = has2 ? __builtin_ctzll(m) : j1;
-      m &= m - (has2 ? 1ull : 0ull);
-      const float4 a0 = s[0][j1], a1 = s[1][j1], a2 = s[2][j1];
-      const float4 b0 = s[0][j2], b1 = s[1][j2], b2 = s[2][j2];
-      const uint32_t id1 = s_id[j1], id2 = s_id[j2];
-      float gr[8], gq[8];
-      const bool c1 = bwd_eval<PX>(a0, a1, a2, true, (uint32_t)(hi - 1 - j1 - (int64_t)start), g.x, px, y, amin, amax,
-                                   gc0, gc1, gc2, K, last, T, S, gr, pairs);
-      const bool c2 = bwd_eval<PX>(b0, b1, b2, has2, (uint32_t)(hi - 1 - j2 - (int64_t)start), g.x, px, y, amin,
-                                   amax, gc0, gc1, gc2, K, last, T, S, gq, pairs);
-      if (__ballot(c1) != 0ull) {
-        const float r = wave_reduce8_transpose(gr, lane);
-        if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id1 + (lane >> 3), r);
+    L.rec[0][lane] = r0; L.rec[1][lane] = r1; L.rec[2][lane] = r2;
+    if constexpr (kLanes) {
+      uint64_t cov[PX];
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        cov[k] = ov ? block_coverage(rx, ry, g.bx0, g.by0 + kSub * k) : 0ull;
+        cnt += (uint32_t)__popcll(cov[k]);
       }
-      if (__ballot(c2) != 0ull) {
-        const float r = wave_reduce8_transpose(gq, lane);
-        if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id2 + (lane >> 3), r);
+      uint32_t inc = cnt;  // inclusive scan of the pair counts over the lanes
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)inc, d, kWave);
+        if (lane >= d) inc += t;
+      }
+      const uint32_t total = (uint32_t)__shfl((int)inc, kWave - 1, kWave);
+      if (total <= (uint32_t)kLaneTab) {
+        uint32_t off = inc - cnt;
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+          L.rec[3 + k][lane] = make_float4(u2f((uint32_t)cov[k]), u2f((uint32_t)(cov[k] >> 32)), u2f(off), 0.f);
+          off += (uint32_t)__popcll(cov[k]);
+        }
+        // the per-pixel block data is written inside, after this barrier-free point: the LDS
+        // writes above are ordered before phase A by its own wave_lds_sync
+        bwd_batch_lanes<PX>(a, L, cov, inc - cnt, hi, start, id, r0, r1, g, px, y, amin, amax, gc0, gc1, gc2, K,
+                            last, T, S, lpairs, lane);
+        continue;
       }
     }
+    L.id[lane] = id;
+    wave_lds_sync();
+    bwd_batch_uniform<PX>(a, L, m, hi, start, g, px, y, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
     wave_lds_sync();
   }
-  pairs = wave_sum_u64(pairs);
+  if constexpr (kLanes) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) lpairs += (uint32_t)__shfl_xor((int)lpairs, d, kWave);
+    pairs += lpairs;
+  }
   if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_bwd, pairs);
 }
 
-template <int PX, bool kPersistent, bool kL2>
+template <int PX, bool kPersistent, bool kL2, bool kLanes>
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
-  __shared__ float4 s_rec[256 / kWave][kRecF4][kWave];
+  constexpr int kRows = kLanes ? kRecF4 + PX : kRecF4;
+  __shared__ float4 s_rec[256 / kWave][kRows][kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
+  __shared__ float4 s_px[kLanes ? 256 / kWave : 1][kWave];
+  __shared__ float2 s_tab[kLanes ? 256 / kWave : 1][kLanes ? kLaneTab : 1];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
   const ViewDev* views = table_views(a.table);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const BwdLds L{s_rec[w], s_id[w], kLanes ? s_px[w] : nullptr, kLanes ? s_tab[w] : nullptr};
   const int items = th->items_total;
   if (kPersistent) {
     while (true) {
@@ -439,45 +779,52 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
       if (lane == 0) item = (int)atomicAdd(&a.hdr->work_bwd, 1u);
       item = __shfl(item, 0, kWave);
       if (item >= items) break;
-      raster_bwd_item<PX, kL2>(a, th, views, item, lane, s_rec[w], s_id[w]);
+      raster_bwd_item<PX, kL2, kLanes>(a, th, views, item, lane, L);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
-    if (item < items) raster_bwd_item<PX, kL2>(a, th, views, item, lane, s_rec[w], s_id[w]);
+    if (item < items) raster_bwd_item<PX, kL2, kLanes>(a, th, views, item, lane, L);
   }
 }
 
-template <int PX>
+template <int PX, bool kLanes>
 static void fwd_dispatch(const FwdArgs& a, int items, int persistent_blocks, hipStream_t s) {
   if (persistent_blocks > 0)
-    hipLaunchKernelGGL((k_raster_fwd<PX, true>), dim3(persistent_blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_raster_fwd<PX, true, kLanes>), dim3(persistent_blocks), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_raster_fwd<PX, false>), dim3((items + 3) / 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_raster_fwd<PX, false, kLanes>), dim3((items + 3) / 4), dim3(256), 0, s, a);
 }
 
-template <int PX>
+template <int PX, bool kLanes>
 static void bwd_dispatch(const BwdArgs& a, bool l2, int items, int persistent_blocks, hipStream_t s) {
   const dim3 grid(persistent_blocks > 0 ? (unsigned)persistent_blocks : (unsigned)((items + 3) / 4));
   if (persistent_blocks > 0) {
-    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, true, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_raster_bwd<PX, true, false>), grid, dim3(256), 0, s, a);
+    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, true, true, kLanes>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_raster_bwd<PX, true, false, kLanes>), grid, dim3(256), 0, s, a);
   } else {
-    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, false, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_raster_bwd<PX, false, false>), grid, dim3(256), 0, s, a);
+    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, false, true, kLanes>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_raster_bwd<PX, false, false, kLanes>), grid, dim3(256), 0, s, a);
   }
 }
 
-void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges,
-                       const uint32_t* vals, const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha,
-                       float* saved_T, uint32_t* saved_n, WsHdr* hdr, hipStream_t s) {
+void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists,
+                       const uint32_t* ranges, const uint32_t* vals, const float4* rec, const KOpts& o, float* out_rgb,
+                       float* out_alpha, float* saved_T, uint32_t* saved_n, WsHdr* hdr, hipStream_t s) {
   FwdArgs a{table, ranges, vals, rec, o, out_rgb, out_alpha, saved_T, saved_n, hdr};
   if (items <= 0) return;
-  if (px == 4) fwd_dispatch<4>(a, items, persistent_blocks, s);
-  else if (px == 2) fwd_dispatch<2>(a, items, persistent_blocks, s);
-  else fwd_dispatch<1>(a, items, persistent_blocks, s);
+  if (lane_lists) {
+    if (px == 4) fwd_dispatch<4, true>(a, items, persistent_blocks, s);
+    else if (px == 2) fwd_dispatch<2, true>(a, items, persistent_blocks, s);
+    else fwd_dispatch<1, true>(a, items, persistent_blocks, s);
+  } else {
+    if (px == 4) fwd_dispatch<4, false>(a, items, persistent_blocks, s);
+    else if (px == 2) fwd_dispatch<2, false>(a, items, persistent_blocks, s);
+    else fwd_dispatch<1, false>(a, items, persistent_blocks, s);
+  }
 }
 
-void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges,
+void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists,
+                       const uint32_t* ranges,
                        const uint32_t* vals, const float4* rec, const KOpts& o, const float* saved_T,
                        const uint32_t* saved_n, const float* d_rgb, const float* d_alpha, const float* rgb,
                        const float* target, float l2_grad_scale, float l2_loss_scale, float* dfv, WsHdr* hdr,
@@ -485,9 +832,15 @@ void launch_raster_bwd(const void* table, int items, int persistent_blocks, int 
   BwdArgs a{table, ranges, vals, rec, o, saved_T, saved_n, d_rgb, d_alpha, rgb, target, l2_grad_scale, l2_loss_scale, dfv, hdr};
   if (items <= 0) return;
   const bool l2 = target != nullptr;
-  if (px == 4) bwd_dispatch<4>(a, l2, items, persistent_blocks, s);
-  else if (px == 2) bwd_dispatch<2>(a, l2, items, persistent_blocks, s);
-  else bwd_dispatch<1>(a, l2, items, persistent_blocks, s);
+  if (lane_lists) {
+    if (px == 4) bwd_dispatch<4, true>(a, l2, items, persistent_blocks, s);
+    else if (px == 2) bwd_dispatch<2, true>(a, l2, items, persistent_blocks, s);
+    else bwd_dispatch<1, true>(a, l2, items, persistent_blocks, s);
+  } else {
+    if (px == 4) bwd_dispatch<4, false>(a, l2, items, persistent_blocks, s);
+    else if (px == 2) bwd_dispatch<2, false>(a, l2, items, persistent_blocks, s);
+    else bwd_dispatch<1, false>(a, l2, items, persistent_blocks, s);
+  }
 }
 
 }  // namespace gmr

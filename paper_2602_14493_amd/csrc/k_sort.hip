@@ -191,13 +191,35 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = val;
 }
 
+// Start / end of each tile's run in the sorted keys.  A thread takes 8 consecutive keys with two
+// 16-B loads plus its two neighbours, so the kernel streams the keys once at full width.
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ keys, const WsHdr* __restrict__ hdr,
                                                      uint32_t* __restrict__ ranges) {
+  constexpr uint32_t kNone = 0xFFFFFFFFu;  // tile ids are < 2^30: never equal to a key
   const uint32_t n = min(hdr->count, hdr->capacity);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t t = keys[i];
-    if (i == 0 || keys[i - 1] != t) ranges[2 * (size_t)t] = i;
-    if (i + 1 == n || keys[i + 1] != t) ranges[2 * (size_t)t + 1] = i + 1;
+  const uint32_t groups = (n + 7u) / 8u;
+  for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < groups; gi += gridDim.x * blockDim.x) {
+    const uint32_t i0 = 8u * gi;
+    uint32_t k[10];
+    if (i0 + 8u <= n) {
+      const uint4 a = reinterpret_cast<const uint4*>(keys + i0)[0];
+      const uint4 b = reinterpret_cast<const uint4*>(keys + i0)[1];
+      k[1] = a.x; k[2] = a.y; k[3] = a.z; k[4] = a.w;
+      k[5] = b.x; k[6] = b.y; k[7] = b.z; k[8] = b.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) k[1 + j] = i0 + j < n ? keys[i0 + j] : kNone;
+    }
+    k[0] = i0 > 0u ? keys[i0 - 1u] : kNone;
+    k[9] = i0 + 8u < n ? keys[i0 + 8u] : kNone;
+#pragma unroll
+    for (int j = 1; j <= 8; ++j) {
+      const uint32_t t = k[j];
+      if (t == kNone) break;
+      const uint32_t i = i0 + (uint32_t)(j - 1);
+      if (k[j - 1] != t) ranges[2 * (size_t)t] = i;
+      if (k[j + 1] != t) ranges[2 * (size_t)t + 1] = i + 1u;
+    }
   }
 }
 

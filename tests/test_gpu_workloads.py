@@ -25,7 +25,8 @@ def say(*a):
 
 
 def test_block_shape_invariance(gpu):
-    """1, 2 or 4 pixels per lane (8x8, 8x16, 8x32 blocks per wavefront) give bit-identical images;
+    """1, 2 or 4 pixels per lane (8x8, 8x16, 8x32 blocks per wavefront), either raster schedule and
+    either list walk (block-uniform or per-lane lists) give bit-identical images and saved states;
     gradients agree to float rounding (atomic order)."""
     import torch
     import paper_2602_14493_amd as gmr
@@ -35,15 +36,27 @@ def test_block_shape_invariance(gpu):
     base, base_a, s0, ws0 = r.forward(verts, colors)
     g = torch.randn_like(base)
     dV0, dC0 = r.backward(verts, colors, g, None, s0, ws0)
-    for tw, th, px, mode in [(16, 16, 2, 0), (32, 32, 4, 0), (8, 32, 4, 1), (16, 16, 2, 1), (64, 32, 4, 0)]:
+    pairs_bwd0 = r.counters(ws0).pairs_bwd
+    for tw, th, px, mode, ll in [(16, 16, 2, 0, 0), (32, 32, 4, 0, 0), (8, 32, 4, 1, 0), (16, 16, 2, 1, 0),
+                                 (64, 32, 4, 0, 0), (16, 16, 1, 0, 1), (8, 8, 1, 1, 1), (32, 32, 2, 0, 1),
+                                 (32, 32, 4, 1, 1), (64, 32, 4, 0, 1)]:
+        cfg = (tw, th, px, mode, ll)
+        say("  tile %dx%d px %d mode %d lane lists %d" % cfg)
         r2 = gmr.Renderer(r.batch, W.faces, gmr.default_options(tile_w=tw, tile_h=th, px_per_lane=px,
-                                                                raster_mode=mode), handle=r.handle)
+                                                                raster_mode=mode, lane_lists=ll), handle=r.handle)
         rgb, a, s2, ws2 = r2.forward(verts, colors)
-        assert torch.equal(rgb, base), (tw, th, px, mode)
-        assert torch.equal(a, base_a), (tw, th, px, mode)
+        assert torch.equal(rgb, base), cfg
+        assert torch.equal(a, base_a), cfg
+        # saved transmittance always; the saved list positions are relative to the tile's list
+        nT = 4 * W.num_pixels
+        assert torch.equal(s2[:nT], s0[:nT]), cfg
+        if (tw, th) == (r.opts.tile_w, r.opts.tile_h):
+            assert torch.equal(s2, s0), cfg
+        assert r2.counters(ws2).pairs_fwd == r.counters(ws0).pairs_fwd, cfg
         dV, dC = r2.backward(verts, colors, g, None, s2, ws2)
-        compare_grads(dV, to_np(dV0), f"px{px} {tw}x{th} m{mode} dV", rel=1e-5)
-        compare_grads(dC, to_np(dC0), f"px{px} {tw}x{th} m{mode} dC", rel=1e-5)
+        assert r2.counters(ws2).pairs_bwd == pairs_bwd0, cfg
+        compare_grads(dV, to_np(dV0), f"px{px} {tw}x{th} m{mode} l{ll} dV", rel=1e-5)
+        compare_grads(dC, to_np(dC0), f"px{px} {tw}x{th} m{mode} l{ll} dC", rel=1e-5)
 
 
 def test_autotune(gpu):
