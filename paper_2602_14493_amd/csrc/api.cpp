@@ -420,8 +420,7 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   const double n3 = 3.0 * (double)p.p_total;
   {
     StageTimer t(h, s, kStRasterBwd);
-    launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0,
-                      w.ranges, w.sorted_vals, w.rec, ko, saved_T,
+    launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals, w.rec, ko, saved_T,
                       saved_n, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
                       w.dfv, w.hdr, s);
   }

@@ -35,8 +35,7 @@ void launch_raster_fwd(const void* table, int items, int persistent_blocks, int 
                        const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
                        uint32_t* saved_n, WsHdr* hdr, hipStream_t s);
 
-void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists,
-                       const uint32_t* ranges, const uint32_t* vals,
+void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges, const uint32_t* vals,
                        const float4* rec, const KOpts& o, const float* saved_T, const uint32_t* saved_n,
                        const float* d_rgb, const float* d_alpha, const float* rgb, const float* target, float l2_grad_scale,
                        float l2_loss_scale, float* dfv, WsHdr* hdr, hipStream_t s);

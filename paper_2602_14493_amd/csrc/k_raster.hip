@@ -7,7 +7,9 @@
 // block are kept (ballot), staged in the wavefront's LDS slots and consumed in list order as
 // wave-uniform broadcasts; the x offset and x extent test of a lane are shared by its PX pixels.
 // The wavefront leaves as soon as every pixel has stopped.  Wavefronts never synchronise with each
-// other, so a tile's blocks finish independently.
+// other, so a tile's blocks finish independently.  With per-lane lists (forward only), the staged
+// batch's pixel-rectangle coverage of the block is transposed across the wavefront so that each
+// lane walks only the Gaussians over its own pixel: same pairs, same arithmetic, fewer idle lanes.
 //
 // Per pixel and Gaussian (exp(power) = exp2(-(w1^2 + w2^2)), w = k L (dx, dy), L^T L = conic):
 //   inside = pixel in the Gaussian's 3-sigma pixel rectangle
@@ -508,15 +510,9 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
   return contrib;
 }
 
-// Pairs a wavefront's per-lane backward can hold for one staged batch (8 B each in LDS); a batch
-// whose pixel-rectangle coverage exceeds it takes the block-uniform walk.
-constexpr int kLaneTab = 1024;
-
 struct BwdLds {
-  float4 (*rec)[kWave];  // [3 + PX][64]: records; with lane lists also {coverage lo, hi, table offset} per row group
-  uint32_t* id;          // [64]
-  float4* px;            // [64] per pixel {g_C, list bound} (lane lists)
-  float2* tab;           // [kLaneTab] per pair {dL/dpower, alpha T} (lane lists)
+  float4 (*rec)[kWave];  // [3][64] staged records
+  uint32_t* id;          // [64] their face-view ids
 };
 
 // Block-uniform walk of one staged batch: every record is evaluated by the whole wavefront, two
@@ -554,103 +550,7 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
   }
 }
 
-// Per-lane walk of one staged batch, in two phases per pixel row group.
-//  A (lane = pixel): walk the lane's own Gaussians back to front (transposed coverage), update T
-//    and S exactly as the block-uniform walk does, and store each pair's {dL/dpower, alpha T} in
-//    the batch's pair table, grouped by Gaussian (offset = the Gaussian's table offset + the rank
-//    of the pixel among the pixels its rectangle covers).
-//  B (lane = Gaussian): walk the pixels the lane's own rectangle covers, read the pairs that
-//    phase A wrote, and sum the geometry and colour partials in registers.
-// The lane then issues its Gaussian's 8 float atomics.  No cross-lane reduction is needed.
-template <int PX>
-__device__ __forceinline__ void bwd_batch_lanes(const BwdArgs& a, const BwdLds& L, const uint64_t (&cov)[PX],
-                                                uint32_t tab_off, int64_t hi, uint32_t start, uint32_t id,
-                                                const float4& r0, const float4& r1, const ItemGeo& g, float px,
-                                                const int (&y)[PX], float amin, float amax, const float (&gc0)[PX],
-                                                const float (&gc1)[PX], const float (&gc2)[PX], const float (&K)[PX],
-                                                const uint32_t (&last)[PX], float (&T)[PX], float (&S)[PX],
-                                                uint32_t& pairs, int lane) {
-  float4 (*s)[kWave] = L.rec;
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
-  const int64_t hs = hi - (int64_t)start;                                // list position of batch slot j: hs - 1 - j
-  const uint32_t prel_own = (uint32_t)(hs - 1 - lane);                   // this lane's Gaussian (valid when cov != 0)
-  float gr[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) gr[i] = 0.f;
-  bool any = false;
-#pragma unroll
-  for (int k = 0; k < PX; ++k) {
-    // slots j with list position < last: j > hs - 1 - last
-    const int64_t jmin = hs - (int64_t)last[k];
-    uint64_t mine = transpose64(cov[k], lane);
-    mine = jmin <= 0 ? mine : (jmin >= 64 ? 0ull : (mine & (~0ull << jmin)));
-    L.px[lane] = make_float4(gc0[k], gc1[k], gc2[k], u2f(last[k]));
-    wave_lds_sync();
-    // ---- phase A: lane = pixel
-    const float py = (float)y[k] + 0.5f;
-    while (mine) {
-      const int j = ctz64(mine);
-      mine &= mine - 1;
-      const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j], c = s[3 + k][j];
-      const uint64_t cj = (uint64_t)f2u(c.x) | ((uint64_t)f2u(c.y) << 32);
-      const uint32_t slot = f2u(c.z) + (uint32_t)__popcll(cj & below);
-      const float dx = (a0.x - px) + a0.z;
-      const float dy = (a0.y - py) + a0.w;
-      float w1, w2;
-      const float e = gauss_exp(a1, dx, dy, w1, w2);
-      const float al = fminf(amax, e);
-      const bool ok = al >= amin;
-      pairs += ok ? 1u : 0u;
-      const float rom = __builtin_amdgcn_rcpf(1.f - al);
-      const float Tk = T[k] * rom;
-      const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
-      const float dal = Tk * cg - (S[k] + K[k]) * rom;
-      const float wt = ok ? al * Tk : 0.f;
-      S[k] = fmaf(wt, cg, S[k]);
-      T[k] = ok ? Tk : T[k];
-      const float dpow = (ok && e < amax) ? e * dal : 0.f;
-      L.tab[slot] = make_float2(dpow, wt);
-    }
-    wave_lds_sync();
-    // ---- phase B: lane = Gaussian
-    uint64_t cm = cov[k];
-    uint32_t slot = f2u(s[3 + k][lane].z);
-    const int yb = g.by0 + kSub * k;
-    while (cm) {
-      const int i = ctz64(cm);
-      cm &= cm - 1;
-      const float4 pd = L.px[i];
-      const float2 t = L.tab[slot];
-      ++slot;
-      if (prel_own >= f2u(pd.w)) continue;  // the pixel stopped before reaching this Gaussian
-      const float pxi = (float)(g.bx0 + (i & 7)) + 0.5f;
-      const float pyi = (float)(yb + (i >> 3)) + 0.5f;
-      const float dx = (r0.x - pxi) + r0.z;
-      const float dy = (r0.y - pyi) + r0.w;
-      const float w1 = fmaf(r1.x, dx, r1.y * dy);
-      const float w2 = r1.z * dy;
-      const float dpow = t.x, wt = t.y;
-      const float q = dpow * kTwoLn2;
-      gr[0] -= q * r1.x * w1;
-      gr[1] -= q * fmaf(r1.y, w1, r1.z * w2);
-      gr[2] -= 0.5f * dpow * dx * dx;
-      gr[3] -= dpow * dx * dy;
-      gr[4] -= 0.5f * dpow * dy * dy;
-      gr[5] = fmaf(wt, pd.x, gr[5]);
-      gr[6] = fmaf(wt, pd.y, gr[6]);
-      gr[7] = fmaf(wt, pd.z, gr[7]);
-      any |= (dpow != 0.f) || (wt != 0.f);
-    }
-    wave_lds_sync();
-  }
-  if (any) {
-    float* d = a.dfv + 8 * (size_t)id;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) atomicAdd(d + i, gr[i]);
-  }
-}
-
-template <int PX, bool kL2, bool kLanes>
+template <int PX, bool kL2>
 __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
                                        const BwdLds& L) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
@@ -701,77 +601,37 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
   if (mx == 0) return;
   const float px = (float)g.x + 0.5f;
   const float amin = a.o.alpha_min, amax = a.o.alpha_max;
-  unsigned long long pairs = 0;   // block-uniform walk: wave-uniform count
-  uint32_t lpairs = 0;            // per-lane walk: per-lane count
+  unsigned long long pairs = 0;  // wave-uniform count
   for (int64_t hi = (int64_t)start + mx; hi > (int64_t)start; hi -= kWave) {
     const int64_t pos = hi - 1 - lane;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-    uint32_t id = 0, rx = 0, ry = 0;
+    uint32_t id = 0;
     bool ov = false;
     if (pos >= (int64_t)start) {
       id = a.vals[pos];
       const float4* rp = a.rec + (size_t)kRecF4 * id;
       r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
-      rx = f2u(r1.w);
-      ry = f2u(r2.w);
-      ov = rect_meets_block(rx, ry, g.bx0, g.by0, kSub * PX);
+      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX);
     }
     const uint64_t m = __ballot(ov);
     if (m == 0ull) continue;
     L.rec[0][lane] = r0; L.rec[1][lane] = r1; L.rec[2][lane] = r2;
-    if constexpr (kLanes) {
-      uint64_t cov[PX];
-      uint32_t cnt = 0;
-#pragma unroll
-      for (int k = 0; k < PX; ++k) {
-        cov[k] = ov ? block_coverage(rx, ry, g.bx0, g.by0 + kSub * k) : 0ull;
-        cnt += (uint32_t)__popcll(cov[k]);
-      }
-      uint32_t inc = cnt;  // inclusive scan of the pair counts over the lanes
-#pragma unroll
-      for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t t = (uint32_t)__shfl_up((int)inc, d, kWave);
-        if (lane >= d) inc += t;
-      }
-      const uint32_t total = (uint32_t)__shfl((int)inc, kWave - 1, kWave);
-      if (total <= (uint32_t)kLaneTab) {
-        uint32_t off = inc - cnt;
-#pragma unroll
-        for (int k = 0; k < PX; ++k) {
-          L.rec[3 + k][lane] = make_float4(u2f((uint32_t)cov[k]), u2f((uint32_t)(cov[k] >> 32)), u2f(off), 0.f);
-          off += (uint32_t)__popcll(cov[k]);
-        }
-        // the per-pixel block data is written inside, after this barrier-free point: the LDS
-        // writes above are ordered before phase A by its own wave_lds_sync
-        bwd_batch_lanes<PX>(a, L, cov, inc - cnt, hi, start, id, r0, r1, g, px, y, amin, amax, gc0, gc1, gc2, K,
-                            last, T, S, lpairs, lane);
-        continue;
-      }
-    }
     L.id[lane] = id;
     wave_lds_sync();
     bwd_batch_uniform<PX>(a, L, m, hi, start, g, px, y, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
     wave_lds_sync();
   }
-  if constexpr (kLanes) {
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) lpairs += (uint32_t)__shfl_xor((int)lpairs, d, kWave);
-    pairs += lpairs;
-  }
   if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_bwd, pairs);
 }
 
-template <int PX, bool kPersistent, bool kL2, bool kLanes>
+template <int PX, bool kPersistent, bool kL2>
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
-  constexpr int kRows = kLanes ? kRecF4 + PX : kRecF4;
-  __shared__ float4 s_rec[256 / kWave][kRows][kWave];
+  __shared__ float4 s_rec[256 / kWave][kRecF4][kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
-  __shared__ float4 s_px[kLanes ? 256 / kWave : 1][kWave];
-  __shared__ float2 s_tab[kLanes ? 256 / kWave : 1][kLanes ? kLaneTab : 1];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
   const ViewDev* views = table_views(a.table);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const BwdLds L{s_rec[w], s_id[w], kLanes ? s_px[w] : nullptr, kLanes ? s_tab[w] : nullptr};
+  const BwdLds L{s_rec[w], s_id[w]};
   const int items = th->items_total;
   if (kPersistent) {
     while (true) {
@@ -779,11 +639,11 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
       if (lane == 0) item = (int)atomicAdd(&a.hdr->work_bwd, 1u);
       item = __shfl(item, 0, kWave);
       if (item >= items) break;
-      raster_bwd_item<PX, kL2, kLanes>(a, th, views, item, lane, L);
+      raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
-    if (item < items) raster_bwd_item<PX, kL2, kLanes>(a, th, views, item, lane, L);
+    if (item < items) raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
   }
 }
 
@@ -795,15 +655,15 @@ static void fwd_dispatch(const FwdArgs& a, int items, int persistent_blocks, hip
     hipLaunchKernelGGL((k_raster_fwd<PX, false, kLanes>), dim3((items + 3) / 4), dim3(256), 0, s, a);
 }
 
-template <int PX, bool kLanes>
+template <int PX>
 static void bwd_dispatch(const BwdArgs& a, bool l2, int items, int persistent_blocks, hipStream_t s) {
   const dim3 grid(persistent_blocks > 0 ? (unsigned)persistent_blocks : (unsigned)((items + 3) / 4));
   if (persistent_blocks > 0) {
-    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, true, true, kLanes>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_raster_bwd<PX, true, false, kLanes>), grid, dim3(256), 0, s, a);
+    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, true, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_raster_bwd<PX, true, false>), grid, dim3(256), 0, s, a);
   } else {
-    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, false, true, kLanes>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_raster_bwd<PX, false, false, kLanes>), grid, dim3(256), 0, s, a);
+    if (l2) hipLaunchKernelGGL((k_raster_bwd<PX, false, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_raster_bwd<PX, false, false>), grid, dim3(256), 0, s, a);
   }
 }
 
@@ -823,8 +683,7 @@ void launch_raster_fwd(const void* table, int items, int persistent_blocks, int 
   }
 }
 
-void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists,
-                       const uint32_t* ranges,
+void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges,
                        const uint32_t* vals, const float4* rec, const KOpts& o, const float* saved_T,
                        const uint32_t* saved_n, const float* d_rgb, const float* d_alpha, const float* rgb,
                        const float* target, float l2_grad_scale, float l2_loss_scale, float* dfv, WsHdr* hdr,
@@ -832,15 +691,9 @@ void launch_raster_bwd(const void* table, int items, int persistent_blocks, int 
   BwdArgs a{table, ranges, vals, rec, o, saved_T, saved_n, d_rgb, d_alpha, rgb, target, l2_grad_scale, l2_loss_scale, dfv, hdr};
   if (items <= 0) return;
   const bool l2 = target != nullptr;
-  if (lane_lists) {
-    if (px == 4) bwd_dispatch<4, true>(a, l2, items, persistent_blocks, s);
-    else if (px == 2) bwd_dispatch<2, true>(a, l2, items, persistent_blocks, s);
-    else bwd_dispatch<1, true>(a, l2, items, persistent_blocks, s);
-  } else {
-    if (px == 4) bwd_dispatch<4, false>(a, l2, items, persistent_blocks, s);
-    else if (px == 2) bwd_dispatch<2, false>(a, l2, items, persistent_blocks, s);
-    else bwd_dispatch<1, false>(a, l2, items, persistent_blocks, s);
-  }
+  if (px == 4) bwd_dispatch<4>(a, l2, items, persistent_blocks, s);
+  else if (px == 2) bwd_dispatch<2>(a, l2, items, persistent_blocks, s);
+  else bwd_dispatch<1>(a, l2, items, persistent_blocks, s);
 }
 
 }  // namespace gmr

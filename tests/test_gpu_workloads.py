@@ -26,8 +26,8 @@ def say(*a):
 
 def test_block_shape_invariance(gpu):
     """1, 2 or 4 pixels per lane (8x8, 8x16, 8x32 blocks per wavefront), either raster schedule and
-    either list walk (block-uniform or per-lane lists) give bit-identical images and saved states;
-    gradients agree to float rounding (atomic order)."""
+    either forward list walk (block-uniform or per-lane lists) give bit-identical images and saved
+    transmittances; gradients agree to float rounding (atomic order)."""
     import torch
     import paper_2602_14493_amd as gmr
     say("pixels-per-lane invariance cfg2")
