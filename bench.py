@@ -34,7 +34,12 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # reads for the plain copy of --copy-probe.  Keyed by workload, kernel and launch configuration
 # (tile, pixels per lane, raster mode, lane lists); `src` is the hash of the kernel's sources when the counters
 # were taken, and a changed source reports null.
-TRAFFIC = {}
+TRAFFIC = {
+    ("icosphere_s5_8x512", "raster_bwd", "32x32", 2, 0, 1):
+        {"fetch": 76340571, "write": 20475392, "src": "41e1ad69a92e722e"},
+    ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
+        {"fetch": 14628903483, "write": 1811400347, "src": "41e1ad69a92e722e"},
+}
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "sort_digits": "k_sort.hip", "tile_ranges": "k_sort.hip",
                 "project": "k_project.hip", "scan_emit": "k_bin.hip", "face_bwd": "k_grad.hip",
@@ -170,7 +175,9 @@ def main():
 
     # ---- batched form ------------------------------------------------------------------------
     if use_graph:
-        loop = gmr.GraphAdamLoop(r, verts, colors, target, lr=1e-3, recompute=True)
+        # lr 1e-4: Adam moves a coordinate by about lr per step, so the 100 steps of the workload
+        # move a vertex by about the noise amplitude (0.01) it is meant to remove
+        loop = gmr.GraphAdamLoop(r, verts, colors, target, lr=1e-4, recompute=True)
         if args.no_graph:
             loop._step_body()
         else:

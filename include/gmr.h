@@ -63,7 +63,7 @@ typedef struct gmr_options {
   int32_t raster_mode;       /* [0] 0: one workgroup per tile group; 1: persistent work queue     */
   int32_t px_per_lane;       /* [1] pixels per lane in the rasteriser: 1, 2 or 4 (a wavefront then
                                 covers an 8 x 8*px_per_lane block); tile_h % (8*px_per_lane) == 0   */
-  int32_t lane_lists;        /* [0] 1: the forward compositing walks per-lane lists -- each lane visits
+  int32_t lane_lists;        /* [1] 1: the forward compositing walks per-lane lists -- each lane visits
                                 only the Gaussians whose pixel rectangle holds its pixel (lists
                                 built per staged batch with a 64 x 64 bit transpose) -- instead of
                                 every Gaussian meeting its block.  Images and saved states are

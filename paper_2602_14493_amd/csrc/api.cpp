@@ -460,7 +460,7 @@ gmr_options gmr_default_options(void) {
   o.tile_h = 16;
   o.raster_mode = 0;
   o.px_per_lane = 1;
-  o.lane_lists = 0;
+  o.lane_lists = 1;
   o.reserved_opt = 0;
   o.instance_capacity = 0;
   return o;
