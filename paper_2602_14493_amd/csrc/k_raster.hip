@@ -24,9 +24,11 @@
 //   dL/dpower = alpha dL/dalpha when unclamped, else 0
 //   (du, dv) = -dL/dpower (conic (dx, dy));  (da, db, dc) = -dL/dpower (dx^2/2, dx dy, dy^2/2)
 //   dL/dc_k = alpha_k T_k g_C
-// A lane first sums its PX pixels' partials; the 8 sums are then reduced over the wavefront with a
-// butterfly that halves the values carried per lane at each of the first three steps (10 shuffles
-// for 8 sums), and 8 lanes issue one float atomic each into the face-view's gradient record.
+// A lane first sums its PX pixels' partials; the 8 sums are then reduced over the wavefront by a
+// transposed butterfly that halves the values carried per lane at each of the first three steps
+// (half-wave and row swaps, then DPP), and 8 lanes issue one float atomic each into the
+// face-view's gradient record.  Gaussians that no pixel of a row group reaches, or that no pixel
+// composites, are skipped wave-uniformly.
 #include "gmr_common.h"
 #include "gmr_launch.h"
 
@@ -481,14 +483,18 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     const bool act = prel < last[k] && inx && in_range(ry, y[k]);
-    if (PX > 1 && __ballot(act) == 0ull) continue;  // wave-uniform skip, as in the forward
+    // wave-uniform skips: no pixel of the row group inside the extent (before its stop), or none
+    // whose alpha reaches the cutoff -- then T, S and every partial are unchanged
+    if (__ballot(act) == 0ull) continue;
     const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
     float w1, w2;
     const float e = gauss_exp(a1, dx, dy, w1, w2);
     const float al = fminf(amax, e);
     const bool ok = act && al >= amin;
+    const uint64_t okm = __ballot(ok);
+    if (okm == 0ull) continue;
     contrib |= ok;
-    pairs += (unsigned long long)__popcll(__ballot(ok));  // wave-uniform, scalar unit
+    pairs += (unsigned long long)__popcll(okm);  // wave-uniform, scalar unit
     const float rom = __builtin_amdgcn_rcpf(1.f - al);  // 1 - al >= 1 - alpha_max > 0
     const float Tk = T[k] * rom;
     const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
@@ -497,12 +503,15 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
     S[k] = fmaf(wt, cg, S[k]);
     T[k] = ok ? Tk : T[k];
     const float dpow = (ok && e < amax) ? e * dal : 0.f;
-    const float q = dpow * kTwoLn2;
-    gr[0] -= q * a1.x * w1;
-    gr[1] -= q * fmaf(a1.y, w1, a1.z * w2);
-    gr[2] -= 0.5f * dpow * dx * dx;
-    gr[3] -= dpow * dx * dy;
-    gr[4] -= 0.5f * dpow * dy * dy;
+    // d/d(l11, l12 | l22 rows of the scaled factor) and d/d(conic) partials, as FMAs into the sums:
+    // -dpow 2 ln2 (l11 w1, l12 w1 + l22 w2) and -dpow / 2 (dx^2, 2 dx dy, dy^2)
+    const float qn = dpow * -kTwoLn2;
+    gr[0] = fmaf(qn, a1.x * w1, gr[0]);
+    gr[1] = fmaf(qn, fmaf(a1.y, w1, a1.z * w2), gr[1]);
+    const float h = -0.5f * dpow, t = h * dx;
+    gr[2] = fmaf(t, dx, gr[2]);
+    gr[3] = fmaf(t + t, dy, gr[3]);
+    gr[4] = fmaf(h * dy, dy, gr[4]);
     gr[5] = fmaf(wt, gc0[k], gr[5]);
     gr[6] = fmaf(wt, gc1[k], gr[6]);
     gr[7] = fmaf(wt, gc2[k], gr[7]);
