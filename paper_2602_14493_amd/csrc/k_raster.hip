@@ -284,20 +284,73 @@ __device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, con
   if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_fwd, pairs);
 }
 
-// Same compositing with per-lane lists: each staged batch's pixel-rectangle coverage of the block
-// (one 64-bit row per Gaussian) is transposed so that every lane holds the batch positions of the
-// Gaussians that contain its pixel, and walks only those, in list order.  Every (pixel, Gaussian)
-// pair takes the same arithmetic as in raster_fwd_item, so images are bit-identical; a lane costs
-// one iteration per Gaussian over its pixel instead of one per Gaussian meeting the block.
+// Walk the n staged Gaussians (slots 0..n-1, in list order) with per-lane lists: lane j < n builds
+// its Gaussian's pixel-rectangle coverage of the block (one 64-bit row per row group), the rows are
+// transposed so that every lane holds the slots of the Gaussians that contain its pixel, and each
+// lane walks only those, in slot order.  Every (pixel, Gaussian) pair takes the same arithmetic as
+// in raster_fwd_item, so images are bit-identical.
+template <int PX>
+__device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const uint32_t* s_pos, uint32_t n,
+                                               const ItemGeo& g, float px, const int (&y)[PX], float amin, float amax,
+                                               float teps, float (&T)[PX], float (&C0)[PX], float (&C1)[PX],
+                                               float (&C2)[PX], uint32_t (&last)[PX], bool (&done)[PX],
+                                               uint32_t& pairs, int lane) {
+  uint64_t mine[PX];
+  {
+    const bool own = (uint32_t)lane < n;
+    const uint32_t rx = own ? f2u(s[1][lane].w) : 0u, ry = own ? f2u(s[2][lane].w) : 0u;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      const uint64_t cov = own ? block_coverage(rx, ry, g.bx0, g.by0 + kSub * k) : 0ull;
+      mine[k] = transpose64(cov, lane);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    uint64_t m = done[k] ? 0ull : mine[k];
+    const float py = (float)y[k] + 0.5f;
+    while (m) {
+      const int j = ctz64(m);
+      m &= m - 1;
+      const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
+      const float dx = (a0.x - px) + a0.z;
+      const float dy = (a0.y - py) + a0.w;
+      float w1, w2;
+      const float e = gauss_exp(a1, dx, dy, w1, w2);
+      const float al = fminf(amax, e);
+      ++pairs;
+      if (al >= amin) {
+        const float Tn = T[k] * (1.f - al);
+        if (Tn < teps) {
+          done[k] = true;
+          m = 0ull;
+        } else {
+          const float wt = al * T[k];
+          C0[k] = fmaf(a2.x, wt, C0[k]);
+          C1[k] = fmaf(a2.y, wt, C1[k]);
+          C2[k] = fmaf(a2.z, wt, C2[k]);
+          T[k] = Tn;
+          last[k] = s_pos[j];
+        }
+      }
+    }
+  }
+}
+
+// Forward with per-lane lists.  The tile's list is read 64 instances at a time; the Gaussians
+// whose rectangle meets the block are appended, in list order, to the wavefront's 64 LDS slots, and
+// each time the slots fill (and at the end of the list) they are walked with fwd_walk_lanes, so one
+// transpose serves 64 kept Gaussians however sparse they are in the list.
 template <int PX>
 __device__ inline void raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
-                                             int lane, float4 (*s)[kWave]) {
+                                             int lane, float4 (*s)[kWave], uint32_t* s_pos) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return;
   const int ly = lane >> 3;
   const float px = (float)g.x + 0.5f;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
   float T[PX], C0[PX], C1[PX], C2[PX];
   uint32_t last[PX];
   bool done[PX];
@@ -310,63 +363,48 @@ __device__ inline void raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* t
     done[k] = !(g.x < g.W && y[k] < g.H);
   }
   uint32_t pairs = 0;
+  uint32_t nk = 0;  // staged Gaussians (wave-uniform)
   for (uint32_t cb = start; cb < end; cb += kWave) {
     bool live = false;
 #pragma unroll
     for (int k = 0; k < PX; ++k) live |= !done[k];
-    if (__ballot(live) == 0ull) break;
+    if (__ballot(live) == 0ull) {
+      nk = 0;  // every pixel has stopped: what is staged no longer matters
+      break;
+    }
     const uint32_t pos = cb + (uint32_t)lane;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-    uint32_t rx = 0, ry = 0;
     bool ov = false;
     if (pos < end) {
       const uint32_t id = a.vals[pos];
       const float4* rp = a.rec + (size_t)kRecF4 * id;
       r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
-      rx = f2u(r1.w);
-      ry = f2u(r2.w);
-      ov = rect_meets_block(rx, ry, g.bx0, g.by0, kSub * PX);
+      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX);
     }
-    if (__ballot(ov) == 0ull) continue;
-    s[0][lane] = r0; s[1][lane] = r1; s[2][lane] = r2;
-    uint64_t mine[PX];
-#pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      const uint64_t cov = ov ? block_coverage(rx, ry, g.bx0, g.by0 + kSub * k) : 0ull;
-      mine[k] = transpose64(cov, lane);
+    const uint64_t m = __ballot(ov);
+    if (m == 0ull) continue;
+    const uint32_t cnt = (uint32_t)__popcll(m), slot = nk + (uint32_t)__popcll(m & below);
+    if (ov && slot < (uint32_t)kWave) {
+      s[0][slot] = r0; s[1][slot] = r1; s[2][slot] = r2;
+      s_pos[slot] = pos - start + 1u;  // list position after this Gaussian
     }
-    wave_lds_sync();
-#pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      uint64_t m = done[k] ? 0ull : mine[k];
-      const float py = (float)y[k] + 0.5f;
-      while (m) {
-        const int j = ctz64(m);
-        m &= m - 1;
-        const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
-        const float dx = (a0.x - px) + a0.z;
-        const float dy = (a0.y - py) + a0.w;
-        float w1, w2;
-        const float e = gauss_exp(a1, dx, dy, w1, w2);
-        const float al = fminf(amax, e);
-        ++pairs;
-        if (al >= amin) {
-          const float Tn = T[k] * (1.f - al);
-          if (Tn < teps) {
-            done[k] = true;
-            m = 0ull;
-          } else {
-            const float wt = al * T[k];
-            C0[k] = fmaf(a2.x, wt, C0[k]);
-            C1[k] = fmaf(a2.y, wt, C1[k]);
-            C2[k] = fmaf(a2.z, wt, C2[k]);
-            T[k] = Tn;
-            last[k] = cb + (uint32_t)j - start + 1u;
-          }
-        }
-      }
+    if (nk + cnt < (uint32_t)kWave) {
+      nk += cnt;
+      continue;
     }
     wave_lds_sync();
+    fwd_walk_lanes<PX>(s, s_pos, (uint32_t)kWave, g, px, y, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
+    wave_lds_sync();
+    if (ov && slot >= (uint32_t)kWave) {  // the overflow starts the next 64
+      const uint32_t t = slot - (uint32_t)kWave;
+      s[0][t] = r0; s[1][t] = r1; s[2][t] = r2;
+      s_pos[t] = pos - start + 1u;
+    }
+    nk = nk + cnt - (uint32_t)kWave;
+  }
+  if (nk > 0) {
+    wave_lds_sync();
+    fwd_walk_lanes<PX>(s, s_pos, nk, g, px, y, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
   }
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
@@ -385,18 +423,20 @@ __device__ inline void raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* t
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) pairs += (uint32_t)__shfl_xor((int)pairs, d, kWave);
   if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_fwd, (unsigned long long)pairs);
+  wave_lds_sync();  // the next item (persistent schedule) restages the slots
 }
 
 template <int PX, bool kPersistent, bool kLanes>
 __device__ __forceinline__ void raster_fwd_any(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
-                                               int lane, float4 (*s)[kWave]) {
-  if constexpr (kLanes) raster_fwd_item_lanes<PX>(a, th, views, item, lane, s);
+                                               int lane, float4 (*s)[kWave], uint32_t* s_pos) {
+  if constexpr (kLanes) raster_fwd_item_lanes<PX>(a, th, views, item, lane, s, s_pos);
   else raster_fwd_item<PX>(a, th, views, item, lane, s);
 }
 
 template <int PX, bool kPersistent, bool kLanes>
 __global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
   __shared__ float4 s_rec[256 / kWave][kRecF4][kWave];
+  __shared__ uint32_t s_pos[kLanes ? 256 / kWave : 1][kWave];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
   const ViewDev* views = table_views(a.table);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -407,11 +447,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
       if (lane == 0) item = (int)atomicAdd(&a.hdr->work_fwd, 1u);
       item = __shfl(item, 0, kWave);
       if (item >= items) break;
-      raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w]);
+      raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w], s_pos[kLanes ? w : 0]);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
-    if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w]);
+    if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w], s_pos[kLanes ? w : 0]);
   }
 }
 
