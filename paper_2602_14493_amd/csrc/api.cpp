@@ -180,7 +180,9 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
     L.tile_mask[j] = (int32_t)((1u << wbits) - 1u);
     sh += wbits;
   }
-  L.scan_blocks = (int32_t)((p.fv_total + kScanTile - 1) / kScanTile);
+  L.scan_items = scan_items_for(p.fv_total);
+  const int64_t scan_tile = (int64_t)kScanBlock * L.scan_items;
+  L.scan_blocks = (int32_t)((p.fv_total + scan_tile - 1) / scan_tile);
   if (L.scan_blocks > 65536) return fail(GMR_ERR_INVALID_ARG, "too many face-views for the single-level scan");
   L.parts_fv = (int32_t)((p.fv_total + kSortPart - 1) / kSortPart);
   L.parts_inst = (int32_t)((cap + kSortPart - 1) / kSortPart);
@@ -351,8 +353,8 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   }
   {
     StageTimer t(h, s, kStScanEmit);
-    launch_bin(table, w.elA, p.fv_total, w.bsum, w.boff, L.scan_blocks, w.hdr, (uint32_t)L.capacity, w.instA, w.hist, tp,
-               w.descI0, inst_words, s);
+    launch_bin(table, w.elA, p.fv_total, L.scan_items, w.bsum, w.boff, L.scan_blocks, w.hdr, (uint32_t)L.capacity,
+               w.instA, w.hist, tp, w.descI0, inst_words, s);
     launch_sort_digits(w.hist, w.dig, kTileRow0, tp.n, 512, s);
   }
   // tile digits on the instances: A -> B -> A ..., the last pass writes keysF / valsF

@@ -12,11 +12,14 @@ constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kSub = 8;              // raster sub-block side: one 8x8 pixel block per wavefront
 constexpr int kRecF4 = 3;            // projected record = 3 x float4 = 48 B per face-view
 constexpr int kSortBlock = 512;      // onesweep workgroup (8 wavefronts)
+constexpr int kScanBlock = 256;
 constexpr int kSortItems = 8;        // elements per thread
 constexpr int kSortPart = kSortBlock * kSortItems;  // elements per partition
-constexpr int kScanBlock = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanBlock * kScanItems;  // face-views per scan block
+// Face-views per thread of the scan / emission blocks: the large variant amortises per-workgroup
+// work on big inputs; inputs too small to give every CU a large block take the small one (4x the
+// workgroups).
+constexpr int kScanItemsLarge = 16, kScanItemsSmall = 4;
+inline int scan_items_for(int64_t n) { return n >= (int64_t{1} << 20) ? kScanItemsLarge : kScanItemsSmall; }
 constexpr int kMaxPasses = 8;        // histogram rows: 0..3 depth digits (face-views), 4..7 tile digits
 constexpr int kDepthPasses = 4;      // 32 depth bits in 8-bit digits
 constexpr int kTileRow0 = 4;
@@ -81,6 +84,7 @@ struct Layout {
       ranges, dfv, fgrad, total;
   int64_t fv_total, faces_total, pixels_total, capacity;
   int32_t tiles_total, items_total, tile_bits, tile_passes, scan_blocks, parts_fv, parts_inst;
+  int32_t scan_items;  // face-views per thread of the scan / emission blocks (scan_items_for)
   int32_t tile_shift[kMaxPasses - kTileRow0], tile_mask[kMaxPasses - kTileRow0];
 };
 

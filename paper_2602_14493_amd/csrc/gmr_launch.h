@@ -14,9 +14,9 @@ void launch_project(const void* table, int64_t faces_total, const float* verts, 
                     const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
                     WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, hipStream_t s);
 
-void launch_bin(const void* table, const uint4* el, int64_t n, uint32_t* bsum, uint64_t* boff, int nb, WsHdr* hdr,
-                uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0, uint32_t desc0_words,
-                hipStream_t s);
+void launch_bin(const void* table, const uint4* el, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
+                WsHdr* hdr, uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0,
+                uint32_t desc0_words, hipStream_t s);
 
 void launch_sort_digits(const uint32_t* hist, uint32_t* dig, int row0, int rows, int radix, hipStream_t s);
 void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* dig, uint32_t* desc_cur,

@@ -29,14 +29,15 @@ __device__ inline uint32_t wave_sum(uint32_t x) {
   return x;
 }
 
+template <int kItems>
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint4* __restrict__ el, int64_t n,
                                                             uint32_t* __restrict__ bsum) {
   __shared__ uint32_t s_w[kScanBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)w * (kScanItems * kWave) + lane;
+  const int64_t base = (int64_t)blockIdx.x * (kScanBlock * kItems) + (int64_t)w * (kItems * kWave) + lane;
   uint32_t acc = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
+  for (int i = 0; i < kItems; ++i) {
     const int64_t idx = base + (int64_t)i * kWave;
     if (idx < n) acc += el_count(el[idx]);
   }
@@ -88,6 +89,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(const uint32_t* __restrict__ 
   }
 }
 
+template <int kItems>
 __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ table, const uint4* __restrict__ el, int64_t n,
                                                      const uint64_t* __restrict__ boff, const WsHdr* __restrict__ hdr,
                                                      uint2* __restrict__ inst, uint32_t* __restrict__ hist, TilePasses tp,
@@ -104,11 +106,11 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
     const uint32_t b1 = min(desc0_words, b0 + chunk);
     for (uint32_t i = b0 + threadIdx.x; i < b1; i += kScanBlock) desc0[i] = 0u;
   }
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)w * (kScanItems * kWave) + lane;
-  uint32_t c[kScanItems];
+  const int64_t base = (int64_t)blockIdx.x * (kScanBlock * kItems) + (int64_t)w * (kItems * kWave) + lane;
+  uint32_t c[kItems];
   uint32_t wtot = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
+  for (int i = 0; i < kItems; ++i) {
     const int64_t idx = base + (int64_t)i * kWave;
     c[i] = idx < n ? el_count(el[idx]) : 0u;
     wtot += c[i];
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
   for (int k = 0; k < w; ++k) off += s_w[k];
   const uint64_t cap = hdr->capacity;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
+  for (int i = 0; i < kItems; ++i) {
     const uint32_t inc = wave_incl_scan(c[i], lane);
     const uint64_t my = off + inc - c[i];
     off += __shfl(inc, kWave - 1, kWave);
@@ -144,14 +146,23 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
     if ((&s_h[0][0])[i]) atomicAdd(&hist[kTileRow0 * kHistStride + i], (&s_h[0][0])[i]);
 }
 
-void launch_bin(const void* table, const uint4* el, int64_t n, uint32_t* bsum, uint64_t* boff, int nb, WsHdr* hdr,
-                uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0, uint32_t desc0_words,
-                hipStream_t s) {
-  if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, s, el, n, bsum);
+void launch_bin(const void* table, const uint4* el, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
+                WsHdr* hdr, uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0,
+                uint32_t desc0_words, hipStream_t s) {
+  const bool large = items == kScanItemsLarge;
+  if (nb > 0) {
+    if (large) hipLaunchKernelGGL(k_scan_reduce<kScanItemsLarge>, dim3(nb), dim3(kScanBlock), 0, s, el, n, bsum);
+    else hipLaunchKernelGGL(k_scan_reduce<kScanItemsSmall>, dim3(nb), dim3(kScanBlock), 0, s, el, n, bsum);
+  }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, boff, hdr, cap);
-  if (nb > 0)
-    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kScanBlock), 0, s, table, el, n, boff, hdr, inst, hist, tp, desc0,
-                       desc0_words);
+  if (nb > 0) {
+    if (large)
+      hipLaunchKernelGGL(k_emit<kScanItemsLarge>, dim3(nb), dim3(kScanBlock), 0, s, table, el, n, boff, hdr, inst, hist,
+                         tp, desc0, desc0_words);
+    else
+      hipLaunchKernelGGL(k_emit<kScanItemsSmall>, dim3(nb), dim3(kScanBlock), 0, s, table, el, n, boff, hdr, inst, hist,
+                         tp, desc0, desc0_words);
+  }
 }
 
 }  // namespace gmr
