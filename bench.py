@@ -41,7 +41,7 @@ TRAFFIC = {
         {"fetch": 14628903483, "write": 1811400347, "src": "41e1ad69a92e722e"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
-                "sort_pass": "k_sort.hip", "sort_digits": "k_sort.hip", "tile_ranges": "k_sort.hip",
+                "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
                 "project": "k_project.hip", "scan_emit": "k_bin.hip", "face_bwd": "k_grad.hip",
                 "vertex_gather": "k_grad.hip", "fill": "k_grad.hip"}
 

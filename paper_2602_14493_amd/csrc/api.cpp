@@ -17,11 +17,11 @@
 using namespace gmr;
 
 // Stages timed by gmr_profile_* (HIP events around each launch group on the call's stream).
-enum Stage { kStProject, kStScanEmit, kStSortHist, kStSortFv, kStSortPass, kStRanges, kStRasterFwd, kStFill,
-             kStRasterBwd, kStFaceBwd, kStGather, kNumStages };
-static const char* kStageNames[kNumStages] = {"project",    "scan_emit",   "sort_digits", "sort_fv_pass",
-                                              "sort_pass",  "tile_ranges", "raster_fwd",  "fill",
-                                              "raster_bwd", "face_bwd",    "vertex_gather"};
+enum Stage { kStProject, kStScanEmit, kStSortFv, kStSortPass, kStRanges, kStRasterFwd, kStFill, kStRasterBwd,
+             kStFaceBwd, kStGather, kNumStages };
+static const char* kStageNames[kNumStages] = {"project",     "scan_emit",  "sort_fv_pass", "sort_pass",
+                                              "tile_ranges", "raster_fwd", "fill",         "raster_bwd",
+                                              "face_bwd",    "vertex_gather"};
 
 struct gmr_ctx {
   int device = 0;
@@ -199,7 +199,6 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   L.keysF = take((size_t)cap * 4);
   L.valsF = take((size_t)cap * 4);
   L.hist = take(kMaxPasses * kHistStride * 4);
-  L.dig = take(kMaxPasses * kHistStride * 4);
   L.descF0 = take((size_t)std::max(L.parts_fv, 1) * 256 * 4);
   L.descF1 = take((size_t)std::max(L.parts_fv, 1) * 256 * 4);
   L.descI0 = take((size_t)L.parts_inst * 512 * 4);
@@ -261,7 +260,6 @@ struct WsPtrs {
   uint32_t* keysF;
   uint32_t* valsF;
   uint32_t* hist;
-  uint32_t* dig;
   uint32_t* descF0;
   uint32_t* descF1;
   uint32_t* descI0;
@@ -286,7 +284,6 @@ WsPtrs ws_ptrs(const Layout& L, void* ws) {
   w.keysF = reinterpret_cast<uint32_t*>(b + L.keysF);
   w.valsF = reinterpret_cast<uint32_t*>(b + L.valsF);
   w.hist = reinterpret_cast<uint32_t*>(b + L.hist);
-  w.dig = reinterpret_cast<uint32_t*>(b + L.dig);
   w.descF0 = reinterpret_cast<uint32_t*>(b + L.descF0);
   w.descF1 = reinterpret_cast<uint32_t*>(b + L.descF1);
   w.descI0 = reinterpret_cast<uint32_t*>(b + L.descI0);
@@ -331,17 +328,14 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   {
     StageTimer t(h, s, kStProject);
     launch_project(table, p.f_total, verts, faces, colors, ko, w.rec, w.elA, w.hist,
-                   zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.hdr, w.descF0, fv_words, s);
+                   zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.hdr, w.descF0, fv_words, w.ranges,
+                   2 * p.tiles_total, s);
   }
   // depth digits on the face-view elements: 4 passes, A -> B -> A -> B -> A
-  {
-    StageTimer t(h, s, kStSortHist);
-    launch_sort_digits(w.hist, w.dig, 0, kDepthPasses, 256, s);
-  }
   for (int pass = 0; pass < kDepthPasses; ++pass) {
     StageTimer t(h, s, kStSortFv);
     const bool odd = pass & 1;
-    launch_sort_fv_pass(odd ? w.elB : w.elA, odd ? w.elA : w.elB, (uint32_t)p.fv_total, w.dig + pass * kHistStride,
+    launch_sort_fv_pass(odd ? w.elB : w.elA, odd ? w.elA : w.elB, (uint32_t)p.fv_total, w.hist + pass * kHistStride,
                         odd ? w.descF1 : w.descF0, odd ? w.descF0 : w.descF1, fv_words, &w.hdr->part_ctr[pass], 8 * pass,
                         s);
   }
@@ -355,7 +349,6 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
     StageTimer t(h, s, kStScanEmit);
     launch_bin(table, w.elA, p.fv_total, L.scan_items, w.bsum, w.boff, L.scan_blocks, w.hdr, (uint32_t)L.capacity,
                w.instA, w.hist, tp, w.descI0, inst_words, s);
-    launch_sort_digits(w.hist, w.dig, kTileRow0, tp.n, 512, s);
   }
   // tile digits on the instances: A -> B -> A ..., the last pass writes keysF / valsF
   for (int j = 0; j < tp.n; ++j) {
@@ -363,12 +356,12 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
     const bool odd = j & 1, last = j + 1 == tp.n;
     launch_sort_inst_pass(odd ? w.instB : w.instA, odd ? w.instA : w.instB, last ? w.keysF : nullptr,
                           last ? w.valsF : nullptr, &w.hdr->count, (uint32_t)L.capacity,
-                          w.dig + (kTileRow0 + j) * kHistStride, odd ? w.descI1 : w.descI0, odd ? w.descI0 : w.descI1,
+                          w.hist + (kTileRow0 + j) * kHistStride, odd ? w.descI1 : w.descI0, odd ? w.descI0 : w.descI1,
                           last ? 0u : inst_words, &w.hdr->part_ctr[kTileRow0 + j], tp.shift[j], tp.mask[j], s);
   }
   {
     StageTimer t(h, s, kStRanges);
-    launch_tile_ranges(w.keysF, w.hdr, w.ranges, p.tiles_total, hist_blocks(h), s);
+    launch_tile_ranges(w.keysF, w.hdr, w.ranges, hist_blocks(h), s);
   }
 }
 
@@ -405,17 +398,10 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   hipStream_t s = static_cast<hipStream_t>(stream);
   const WsPtrs w = ws_ptrs(p.L, ws);
   const KOpts ko = kopts(opt);
-  if (recompute) {
-    build_lists(h, p, opt, table, verts, faces, colors, w, true, s);
-  } else {
-    StageTimer t(h, s, kStFill);
-    launch_fill_f32(w.dfv, p.fv_total * 8, 0.f, s);
-  }
+  if (recompute) build_lists(h, p, opt, table, verts, faces, colors, w, true, s);
   {
     StageTimer t(h, s, kStFill);
-    launch_fill_u32(&w.hdr->work_bwd, 1, 0u, s);
-    launch_fill_f32(&w.hdr->loss, 1, 0.f, s);
-    launch_fill_u32(reinterpret_cast<uint32_t*>(&w.hdr->pairs_bwd), 2, 0u, s);
+    launch_bwd_prologue(w.hdr, w.dfv, recompute ? 0 : p.fv_total * 8, s);
   }
   const float* saved_T = static_cast<const float*>(saved);
   const uint32_t* saved_n = reinterpret_cast<const uint32_t*>(saved_T + p.p_total);

@@ -80,7 +80,7 @@ struct KOpts {
 
 // Workspace layout, computed on the host (byte offsets) -------------------------------------------
 struct Layout {
-  size_t hdr, rec, elA, elB, bsum, boff, instA, instB, keysF, valsF, hist, dig, descF0, descF1, descI0, descI1,
+  size_t hdr, rec, elA, elB, bsum, boff, instA, instB, keysF, valsF, hist, descF0, descF1, descI0, descI1,
       ranges, dfv, fgrad, total;
   int64_t fv_total, faces_total, pixels_total, capacity;
   int32_t tiles_total, items_total, tile_bits, tile_passes, scan_blocks, parts_fv, parts_inst;

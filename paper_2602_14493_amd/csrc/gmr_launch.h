@@ -12,23 +12,24 @@ namespace gmr {
 // projects every face into every view of its mesh.
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
                     const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
-                    WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, hipStream_t s);
+                    WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, uint32_t* ranges, int64_t ranges_words,
+                    hipStream_t s);
 
 void launch_bin(const void* table, const uint4* el, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
                 WsHdr* hdr, uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0,
                 uint32_t desc0_words, hipStream_t s);
 
-void launch_sort_digits(const uint32_t* hist, uint32_t* dig, int row0, int rows, int radix, hipStream_t s);
-void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* dig, uint32_t* desc_cur,
+void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* hist, uint32_t* desc_cur,
                          uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int shift, hipStream_t s);
 void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
-                           uint32_t cap, const uint32_t* dig, uint32_t* desc_cur, uint32_t* desc_next,
+                           uint32_t cap, const uint32_t* hist, uint32_t* desc_cur, uint32_t* desc_next,
                            uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, hipStream_t s);
-void launch_tile_ranges(const uint32_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int64_t tiles_total,
-                        int blocks, hipStream_t s);
+void launch_tile_ranges(const uint32_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int blocks, hipStream_t s);
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float val, hipStream_t s);
+// zeroes the backward counters of hdr and dfv[0, n)
+void launch_bwd_prologue(WsHdr* hdr, float* dfv, int64_t n, hipStream_t s);
 
 void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists, const uint32_t* ranges,
                        const uint32_t* vals,

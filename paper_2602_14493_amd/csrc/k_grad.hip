@@ -190,6 +190,18 @@ __global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = val;
 }
 
+// Start of a backward: the workspace's backward counters and, unless a rebuild of the lists has
+// already cleared them, the face-view gradient accumulators.
+__global__ __launch_bounds__(256) void k_bwd_prologue(WsHdr* __restrict__ hdr, float* __restrict__ dfv, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t; i < n; i += (int64_t)gridDim.x * blockDim.x) dfv[i] = 0.f;
+  if (t == 0) {
+    hdr->work_bwd = 0u;
+    hdr->loss = 0.f;
+    hdr->pairs_bwd = 0ull;
+  }
+}
+
 // Adam with bias correction; t = step + 1 is read from the device (advanced by k_adam_tick).
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                                               float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
@@ -228,6 +240,12 @@ void launch_fill_f32(float* p, int64_t n, float val, hipStream_t s) {
   int64_t nb = (n + 255) / 256;
   if (nb > 8192) nb = 8192;
   hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)nb), dim3(256), 0, s, p, n, val);
+}
+
+void launch_bwd_prologue(WsHdr* hdr, float* dfv, int64_t n, hipStream_t s) {
+  int64_t nb = (n + 255) / 256;
+  nb = nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);
+  hipLaunchKernelGGL(k_bwd_prologue, dim3((unsigned)nb), dim3(256), 0, s, hdr, dfv, n);
 }
 
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,

@@ -99,10 +99,12 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
 
 // Clears the per-build counters, every histogram row and the first depth pass's descriptors.
 __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restrict__ hist,
-                                                  uint32_t* __restrict__ desc0, int64_t desc0_words) {
+                                                  uint32_t* __restrict__ desc0, int64_t desc0_words,
+                                                  uint32_t* __restrict__ ranges, int64_t ranges_words) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t; i < desc0_words; i += stride) desc0[i] = 0u;
+  for (int64_t i = t; i < ranges_words; i += stride) ranges[i] = 0u;  // empty tiles keep [0, 0)
   for (int64_t i = t; i < kMaxPasses * kHistStride; i += stride) hist[i] = 0u;
   if (t == 0) {
     for (int p = 0; p < kMaxPasses; ++p) hdr->part_ctr[p] = 0u;
@@ -114,10 +116,12 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
 
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
                     const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
-                    WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, hipStream_t s) {
-  int64_t pb = (desc0_words + 255) / 256;
+                    WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, uint32_t* ranges, int64_t ranges_words,
+                    hipStream_t s) {
+  int64_t pb = (std::max(desc0_words, ranges_words) + 255) / 256;
   pb = pb < 1 ? 1 : (pb > 4096 ? 4096 : pb);
-  hipLaunchKernelGGL(k_prologue, dim3((unsigned)pb), dim3(256), 0, s, hdr, hist, desc0, desc0_words);
+  hipLaunchKernelGGL(k_prologue, dim3((unsigned)pb), dim3(256), 0, s, hdr, hist, desc0, desc0_words, ranges,
+                     ranges_words);
   if (faces_total <= 0) return;
   const int bs = 256;
   const int64_t nb = (faces_total + bs - 1) / bs;

@@ -36,7 +36,7 @@ template <typename E, int kRadix, bool kSplit>
 __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ in, E* __restrict__ out,
                                                          uint32_t* __restrict__ out_k, uint32_t* __restrict__ out_v,
                                                          const uint32_t* __restrict__ n_dev, uint32_t n_max,
-                                                         const uint32_t* __restrict__ dig, uint32_t* desc_cur,
+                                                         const uint32_t* __restrict__ hist, uint32_t* desc_cur,
                                                          uint32_t* desc_next, uint32_t next_words, uint32_t* ticket,
                                                          int shift, uint32_t mask) {
   constexpr int kNW = kSortBlock / kWave;
@@ -46,6 +46,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   __shared__ uint32_t s_bstart[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
   __shared__ uint32_t s_wsum[kNW];
+  __shared__ uint32_t s_hsum[kNW];
   __shared__ uint32_t s_part;
 
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -58,7 +59,19 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   }
   if (threadIdx.x == 0) s_part = atomicAdd(ticket, 1u);
   for (int i = threadIdx.x; i < kNW * kRadix; i += kSortBlock) (&s_wcnt[0][0])[i] = 0u;
+  // global start of this thread's digit: exclusive scan of the pass's digit histogram
+  const int d = threadIdx.x;
+  const uint32_t hcount = d < kRadix ? hist[d] : 0u;
+  uint32_t hinc = hcount;
+#pragma unroll
+  for (int s = 1; s < kWave; s <<= 1) {
+    const uint32_t y = __shfl_up(hinc, s, kWave);
+    if (lane >= s) hinc += y;
+  }
+  if (lane == kWave - 1) s_hsum[w] = hinc;
   __syncthreads();
+  uint32_t dig_d = hinc - hcount;
+  for (int ww = 0; ww < w; ++ww) dig_d += s_hsum[ww];
   const uint32_t n = n_dev ? min(*n_dev, n_max) : n_max;
   const uint32_t part = s_part;
   const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
@@ -100,7 +113,6 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
 
   // ---- per digit: wavefront-exclusive offsets, publish, look back
   uint32_t tot = 0;
-  const int d = threadIdx.x;
   if (d < kRadix) {
     for (int ww = 0; ww < kNW; ++ww) {
       const uint32_t c = s_wcnt[ww][d];
@@ -124,7 +136,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
       }
       desc_store(my, kFlagInc | (excl + tot));
     }
-    s_gbase[d] = dig[d] + excl;
+    s_gbase[d] = dig_d + excl;
   }
   // block-local exclusive scan of the digit totals (threads >= kRadix contribute 0)
   {
@@ -163,27 +175,6 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
     } else {
       out[g] = x;
     }
-  }
-}
-
-// Exclusive scan of `rows` histograms of `radix` bins: dig[r][b] = sum of hist[r][< b].
-__global__ __launch_bounds__(512) void k_sort_digits(const uint32_t* __restrict__ hist, uint32_t* __restrict__ dig,
-                                                     int row0, int rows, int radix) {
-  __shared__ uint32_t s_w[512 / kWave];
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  for (int r = row0; r < row0 + rows; ++r) {
-    const uint32_t x = threadIdx.x < radix ? hist[r * kHistStride + threadIdx.x] : 0u;
-    uint32_t inc = x;
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint32_t y = __shfl_up(inc, d, kWave);
-      if (lane >= d) inc += y;
-    }
-    if (lane == kWave - 1) s_w[w] = inc;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int k = 0; k < w; ++k) before += s_w[k];
-    if (threadIdx.x < radix) dig[r * kHistStride + threadIdx.x] = before + inc - x;
-    __syncthreads();
   }
 }
 
@@ -230,20 +221,16 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)nb), dim3(256), 0, s, p, n, val);
 }
 
-void launch_sort_digits(const uint32_t* hist, uint32_t* dig, int row0, int rows, int radix, hipStream_t s) {
-  if (rows > 0) hipLaunchKernelGGL(k_sort_digits, dim3(1), dim3(512), 0, s, hist, dig, row0, rows, radix);
-}
-
-void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* dig, uint32_t* desc_cur,
+void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* hist, uint32_t* desc_cur,
                          uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int shift, hipStream_t s) {
   const uint32_t parts = (n + kSortPart - 1) / kSortPart;
   if (parts == 0) return;
   hipLaunchKernelGGL((k_onesweep<uint4, 256, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, nullptr, nullptr,
-                     nullptr, n, dig, desc_cur, desc_next, next_words, ticket, shift, 255u);
+                     nullptr, n, hist, desc_cur, desc_next, next_words, ticket, shift, 255u);
 }
 
 void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
-                           uint32_t cap, const uint32_t* dig, uint32_t* desc_cur, uint32_t* desc_next,
+                           uint32_t cap, const uint32_t* hist, uint32_t* desc_cur, uint32_t* desc_next,
                            uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, hipStream_t s) {
   const uint32_t parts = (cap + kSortPart - 1) / kSortPart;
   if (parts == 0) return;
@@ -251,23 +238,22 @@ void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_
   if (mask <= 255u) {
     if (out_k)
       hipLaunchKernelGGL((k_onesweep<uint2, 256, true>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
-                         n_dev, cap, dig, desc_cur, desc_next, next_words, ticket, shift, mask);
+                         n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask);
     else
       hipLaunchKernelGGL((k_onesweep<uint2, 256, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
-                         n_dev, cap, dig, desc_cur, desc_next, next_words, ticket, shift, mask);
+                         n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask);
     return;
   }
   if (out_k)
     hipLaunchKernelGGL((k_onesweep<uint2, 512, true>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v, n_dev,
-                       cap, dig, desc_cur, desc_next, next_words, ticket, shift, mask);
+                       cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask);
   else
     hipLaunchKernelGGL((k_onesweep<uint2, 512, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
-                       n_dev, cap, dig, desc_cur, desc_next, next_words, ticket, shift, mask);
+                       n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask);
 }
 
-void launch_tile_ranges(const uint32_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int64_t tiles_total, int blocks,
-                        hipStream_t s) {
-  launch_fill_u32(ranges, 2 * tiles_total, 0u, s);
+// ranges[] was zeroed by the list-building prologue (tiles without instances stay [0, 0)).
+void launch_tile_ranges(const uint32_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_tile_ranges, dim3(blocks), dim3(256), 0, s, sorted_keys, hdr, ranges);
 }
 
