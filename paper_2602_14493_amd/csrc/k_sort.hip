@@ -123,16 +123,31 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
     desc_store(my, (part == 0 ? kFlagInc : kFlagAgg) | tot);
     uint32_t excl = 0;
     if (part > 0) {
+      // look back kLook predecessors at a time (all loads in flight together), consuming them in
+      // order until an inclusive prefix; an empty descriptor ends the window and is read again
+      constexpr int kLook = 8;
       int j = (int)part - 1;
       while (true) {
-        const uint32_t x = desc_load(desc_cur + (size_t)j * kRadix + d);
-        if ((x & ~kValMask) == 0u) {
-          __builtin_amdgcn_s_sleep(1);
-          continue;
+        uint32_t x[kLook];
+#pragma unroll
+        for (int i = 0; i < kLook; ++i)  // below partition 0 (never reached: it is inclusive) read nothing
+          x[i] = j - i >= 0 ? desc_load(desc_cur + (size_t)(j - i) * kRadix + d) : kFlagInc;
+        int used = 0;
+        bool done = false, empty = false;
+#pragma unroll
+        for (int i = 0; i < kLook; ++i) {
+          if (done || empty) continue;
+          if ((x[i] & ~kValMask) == 0u) {
+            empty = true;
+            continue;
+          }
+          excl += x[i] & kValMask;
+          ++used;
+          done = (x[i] & kFlagInc) != 0u;
         }
-        excl += x & kValMask;
-        if (x & kFlagInc) break;
-        --j;
+        if (done) break;
+        j -= used;
+        if (empty) __builtin_amdgcn_s_sleep(1);
       }
       desc_store(my, kFlagInc | (excl + tot));
     }
