@@ -507,7 +507,7 @@ __device__ inline float wave_reduce8_transpose(const float (&g)[8], int lane) {
 }
 
 // One record's adjoint over a lane's PX pixels (summed into gr); `valid` = false is a no-op.
-// Returns whether any of the lane's pixels composited it.
+// Returns (wave-uniformly) whether any pixel of the wavefront composited it.
 template <int PX>
 __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, const float4& a2, bool valid,
                                          uint32_t prel, int x, float px, const int (&y)[PX], float amin, float amax,
@@ -516,7 +516,7 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
                                          float (&S)[PX], float (&gr)[8], unsigned long long& pairs) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) gr[i] = 0.f;
-  bool contrib = false;
+  bool contrib = false;  // wave-uniform: some pixel composited the Gaussian
   const bool inx = valid && in_range(f2u(a1.w), x);
   const float dx = (a0.x - px) + a0.z;
   const uint32_t ry = f2u(a2.w);
@@ -525,15 +525,16 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
     const bool act = prel < last[k] && inx && in_range(ry, y[k]);
     // wave-uniform skips: no pixel of the row group inside the extent (before its stop), or none
     // whose alpha reaches the cutoff -- then T, S and every partial are unchanged
-    if (__ballot(act) == 0ull) continue;
+    const uint64_t actm = __ballot(act);
+    if (actm == 0ull) continue;
     const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
     float w1, w2;
     const float e = gauss_exp(a1, dx, dy, w1, w2);
     const float al = fminf(amax, e);
     const bool ok = act && al >= amin;
-    const uint64_t okm = __ballot(ok);
+    const uint64_t okm = actm & __ballot(al >= amin);  // ballot of the compare alone stays a scalar mask
     if (okm == 0ull) continue;
-    contrib |= ok;
+    contrib = true;
     pairs += (unsigned long long)__popcll(okm);  // wave-uniform, scalar unit
     const float rom = __builtin_amdgcn_rcpf(1.f - al);  // 1 - al >= 1 - alpha_max > 0
     const float Tk = T[k] * rom;
@@ -588,11 +589,11 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
                                  gc0, gc1, gc2, K, last, T, S, gr, pairs);
     const bool c2 = bwd_eval<PX>(b0, b1, b2, has2, (uint32_t)(hi - 1 - j2 - (int64_t)start), g.x, px, y, amin, amax,
                                  gc0, gc1, gc2, K, last, T, S, gq, pairs);
-    if (__ballot(c1) != 0ull) {
+    if (c1) {
       const float r = wave_reduce8_transpose(gr, lane);
       if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id1 + (lane >> 3), r);
     }
-    if (__ballot(c2) != 0ull) {
+    if (c2) {
       const float r = wave_reduce8_transpose(gq, lane);
       if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id2 + (lane >> 3), r);
     }
