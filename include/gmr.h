@@ -191,14 +191,13 @@ gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_opt
 /* Where the forward's tile lists live inside a workspace laid out for (batch, opt): byte offsets
  * of the tile ranges (uint32 [tiles][2] = start, end into the sorted instances), the sorted
  * instance values (uint32 [instance_capacity] face-view indices, sorted by (tile, float32 depth,
- * face-view)), the projected records (float32 [face-views][12]) and the face-view elements in
- * depth order (uint32 [face-views][4]: float32 depth bits, face-view, first tile,
- * nx | ny << 16 tiles covered; culled face-views have nx = ny = 0).  Tiles of
- * view v are numbered from the sum of the earlier views' tile counts, row-major.  Face-views of
- * view v are numbered from the sum of the earlier views' face counts, in face order.  Pure host
- * arithmetic; the contents are valid after gmr_render_fwd (or a recomputing gmr_render_bwd). */
+ * face-view)), the projected records (float32 [face-views][12]) and the sorted instance keys
+ * (uint32 [instance_capacity] global tile ids).  Tiles of view v are numbered from the sum of the
+ * earlier views' tile counts, row-major.  Face-views of view v are numbered from the sum of the
+ * earlier views' face counts, in face order.  Pure host arithmetic; the contents are valid after
+ * gmr_render_fwd (or a recomputing gmr_render_bwd). */
 gmr_status gmr_workspace_view(const gmr_batch* batch, const gmr_options* opt, size_t* ranges_off, size_t* vals_off,
-                              size_t* rec_off, size_t* bin_off);
+                              size_t* rec_off, size_t* keys_off);
 
 /* Reads the workspace's device counters (synchronises `stream`).  Not capturable. */
 gmr_status gmr_read_counters(const void* ws_dev, size_t ws_bytes, gmr_counters* out_host, void* stream);

@@ -336,8 +336,8 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
     StageTimer t(h, s, kStSortFv);
     const bool odd = pass & 1;
     launch_sort_fv_pass(odd ? w.elB : w.elA, odd ? w.elA : w.elB, (uint32_t)p.fv_total, w.hist + pass * kHistStride,
-                        odd ? w.descF1 : w.descF0, odd ? w.descF0 : w.descF1, fv_words, &w.hdr->part_ctr[pass], 8 * pass,
-                        s);
+                        odd ? w.descF1 : w.descF0, odd ? w.descF0 : w.descF1, fv_words, &w.hdr->part_ctr[pass], pass,
+                        w.hdr, s);
   }
   TilePasses tp;
   tp.n = L.tile_passes;
@@ -347,7 +347,7 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   }
   {
     StageTimer t(h, s, kStScanEmit);
-    launch_bin(table, w.elA, p.fv_total, L.scan_items, w.bsum, w.boff, L.scan_blocks, w.hdr, (uint32_t)L.capacity,
+    launch_bin(table, w.elA, w.elB, p.fv_total, L.scan_items, w.bsum, w.boff, L.scan_blocks, w.hdr, (uint32_t)L.capacity,
                w.instA, w.hist, tp, w.descI0, inst_words, s);
   }
   // tile digits on the instances: A -> B -> A ..., the last pass writes keysF / valsF
@@ -610,15 +610,15 @@ gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_opt
 }
 
 gmr_status gmr_workspace_view(const gmr_batch* batch, const gmr_options* opt, size_t* ranges_off, size_t* vals_off,
-                              size_t* rec_off, size_t* bin_off) {
-  if (!ranges_off || !vals_off || !rec_off || !bin_off) return fail(GMR_ERR_INVALID_ARG, "output pointer is NULL");
+                              size_t* rec_off, size_t* keys_off) {
+  if (!ranges_off || !vals_off || !rec_off || !keys_off) return fail(GMR_ERR_INVALID_ARG, "output pointer is NULL");
   Plan p;
   gmr_status st = make_plan(batch, opt, true, p);
   if (st != GMR_OK) return st;
   *ranges_off = p.L.ranges;
   *vals_off = p.L.valsF;
   *rec_off = p.L.rec;
-  *bin_off = p.L.elA;
+  *keys_off = p.L.keysF;
   return GMR_OK;
 }
 

@@ -67,9 +67,18 @@ struct WsHdr {                 // 256 B at the start of the workspace
   float loss;                      // L2 loss value of the last fused backward
   uint32_t pad0;
   unsigned long long pairs_bwd;    // (pixel, Gaussian) pairs the backward differentiated
-  uint32_t pad1[44];
+  uint32_t key_hi_min, key_hi_max; // range of the high 16 depth-key bits over visible face-views
+  uint32_t pad1[42];
 };
 static_assert(sizeof(WsHdr) == 256, "ws header");
+
+// When the visible face-views' depth keys span fewer than 256 values of their high 16 bits, the
+// third depth pass sorts on (key >> 16) - key_hi_min (one 8-bit digit that orders them exactly)
+// and the fourth pass is skipped; the sorted elements then end in the second element buffer.
+// Culled face-views (key 0xffffffff, no instances) may land anywhere: they emit nothing.
+__device__ inline bool depth_keys_narrow(const WsHdr* h) {
+  return h->key_hi_max >= h->key_hi_min && h->key_hi_max - h->key_hi_min < 256u;
+}
 
 // Kernel-side options (plain values) ---------------------------------------------------------------
 struct KOpts {

@@ -15,12 +15,13 @@ void launch_project(const void* table, int64_t faces_total, const float* verts, 
                     WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, uint32_t* ranges, int64_t ranges_words,
                     hipStream_t s);
 
-void launch_bin(const void* table, const uint4* el, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
+void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
                 WsHdr* hdr, uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0,
                 uint32_t desc0_words, hipStream_t s);
 
 void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* hist, uint32_t* desc_cur,
-                         uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int shift, hipStream_t s);
+                         uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int pass, const WsHdr* hdr,
+                         hipStream_t s);
 void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
                            uint32_t cap, const uint32_t* hist, uint32_t* desc_cur, uint32_t* desc_next,
                            uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, hipStream_t s);

@@ -30,9 +30,11 @@ __device__ inline uint32_t wave_sum(uint32_t x) {
 }
 
 template <int kItems>
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint4* __restrict__ el, int64_t n,
-                                                            uint32_t* __restrict__ bsum) {
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint4* __restrict__ el_a,
+                                                            const uint4* __restrict__ el_b, const WsHdr* __restrict__ hdr,
+                                                            int64_t n, uint32_t* __restrict__ bsum) {
   __shared__ uint32_t s_w[kScanBlock / kWave];
+  const uint4* __restrict__ el = depth_keys_narrow(hdr) ? el_b : el_a;  // where the depth passes ended
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int64_t base = (int64_t)blockIdx.x * (kScanBlock * kItems) + (int64_t)w * (kItems * kWave) + lane;
   uint32_t acc = 0;
@@ -90,10 +92,12 @@ __global__ __launch_bounds__(1024) void k_scan_top(const uint32_t* __restrict__ 
 }
 
 template <int kItems>
-__global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ table, const uint4* __restrict__ el, int64_t n,
+__global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ table, const uint4* __restrict__ el_a,
+                                                     const uint4* __restrict__ el_b, int64_t n,
                                                      const uint64_t* __restrict__ boff, const WsHdr* __restrict__ hdr,
                                                      uint2* __restrict__ inst, uint32_t* __restrict__ hist, TilePasses tp,
                                                      uint32_t* __restrict__ desc0, uint32_t desc0_words) {
+  const uint4* __restrict__ el = depth_keys_narrow(hdr) ? el_b : el_a;  // where the depth passes ended
   __shared__ uint32_t s_w[kScanBlock / kWave];
   __shared__ uint32_t s_h[kMaxPasses - kTileRow0][kHistStride];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -146,21 +150,21 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
     if ((&s_h[0][0])[i]) atomicAdd(&hist[kTileRow0 * kHistStride + i], (&s_h[0][0])[i]);
 }
 
-void launch_bin(const void* table, const uint4* el, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
+void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
                 WsHdr* hdr, uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0,
                 uint32_t desc0_words, hipStream_t s) {
   const bool large = items == kScanItemsLarge;
   if (nb > 0) {
-    if (large) hipLaunchKernelGGL(k_scan_reduce<kScanItemsLarge>, dim3(nb), dim3(kScanBlock), 0, s, el, n, bsum);
-    else hipLaunchKernelGGL(k_scan_reduce<kScanItemsSmall>, dim3(nb), dim3(kScanBlock), 0, s, el, n, bsum);
+    if (large) hipLaunchKernelGGL(k_scan_reduce<kScanItemsLarge>, dim3(nb), dim3(kScanBlock), 0, s, el_a, el_b, hdr, n, bsum);
+    else hipLaunchKernelGGL(k_scan_reduce<kScanItemsSmall>, dim3(nb), dim3(kScanBlock), 0, s, el_a, el_b, hdr, n, bsum);
   }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, boff, hdr, cap);
   if (nb > 0) {
     if (large)
-      hipLaunchKernelGGL(k_emit<kScanItemsLarge>, dim3(nb), dim3(kScanBlock), 0, s, table, el, n, boff, hdr, inst, hist,
+      hipLaunchKernelGGL(k_emit<kScanItemsLarge>, dim3(nb), dim3(kScanBlock), 0, s, table, el_a, el_b, n, boff, hdr, inst, hist,
                          tp, desc0, desc0_words);
     else
-      hipLaunchKernelGGL(k_emit<kScanItemsSmall>, dim3(nb), dim3(kScanBlock), 0, s, table, el, n, boff, hdr, inst, hist,
+      hipLaunchKernelGGL(k_emit<kScanItemsSmall>, dim3(nb), dim3(kScanBlock), 0, s, table, el_a, el_b, n, boff, hdr, inst, hist,
                          tp, desc0, desc0_words);
   }
 }

@@ -8,7 +8,8 @@
 //   el[fv]   uint4 = 16 B      {float32 depth bits, fv, first tile, nx | ny << 16}: the element the
 //                              depth passes of the radix sort move (culled: nx = ny = 0)
 // and adds each element's four 8-bit depth digits to the sort's histograms (LDS, then one global
-// atomic per bin and workgroup).
+// atomic per bin and workgroup), and the range of the visible keys' high 16 bits to the workspace
+// header (per-thread, then one atomic pair per wavefront).
 // The mean stays in double until it is split into two floats: a float32 pixel coordinate near
 // x = 1920 carries ~1e-4 px of rounding, which alone would move alpha by ~1e-4.
 #include "gmr_common.h"
@@ -19,7 +20,7 @@ namespace gmr {
 __device__ inline void project_face(const TableHdr* th, const void* __restrict__ table, const float* __restrict__ verts,
                                     const int32_t* __restrict__ faces, const float* __restrict__ colors, const KOpts& o,
                                     float4* __restrict__ rec, uint4* __restrict__ el, uint32_t* s_h,
-                                    float4* __restrict__ dfv_zero, int64_t f) {
+                                    uint32_t& kmin, uint32_t& kmax, float4* __restrict__ dfv_zero, int64_t f) {
   const int32_t* mfo = table_i32(table, th->mesh_face_off);
   const int32_t* mvo = table_i32(table, th->mesh_view_off);
   const int32_t* mvs = table_i32(table, th->mesh_views_off);
@@ -70,6 +71,8 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
         r[2] = make_float4(col[0], col[1], col[2], u2f((uint32_t)iy0 | ((uint32_t)iy1 << 16)));
         e = make_uint4(f2u((float)q.p[2]), (uint32_t)fv, (uint32_t)(V.tile_base + ty0 * V.tiles_x + tx0),
                        (uint32_t)nx | ((uint32_t)ny << 16));
+        kmin = min(kmin, e.x >> 16);
+        kmax = max(kmax, e.x >> 16);
       }
     }
     el[fv] = e;
@@ -85,13 +88,24 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
 __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table, const float* __restrict__ verts,
                                                  const int32_t* __restrict__ faces, const float* __restrict__ colors,
                                                  KOpts o, float4* __restrict__ rec, uint4* __restrict__ el,
-                                                 uint32_t* __restrict__ hist, float4* __restrict__ dfv_zero) {
+                                                 uint32_t* __restrict__ hist, WsHdr* __restrict__ hdr,
+                                                 float4* __restrict__ dfv_zero) {
   __shared__ uint32_t s_h[kDepthPasses * 256];
   for (int i = threadIdx.x; i < kDepthPasses * 256; i += blockDim.x) s_h[i] = 0u;
   __syncthreads();
   const TableHdr* th = static_cast<const TableHdr*>(table);
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f < th->faces_total) project_face(th, table, verts, faces, colors, o, rec, el, s_h, dfv_zero, f);
+  uint32_t kmin = 0xffffffffu, kmax = 0u;  // high 16 key bits of this thread's visible face-views
+  if (f < th->faces_total) project_face(th, table, verts, faces, colors, o, rec, el, s_h, kmin, kmax, dfv_zero, f);
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, kWave));
+    kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d, kWave));
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0 && kmin <= kmax) {
+    atomicMin(&hdr->key_hi_min, kmin);
+    atomicMax(&hdr->key_hi_max, kmax);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < kDepthPasses * 256; i += blockDim.x)
     if (s_h[i]) atomicAdd(&hist[(i >> 8) * kHistStride + (i & 255)], s_h[i]);
@@ -111,6 +125,8 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
     hdr->work_fwd = 0u;
     hdr->work_bwd = 0u;
     hdr->pairs_fwd = 0ull;
+    hdr->key_hi_min = 0xffffffffu;
+    hdr->key_hi_max = 0u;
   }
 }
 
@@ -125,7 +141,7 @@ void launch_project(const void* table, int64_t faces_total, const float* verts, 
   if (faces_total <= 0) return;
   const int bs = 256;
   const int64_t nb = (faces_total + bs - 1) / bs;
-  hipLaunchKernelGGL(k_project, dim3((unsigned)nb), dim3(bs), 0, s, table, verts, faces, colors, o, rec, el, hist,
+  hipLaunchKernelGGL(k_project, dim3((unsigned)nb), dim3(bs), 0, s, table, verts, faces, colors, o, rec, el, hist, hdr,
                      dfv_zero);
 }
 

@@ -6,7 +6,10 @@
 // first tile, nx | ny << 16}); emission then walks face-views in depth order, and the tile digits
 // are sorted on the instances (uint2 {tile, face-view}, passes of up to 9 bits).  The result is the
 // stable sort of the instances by (tile, float32 depth, face-view), i.e. ties in depth broken by
-// ascending global id, with far fewer bytes moved than sorting 64-bit keys per instance.
+// ascending global id, with far fewer bytes moved than sorting 64-bit keys per instance.  When the
+// visible face-views' keys span fewer than 256 values of their high 16 bits (depths within a
+// factor of ~3.7, the usual object-centric view), the third depth pass sorts on the offset
+// (key >> 16) - min, which orders those bits exactly, and the fourth pass exits at once.
 //
 // k_onesweep (one launch per pass): each workgroup takes a partition ticket, so every earlier
 // partition is already resident; it loads its 4096 elements, ranks them stably in LDS with
@@ -15,7 +18,7 @@
 // descriptors, stages the elements in LDS in digit order and writes them out in coalesced runs.
 // Descriptor word: bits 31..30 = {0 empty, 1 aggregate, 2 inclusive prefix}, bits 29..0 = count,
 // so a single 32-bit atomic load observes flag and value together.  Each pass also clears its
-// share of the descriptor buffer the next pass will use.
+// share of the descriptor buffer the next pass will use, and scans its own digit histogram.
 #include "gmr_common.h"
 #include "gmr_launch.h"
 
@@ -38,7 +41,8 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
                                                          const uint32_t* __restrict__ n_dev, uint32_t n_max,
                                                          const uint32_t* __restrict__ hist, uint32_t* desc_cur,
                                                          uint32_t* desc_next, uint32_t next_words, uint32_t* ticket,
-                                                         int shift, uint32_t mask) {
+                                                         int shift, uint32_t mask, const WsHdr* range_hdr,
+                                                         int depth_pass) {
   constexpr int kNW = kSortBlock / kWave;
   constexpr int kBits = kRadix == 256 ? 8 : 9;
   __shared__ E s_el[kSortPart];
@@ -50,6 +54,12 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   __shared__ uint32_t s_part;
 
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  // narrow depth range: the third depth pass sorts on (key >> 16) - key_hi_min, the fourth is void
+  uint32_t sub = 0u;
+  if (range_hdr && depth_pass >= 2 && depth_keys_narrow(range_hdr)) {
+    if (depth_pass == 3) return;
+    sub = range_hdr->key_hi_min;
+  }
   // clear this workgroup's slice of the next pass's descriptors (every workgroup, before any exit)
   {
     const uint32_t chunk = (next_words + gridDim.x - 1) / gridDim.x;
@@ -61,7 +71,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   for (int i = threadIdx.x; i < kNW * kRadix; i += kSortBlock) (&s_wcnt[0][0])[i] = 0u;
   // global start of this thread's digit: exclusive scan of the pass's digit histogram
   const int d = threadIdx.x;
-  const uint32_t hcount = d < kRadix ? hist[d] : 0u;
+  const uint32_t hcount = d < kRadix ? hist[sub ? ((uint32_t)d + sub) & 0xffu : (uint32_t)d] : 0u;
   uint32_t hinc = hcount;
 #pragma unroll
   for (int s = 1; s < kWave; s <<= 1) {
@@ -93,7 +103,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   for (int i = 0; i < kSortItems; ++i) {
     const uint32_t idx = base + (uint32_t)w * (kSortItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
     const bool have = idx < n;
-    const uint32_t d = (elem_key(e[i]) >> shift) & mask;
+    const uint32_t d = ((elem_key(e[i]) >> shift) - sub) & mask;
     uint64_t peers = __ballot(have);
 #pragma unroll
     for (int b = 0; b < kBits; ++b) {
@@ -174,7 +184,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   for (int i = 0; i < kSortItems; ++i) {
     const uint32_t idx = base + (uint32_t)w * (kSortItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
     if (idx < n) {
-      const uint32_t dd = (elem_key(e[i]) >> shift) & mask;
+      const uint32_t dd = ((elem_key(e[i]) >> shift) - sub) & mask;
       s_el[s_bstart[dd] + s_wcnt[w][dd] + rank[i]] = e[i];
     }
   }
@@ -182,7 +192,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   const uint32_t nb = min((uint32_t)kSortPart, n - base);
   for (uint32_t s = threadIdx.x; s < nb; s += kSortBlock) {
     const E x = s_el[s];
-    const uint32_t dd = (elem_key(x) >> shift) & mask;
+    const uint32_t dd = ((elem_key(x) >> shift) - sub) & mask;
     const uint32_t g = s_gbase[dd] + (s - s_bstart[dd]);
     if constexpr (kSplit) {
       out_k[g] = elem_key(x);
@@ -237,11 +247,12 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s) {
 }
 
 void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* hist, uint32_t* desc_cur,
-                         uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int shift, hipStream_t s) {
+                         uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int pass, const WsHdr* hdr,
+                         hipStream_t s) {
   const uint32_t parts = (n + kSortPart - 1) / kSortPart;
   if (parts == 0) return;
   hipLaunchKernelGGL((k_onesweep<uint4, 256, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, nullptr, nullptr,
-                     nullptr, n, hist, desc_cur, desc_next, next_words, ticket, shift, 255u);
+                     nullptr, n, hist, desc_cur, desc_next, next_words, ticket, 8 * pass, 255u, hdr, pass);
 }
 
 void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
@@ -253,18 +264,18 @@ void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_
   if (mask <= 255u) {
     if (out_k)
       hipLaunchKernelGGL((k_onesweep<uint2, 256, true>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
-                         n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask);
+                         n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
     else
       hipLaunchKernelGGL((k_onesweep<uint2, 256, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
-                         n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask);
+                         n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
     return;
   }
   if (out_k)
     hipLaunchKernelGGL((k_onesweep<uint2, 512, true>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v, n_dev,
-                       cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask);
+                       cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
   else
     hipLaunchKernelGGL((k_onesweep<uint2, 512, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
-                       n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask);
+                       n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
 }
 
 // ranges[] was zeroed by the list-building prologue (tiles without instances stay [0, 0)).

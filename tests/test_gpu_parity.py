@@ -149,6 +149,48 @@ def test_tile_lists_bit_exact(gpu, tile):
     assert checked > 100000
 
 
+def test_tile_lists_and_image_wide_depth_range(gpu):
+    """A camera 0.3 units from the surface and one at radius 3: the visible depths span 0.3 .. 4,
+    more than the 256 values of the high 16 key bits that let the depth sort take three passes, so
+    this checks the four-pass path (lists bit-exact, image against the oracle); the narrow range of
+    the other workloads checks the three-pass path."""
+    W2 = wl.make_workload(2)
+    cams = [wl.look_at_camera((0.0, 0.0, 1.3), width=256, height=256),
+            wl.look_at_camera((1.2, 2.0, 2.0), width=256, height=256)]
+    W = wl._single("icosphere_s5_near_far", W2.verts, W2.faces, W2.colors, cams)
+    ca = W.cam_array()
+    his = []
+    for v in range(W.num_views):
+        G = oracle.gaussians(W.verts, W.faces, W.colors, ca[v])
+        depth = G[G[:, 0] > 0, 8].astype(np.float32)
+        his.append(depth.view(np.uint32) >> 16)
+    his = np.concatenate(his)
+    assert int(his.max()) - int(his.min()) >= 256, "the scene must exercise the four-pass depth sort"
+    say(f"wide depth range: high key bits span {int(his.max()) - int(his.min())}")
+    r, verts, colors = gpu_setup(W, tile_w=16, tile_h=16)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W)
+    compare_images(rgb, alpha, o_rgb, o_tf, o_mask, label="wide depth")
+    ranges, vals = workspace_lists(r, ws)
+    conv = fv_to_face(W)
+    tbase, checked = 0, 0
+    for v in range(W.num_views):
+        off, ids, amb = oracle.tile_lists_view(W.verts, W.faces, W.colors, ca[v], 16, 16)
+        nt = len(off) - 1
+        for t in range(nt):
+            s, e = ranges[tbase + t]
+            vv, gl = conv(vals[s:e])
+            assert (vv == v).all()
+            o_ids, o_amb = ids[off[t]:off[t + 1]], amb[off[t]:off[t + 1]]
+            ambiguous = set(o_ids[o_amb != 0].tolist())
+            want = [i for i, a in zip(o_ids.tolist(), o_amb.tolist()) if a == 0]
+            assert [i for i in gl.tolist() if i not in ambiguous] == want, f"view {v} tile {t}"
+            checked += len(want)
+        tbase += nt
+    say(f"checked {checked} list entries")
+    assert checked > 10000
+
+
 # ------------------------------------------------------------------------------------------------
 # GPU invariants
 # ------------------------------------------------------------------------------------------------
