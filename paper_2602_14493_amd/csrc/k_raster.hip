@@ -307,30 +307,37 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
   }
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
-    uint64_t m = done[k] ? 0ull : mine[k];
+    const uint64_t mk = done[k] ? 0ull : mine[k];
+    // every slot of the lane's list is evaluated unless the pixel stops first (subtracted below)
+    pairs += (uint32_t)__popcll(mk);
     const float py = (float)y[k] + 0.5f;
-    while (m) {
-      const int j = ctz64(m);
-      m &= m - 1;
-      const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
-      const float dx = (a0.x - px) + a0.z;
-      const float dy = (a0.y - py) + a0.w;
-      float w1, w2;
-      const float e = gauss_exp(a1, dx, dy, w1, w2);
-      const float al = fminf(amax, e);
-      ++pairs;
-      if (al >= amin) {
-        const float Tn = T[k] * (1.f - al);
-        if (Tn < teps) {
-          done[k] = true;
-          m = 0ull;
-        } else {
-          const float wt = al * T[k];
-          C0[k] = fmaf(a2.x, wt, C0[k]);
-          C1[k] = fmaf(a2.y, wt, C1[k]);
-          C2[k] = fmaf(a2.z, wt, C2[k]);
-          T[k] = Tn;
-          last[k] = s_pos[j];
+    // the two 32-slot halves are walked with 32-bit masks (one find-first-set per step)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint32_t m = done[k] ? 0u : (uint32_t)(mk >> (32 * h));
+      while (m) {
+        const int j = 32 * h + __builtin_ctz(m);
+        m &= m - 1u;
+        const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
+        const float dx = (a0.x - px) + a0.z;
+        const float dy = (a0.y - py) + a0.w;
+        float w1, w2;
+        const float e = gauss_exp(a1, dx, dy, w1, w2);
+        const float al = fminf(amax, e);
+        if (al >= amin) {
+          const float Tn = T[k] * (1.f - al);
+          if (Tn < teps) {
+            done[k] = true;
+            pairs -= (uint32_t)__popc(m) + (h == 0 ? (uint32_t)__popc((uint32_t)(mk >> 32)) : 0u);
+            m = 0u;
+          } else {
+            const float wt = al * T[k];
+            C0[k] = fmaf(a2.x, wt, C0[k]);
+            C1[k] = fmaf(a2.y, wt, C1[k]);
+            C2[k] = fmaf(a2.z, wt, C2[k]);
+            T[k] = Tn;
+            last[k] = s_pos[j];
+          }
         }
       }
     }
