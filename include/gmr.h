@@ -60,7 +60,8 @@ typedef struct gmr_options {
   float t_eps;               /* [1e-4] compositing stops before transmittance would fall below it */
   float bg[3];               /* [0,0,0] background colour                                         */
   int32_t tile_w, tile_h;    /* [16,16] binning tile in pixels: multiples of 8 in [8, 64]          */
-  int32_t raster_mode;       /* [0] 0: one workgroup per tile group; 1: persistent work queue     */
+  int32_t raster_mode;       /* [0] 0: one workgroup per 4 work items; 1: persistent grid (4
+                                workgroups per CU striding over the work items)                    */
   int32_t px_per_lane;       /* [1] pixels per lane in the rasteriser: 1, 2 or 4 (a wavefront then
                                 covers an 8 x 8*px_per_lane block); tile_h % (8*px_per_lane) == 0   */
   int32_t lane_lists;        /* [1] 1: the forward compositing walks per-lane lists -- each lane visits

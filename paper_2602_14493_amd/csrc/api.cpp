@@ -365,7 +365,8 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   }
 }
 
-int persistent_blocks(const gmr_ctx* h, const gmr_options* o) { return o->raster_mode == 1 ? h->num_cus * 8 : 0; }
+// Persistent schedule: 4 resident workgroups (16 wavefronts) per CU, a multiple of the 8 XCDs.
+int persistent_blocks(const gmr_ctx* h, const gmr_options* o) { return o->raster_mode == 1 ? h->num_cus * 4 : 0; }
 
 gmr_status check_launch() {
   hipError_t e = hipGetLastError();

@@ -62,7 +62,7 @@ struct WsHdr {                 // 256 B at the start of the workspace
   uint32_t capacity;
   uint32_t passes;
   uint32_t part_ctr[kMaxPasses];   // onesweep partition tickets, one per pass (same rows as the histograms)
-  uint32_t work_fwd, work_bwd;     // persistent raster queues
+  uint32_t work_fwd, work_bwd;     // unused (kept for the header layout)
   unsigned long long pairs_fwd;    // (pixel, Gaussian) pairs the forward evaluated
   float loss;                      // L2 loss value of the last fused backward
   uint32_t pad0;

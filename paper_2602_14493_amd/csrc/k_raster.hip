@@ -449,12 +449,13 @@ __global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int items = th->items_total;
   if (kPersistent) {
-    while (true) {
-      int item = 0;
-      if (lane == 0) item = (int)atomicAdd(&a.hdr->work_fwd, 1u);
-      item = __shfl(item, 0, kWave);
-      if (item >= items) break;
-      raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w], s_pos[kLanes ? w : 0]);
+    // grid-stride over groups of 4 items; the grid is a multiple of 8 blocks, so group v runs on
+    // XCD v mod 8 and xcd_remap keeps each XCD on a contiguous run of tiles
+    const int groups = (items + 3) / 4;
+    for (int v = (int)blockIdx.x; v < groups; v += (int)gridDim.x) {
+      const int item = xcd_remap(v, groups) * 4 + w;
+      if (item < items)
+        raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w], s_pos[kLanes ? w : 0]);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
@@ -691,12 +692,10 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   const BwdLds L{s_rec[w], s_id[w]};
   const int items = th->items_total;
   if (kPersistent) {
-    while (true) {
-      int item = 0;
-      if (lane == 0) item = (int)atomicAdd(&a.hdr->work_bwd, 1u);
-      item = __shfl(item, 0, kWave);
-      if (item >= items) break;
-      raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
+    const int groups = (items + 3) / 4;  // grid-stride, as in the forward
+    for (int v = (int)blockIdx.x; v < groups; v += (int)gridDim.x) {
+      const int item = xcd_remap(v, groups) * 4 + w;
+      if (item < items) raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
