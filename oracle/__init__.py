@@ -5,7 +5,8 @@ leg may use this package; the product path (``paper_2602_14493_amd``) never impo
 two share no code.  The arithmetic lives in ``gmr_oracle.cpp`` (see its header for what each
 function follows in the paper); this module only marshals arrays, builds the library with g++,
 and adds the plain L2 loss (Sec. 3.1, colour loss = mean squared error) and an FP64
-central-difference harness.
+central-difference harness.  ``oracle.recon`` holds the reconstruction step around the renderer
+(silhouette BCE, edge-length and Laplacian regularisers, VectorAdam), in NumPy float64.
 """
 from __future__ import annotations
 
