@@ -94,8 +94,8 @@ typedef struct gmr_counters {
   int32_t reserved;
   int64_t pairs_fwd;   /* (pixel, Gaussian) pairs the last forward evaluated inside extents   */
   int64_t pairs_bwd;   /* pairs the last backward differentiated (composited ones)           */
-  float loss;          /* loss value of the last fused L2 backward                           */
-  int32_t reserved2;
+  float loss;          /* colour loss of the last fused backward (L2 or reconstruction)       */
+  float loss_sil;      /* silhouette loss of the last gmr_render_bwd_recon (0 otherwise)      */
 } gmr_counters;
 
 typedef struct gmr_ctx* gmr_handle;
@@ -189,6 +189,23 @@ gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_opt
                              int32_t recompute_lists, float* d_verts_dev, float* d_colors_dev, float* loss_dev,
                              void* ws_dev, size_t ws_bytes, void* stream);
 
+/* The reconstruction objective's image terms (Sec. 3.1, Loss Functions): gmr_render_bwd_l2's colour
+ * loss (weight color_weight) plus the silhouette loss, color_weight * MSE(rgb, target) +
+ * sil_weight * mean over every pixel of every view of -(s log a + (1 - s) log(1 - a)), with
+ * a = 1 - T_final clamped to [1e-6, 1 - 1e-6] (the clamp is part of the loss: zero derivative
+ * where it is active) and s = mask_dev [P] f32 (a binary silhouette; any value in [0, 1] is
+ * accepted).  dL/d alpha is formed inside the backward kernel from the saved T_final.
+ * losses_dev (may be NULL) receives two f32: the colour loss and the silhouette loss, each with
+ * its weight applied.  Other arguments and errors as gmr_render_bwd_l2; rgb_dev, target_dev and
+ * mask_dev must not be NULL. */
+gmr_status gmr_render_bwd_recon(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table_dev,
+                                const float* verts_dev, const int32_t* faces_dev, const float* colors_dev,
+                                const float* rgb_dev, const float* target_dev, float color_weight,
+                                const float* mask_dev, float sil_weight, const void* saved_dev,
+                                const int32_t* adj_off_dev, const int32_t* adj_ent_dev, int32_t recompute_lists,
+                                float* d_verts_dev, float* d_colors_dev, float* losses_dev, void* ws_dev,
+                                size_t ws_bytes, void* stream);
+
 /* Where the forward's tile lists live inside a workspace laid out for (batch, opt): byte offsets
  * of the tile ranges (uint32 [tiles][2] = start, end into the sorted instances), the sorted
  * instance values (uint32 [instance_capacity] face-view indices, sorted by (tile, float32 depth,
@@ -214,8 +231,9 @@ gmr_status gmr_profile_enable(gmr_handle h, int32_t enable);
 
 /* Waits for the recorded events and returns, per stage, its name (names: max_stages x 32 chars),
  * the summed milliseconds and the number of timed launch groups; then discards the records.
- * Stages: project, scan_emit, sort_hist, sort_pass (one group per radix pass), tile_ranges,
- * raster_fwd, fill, raster_bwd, face_bwd, vertex_gather.  max_stages must be >= 10. */
+ * Stages: project, scan_emit, sort_fv_pass (the depth passes over face-views), sort_pass (the
+ * instance passes), tile_ranges, raster_fwd, fill, raster_bwd, face_bwd, vertex_gather,
+ * loss_reduce (the fused-loss backwards' fixed-order loss sum).  max_stages must be >= 11. */
 gmr_status gmr_profile_read(gmr_handle h, int32_t max_stages, char* names, float* ms_total, int32_t* launches,
                             int32_t* n_stages);
 
@@ -229,6 +247,48 @@ gmr_status gmr_profile_read(gmr_handle h, int32_t max_stages, char* names, float
  * step_dev: one int32 on the device, 0 before the first step. */
 gmr_status gmr_adam_step(float* param_dev, const float* grad_dev, float* m_dev, float* v_dev, int64_t n,
                          float lr, float beta1, float beta2, float eps, int32_t* step_dev, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Mesh regularisers and VectorAdam (Sec. 3.1, Implementation Details and Loss Functions): the
+ * rest of the reconstruction step around the renderer.  The paper names the edge-length and
+ * Laplacian-smoothing terms without formulas; the forms used are
+ *   edge     edge_weight / E * sum over unique edges (i, j) of (|v_i - v_j| - target_length)^2
+ *   Laplacian lap_weight / V * sum over vertices of |(1/deg i) sum over neighbours j of v_j - v_i|
+ * (uniform weights; neighbours share an edge; an isolated vertex contributes 0).
+ * ------------------------------------------------------------------------------------------- */
+
+/* Number of unique undirected edges of a triangle list (host).  faces_host [num_faces][3] global
+ * indices.  Errors: GMR_ERR_INVALID_ARG for an index outside [0, num_verts). */
+gmr_status gmr_mesh_graph_size(const int32_t* faces_host, int64_t num_faces, int64_t num_verts, int64_t* num_edges);
+
+/* Edge list and vertex -> incident-edge CSR (host): edges_host [num_edges][2] = (i, j), i < j,
+ * sorted lexicographically (degenerate face corners i == j are skipped); vedge_off_host
+ * [num_verts + 1]; vedge_ent_host [2 num_edges], entry = edge << 1 | side (side 0: the vertex is
+ * the edge's first end), ascending per vertex.  num_edges must be gmr_mesh_graph_size's value.
+ * Build once per topology and copy to the device for gmr_regularizers. */
+gmr_status gmr_build_mesh_graph(const int32_t* faces_host, int64_t num_faces, int64_t num_verts, int64_t num_edges,
+                                int32_t* edges_host, int32_t* vedge_off_host, int32_t* vedge_ent_host);
+
+/* Device scratch bytes gmr_regularizers needs (16 B per edge and per vertex, plus 8 B per 256 of
+ * each for the loss partials). */
+gmr_status gmr_regularizers_scratch_size(int64_t num_verts, int64_t num_edges, size_t* bytes);
+
+/* Adds the gradients of the two regularisers to d_verts_dev [V][3] (accumulates: call it after the
+ * render backward has written its gradient) and writes their values, weights applied, to
+ * losses_dev [2] f32 (edge, Laplacian).  Deterministic (no atomics; fixed summation order).  A weight
+ * of 0 skips its term.  Stream-ordered and capturable (no allocation, no memset node). */
+gmr_status gmr_regularizers(const float* verts_dev, int64_t num_verts, const int32_t* edges_dev, int64_t num_edges,
+                            const int32_t* vedge_off_dev, const int32_t* vedge_ent_dev, float target_length,
+                            float edge_weight, float lap_weight, void* scratch_dev, size_t scratch_bytes,
+                            float* losses_dev, float* d_verts_dev, void* stream);
+
+/* One VectorAdam step on num_verts 3-vectors (one second moment per vertex, on the squared norm
+ * of its gradient, so a rotation of the gradients rotates the update):
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) |g|^2;  p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ * with t = ++(*step_dev) as in gmr_adam_step.  param/grad/m [V][3] f32, v [V] f32. */
+gmr_status gmr_vector_adam_step(float* param_dev, const float* grad_dev, float* m_dev, float* v_dev,
+                                int64_t num_verts, float lr, float beta1, float beta2, float eps, int32_t* step_dev,
+                                void* stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Autotuning (tile shape and raster mode).  Allocates its own scratch and synchronises: call it

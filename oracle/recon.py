@@ -27,11 +27,14 @@ BCE_EPS = 1e-6
 
 
 def mesh_edges(faces) -> np.ndarray:
-    """Unique undirected edges [E, 2] (i < j) of a triangle list, sorted lexicographically."""
+    """Unique undirected edges [E, 2] (i < j) of a triangle list, sorted lexicographically.  An
+    edge joins two distinct vertices: the corner pair of a degenerate face with a repeated index
+    is not an edge."""
     f = np.asarray(faces, np.int64)
     e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]])
     e = np.sort(e, axis=1)
-    return np.unique(e, axis=0)
+    e = e[e[:, 0] != e[:, 1]]
+    return np.unique(e, axis=0).reshape(-1, 2)
 
 
 def neighbours(num_verts: int, edges) -> list[np.ndarray]:

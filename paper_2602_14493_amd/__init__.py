@@ -8,8 +8,9 @@ from ._lib import GMRError, gmr_options
 
 _lib.load()
 
-from .render import (Batch, GraphAdamLoop, Handle, Renderer, adam_step, copy_options,  # noqa: E402
-                     default_options, options_dict, render)
+from .render import (Batch, GraphAdamLoop, Handle, MeshGraph, ReconLoop, ReconWeights, Renderer,  # noqa: E402
+                     adam_step, copy_options, default_options, options_dict, render, vector_adam_step)
 
-__all__ = ["Batch", "GraphAdamLoop", "Handle", "Renderer", "adam_step", "copy_options", "default_options",
-           "options_dict", "render", "GMRError", "gmr_options"]
+__all__ = ["Batch", "GraphAdamLoop", "Handle", "MeshGraph", "ReconLoop", "ReconWeights", "Renderer", "adam_step",
+           "copy_options", "default_options", "options_dict", "render", "vector_adam_step", "GMRError",
+           "gmr_options"]

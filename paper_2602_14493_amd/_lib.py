@@ -34,7 +34,7 @@ class gmr_batch(ctypes.Structure):
 
 class gmr_counters(ctypes.Structure):
     _fields_ = [("instances", c_int64), ("capacity", c_int64), ("overflow", c_int32), ("reserved", c_int32),
-                ("pairs_fwd", c_int64), ("pairs_bwd", c_int64), ("loss", c_float), ("reserved2", c_int32)]
+                ("pairs_fwd", c_int64), ("pairs_bwd", c_int64), ("loss", c_float), ("loss_sil", c_float)]
 
 
 # name -> (restype, argtypes)
@@ -58,6 +58,10 @@ _SIGS = {
     "gmr_render_bwd_l2": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p,
                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p,
                                     c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gmr_render_bwd_recon": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p,
+                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_float,
+                                       c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_size_t, c_void_p]),
     "gmr_workspace_view": (c_int32, [ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), ctypes.POINTER(c_size_t),
                                      ctypes.POINTER(c_size_t), ctypes.POINTER(c_size_t), ctypes.POINTER(c_size_t)]),
     "gmr_read_counters": (c_int32, [c_void_p, c_size_t, ctypes.POINTER(gmr_counters), c_void_p]),
@@ -65,6 +69,13 @@ _SIGS = {
     "gmr_profile_read": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gmr_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_float, c_float, c_float, c_float,
                                 c_void_p, c_void_p]),
+    "gmr_mesh_graph_size": (c_int32, [c_void_p, c_int64, c_int64, ctypes.POINTER(c_int64)]),
+    "gmr_build_mesh_graph": (c_int32, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p]),
+    "gmr_regularizers_scratch_size": (c_int32, [c_int64, c_int64, ctypes.POINTER(c_size_t)]),
+    "gmr_regularizers": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_float, c_float,
+                                   c_float, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
+    "gmr_vector_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_float, c_float, c_float,
+                                       c_float, c_void_p, c_void_p]),
     "gmr_autotune": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(gmr_options),
                                ctypes.POINTER(c_float), c_void_p]),

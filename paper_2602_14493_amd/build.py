@@ -20,7 +20,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmr.so")
-SOURCES = ["k_project.hip", "k_bin.hip", "k_sort.hip", "k_raster.hip", "k_grad.hip", "api.cpp"]
+SOURCES = ["k_project.hip", "k_bin.hip", "k_sort.hip", "k_raster.hip", "k_grad.hip", "k_recon.hip", "api.cpp"]
 ARCH = "gfx950"
 
 

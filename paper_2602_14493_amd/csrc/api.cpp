@@ -18,10 +18,10 @@ using namespace gmr;
 
 // Stages timed by gmr_profile_* (HIP events around each launch group on the call's stream).
 enum Stage { kStProject, kStScanEmit, kStSortFv, kStSortPass, kStRanges, kStRasterFwd, kStFill, kStRasterBwd,
-             kStFaceBwd, kStGather, kNumStages };
+             kStFaceBwd, kStGather, kStLoss, kNumStages };
 static const char* kStageNames[kNumStages] = {"project",     "scan_emit",  "sort_fv_pass", "sort_pass",
                                               "tile_ranges", "raster_fwd", "fill",         "raster_bwd",
-                                              "face_bwd",    "vertex_gather"};
+                                              "face_bwd",    "vertex_gather", "loss_reduce"};
 
 struct gmr_ctx {
   int device = 0;
@@ -206,6 +206,9 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   L.ranges = take((size_t)p.tiles_total * 8);
   L.dfv = take((size_t)p.fv_total * 32);
   L.fgrad = take((size_t)p.f_total * 48);
+  L.statF = take((size_t)std::max(p.items_total, 1) * 8);
+  L.statB = take((size_t)std::max(p.items_total, 1) * 16);
+  L.statR = take((size_t)kLossReduceBlocks * 16);
   L.total = off;
   return GMR_OK;
 }
@@ -267,6 +270,9 @@ struct WsPtrs {
   uint32_t* ranges;
   float* dfv;
   float4* fgrad;
+  unsigned long long* statF;
+  float4* statB;
+  unsigned long long* statR;
   uint32_t* sorted_vals;
 };
 
@@ -291,6 +297,9 @@ WsPtrs ws_ptrs(const Layout& L, void* ws) {
   w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
   w.dfv = reinterpret_cast<float*>(b + L.dfv);
   w.fgrad = reinterpret_cast<float4*>(b + L.fgrad);
+  w.statF = reinterpret_cast<unsigned long long*>(b + L.statF);
+  w.statB = reinterpret_cast<float4*>(b + L.statB);
+  w.statR = reinterpret_cast<unsigned long long*>(b + L.statR);
   w.sorted_vals = w.valsF;
   return w;
 }
@@ -327,9 +336,10 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   const uint32_t inst_words = (uint32_t)L.parts_inst * 512u;
   {
     StageTimer t(h, s, kStProject);
+    const StatsInfo si{(uint32_t)p.items_total, (unsigned long long)L.statF, (unsigned long long)L.statB};
     launch_project(table, p.f_total, verts, faces, colors, ko, w.rec, w.elA, w.hist,
                    zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.hdr, w.descF0, fv_words, w.ranges,
-                   2 * p.tiles_total, s);
+                   2 * p.tiles_total, si, s);
   }
   // depth digits on the face-view elements: 4 passes, A -> B -> A -> B -> A
   for (int pass = 0; pass < kDepthPasses; ++pass) {
@@ -384,9 +394,9 @@ gmr_status common_checks(gmr_handle h, const void* table, const void* ws, size_t
 
 gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table, const float* verts,
                     const int32_t* faces, const float* colors, const float* d_rgb, const float* d_alpha, const float* rgb,
-                    const float* target, float loss_weight, const void* saved, const int32_t* adj_off,
-                    const int32_t* adj_ent, int32_t recompute, float* d_verts, float* d_colors, float* loss_dev, void* ws,
-                    size_t ws_bytes, void* stream) {
+                    const float* target, float loss_weight, const float* mask, float sil_weight, const void* saved,
+                    const int32_t* adj_off, const int32_t* adj_ent, int32_t recompute, float* d_verts, float* d_colors,
+                    float* loss_dev, int n_losses, void* ws, size_t ws_bytes, void* stream) {
   Plan p;
   gmr_status st = make_plan(batch, opt, true, p);
   if (st != GMR_OK) return st;
@@ -411,7 +421,11 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
     StageTimer t(h, s, kStRasterBwd);
     launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals, w.rec, ko, saved_T,
                       saved_n, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
-                      w.dfv, w.hdr, s);
+                      mask, (float)(sil_weight / (double)p.p_total), w.dfv, w.statB, s);
+  }
+  if (target) {  // fused loss: fixed-order sum of the per-item slots into the header (and loss_dev)
+    StageTimer t(h, s, kStLoss);
+    launch_loss_reduce(w.statB, p.items_total, w.statR, w.hdr, loss_dev, n_losses, s);
   }
   {
     StageTimer t(h, s, kStFaceBwd);
@@ -421,8 +435,30 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
     StageTimer t(h, s, kStGather);
     launch_vertex_gather(adj_off, adj_ent, reinterpret_cast<const float*>(w.fgrad), p.v_total, d_verts, d_colors, s);
   }
-  if (loss_dev) GMR_CHECK_HIP(hipMemcpyAsync(loss_dev, &w.hdr->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
   return check_launch();
+}
+
+// Regulariser scratch: a float4 per edge and per vertex, then a double per 256-edge and per
+// 256-vertex block (the loss partials).
+size_t reg_scratch_bytes(int64_t nv, int64_t ne) {
+  return (size_t)(ne + nv) * 16 + (size_t)((ne + 255) / 256 + (nv + 255) / 256) * 8;
+}
+
+// Unique undirected edges of a triangle list as (i << 32 | j), i < j, ascending.
+gmr_status unique_edges(const int32_t* faces, int64_t nf, int64_t nv, std::vector<uint64_t>& keys) {
+  keys.clear();
+  keys.reserve((size_t)(3 * nf));
+  for (int64_t f = 0; f < nf; ++f)
+    for (int c = 0; c < 3; ++c) {
+      const int32_t a = faces[3 * f + c], b = faces[3 * f + (c + 1) % 3];
+      if (a < 0 || a >= nv || b < 0 || b >= nv) return fail(GMR_ERR_INVALID_ARG, "face index out of range");
+      if (a == b) continue;
+      const uint64_t lo = (uint64_t)std::min(a, b), hi = (uint64_t)std::max(a, b);
+      keys.push_back(lo << 32 | hi);
+    }
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  return GMR_OK;
 }
 
 std::string tune_key(const Plan& p, const gmr_options* o) {
@@ -551,7 +587,7 @@ gmr_status gmr_render_fwd(gmr_handle h, const gmr_batch* batch, const gmr_option
     StageTimer t(h, s, kStRasterFwd);
     launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0, w.ranges,
                       w.sorted_vals, w.rec, kopts(opt),
-                      out_rgb, out_alpha, saved_T, saved_n, w.hdr, s);
+                      out_rgb, out_alpha, saved_T, saved_n, w.statF, s);
   }
   return check_launch();
 }
@@ -595,8 +631,8 @@ gmr_status gmr_render_bwd(gmr_handle h, const gmr_batch* batch, const gmr_option
                           const float* verts, const int32_t* faces, const float* colors, const float* d_rgb,
                           const float* d_alpha, const void* saved, const int32_t* adj_off, const int32_t* adj_ent,
                           int32_t recompute, float* d_verts, float* d_colors, void* ws, size_t ws_bytes, void* stream) {
-  return bwd_impl(h, batch, opt, table, verts, faces, colors, d_rgb, d_alpha, nullptr, nullptr, 0.f, saved, adj_off,
-                  adj_ent, recompute, d_verts, d_colors, nullptr, ws, ws_bytes, stream);
+  return bwd_impl(h, batch, opt, table, verts, faces, colors, d_rgb, d_alpha, nullptr, nullptr, 0.f, nullptr, 0.f, saved,
+                  adj_off, adj_ent, recompute, d_verts, d_colors, nullptr, 0, ws, ws_bytes, stream);
 }
 
 gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
@@ -606,8 +642,86 @@ gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_opt
                              void* ws, size_t ws_bytes, void* stream) {
   if (!rgb || !target) return fail(GMR_ERR_INVALID_ARG, "rgb and target must not be NULL");
   if (!std::isfinite(loss_weight)) return fail(GMR_ERR_INVALID_ARG, "loss_weight must be finite");
-  return bwd_impl(h, batch, opt, table, verts, faces, colors, nullptr, nullptr, rgb, target, loss_weight, saved, adj_off,
-                  adj_ent, recompute, d_verts, d_colors, loss_dev, ws, ws_bytes, stream);
+  return bwd_impl(h, batch, opt, table, verts, faces, colors, nullptr, nullptr, rgb, target, loss_weight, nullptr, 0.f,
+                  saved, adj_off, adj_ent, recompute, d_verts, d_colors, loss_dev, 1, ws, ws_bytes, stream);
+}
+
+gmr_status gmr_render_bwd_recon(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
+                                const float* verts, const int32_t* faces, const float* colors, const float* rgb,
+                                const float* target, float color_weight, const float* mask, float sil_weight,
+                                const void* saved, const int32_t* adj_off, const int32_t* adj_ent, int32_t recompute,
+                                float* d_verts, float* d_colors, float* losses_dev, void* ws, size_t ws_bytes,
+                                void* stream) {
+  if (!rgb || !target || !mask) return fail(GMR_ERR_INVALID_ARG, "rgb, target and mask must not be NULL");
+  if (!std::isfinite(color_weight) || !std::isfinite(sil_weight))
+    return fail(GMR_ERR_INVALID_ARG, "loss weights must be finite");
+  return bwd_impl(h, batch, opt, table, verts, faces, colors, nullptr, nullptr, rgb, target, color_weight, mask,
+                  sil_weight, saved, adj_off, adj_ent, recompute, d_verts, d_colors, losses_dev, 2, ws, ws_bytes, stream);
+}
+
+gmr_status gmr_mesh_graph_size(const int32_t* faces, int64_t nf, int64_t nv, int64_t* num_edges) {
+  if (!faces || !num_edges || nf < 0 || nv < 0) return fail(GMR_ERR_INVALID_ARG, "bad mesh graph arguments");
+  std::vector<uint64_t> keys;
+  gmr_status st = unique_edges(faces, nf, nv, keys);
+  if (st != GMR_OK) return st;
+  *num_edges = (int64_t)keys.size();
+  return GMR_OK;
+}
+
+gmr_status gmr_build_mesh_graph(const int32_t* faces, int64_t nf, int64_t nv, int64_t num_edges, int32_t* edges,
+                                int32_t* vedge_off, int32_t* vedge_ent) {
+  if (!faces || !edges || !vedge_off || !vedge_ent || nf < 0 || nv < 0) return fail(GMR_ERR_INVALID_ARG, "bad mesh graph arguments");
+  std::vector<uint64_t> keys;
+  gmr_status st = unique_edges(faces, nf, nv, keys);
+  if (st != GMR_OK) return st;
+  if ((int64_t)keys.size() != num_edges) return fail(GMR_ERR_INVALID_ARG, "num_edges does not match the mesh");
+  if (2 * num_edges >= (1ll << 30)) return fail(GMR_ERR_INVALID_ARG, "too many edges");
+  std::vector<int32_t> cnt(nv + 1, 0);
+  for (int64_t e = 0; e < num_edges; ++e) {
+    edges[2 * e] = (int32_t)(keys[e] >> 32);
+    edges[2 * e + 1] = (int32_t)(keys[e] & 0xffffffffu);
+    cnt[edges[2 * e] + 1]++;
+    cnt[edges[2 * e + 1] + 1]++;
+  }
+  vedge_off[0] = 0;
+  for (int64_t v = 0; v < nv; ++v) vedge_off[v + 1] = vedge_off[v] + cnt[v + 1];
+  std::vector<int32_t> cur(vedge_off, vedge_off + nv);
+  for (int64_t e = 0; e < num_edges; ++e) {  // ascending edge index per vertex
+    vedge_ent[cur[edges[2 * e]]++] = (int32_t)(e << 1);            // side 0: first end
+    vedge_ent[cur[edges[2 * e + 1]]++] = (int32_t)((e << 1) | 1);  // side 1: second end
+  }
+  return GMR_OK;
+}
+
+gmr_status gmr_regularizers_scratch_size(int64_t nv, int64_t num_edges, size_t* bytes) {
+  if (!bytes || nv < 0 || num_edges < 0) return fail(GMR_ERR_INVALID_ARG, "bad arguments");
+  *bytes = reg_scratch_bytes(nv, num_edges);
+  return GMR_OK;
+}
+
+gmr_status gmr_regularizers(const float* verts, int64_t nv, const int32_t* edges, int64_t num_edges,
+                            const int32_t* vedge_off, const int32_t* vedge_ent, float target_length, float edge_weight,
+                            float lap_weight, void* scratch, size_t scratch_bytes, float* losses, float* d_verts,
+                            void* stream) {
+  if (!verts || !edges || !vedge_off || !vedge_ent || !scratch || !losses || !d_verts || nv < 0 || num_edges < 0)
+    return fail(GMR_ERR_INVALID_ARG, "bad regularizer arguments");
+  if (scratch_bytes < reg_scratch_bytes(nv, num_edges)) return fail(GMR_ERR_WORKSPACE, "regularizer scratch too small");
+  if (!std::isfinite(target_length) || !std::isfinite(edge_weight) || !std::isfinite(lap_weight))
+    return fail(GMR_ERR_INVALID_ARG, "regularizer parameters must be finite");
+  float4* ge = static_cast<float4*>(scratch);
+  launch_regularizers(verts, nv, edges, num_edges, vedge_off, vedge_ent, target_length, edge_weight, lap_weight, ge,
+                      ge + num_edges, reinterpret_cast<double*>(ge + num_edges + nv), losses, d_verts,
+                      static_cast<hipStream_t>(stream));
+  return check_launch();
+}
+
+gmr_status gmr_vector_adam_step(float* param, const float* grad, float* m, float* v, int64_t nv, float lr, float beta1,
+                                float beta2, float eps, int32_t* step, void* stream) {
+  if (!param || !grad || !m || !v || !step || nv < 0) return fail(GMR_ERR_INVALID_ARG, "bad VectorAdam arguments");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(GMR_ERR_INVALID_ARG, "bad VectorAdam hyper-parameters");
+  launch_vector_adam(param, grad, m, v, nv, lr, beta1, beta2, eps, step, static_cast<hipStream_t>(stream));
+  return check_launch();
 }
 
 gmr_status gmr_workspace_view(const gmr_batch* batch, const gmr_options* opt, size_t* ranges_off, size_t* vals_off,
@@ -633,10 +747,25 @@ gmr_status gmr_read_counters(const void* ws, size_t ws_bytes, gmr_counters* out,
   out->capacity = hdr.capacity;
   out->overflow = (int32_t)hdr.overflow;
   out->reserved = 0;
-  out->pairs_fwd = (int64_t)hdr.pairs_fwd;
-  out->pairs_bwd = (int64_t)hdr.pairs_bwd;
+  // pair counts: sums of the raster kernels' per-item slots
+  out->pairs_fwd = 0;
+  out->pairs_bwd = 0;
+  const size_t items = hdr.stats_items;
+  if (items > 0 && hdr.stats_fwd_off + items * 8 <= ws_bytes && hdr.stats_bwd_off + items * 16 <= ws_bytes) {
+    const char* b = static_cast<const char*>(ws);
+    std::vector<unsigned long long> f(items);
+    GMR_CHECK_HIP(hipMemcpyAsync(f.data(), b + hdr.stats_fwd_off, items * 8, hipMemcpyDeviceToHost, s));
+    std::vector<uint32_t> bw;
+    if (hdr.bwd_stats) {
+      bw.resize(items * 4);
+      GMR_CHECK_HIP(hipMemcpyAsync(bw.data(), b + hdr.stats_bwd_off, items * 16, hipMemcpyDeviceToHost, s));
+    }
+    GMR_CHECK_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < items; ++i) out->pairs_fwd += (int64_t)f[i];
+    for (size_t i = 0; i < bw.size(); i += 4) out->pairs_bwd += (int64_t)((uint64_t)bw[i + 2] | ((uint64_t)bw[i + 3] << 32));
+  }
   out->loss = hdr.loss;
-  out->reserved2 = 0;
+  out->loss_sil = hdr.loss_sil;
   return GMR_OK;
 }
 

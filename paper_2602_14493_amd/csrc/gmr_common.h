@@ -62,15 +62,20 @@ struct WsHdr {                 // 256 B at the start of the workspace
   uint32_t capacity;
   uint32_t passes;
   uint32_t part_ctr[kMaxPasses];   // onesweep partition tickets, one per pass (same rows as the histograms)
-  uint32_t work_fwd, work_bwd;     // unused (kept for the header layout)
-  unsigned long long pairs_fwd;    // (pixel, Gaussian) pairs the forward evaluated
-  float loss;                      // L2 loss value of the last fused backward
-  uint32_t pad0;
-  unsigned long long pairs_bwd;    // (pixel, Gaussian) pairs the backward differentiated
+  uint32_t stats_items;            // raster items; each writes its own statistics slot
+  uint32_t bwd_stats;              // 1 once a backward has written its per-item slots
+  unsigned long long stats_fwd_off;  // byte offset in the workspace: [items] u64 pairs of the forward
+  unsigned long long stats_bwd_off;  // [items] float4 {colour loss, silhouette loss, pairs lo, hi} of the backward
+  float loss;                      // colour loss of the last fused backward (fixed-order sum of the slots)
+  float loss_sil;                  // its silhouette loss
+  uint32_t red_ticket;             // last-block ticket of that sum (left at 0)
   uint32_t key_hi_min, key_hi_max; // range of the high 16 depth-key bits over visible face-views
-  uint32_t pad1[42];
+  uint32_t pad1[41];
 };
 static_assert(sizeof(WsHdr) == 256, "ws header");
+
+// Silhouette term: alpha is clamped to [kBceEps, 1 - kBceEps] inside the binary cross-entropy.
+constexpr float kBceEps = 1e-6f;
 
 // When the visible face-views' depth keys span fewer than 256 values of their high 16 bits, the
 // third depth pass sorts on (key >> 16) - key_hi_min (one 8-bit digit that orders them exactly)
@@ -87,10 +92,19 @@ struct KOpts {
   float bg0, bg1, bg2;
 };
 
+// Where the per-item raster statistics live (recorded in the header by the build prologue).
+struct StatsInfo {
+  uint32_t items;
+  unsigned long long fwd_off, bwd_off;
+};
+
+// Blocks of the fixed-order loss sum (a multiple of nothing in particular; at most this many).
+constexpr int kLossReduceBlocks = 256;
+
 // Workspace layout, computed on the host (byte offsets) -------------------------------------------
 struct Layout {
   size_t hdr, rec, elA, elB, bsum, boff, instA, instB, keysF, valsF, hist, descF0, descF1, descI0, descI1,
-      ranges, dfv, fgrad, total;
+      ranges, dfv, fgrad, statF, statB, statR, total;
   int64_t fv_total, faces_total, pixels_total, capacity;
   int32_t tiles_total, items_total, tile_bits, tile_passes, scan_blocks, parts_fv, parts_inst;
   int32_t scan_items;  // face-views per thread of the scan / emission blocks (scan_items_for)

@@ -13,7 +13,7 @@ namespace gmr {
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
                     const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
                     WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, uint32_t* ranges, int64_t ranges_words,
-                    hipStream_t s);
+                    const StatsInfo& si, hipStream_t s);
 
 void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
                 WsHdr* hdr, uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0,
@@ -32,15 +32,19 @@ void launch_fill_f32(float* p, int64_t n, float val, hipStream_t s);
 // zeroes the backward counters of hdr and dfv[0, n)
 void launch_bwd_prologue(WsHdr* hdr, float* dfv, int64_t n, hipStream_t s);
 
+void launch_loss_reduce(const float4* stats, int items, unsigned long long* part, WsHdr* hdr, float* out, int n_out,
+                        hipStream_t s);
+
 void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists, const uint32_t* ranges,
                        const uint32_t* vals,
                        const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
-                       uint32_t* saved_n, WsHdr* hdr, hipStream_t s);
+                       uint32_t* saved_n, unsigned long long* stats, hipStream_t s);
 
 void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges, const uint32_t* vals,
                        const float4* rec, const KOpts& o, const float* saved_T, const uint32_t* saved_n,
                        const float* d_rgb, const float* d_alpha, const float* rgb, const float* target, float l2_grad_scale,
-                       float l2_loss_scale, float* dfv, WsHdr* hdr, hipStream_t s);
+                       float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats,
+                       hipStream_t s);
 
 void launch_face_bwd(const void* table, int64_t faces_total, const float* verts, const int32_t* faces, const KOpts& o,
                      const float4* dfv, float4* fgrad, hipStream_t s);
@@ -50,5 +54,11 @@ void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* f
 
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                  int32_t* step, hipStream_t s);
+void launch_adam_tick(int32_t* step, hipStream_t s);
+void launch_regularizers(const float* verts, int64_t V, const int32_t* edges, int64_t E, const int32_t* voff,
+                         const int32_t* vent, float l0, float w_edge, float w_lap, float4* ge, float4* lu,
+                         double* part, float* losses, float* grad, hipStream_t s);
+void launch_vector_adam(float* p, const float* g, float* m, float* v, int64_t V, float lr, float b1, float b2, float eps,
+                        int32_t* step, hipStream_t s);
 
 }  // namespace gmr

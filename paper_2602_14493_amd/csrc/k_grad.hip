@@ -196,10 +196,81 @@ __global__ __launch_bounds__(256) void k_bwd_prologue(WsHdr* __restrict__ hdr, f
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t; i < n; i += (int64_t)gridDim.x * blockDim.x) dfv[i] = 0.f;
   if (t == 0) {
-    hdr->work_bwd = 0u;
+    hdr->bwd_stats = 1u;
     hdr->loss = 0.f;
-    hdr->pairs_bwd = 0ull;
+    hdr->loss_sil = 0.f;
+    hdr->red_ticket = 0u;
   }
+}
+
+namespace {
+// Sum of (a, b) over the 256 threads of a block in a fixed order; valid in thread 0.
+__device__ inline void block_sum2(double& a, double& b, double* s_a, double* s_b) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    a += __shfl_xor(a, d, kWave);
+    b += __shfl_xor(b, d, kWave);
+  }
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) { s_a[w] = a; s_b[w] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = s_a[0]; b = s_b[0];
+    for (int i = 1; i < 256 / kWave; ++i) { a += s_a[i]; b += s_b[i]; }
+  }
+  __syncthreads();
+}
+__device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
+__device__ inline double bitsd(unsigned long long x) { return __longlong_as_double((long long)x); }
+}  // namespace
+
+// Fused-loss backward: the colour and silhouette losses as a deterministic sum of the per-item
+// slots.  Block b sums a contiguous chunk; the block that takes the last ticket sums the block
+// results in block order and writes the header (and `out`, n_out floats, when given).
+__global__ __launch_bounds__(256) void k_loss_reduce(const float4* __restrict__ stats, int items,
+                                                     unsigned long long* part, WsHdr* hdr, float* out, int n_out) {
+  __shared__ double s_a[256 / kWave], s_b[256 / kWave];
+  __shared__ bool s_last;
+  const int nb = (int)gridDim.x;
+  const int chunk = (items + nb - 1) / nb;
+  const int lo = (int)blockIdx.x * chunk, hi = min(items, lo + chunk);
+  double l = 0.0, ls = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += 256) {
+    const float4 v = stats[i];
+    l += (double)v.x;
+    ls += (double)v.y;
+  }
+  block_sum2(l, ls, s_a, s_b);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&part[2 * blockIdx.x], dbits(l), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&part[2 * blockIdx.x + 1], dbits(ls), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t t = __hip_atomic_fetch_add(&hdr->red_ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = t == (uint32_t)nb - 1u;
+  }
+  __syncthreads();
+  if (!s_last) return;  // uniform across the block
+  __threadfence();
+  l = 0.0; ls = 0.0;
+  if ((int)threadIdx.x < nb) {
+    l = bitsd(__hip_atomic_load(&part[2 * threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    ls = bitsd(__hip_atomic_load(&part[2 * threadIdx.x + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  }
+  block_sum2(l, ls, s_a, s_b);
+  if (threadIdx.x == 0) {
+    hdr->loss = (float)l;
+    hdr->loss_sil = (float)ls;
+    if (out) {
+      out[0] = (float)l;
+      if (n_out > 1) out[1] = (float)ls;
+    }
+    hdr->red_ticket = 0u;
+  }
+}
+
+void launch_loss_reduce(const float4* stats, int items, unsigned long long* part, WsHdr* hdr, float* out, int n_out,
+                        hipStream_t s) {
+  const int nb = std::max(1, std::min(kLossReduceBlocks, (items + 2047) / 2048));
+  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)nb), dim3(256), 0, s, stats, items, part, hdr, out, n_out);
 }
 
 // Adam with bias correction; t = step + 1 is read from the device (advanced by k_adam_tick).
@@ -252,7 +323,9 @@ void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float 
                  int32_t* step, hipStream_t s) {
   if (n > 0)
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, step);
-  hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(64), 0, s, step);
+  launch_adam_tick(step, s);
 }
+
+void launch_adam_tick(int32_t* step, hipStream_t s) { hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(64), 0, s, step); }
 
 }  // namespace gmr

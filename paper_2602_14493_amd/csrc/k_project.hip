@@ -111,10 +111,12 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
     if (s_h[i]) atomicAdd(&hist[(i >> 8) * kHistStride + (i & 255)], s_h[i]);
 }
 
-// Clears the per-build counters, every histogram row and the first depth pass's descriptors.
+// Clears the per-build counters, every histogram row and the first depth pass's descriptors, and
+// records where the raster kernels' per-item statistics live.
 __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restrict__ hist,
                                                   uint32_t* __restrict__ desc0, int64_t desc0_words,
-                                                  uint32_t* __restrict__ ranges, int64_t ranges_words) {
+                                                  uint32_t* __restrict__ ranges, int64_t ranges_words,
+                                                  StatsInfo si) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t; i < desc0_words; i += stride) desc0[i] = 0u;
@@ -122,9 +124,11 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
   for (int64_t i = t; i < kMaxPasses * kHistStride; i += stride) hist[i] = 0u;
   if (t == 0) {
     for (int p = 0; p < kMaxPasses; ++p) hdr->part_ctr[p] = 0u;
-    hdr->work_fwd = 0u;
-    hdr->work_bwd = 0u;
-    hdr->pairs_fwd = 0ull;
+    hdr->stats_items = si.items;
+    hdr->bwd_stats = 0u;
+    hdr->stats_fwd_off = si.fwd_off;
+    hdr->stats_bwd_off = si.bwd_off;
+    hdr->red_ticket = 0u;
     hdr->key_hi_min = 0xffffffffu;
     hdr->key_hi_max = 0u;
   }
@@ -133,11 +137,11 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
                     const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
                     WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, uint32_t* ranges, int64_t ranges_words,
-                    hipStream_t s) {
+                    const StatsInfo& si, hipStream_t s) {
   int64_t pb = (std::max(desc0_words, ranges_words) + 255) / 256;
   pb = pb < 1 ? 1 : (pb > 4096 ? 4096 : pb);
   hipLaunchKernelGGL(k_prologue, dim3((unsigned)pb), dim3(256), 0, s, hdr, hist, desc0, desc0_words, ranges,
-                     ranges_words);
+                     ranges_words, si);
   if (faces_total <= 0) return;
   const int bs = 256;
   const int64_t nb = (faces_total + bs - 1) / bs;

@@ -171,7 +171,7 @@ struct FwdArgs {
   float* out_alpha;
   float* saved_T;
   uint32_t* saved_n;
-  WsHdr* hdr;
+  unsigned long long* stats;  // [items] pairs evaluated per item (summed on the host when read)
 };
 
 // One record against a lane's PX pixels; `valid` = false makes it a no-op (predicated).
@@ -207,11 +207,12 @@ __device__ __forceinline__ void fwd_eval(const float4& a0, const float4& a1, con
   }
 }
 
+// Returns the item's pair count (wave-uniform).
 template <int PX>
-__device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
-                                       float4 (*s)[kWave]) {
+__device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const TableHdr* th, const ViewDev* views,
+                                                     int item, int lane, float4 (*s)[kWave]) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
-  if (!g.any) return;
+  if (!g.any) return 0ull;
   const int ly = lane >> 3;
   const float px = (float)g.x + 0.5f;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
@@ -281,7 +282,7 @@ __device__ inline void raster_fwd_item(const FwdArgs& a, const TableHdr* th, con
       a.saved_n[p] = last[k];
     }
   }
-  if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_fwd, pairs);
+  return pairs;
 }
 
 // Walk the n staged Gaussians (slots 0..n-1, in list order) with per-lane lists: lane j < n builds
@@ -349,10 +350,10 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
 // each time the slots fill (and at the end of the list) they are walked with fwd_walk_lanes, so one
 // transpose serves 64 kept Gaussians however sparse they are in the list.
 template <int PX>
-__device__ inline void raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
-                                             int lane, float4 (*s)[kWave], uint32_t* s_pos) {
+__device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* th, const ViewDev* views,
+                                                           int item, int lane, float4 (*s)[kWave], uint32_t* s_pos) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
-  if (!g.any) return;
+  if (!g.any) return 0ull;
   const int ly = lane >> 3;
   const float px = (float)g.x + 0.5f;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
@@ -429,15 +430,19 @@ __device__ inline void raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* t
   // wave sum of the per-lane pair counts
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) pairs += (uint32_t)__shfl_xor((int)pairs, d, kWave);
-  if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_fwd, (unsigned long long)pairs);
   wave_lds_sync();  // the next item (persistent schedule) restages the slots
+  return (unsigned long long)pairs;
 }
 
+// Every item writes its own statistics slot (no atomics on a shared counter: one float or 64-bit
+// atomic per wavefront on one address serialises at the L2 and bounded these kernels).
 template <int PX, bool kPersistent, bool kLanes>
 __device__ __forceinline__ void raster_fwd_any(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
                                                int lane, float4 (*s)[kWave], uint32_t* s_pos) {
-  if constexpr (kLanes) raster_fwd_item_lanes<PX>(a, th, views, item, lane, s, s_pos);
-  else raster_fwd_item<PX>(a, th, views, item, lane, s);
+  unsigned long long pairs;
+  if constexpr (kLanes) pairs = raster_fwd_item_lanes<PX>(a, th, views, item, lane, s, s_pos);
+  else pairs = raster_fwd_item<PX>(a, th, views, item, lane, s);
+  if (lane == 0) a.stats[item] = pairs;
 }
 
 template <int PX, bool kPersistent, bool kLanes>
@@ -480,8 +485,10 @@ struct BwdArgs {
   const float* target;    // L2 form: target image
   float l2_grad_scale;    // loss_weight * 2 / (3P)
   float l2_loss_scale;    // loss_weight / (3P)
+  const float* mask;      // L2 form, optional: target silhouette per pixel (0 / 1) for the BCE term
+  float sil_scale;        // silhouette weight / P
   float* dfv;             // [FV][8]
-  WsHdr* hdr;
+  float4* stats;          // [items] {colour loss, silhouette loss, pairs lo, pairs hi bits} per item
 };
 
 // gfx950 half-wave / row swaps: after the swap, adding the two registers leaves in lanes 0-31
@@ -609,16 +616,16 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
 }
 
 template <int PX, bool kL2>
-__device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
+__device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
                                        const BwdLds& L) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
-  if (!g.any) return;
+  if (!g.any) return make_float4(0.f, 0.f, 0.f, 0.f);
   const int ly = lane >> 3;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   float gc0[PX], gc1[PX], gc2[PX], K[PX], T[PX], S[PX];
   uint32_t last[PX];
   int y[PX];
-  float loss = 0.f;
+  float loss = 0.f, loss_sil = 0.f;
   uint32_t mx = 0;
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
@@ -638,6 +645,20 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
         gc1[k] = a.l2_grad_scale * e1;
         gc2[k] = a.l2_grad_scale * e2;
         loss += fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+        if (a.mask) {
+          // silhouette BCE on alpha = 1 - T_final (Sec. 3.1), clamped; dL/dalpha enters as g_A.
+          // alpha and 1 - alpha are clamped separately (ac from 1 - T, exact for T >= 1/2; tc = T)
+          // and each log takes the form that keeps its small argument's precision.
+          const float sm = a.mask[p];
+          const float ac = fminf(fmaxf(1.f - Tf, kBceEps), 1.f - kBceEps);
+          const float tc = fminf(fmaxf(Tf, kBceEps), 1.f - kBceEps);
+          const bool inside = Tf > kBceEps && Tf < 1.f - kBceEps;
+          const bool opaque = Tf < 0.5f;
+          const float log_a = opaque ? log1pf(-tc) : logf(ac);
+          const float log_t = opaque ? logf(tc) : log1pf(-ac);
+          ga = inside ? a.sil_scale * (ac - sm) / (ac * tc) : 0.f;
+          loss_sil -= fmaf(sm, log_a, (1.f - sm) * log_t);
+        }
       } else {
         const float* dp = a.d_rgb + 3 * p;
         gc0[k] = dp[0]; gc1[k] = dp[1]; gc2[k] = dp[2];
@@ -652,11 +673,16 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
   if (kL2) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) loss += __shfl_xor(loss, d, kWave);
-    if (lane == 0 && loss != 0.f) atomicAdd(&a.hdr->loss, loss * a.l2_loss_scale);
+    loss *= a.l2_loss_scale;
+    if (a.mask) {
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) loss_sil += __shfl_xor(loss_sil, d, kWave);
+      loss_sil *= a.sil_scale;
+    }
   }
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
-  if (mx == 0) return;
+  if (mx == 0) return make_float4(loss, loss_sil, 0.f, 0.f);
   const float px = (float)g.x + 0.5f;
   const float amin = a.o.alpha_min, amax = a.o.alpha_max;
   unsigned long long pairs = 0;  // wave-uniform count
@@ -679,7 +705,7 @@ __device__ inline void raster_bwd_item(const BwdArgs& a, const TableHdr* th, con
     bwd_batch_uniform<PX>(a, L, m, hi, start, g, px, y, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
     wave_lds_sync();
   }
-  if (lane == 0 && pairs) atomicAdd(&a.hdr->pairs_bwd, pairs);
+  return make_float4(loss, loss_sil, u2f((uint32_t)pairs), u2f((uint32_t)(pairs >> 32)));
 }
 
 template <int PX, bool kPersistent, bool kL2>
@@ -695,11 +721,17 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     const int groups = (items + 3) / 4;  // grid-stride, as in the forward
     for (int v = (int)blockIdx.x; v < groups; v += (int)gridDim.x) {
       const int item = xcd_remap(v, groups) * 4 + w;
-      if (item < items) raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
+      if (item < items) {
+        const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
+        if (lane == 0) a.stats[item] = st;
+      }
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
-    if (item < items) raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
+    if (item < items) {
+      const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
+      if (lane == 0) a.stats[item] = st;
+    }
   }
 }
 
@@ -725,8 +757,9 @@ static void bwd_dispatch(const BwdArgs& a, bool l2, int items, int persistent_bl
 
 void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists,
                        const uint32_t* ranges, const uint32_t* vals, const float4* rec, const KOpts& o, float* out_rgb,
-                       float* out_alpha, float* saved_T, uint32_t* saved_n, WsHdr* hdr, hipStream_t s) {
-  FwdArgs a{table, ranges, vals, rec, o, out_rgb, out_alpha, saved_T, saved_n, hdr};
+                       float* out_alpha, float* saved_T, uint32_t* saved_n, unsigned long long* stats,
+                       hipStream_t s) {
+  FwdArgs a{table, ranges, vals, rec, o, out_rgb, out_alpha, saved_T, saved_n, stats};
   if (items <= 0) return;
   if (lane_lists) {
     if (px == 4) fwd_dispatch<4, true>(a, items, persistent_blocks, s);
@@ -742,9 +775,10 @@ void launch_raster_fwd(const void* table, int items, int persistent_blocks, int 
 void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges,
                        const uint32_t* vals, const float4* rec, const KOpts& o, const float* saved_T,
                        const uint32_t* saved_n, const float* d_rgb, const float* d_alpha, const float* rgb,
-                       const float* target, float l2_grad_scale, float l2_loss_scale, float* dfv, WsHdr* hdr,
-                       hipStream_t s) {
-  BwdArgs a{table, ranges, vals, rec, o, saved_T, saved_n, d_rgb, d_alpha, rgb, target, l2_grad_scale, l2_loss_scale, dfv, hdr};
+                       const float* target, float l2_grad_scale, float l2_loss_scale, const float* mask,
+                       float sil_scale, float* dfv, float4* stats, hipStream_t s) {
+  BwdArgs a{table,    ranges,        vals, rec,       o,   saved_T, saved_n, d_rgb, d_alpha, rgb, target,
+            l2_grad_scale, l2_loss_scale, mask, sil_scale, dfv, stats};
   if (items <= 0) return;
   const bool l2 = target != nullptr;
   if (px == 4) bwd_dispatch<4>(a, l2, items, persistent_blocks, s);

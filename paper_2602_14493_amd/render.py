@@ -128,6 +128,7 @@ class Counters:
     pairs_fwd: int = 0
     pairs_bwd: int = 0
     loss: float = 0.0
+    loss_sil: float = 0.0
 
 
 class Renderer:
@@ -197,7 +198,7 @@ class Renderer:
         c = gmr_counters()
         call("gmr_read_counters", _ptr(ws), ws.numel(), ctypes.byref(c), _stream(self.device))
         return Counters(int(c.instances), int(c.capacity), bool(c.overflow), int(c.pairs_fwd), int(c.pairs_bwd),
-                        float(c.loss))
+                        float(c.loss), float(c.loss_sil))
 
     # -- raw calls (no capacity management) --------------------------------------------------------
     def fwd_raw(self, verts, colors, rgb, alpha, saved, ws):
@@ -216,6 +217,13 @@ class Renderer:
              _ptr(self.table), _ptr(verts), _ptr(self.faces), _ptr(colors), _ptr(rgb), _ptr(target),
              float(loss_weight), _ptr(saved), _ptr(self.adj_off), _ptr(self.adj_ent), int(recompute), _ptr(d_verts),
              _ptr(d_colors), _ptr(loss), _ptr(ws), ws.numel(), _stream(self.device))
+
+    def bwd_recon_raw(self, verts, colors, rgb, target, color_weight, mask, sil_weight, saved, ws, recompute,
+                      d_verts, d_colors, losses=None):
+        call("gmr_render_bwd_recon", self.handle.ptr, ctypes.byref(self.batch.c), ctypes.byref(self.opts),
+             _ptr(self.table), _ptr(verts), _ptr(self.faces), _ptr(colors), _ptr(rgb), _ptr(target),
+             float(color_weight), _ptr(mask), float(sil_weight), _ptr(saved), _ptr(self.adj_off), _ptr(self.adj_ent),
+             int(recompute), _ptr(d_verts), _ptr(d_colors), _ptr(losses), _ptr(ws), ws.numel(), _stream(self.device))
 
     # -- managed calls -------------------------------------------------------------------------------
     def _alloc_outputs(self):
@@ -276,6 +284,20 @@ class Renderer:
                         recompute, dV, dC, loss)
         return (dV, dC, loss) if want_loss else (dV, dC)
 
+    def backward_recon(self, verts, colors, rgb, target, mask, saved, ws=None, recompute=False, color_weight=1.0,
+                       sil_weight=1.0):
+        """Gradients of color_weight * MSE(rgb, target) + sil_weight * BCE(alpha, mask) (Sec. 3.1).
+        Returns (dV, dC, losses [2] = colour, silhouette)."""
+        if ws is None:
+            ws = self.new_workspace()
+            recompute = True
+        dV = torch.empty_like(verts)
+        dC = torch.empty_like(colors)
+        losses = torch.empty((2,), dtype=torch.float32, device=self.device)
+        self.bwd_recon_raw(verts.contiguous(), colors.contiguous(), rgb, target.contiguous(), color_weight,
+                           mask.contiguous(), sil_weight, saved, ws, recompute, dV, dC, losses)
+        return dV, dC, losses
+
     def autotune(self, verts, colors, target, iters: int = 3):
         """gmr_autotune over tile shapes and raster modes; adopts and returns the best options."""
         best = gmr_options()
@@ -331,6 +353,134 @@ def render(verts: torch.Tensor, colors: torch.Tensor, renderer: Renderer, save_l
 def adam_step(param, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     call("gmr_adam_step", _ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), float(lr), float(beta1),
          float(beta2), float(eps), _ptr(step), _stream(param.device))
+
+
+def vector_adam_step(param, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """VectorAdam on [V,3] parameters: v [V] holds one second moment per vertex."""
+    if param.dim() != 2 or param.shape[1] != 3 or v.numel() != param.shape[0]:
+        raise ValueError("vector_adam_step expects param/grad/m [V,3] and v [V]")
+    call("gmr_vector_adam_step", _ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.shape[0], float(lr), float(beta1),
+         float(beta2), float(eps), _ptr(step), _stream(param.device))
+
+
+class MeshGraph:
+    """Unique edges and the vertex -> incident-edge CSR of a triangle mesh (built on the host once
+    per topology), and the edge-length + Laplacian regularisers on it."""
+
+    def __init__(self, faces, num_verts: int, device: int | torch.device = 0):
+        f = faces.detach().cpu().numpy() if torch.is_tensor(faces) else np.asarray(faces)
+        f = np.ascontiguousarray(f, dtype=np.int32)
+        self.num_verts = int(num_verts)
+        ne = ctypes.c_int64()
+        call("gmr_mesh_graph_size", f.ctypes.data, len(f), self.num_verts, ctypes.byref(ne))
+        self.num_edges = int(ne.value)
+        edges = np.zeros((self.num_edges, 2), np.int32)
+        off = np.zeros(self.num_verts + 1, np.int32)
+        ent = np.zeros(2 * self.num_edges, np.int32)
+        call("gmr_build_mesh_graph", f.ctypes.data, len(f), self.num_verts, self.num_edges, edges.ctypes.data,
+             off.ctypes.data, ent.ctypes.data)
+        dev = device if isinstance(device, torch.device) else torch.device("cuda", device)
+        self.device = dev
+        self.edges_host, self.off_host, self.ent_host = edges, off, ent
+        self.edges = torch.from_numpy(edges).to(dev)
+        self.off = torch.from_numpy(off).to(dev)
+        self.ent = torch.from_numpy(ent).to(dev)
+        nb = ctypes.c_size_t()
+        call("gmr_regularizers_scratch_size", self.num_verts, self.num_edges, ctypes.byref(nb))
+        self.scratch = torch.empty(max(16, nb.value), dtype=torch.uint8, device=dev)
+
+    def regularizers_raw(self, verts, d_verts, losses, target_length=0.0, edge_weight=1.0, lap_weight=1.0):
+        call("gmr_regularizers", _ptr(verts), self.num_verts, _ptr(self.edges), self.num_edges, _ptr(self.off),
+             _ptr(self.ent), float(target_length), float(edge_weight), float(lap_weight), _ptr(self.scratch),
+             self.scratch.numel(), _ptr(losses), _ptr(d_verts), _stream(self.device))
+
+    def regularizers(self, verts, d_verts=None, target_length=0.0, edge_weight=1.0, lap_weight=1.0):
+        """Adds the regulariser gradients to d_verts (zeros if None) and returns (d_verts, losses
+        [2] = edge, Laplacian)."""
+        verts = verts.contiguous()
+        if d_verts is None:
+            d_verts = torch.zeros_like(verts)
+        losses = torch.empty((2,), dtype=torch.float32, device=self.device)
+        self.regularizers_raw(verts, d_verts, losses, target_length, edge_weight, lap_weight)
+        return d_verts, losses
+
+
+@dataclass
+class ReconWeights:
+    """Weights of the reconstruction objective (Sec. 3.1, Loss Functions); the paper does not give
+    its values, so every term defaults to 1 and the edge target length to 0."""
+    color: float = 1.0
+    silhouette: float = 1.0
+    edge: float = 1.0
+    laplacian: float = 1.0
+    edge_length: float = 0.0
+
+
+class ReconLoop:
+    """The full reconstruction step of Sec. 3.1 -- forward, colour + silhouette backward (lists
+    rebuilt), edge-length and Laplacian regularisers, VectorAdam on the vertices -- captured once as
+    a HIP graph and replayed.  losses [4] after a step: colour, silhouette, edge, Laplacian, each
+    weighted, evaluated at the vertices before that step's update."""
+
+    def __init__(self, renderer: Renderer, verts: torch.Tensor, colors: torch.Tensor, target: torch.Tensor,
+                 mask: torch.Tensor, weights: ReconWeights | None = None, lr=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                 recompute=True):
+        self.r = renderer
+        dev = renderer.device
+        self.w = weights or ReconWeights()
+        self.verts = verts.detach().clone().contiguous()
+        self.colors = colors.detach().contiguous()
+        self.target = target.detach().contiguous()
+        self.mask = mask.detach().to(torch.float32).contiguous()
+        if self.mask.numel() != renderer.batch.num_pixels:
+            raise ValueError("mask must hold one value per pixel of every view")
+        self.graph_mesh = MeshGraph(renderer.faces, renderer.batch.num_verts, dev)
+        self.m = torch.zeros_like(self.verts)
+        self.v = torch.zeros((self.verts.shape[0],), dtype=torch.float32, device=dev)
+        self.step_count = torch.zeros((1,), dtype=torch.int32, device=dev)
+        self.lr, self.betas, self.eps, self.recompute = lr, betas, eps, recompute
+        rgb, alpha, saved, ws = renderer.forward(self.verts, self.colors, check=True)
+        self.ws_fwd = ws
+        self.ws_bwd = renderer.new_workspace() if recompute else ws
+        self.rgb, self.alpha, self.saved = rgb, alpha, saved
+        self.dV = torch.empty_like(self.verts)
+        self.dC = torch.empty_like(self.colors)
+        self.losses = torch.zeros((4,), dtype=torch.float32, device=dev)
+        self.graph = None
+
+    def _step_body(self):
+        r, w = self.r, self.w
+        r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws_fwd)
+        r.bwd_recon_raw(self.verts, self.colors, self.rgb, self.target, w.color, self.mask, w.silhouette, self.saved,
+                        self.ws_bwd, 1 if self.recompute else 0, self.dV, self.dC, self.losses[0:2])
+        self.graph_mesh.regularizers_raw(self.verts, self.dV, self.losses[2:4], w.edge_length, w.edge, w.laplacian)
+        vector_adam_step(self.verts, self.dV, self.m, self.v, self.step_count, self.lr, self.betas[0],
+                         self.betas[1], self.eps)
+
+    def capture(self):
+        s = torch.cuda.Stream(self.r.device)
+        s.wait_stream(torch.cuda.current_stream(self.r.device))
+        with torch.cuda.stream(s):
+            self._step_body()  # one eager step on the side stream before capture
+        torch.cuda.current_stream(self.r.device).wait_stream(s)
+        torch.cuda.synchronize(self.r.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step_body()
+        return self
+
+    def run(self, steps: int):
+        if self.graph is None:
+            self.capture()
+        for _ in range(steps):
+            self.graph.replay()
+
+    def run_eager(self, steps: int):
+        for _ in range(steps):
+            self._step_body()
+
+    def overflow(self) -> bool:
+        return self.r.counters(self.ws_fwd).overflow or self.r.counters(self.ws_bwd).overflow
 
 
 class GraphAdamLoop:

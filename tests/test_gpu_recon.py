@@ -1,0 +1,222 @@
+"""Parity of the reconstruction step around the renderer (Sec. 3.1: colour MSE + silhouette BCE
+backward, edge-length and Laplacian regularisers, VectorAdam) with the FP64 oracle, through the C
+ABI, and the captured step against the same step run eagerly.
+
+Tolerances: losses 1e-5 relative where the arithmetic is a float32 sum of P terms checked against
+the same terms in FP64 (1e-4 for the regularisers, whose per-vertex Laplacian is a float32
+difference of nearby coordinates); gradients as the renderer's parity tests (||d||/||g|| <= 1e-3,
+per element 1e-3 |g| + 1e-5 max|g|); VectorAdam parameters 1e-6 absolute after five steps."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gmr_testutil import compare_grads, gpu_setup, to_np
+from oracle import recon
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _silhouette(W):
+    """Binary target mask: the oracle's alpha of the target mesh above one half."""
+    _, tf, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    return (1.0 - tf > 0.5).astype(np.float64)
+
+
+@pytest.mark.parametrize("k,scale", [(1, 1.0), (2, 0.25)])
+def test_recon_backward_vs_oracle(gpu, k, scale):
+    import torch
+    say(f"recon backward cfg{k} scale {scale}")
+    W = wl.make_workload(k, scale=scale)
+    r, verts, colors = gpu_setup(W)
+    tgt, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    sil = _silhouette(W)
+    target = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    mask = torch.from_numpy(sil.astype(np.float32)).cuda()
+    cw, sw = 0.7, 0.4
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    dV, dC, losses = r.backward_recon(verts, colors, rgb, target, mask, saved, ws, color_weight=cw, sil_weight=sw)
+    c = r.counters(ws)
+    losses = to_np(losses).astype(np.float64)
+    assert c.loss == pytest.approx(losses[0], rel=1e-7) and c.loss_sil == pytest.approx(losses[1], rel=1e-7)
+
+    # the fused terms against the same terms in FP64 from the GPU's own image; alpha is taken as
+    # 1 - T_final from the saved state (the float32 alpha output rounds away T's low bits, which
+    # the BCE derivative 1 / (alpha (1 - alpha)) magnifies near opaque pixels)
+    T = saved.view(torch.float32)[:W.num_pixels]
+    g_rgb_np, g_a_np = to_np(rgb).astype(np.float64), 1.0 - to_np(T).astype(np.float64)
+    Lc_g, gr_g = oracle.l2_loss(g_rgb_np, tgt)
+    Ls_g, ga_g = recon.silhouette_bce(g_a_np, sil, weight=sw)
+    say(f"losses gpu {losses} fp64-of-gpu-image {cw * Lc_g:.8e} {Ls_g:.8e}")
+    assert losses[0] == pytest.approx(cw * Lc_g, rel=1e-5)
+    assert losses[1] == pytest.approx(Ls_g, rel=1e-5)
+    dV2, dC2 = r.backward(verts, colors, torch.from_numpy((cw * gr_g).astype(np.float32)).cuda(),
+                          torch.from_numpy(ga_g.astype(np.float32)).cuda(), saved, ws)
+    compare_grads(dV, to_np(dV2), "fused recon vs explicit dV", rel=1e-5)
+    compare_grads(dC, to_np(dC2), "fused recon vs explicit dC", rel=1e-5)
+
+    # against the oracle's image and adjoint
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W)
+    Lc, g_rgb = oracle.l2_loss(o_rgb, tgt)
+    Ls, g_a = recon.silhouette_bce(1.0 - o_tf, sil, weight=sw)
+    g_rgb = cw * g_rgb
+    if not o_mask.any():
+        assert losses[0] == pytest.approx(cw * Lc, rel=1e-5)
+        assert losses[1] == pytest.approx(Ls, rel=1e-5)
+        oV, oC = oracle.adjoint_workload(W, g_rgb, g_a)
+        compare_grads(dV, oV, f"cfg{k} recon dV vs oracle")
+        compare_grads(dC, oC, f"cfg{k} recon dC vs oracle")
+    else:
+        keep = ~o_mask
+        g_rgb = g_rgb * keep[:, None]
+        g_a = g_a * keep
+        dV3, dC3 = r.backward(verts, colors, torch.from_numpy(g_rgb.astype(np.float32)).cuda(),
+                              torch.from_numpy(g_a.astype(np.float32)).cuda(), saved, ws)
+        oV, oC = oracle.adjoint_workload(W, g_rgb, g_a)
+        compare_grads(dV3, oV, f"cfg{k} recon (masked) dV vs oracle")
+        compare_grads(dC3, oC, f"cfg{k} recon (masked) dC vs oracle")
+
+
+def test_recon_silhouette_only_and_clamp(gpu):
+    """Colour weight 0 leaves the silhouette gradient alone; an all-background view (every pixel at
+    alpha = 0, inside the clamp) gives the closed-form loss -log(1 - 1e-6) or -log(1e-6) per pixel
+    and a zero gradient."""
+    import torch
+    W = wl.make_workload(1)
+    r, verts, colors = gpu_setup(W)
+    P = W.num_pixels
+    far = verts + torch.tensor([0.0, 0.0, 100.0], device=verts.device)   # behind the camera: culled
+    rgb, alpha, saved, ws = r.forward(far, colors)
+    assert float(alpha.abs().max()) == 0.0
+    for s_val, want in [(0.0, -np.log1p(-1e-6)), (1.0, -np.log(1e-6))]:
+        mask = torch.full((P,), s_val, dtype=torch.float32, device=verts.device)
+        dV, dC, losses = r.backward_recon(far, colors, rgb, rgb, mask, saved, ws, color_weight=0.0,
+                                          sil_weight=1.0)
+        l = to_np(losses)
+        say(f"empty view, mask {s_val}: losses {l}")
+        assert l[0] == 0.0
+        assert l[1] == pytest.approx(want, rel=1e-4)
+        assert float(dV.abs().max()) == 0.0 and float(dC.abs().max()) == 0.0
+    sil = _silhouette(W)
+    mask = torch.from_numpy(sil.astype(np.float32)).cuda()
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    dV, dC, losses = r.backward_recon(verts, colors, rgb, rgb, mask, saved, ws, color_weight=0.0, sil_weight=1.0)
+    T = saved.view(torch.float32)[:P]
+    _, ga = recon.silhouette_bce(1.0 - to_np(T).astype(np.float64), sil)
+    dV2, dC2 = r.backward(verts, colors, torch.zeros_like(rgb), torch.from_numpy(ga.astype(np.float32)).cuda(),
+                          saved, ws)
+    compare_grads(dV, to_np(dV2), "silhouette-only dV", rel=1e-5)
+    assert float(to_np(losses)[0]) == 0.0
+
+
+def _graph(faces, nv):
+    import paper_2602_14493_amd as gmr
+    return gmr.MeshGraph(faces, nv, 0)
+
+
+def _reg_mesh(name):
+    rng = np.random.default_rng(3)
+    if name == "icosphere3":
+        v, f = wl.icosphere(3)
+    elif name == "uv_sphere":                          # pole vertices of degree 40
+        v, f = wl.uv_sphere(40, 30)
+    else:                                              # two meshes back to back, as in a batch
+        v1, f1 = wl.torus(30, 20)
+        v2, f2 = wl.icosphere(2)
+        v, f = np.concatenate([v1, v2 + 3.0]), np.concatenate([f1, f2 + len(v1)]).astype(np.int32)
+    return v + rng.normal(0.0, 0.01, v.shape), f
+
+
+@pytest.mark.parametrize("name", ["icosphere3", "uv_sphere", "torus+icosphere"])
+def test_regularizers_vs_oracle(gpu, name):
+    import torch
+    verts, faces = _reg_mesh(name)
+    say(f"regularisers on {name}: V={len(verts)} F={len(faces)}")
+    g = _graph(faces, len(verts))
+    edges = recon.mesh_edges(faces)
+    nb = recon.neighbours(len(verts), edges)
+    v = torch.from_numpy(verts.astype(np.float32)).cuda()
+    v64 = verts.astype(np.float32).astype(np.float64)
+    for l0, we, wlap in [(0.0, 1.0, 1.0), (0.05, 2.5, 0.0), (0.0, 0.0, 0.3)]:
+        # a small incoming gradient, so that d - base carries no rounding of note
+        base = 1e-3 * torch.randn(v.shape, device=v.device, generator=torch.Generator(device="cuda").manual_seed(7))
+        d, losses = g.regularizers(v, base.clone(), l0, we, wlap)
+        Le, ge = recon.edge_length(v64, edges, l0=l0, weight=we)
+        Ll, gl = recon.laplacian_smoothing(v64, nb, weight=wlap)
+        l = to_np(losses).astype(np.float64)
+        say(f"l0={l0} we={we} wl={wlap}: gpu {l} fp64 {Le:.8e} {Ll:.8e}")
+        assert l[0] == pytest.approx(Le, rel=1e-4, abs=1e-30)
+        assert l[1] == pytest.approx(Ll, rel=1e-4, abs=1e-30)
+        compare_grads(d - base, ge + gl, f"{name} regulariser grad l0={l0} we={we} wl={wlap}")
+    # determinism: no float atomics on the gradient
+    d1, _ = g.regularizers(v)
+    d2, _ = g.regularizers(v)
+    assert torch.equal(d1, d2)
+
+
+def test_vector_adam_vs_oracle(gpu):
+    import torch
+    import paper_2602_14493_amd as gmr
+    rng = np.random.default_rng(11)
+    V = 1000
+    p = rng.normal(size=(V, 3)).astype(np.float32)
+    gs = [rng.normal(size=(V, 3)).astype(np.float32) for _ in range(5)]
+    for gg in gs:
+        gg[17] = 0.0                                   # a vertex that never receives a gradient
+    pt = torch.from_numpy(p).cuda()
+    m = torch.zeros_like(pt)
+    vv = torch.zeros((V,), dtype=torch.float32, device=pt.device)
+    step = torch.zeros((1,), dtype=torch.int32, device=pt.device)
+    po, mo, vo = p.astype(np.float64), np.zeros((V, 3)), np.zeros(V)
+    for t, gg in enumerate(gs, start=1):
+        gmr.vector_adam_step(pt, torch.from_numpy(gg).cuda(), m, vv, step, lr=1e-2)
+        # the kernel receives the hyper-parameters as float32: give the oracle the same values
+        po, mo, vo = recon.vector_adam_step(po, gg.astype(np.float64), mo, vo, t, lr=float(np.float32(1e-2)),
+                                            b1=float(np.float32(0.9)), b2=float(np.float32(0.999)),
+                                            eps=float(np.float32(1e-8)))
+        err = np.abs(to_np(pt).astype(np.float64) - po).max()
+        say(f"vector adam step {t}: max |dp| = {err:.3e}")
+        assert err <= 1e-6
+    assert int(step.item()) == 5
+    np.testing.assert_allclose(to_np(vv), vo, rtol=1e-5)
+    assert np.array_equal(to_np(pt)[17], p[17])
+
+
+def test_recon_loop_graph_matches_eager_and_descends(gpu):
+    """The captured reconstruction step replayed tracks the eager step (every replay checked), and
+    from the jittered sphere towards the target the weighted objective goes down."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("recon loop cfg1")
+    W = wl.make_workload(1)
+    r, verts, colors = gpu_setup(W)
+    tgt, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    target = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    mask = torch.from_numpy(_silhouette(W).astype(np.float32)).cuda()
+    w = gmr.ReconWeights(color=1.0, silhouette=0.1, edge=0.01, laplacian=0.01)
+    eager = gmr.ReconLoop(r, verts, colors, target, mask, w, lr=1e-3)
+    graph = gmr.ReconLoop(r, verts, colors, target, mask, w, lr=1e-3)
+    graph.capture()
+    graph.verts.copy_(verts)
+    graph.m.zero_(); graph.v.zero_(); graph.step_count.zero_()
+    for k in range(5):
+        eager.run_eager(1)
+        graph.graph.replay()
+        torch.cuda.synchronize()
+        d = (eager.verts - graph.verts).abs().max().item()
+        le, lg = to_np(eager.losses), to_np(graph.losses)
+        say(f"replay {k}: max |dverts| = {d:.3e} losses eager {le} graph {lg}")
+        assert d <= 1e-5
+        np.testing.assert_allclose(lg, le, rtol=1e-4)
+    assert int(graph.step_count.item()) == 5
+    first = to_np(graph.losses).sum()
+    graph.run(60)
+    torch.cuda.synchronize()
+    last = to_np(graph.losses).sum()
+    say(f"objective after 5 steps {first:.6e}, after 65 {last:.6e}")
+    assert np.isfinite(last) and last < first
+    assert not graph.overflow()
