@@ -78,7 +78,8 @@ class Params:
     """Renderer constants.  Thresholds are the float32-rounded values (a pixel where two clamped
     Gaussians overlap has T(1-a) = (1 - a_max)^2, right at the stop threshold; rounding both sides'
     constants identically keeps that decision the same)."""
-    cov_mode: int = 0                    # 0: Eq. 13 (area matched), 1: Eq. 15 (embedded Sigma2D)
+    cov_mode: int = 0                    # 0: Eq. 13 (area matched), 1: Eq. 15 (embedded Sigma2D),
+    #                                      2: the "3DGS-based" edge-frame baseline (Sec. 3.1, Baselines)
     dilation: float = float(f32(0.3))    # screen-space low-pass, px^2
     alpha_min: float = float(f32(1.0 / 255.0))
     alpha_max: float = float(f32(0.99))

@@ -12,6 +12,11 @@
 //     decomposition (Eq. 10), lifted eigenvectors (Eq. 11), area matching (Eq. 12), the 3D
 //     covariance (Eq. 13 with R_local of Eq. 14, or the embedded form Eq. 15), opacity 1 and the
 //     vertex-average colour (Eq. 16);
+//   * the "3DGS-based" baseline conversion the paper compares against (Sec. 3.1, Baselines): the
+//     mean at the centroid, the frame from the facet normal (z) and the first edge (x); its scales
+//     are not given, so they are read as the area-matched covariance's variances along those two
+//     axes (kappa Sigma2D_xx, kappa Sigma2D_yy) and s_z along the normal -- the two conversions
+//     then differ only in the frame, which is what the comparison is about;
 //   * the standard 3DGS splatting the paper adopts (Sec. 2.1): first-order EWA projection of
 //     each Gaussian to a screen-space conic with a 0.3 px^2 low-pass dilation, a 3-sigma
 //     axis-aligned extent tested per pixel centre, and front-to-back alpha compositing with the
@@ -164,7 +169,7 @@ struct FaceSteps {
   double xp[3], yp[3];                    // Eq. 11 lifted eigenvectors
   double area, kappa;                     // |A|, Eq. 12
   double mu[3];                           // 3D mean: Eq. 3 applied to Eq. 4
-  double S[9];                            // Eq. 13 (cov_mode 0) or Eq. 15 (cov_mode 1)
+  double S[9];                            // Eq. 13 (cov_mode 0), Eq. 15 (1), edge-frame baseline (2)
 };
 
 bool face_literal(const double* vi, const double* vj, const double* vk, int cov_mode, FaceSteps* o) {
@@ -218,6 +223,14 @@ bool face_literal(const double* vi, const double* vj, const double* vk, int cov_
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c)
         o->S[3 * r + c] = sx2 * o->xp[r] * o->xp[c] + sy2 * o->yp[r] * o->yp[c] + sz2 * o->n_f[r] * o->n_f[c];
+  } else if (cov_mode == 2) {
+    // Baseline: rotation [x_axis (first edge), y_axis, n_f], diagonal scales in that frame.
+    const double sx2 = o->kappa * o->S2[0], sy2 = o->kappa * o->S2[2], sz2 = kSz * kSz;
+    const double* X = o->x_axis;
+    const double* Y = o->y_axis;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        o->S[3 * r + c] = sx2 * X[r] * X[c] + sy2 * Y[r] * Y[c] + sz2 * o->n_f[r] * o->n_f[c];
   } else {
     // Eq. 15: R_f blockdiag(Sigma2D, 0) R_f^T, R_f = [x_axis, y_axis, n_f].
     const double* X = o->x_axis;
@@ -258,6 +271,22 @@ bool convert_closed(const T* vi, const T* vj, const T* vk, int cov_mode, T* mu, 
   T det2 = area * area / 108.0;
   T kappa = (val(det2) >= kEps) ? area / (kPi * sqrt(det2)) : area / (kPi * std::sqrt(kEps));
   T n[3] = {m[0] / mm, m[1] / mm, m[2] / mm};
+  if (cov_mode == 2) {
+    // edge-frame baseline: x = e1 / |e1|, y = n x x; variances of kappa C along x and y
+    T l1 = sqrt(dot3(e1, e1));
+    T x[3] = {e1[0] / l1, e1[1] / l1, e1[2] / l1};
+    T y[3];
+    cross3(n, x, y);
+    T Cx[3], Cy[3];
+    for (int r = 0; r < 3; ++r) {
+      Cx[r] = C[3 * r] * x[0] + C[3 * r + 1] * x[1] + C[3 * r + 2] * x[2];
+      Cy[r] = C[3 * r] * y[0] + C[3 * r + 1] * y[1] + C[3 * r + 2] * y[2];
+    }
+    T sx2 = kappa * dot3(x, Cx), sy2 = kappa * dot3(y, Cy);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) S[3 * r + c] = sx2 * x[r] * x[c] + sy2 * y[r] * y[c] + (kSz * kSz) * n[r] * n[c];
+    return true;
+  }
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) S[3 * r + c] = kappa * C[3 * r + c] + (kSz * kSz) * n[r] * n[c];
   return true;

@@ -163,7 +163,7 @@ def test_literal_equals_closed_form_both_modes():
     Fc = rng.integers(0, 300, size=(400, 3)).astype(np.int32)
     Fc = Fc[(Fc[:, 0] != Fc[:, 1]) & (Fc[:, 1] != Fc[:, 2]) & (Fc[:, 0] != Fc[:, 2])]
     C = rng.uniform(size=(300, 3)).astype(f32)
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         mu, S, col, ok = oracle.convert(V, Fc, C, mode)
         mu2, S2, ok2 = oracle.convert_closed(V, Fc, mode)
         assert ok.all() and ok2.all()
@@ -178,6 +178,60 @@ def test_literal_equals_closed_form_both_modes():
             m = V.astype(float)[Fc].mean(1)
             q = V.astype(float)[Fc] - m[:, None, :]
             np.testing.assert_allclose(S, np.einsum("fki,fkj->fij", q, q) / 12.0, rtol=1e-12, atol=1e-15)
+
+
+# ---- the "3DGS-based" baseline conversion (Sec. 3.1, Baselines): frame from the normal and the
+# ---- first edge; scales read as the area-matched variances along those axes ------------------
+
+def test_baseline_right_triangle_worked_example():
+    """Right triangle in the xy plane, first edge along x: the frame is the world frame, so the
+    baseline keeps the diagonal of kappa Sigma2D (hand-derived values) and drops its -1/36."""
+    g = GOLD["right_triangle"]
+    s = oracle.face_steps(*np.array(g["vertices"], float), cov_mode=2)
+    k = g["kappa"]
+    want = np.diag([k * g["S2"][0], k * g["S2"][2], 1e-12])
+    np.testing.assert_allclose(s["S"], want, rtol=1e-13, atol=1e-16)
+    s0 = oracle.face_steps(*np.array(g["vertices"], float), cov_mode=0)
+    assert s0["S"][0, 1] == pytest.approx(k * g["S2"][1], rel=1e-13)      # what the baseline drops
+
+
+def test_baseline_equals_eq13_when_first_edge_is_principal():
+    """Isosceles triangle with its base as the first edge: by symmetry the base direction is a
+    principal axis of the triangle's covariance, so the edge frame is Eq. 14's frame."""
+    rng = np.random.default_rng(30)
+    for h in (0.3, 0.7, 2.5):
+        v = np.array([[-1.0, 0, 0], [1.0, 0, 0], [0, h, 0]])
+        q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        v = v @ q.T + rng.normal(size=3)
+        s0, s2 = oracle.face_steps(*v, cov_mode=0), oracle.face_steps(*v, cov_mode=2)
+        np.testing.assert_allclose(s2["S"], s0["S"], atol=1e-13 * np.abs(s0["S"]).max())
+
+
+def test_baseline_frame_and_invariants():
+    """For any triangle: the first edge and the normal are eigenvectors of the baseline's
+    covariance; its variance along the first edge and its in-plane trace are those of Eq. 13; it
+    moves rigidly with the triangle; unlike Eq. 13 it depends on which edge comes first."""
+    rng = np.random.default_rng(31)
+    changed = 0
+    for v in rand_tris(rng, 20):
+        s0, s2 = oracle.face_steps(*v, cov_mode=0), oracle.face_steps(*v, cov_mode=2)
+        S0, S2 = s0["S"], s2["S"]
+        tol = 1e-12 * np.abs(S0).max()
+        x = (v[1] - v[0]) / np.linalg.norm(v[1] - v[0])
+        n = np.cross(v[1] - v[0], v[2] - v[0]); n /= np.linalg.norm(n)
+        y = np.cross(n, x)
+        np.testing.assert_allclose(S2 @ x, (x @ S2 @ x) * x, atol=tol)
+        np.testing.assert_allclose(S2 @ n, 1e-12 * n, atol=tol)
+        assert x @ S2 @ x == pytest.approx(x @ S0 @ x, abs=tol)
+        assert np.trace(S2) == pytest.approx(np.trace(S0), abs=tol)
+        assert abs(x @ S2 @ y) <= tol
+        Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        t = rng.normal(size=3)
+        sr = oracle.face_steps(*(v @ Q.T + t), cov_mode=2)
+        np.testing.assert_allclose(sr["S"], Q @ S2 @ Q.T, atol=1e-13 * np.abs(S2).max())
+        sc = oracle.face_steps(*v[[1, 2, 0]], cov_mode=2)
+        changed += np.abs(sc["S"] - S2).max() > 1e-6 * np.abs(S2).max()
+    assert changed >= 18
 
 
 def test_permutation_and_rigid_invariance():
@@ -459,7 +513,7 @@ def _fd_check(V, Fc, C, cam, P, vids, seed=0, rtol=1e-5):
     assert l_c - l_0 == pytest.approx(float((dC * C.astype(float)).sum()), rel=1e-10, abs=1e-10)
 
 
-@pytest.mark.parametrize("cov_mode", [0, 1])
+@pytest.mark.parametrize("cov_mode", [0, 1, 2])
 def test_adjoint_vs_finite_differences(cov_mode):
     V, Fc, C, cam = small_scene(9, 12, W=48, H=40)
     P = oracle.Params(cov_mode=cov_mode, bg=(0.2, 0.3, 0.1))
