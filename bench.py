@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--raster-mode", type=int, default=None)
     ap.add_argument("--px-per-lane", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--lane-lists", type=int, default=None, choices=[0, 1])
+    ap.add_argument("--cov-mode", type=int, default=0, choices=[0, 1, 2],
+                    help="conversion: 0 Eq. 13, 1 Eq. 15, 2 the 3DGS-based edge-frame baseline")
     ap.add_argument("--no-graph", action="store_true", help="run the Adam loop eagerly (no HIP graph replay)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
@@ -151,6 +153,8 @@ def main():
     W = wl.make_workload(args.config)
     batch = gmr.Batch.from_workload(W)
     kw = {}
+    if args.cov_mode:
+        kw["cov_mode"] = args.cov_mode
     if args.tile:
         tw, th = (int(x) for x in args.tile.lower().split("x"))
         kw.update(tile_w=tw, tile_h=th)
@@ -168,8 +172,9 @@ def main():
         target, _, _, _ = r.forward(tverts, colors, check=True)
     target = target.clone()
     tuned_ms = None
-    if not args.no_autotune and not kw:
-        _, tuned_ms = r.autotune(verts, colors, target, iters=3)
+    if not args.no_autotune and not any(k != "cov_mode" for k in kw):
+        # more timed iterations where a step is short (the ranking of close candidates is noisy)
+        _, tuned_ms = r.autotune(verts, colors, target, iters=10 if W.num_pixels < (1 << 23) else 3)
     recompute = args.config in (3, 5)
     use_graph = args.config == 5
     P = W.num_pixels
@@ -366,7 +371,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": W.name, "faces": F, "verts": V, "views": W.num_views, "pixels": P,
                    "instances": I, "tile": f"{r.opts.tile_w}x{r.opts.tile_h}", "px_per_lane": r.opts.px_per_lane,
-                   "lane_lists": r.opts.lane_lists,
+                   "lane_lists": r.opts.lane_lists, "cov_mode": r.opts.cov_mode,
                    "raster_mode": r.opts.raster_mode, "autotune_ms": tuned_ms,
                    "recompute_lists": recompute, "adam_graph": use_graph},
         "roofline": roofline,

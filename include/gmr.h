@@ -53,7 +53,9 @@ typedef struct gmr_camera {
 
 /* Renderer options.  gmr_default_options() fills the defaults given in brackets. */
 typedef struct gmr_options {
-  int32_t cov_mode;          /* [0] 0: area-matched covariance (Eq. 13); 1: embedded Sigma2D (Eq. 15) */
+  int32_t cov_mode;          /* [0] 0: area-matched covariance (Eq. 13); 1: embedded Sigma2D (Eq. 15);
+                                2: the "3DGS-based" baseline of Sec. 3.1 (Baselines): frame from the
+                                normal and the first edge, diagonal scales kappa Sigma2D_xx, _yy, s_z */
   float dilation;            /* [0.3] screen-space low-pass added to the 2D covariance, px^2      */
   float alpha_min;           /* [1/255] Gaussians with alpha below it are skipped at a pixel       */
   float alpha_max;           /* [0.99] alpha clamp (keeps 1 - alpha >= 0.01)                      */

@@ -65,7 +65,7 @@ bool finite_pos(float x) { return std::isfinite(x) && x > 0.f; }
 
 gmr_status validate_options(const gmr_options* o) {
   if (!o) return fail(GMR_ERR_INVALID_ARG, "options is NULL");
-  if (o->cov_mode != 0 && o->cov_mode != 1) return fail(GMR_ERR_INVALID_ARG, "cov_mode must be 0 or 1");
+  if (o->cov_mode < 0 || o->cov_mode > 2) return fail(GMR_ERR_INVALID_ARG, "cov_mode must be 0, 1 or 2");
   if (!(std::isfinite(o->dilation) && o->dilation >= 0.f)) return fail(GMR_ERR_INVALID_ARG, "dilation must be finite and >= 0");
   if (!(o->alpha_min > 0.f && o->alpha_min < 1.f)) return fail(GMR_ERR_INVALID_ARG, "alpha_min must be in (0, 1)");
   if (!(o->alpha_max >= o->alpha_min && o->alpha_max < 1.f)) return fail(GMR_ERR_INVALID_ARG, "alpha_max must be in [alpha_min, 1)");

@@ -164,9 +164,12 @@ __device__ inline int find_view_by_tile(const ViewDev* views, int nv, int32_t t)
 
 // Conversion of one face (Sec. 2.2) in closed form, double precision.  The uniform triangle's
 // covariance sum_q (q - mu)(q - mu)^T / 12 written with the edges e1 = v_j - v_i, e2 = v_k - v_i
-// is (2 e1 e1^T + 2 e2 e2^T - e1 e2^T - e2 e1^T) / 36: the embedded 2D covariance of Eq. 15.
+// is C = (2 e1 e1^T + 2 e2 e2^T - e1 e2^T - e2 e1^T) / 36: the embedded 2D covariance of Eq. 15.
 // Eq. 13 scales it by kappa = |A| / (pi sqrt(max(lambda1 lambda2, eps))) with lambda1 lambda2 =
 // |A|^2 / 108 and adds s_z^2 n n^T.
+// cov_mode 2 is the "3DGS-based" baseline of Sec. 3.1 (Baselines): rotation from the normal (z)
+// and the first edge (x = e1 / |e1|, y = n x x), scales read as kappa C's variances along x and y
+// and s_z along n: S = kappa (x'Cx) x x' + kappa (y'Cy) y y' + s_z^2 n n'.
 struct FaceGeo {
   double e1[3], e2[3], m[3];   // edges and their cross product
   double mm, area, kappa;      // |m|, |A|, kappa (1 in the embedded form)
@@ -209,6 +212,21 @@ __device__ inline bool face_convert(const double* vi, const double* vj, const do
   g.kappa = g.area / (kPi * sqrt(g.clamped ? kEpsL : det2));
   double inv = 1.0 / g.mm;
   double n0 = g.m[0] * inv, n1 = g.m[1] * inv, n2 = g.m[2] * inv;
+  if (cov_mode == 2) {
+    const double il = 1.0 / sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    const double x[3] = {e1[0] * il, e1[1] * il, e1[2] * il};
+    const double y[3] = {n1 * x[2] - n2 * x[1], n2 * x[0] - n0 * x[2], n0 * x[1] - n1 * x[0]};
+    const double xMx = M[0] * x[0] * x[0] + M[3] * x[1] * x[1] + M[5] * x[2] * x[2] +
+                       2.0 * (M[1] * x[0] * x[1] + M[2] * x[0] * x[2] + M[4] * x[1] * x[2]);
+    const double yMy = M[0] * y[0] * y[0] + M[3] * y[1] * y[1] + M[5] * y[2] * y[2] +
+                       2.0 * (M[1] * y[0] * y[1] + M[2] * y[0] * y[2] + M[4] * y[1] * y[2]);
+    const double sx2 = g.kappa * xMx * (1.0 / 36.0), sy2 = g.kappa * yMy * (1.0 / 36.0);
+    const double n[3] = {n0, n1, n2};
+    const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
+    for (int a = 0; a < 6; ++a)
+      g.S[a] = sx2 * x[rr[a]] * x[cc[a]] + sy2 * y[rr[a]] * y[cc[a]] + kSz2 * n[rr[a]] * n[cc[a]];
+    return true;
+  }
   double k36 = g.kappa * (1.0 / 36.0);
   g.S[0] = k36 * M[0] + kSz2 * n0 * n0;
   g.S[1] = k36 * M[1] + kSz2 * n0 * n1;

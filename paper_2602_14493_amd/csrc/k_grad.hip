@@ -115,8 +115,70 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
     }
   const double* e1 = g.e1;
   const double* e2 = g.e2;
-  const double scale = (o.cov_mode == 1 ? 1.0 : g.kappa) / 36.0;
   double Ge1[3], Ge2[3];
+  if (o.cov_mode == 2) {
+    // S = kappa a x x' + kappa b y y' + s_z^2 n n', a = x'Cx, b = y'Cy, x = e1/|e1|, y = n x x
+    const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    const double inv = 1.0 / g.mm;
+    const double n[3] = {g.m[0] * inv, g.m[1] * inv, g.m[2] * inv};
+    const double x[3] = {e1[0] / l1, e1[1] / l1, e1[2] / l1};
+    const double y[3] = {n[1] * x[2] - n[2] * x[1], n[2] * x[0] - n[0] * x[2], n[0] * x[1] - n[1] * x[0]};
+    double Cm[3][3];  // C = M / 36
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc)
+        Cm[r][cc] = (2.0 * e1[r] * e1[cc] + 2.0 * e2[r] * e2[cc] - e1[r] * e2[cc] - e2[r] * e1[cc]) * (1.0 / 36.0);
+    double Cx[3], Cy[3], Gx_[3], Gy_[3];
+    for (int r = 0; r < 3; ++r) {
+      Cx[r] = Cm[r][0] * x[0] + Cm[r][1] * x[1] + Cm[r][2] * x[2];
+      Cy[r] = Cm[r][0] * y[0] + Cm[r][1] * y[1] + Cm[r][2] * y[2];
+      Gx_[r] = GS[r][0] * x[0] + GS[r][1] * x[1] + GS[r][2] * x[2];
+      Gy_[r] = GS[r][0] * y[0] + GS[r][1] * y[1] + GS[r][2] * y[2];
+    }
+    const double a = x[0] * Cx[0] + x[1] * Cx[1] + x[2] * Cx[2];
+    const double b = y[0] * Cy[0] + y[1] * Cy[1] + y[2] * Cy[2];
+    const double gxs = x[0] * Gx_[0] + x[1] * Gx_[1] + x[2] * Gx_[2];
+    const double gys = y[0] * Gy_[0] + y[1] * Gy_[1] + y[2] * Gy_[2];
+    const double kp = g.kappa;
+    // through C: G_C = kappa (gxs x x' + gys y y'), and C's edge form as in the other modes
+    for (int r = 0; r < 3; ++r) {
+      const double xe1 = x[0] * e1[0] + x[1] * e1[1] + x[2] * e1[2], xe2 = x[0] * e2[0] + x[1] * e2[1] + x[2] * e2[2];
+      const double ye1 = y[0] * e1[0] + y[1] * e1[1] + y[2] * e1[2], ye2 = y[0] * e2[0] + y[1] * e2[1] + y[2] * e2[2];
+      const double G1 = kp * (gxs * x[r] * xe1 + gys * y[r] * ye1);
+      const double G2 = kp * (gxs * x[r] * xe2 + gys * y[r] * ye2);
+      Ge1[r] = (4.0 * G1 - 2.0 * G2) * (1.0 / 36.0);
+      Ge2[r] = (4.0 * G2 - 2.0 * G1) * (1.0 / 36.0);
+    }
+    // through the frame
+    double Gx[3], Gy[3], Gn[3];
+    for (int r = 0; r < 3; ++r) {
+      Gx[r] = 2.0 * kp * (gxs * Cx[r] + a * Gx_[r]);
+      Gy[r] = 2.0 * kp * (gys * Cy[r] + b * Gy_[r]);
+      Gn[r] = 2.0 * kSz2 * (GS[r][0] * n[0] + GS[r][1] * n[1] + GS[r][2] * n[2]);
+    }
+    // y = n x x: dL/dn += x x Gy, dL/dx += Gy x n
+    Gn[0] += x[1] * Gy[2] - x[2] * Gy[1];
+    Gn[1] += x[2] * Gy[0] - x[0] * Gy[2];
+    Gn[2] += x[0] * Gy[1] - x[1] * Gy[0];
+    Gx[0] += Gy[1] * n[2] - Gy[2] * n[1];
+    Gx[1] += Gy[2] * n[0] - Gy[0] * n[2];
+    Gx[2] += Gy[0] * n[1] - Gy[1] * n[0];
+    const double xGx = x[0] * Gx[0] + x[1] * Gx[1] + x[2] * Gx[2];
+    for (int r = 0; r < 3; ++r) Ge1[r] += (Gx[r] - x[r] * xGx) / l1;
+    const double nGn = n[0] * Gn[0] + n[1] * Gn[1] + n[2] * Gn[2];
+    double Gm[3];
+    for (int r = 0; r < 3; ++r) Gm[r] = (Gn[r] - n[r] * nGn) * inv;
+    if (g.clamped) {  // kappa = |m| / (2 pi sqrt(eps))
+      const double gk = a * gxs + b * gys;
+      for (int r = 0; r < 3; ++r) Gm[r] += gk * n[r] / (2.0 * kPi * sqrt(kEpsL));
+    }
+    Ge1[0] += e2[1] * Gm[2] - e2[2] * Gm[1];
+    Ge1[1] += e2[2] * Gm[0] - e2[0] * Gm[2];
+    Ge1[2] += e2[0] * Gm[1] - e2[1] * Gm[0];
+    Ge2[0] += Gm[1] * e1[2] - Gm[2] * e1[1];
+    Ge2[1] += Gm[2] * e1[0] - Gm[0] * e1[2];
+    Ge2[2] += Gm[0] * e1[1] - Gm[1] * e1[0];
+  } else {
+  const double scale = (o.cov_mode == 1 ? 1.0 : g.kappa) / 36.0;
   for (int r = 0; r < 3; ++r) {
     const double G1 = GS[r][0] * e1[0] + GS[r][1] * e1[1] + GS[r][2] * e1[2];
     const double G2 = GS[r][0] * e2[0] + GS[r][1] * e2[1] + GS[r][2] * e2[2];
@@ -151,6 +213,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
     Ge2[0] += Gm[1] * e1[2] - Gm[2] * e1[1];
     Ge2[1] += Gm[2] * e1[0] - Gm[0] * e1[2];
     Ge2[2] += Gm[0] * e1[1] - Gm[1] * e1[0];
+  }
   }
   float gv[9];
   for (int r = 0; r < 3; ++r) {

@@ -70,7 +70,7 @@ def test_view_table_and_workspace_sizes():
     assert ws.value >= (1 << 20) * 24 + fv_total * (48 + 16 + 4 + 32)
 
 
-@pytest.mark.parametrize("field,value", [("cov_mode", 2), ("tile_w", 12), ("tile_h", 72), ("alpha_min", 0.0),
+@pytest.mark.parametrize("field,value", [("cov_mode", 3), ("tile_w", 12), ("tile_h", 72), ("alpha_min", 0.0),
                                          ("t_eps", 1.5), ("raster_mode", 3), ("px_per_lane", 3),
                                          ("lane_lists", 2), ("lane_lists", -1), ("reserved_opt", 1),
                                          ("instance_capacity", 0), ("instance_capacity", 1 << 30)])

@@ -28,7 +28,7 @@ def oracle_params(**kw):
 # images and gradients vs the oracle
 # ------------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("cov_mode", [0, 1])
+@pytest.mark.parametrize("cov_mode", [0, 1, 2])
 def test_cfg1_image_and_grads(gpu, cov_mode):
     say(f"cfg1 icosphere s2 128^2 cov_mode={cov_mode}")
     W = wl.make_workload(1)
@@ -98,6 +98,28 @@ def test_cfg2_images_and_crop_loss_grads(gpu):
     oV, oC = oracle.adjoint_workload(W, g)
     compare_grads(dV, oV, "cfg2 crop dV")
     compare_grads(dC, oC, "cfg2 crop dC")
+
+
+def test_baseline_conversion_multiview(gpu):
+    """The "3DGS-based" baseline conversion (cov_mode 2) through the whole path on the 8-view
+    icosphere (128^2 views): images and the L2 gradients vs the oracle, and it differs from Eq. 13."""
+    import torch
+    say("cfg2 scale 0.25, cov_mode 2")
+    W = wl.make_workload(2, scale=0.25)
+    r, verts, colors = gpu_setup(W, cov_mode=2)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    P = oracle_params(cov_mode=2)
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W, P)
+    compare_images(rgb, alpha, o_rgb, o_tf, o_mask, label="cfg2/4 mode2")
+    tgt, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    _, g = oracle.l2_loss(o_rgb, tgt)
+    g = g * (~o_mask)[:, None]
+    dV, dC = r.backward(verts, colors, torch.from_numpy(g.astype(np.float32)).cuda(), None, saved, ws)
+    oV, oC = oracle.adjoint_workload(W, g, None, P)
+    compare_grads(dV, oV, "cfg2/4 mode2 dV")
+    compare_grads(dC, oC, "cfg2/4 mode2 dC")
+    o0, _, _, _ = oracle.render_workload(W)
+    assert np.abs(o0 - o_rgb).max() > 1e-2
 
 
 def test_cfg5_view0_image_full_size(gpu):
