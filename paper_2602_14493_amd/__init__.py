@@ -3,6 +3,11 @@ rasteriser as hand-written HIP kernels behind the C ABI of include/gmr.h (libgmr
 
 Importing the package loads libgmr.so and fails if it has not been built; there is no fallback.
 """
+# torch first: libgmr.so then binds to the HIP runtime torch has already loaded, so the library
+# and torch's allocator and streams share one runtime (loading the library first pulled in a second
+# runtime, which found no device)
+import torch  # noqa: F401
+
 from . import _lib
 from ._lib import GMRError, gmr_options
 

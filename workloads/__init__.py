@@ -59,6 +59,37 @@ def icosphere(subdiv: int):
     return np.stack(verts).astype(np.float64), np.asarray(faces, dtype=np.int32)
 
 
+def geodesic_sphere(freq: int):
+    """Unit geodesic sphere of frequency `freq`: every icosahedron face split into freq^2
+    triangles on its barycentric grid, points pushed onto the sphere, shared points merged.
+    20 freq^2 faces, 10 freq^2 + 2 vertices (freq = 45: 40,500 faces)."""
+    base_v, base_f = icosphere(0)
+    index: dict[tuple[int, int, int], int] = {}
+    verts: list[np.ndarray] = []
+
+    def vid(p):
+        p = p / np.linalg.norm(p)
+        key = tuple(int(round(x * 1e9)) for x in p)
+        if key not in index:
+            index[key] = len(verts)
+            verts.append(p)
+        return index[key]
+
+    faces = []
+    for a, b, c in base_f:
+        A, B, C = base_v[a], base_v[b], base_v[c]
+        grid = {}
+        for i in range(freq + 1):
+            for j in range(freq + 1 - i):
+                grid[i, j] = vid(A + (B - A) * (i / freq) + (C - A) * (j / freq))
+        for i in range(freq):
+            for j in range(freq - i):
+                faces.append((grid[i, j], grid[i + 1, j], grid[i, j + 1]))
+                if i + j < freq - 1:
+                    faces.append((grid[i + 1, j], grid[i + 1, j + 1], grid[i, j + 1]))
+    return np.stack(verts), np.asarray(faces, dtype=np.int32)
+
+
 def uv_sphere(n_az: int, n_polar: int, radius_fn=None):
     """UV sphere with `n_az` azimuth segments and `n_polar` polar bands: two pole vertices,
     n_polar-1 rings of n_az vertices, pole fans and quads split into two triangles.
@@ -180,6 +211,16 @@ def fibonacci_dirs(n: int) -> np.ndarray:
     rad = np.sqrt(np.maximum(0.0, 1.0 - y * y))
     ga = math.pi * (3.0 - math.sqrt(5.0))
     th = ga * i
+    return np.stack([rad * np.cos(th), y, rad * np.sin(th)], axis=-1)
+
+
+def hemisphere_dirs(n: int) -> np.ndarray:
+    """n unit vectors spread uniformly over the upper (y >= 0) hemisphere: y_i = 1 - (i + 1/2)/n,
+    golden-angle azimuth."""
+    i = np.arange(n, dtype=np.float64)
+    y = 1.0 - (i + 0.5) / n
+    rad = np.sqrt(np.maximum(0.0, 1.0 - y * y))
+    th = math.pi * (3.0 - math.sqrt(5.0)) * i
     return np.stack([rad * np.cos(th), y, rad * np.sin(th)], axis=-1)
 
 
