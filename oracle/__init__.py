@@ -60,6 +60,8 @@ def lib():
             L.gmro_render_adjoint.restype = i64
             L.gmro_tile_lists.argtypes = [i64, P, i64, P, P, i64, P, P, i32, i32, P, P, P, i64]
             L.gmro_tile_lists.restype = i64
+            L.gmro_sh_basis.argtypes = [i32, i64, P, P]
+            L.gmro_sh_basis.restype = i64
             L.gmro_num_threads.restype = i32
             _lib = L
     return _lib
@@ -71,6 +73,16 @@ def _p(a):
 
 def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
+
+
+def _colours(colors, nv: int, params: "Params") -> np.ndarray:
+    """Colour input as float32, checked against the colour model: [V,3] at degree 0, else
+    [V, (degree + 1)^2, 3] coefficients (coefficient 0 is the colour itself)."""
+    C = _c(colors, f32)
+    k = (params.sh_degree + 1) ** 2
+    if C.size != nv * 3 * k:
+        raise ValueError(f"colours must hold {k} x 3 values per vertex for sh_degree {params.sh_degree}")
+    return C
 
 
 @dataclass
@@ -89,10 +101,21 @@ class Params:
     d_alpha: float = 1e-5                # relative
     alpha_err: float = 2e-6              # relative error bound of a float32 alpha
     nsig: float = 3.0
+    sh_degree: int = 0                   # 0: Eq. 16 colours [V,3]; 1-3: coefficients [V,(d+1)^2,3]
 
     def array(self) -> np.ndarray:
         return np.array([self.cov_mode, self.dilation, self.alpha_min, self.alpha_max, self.t_eps,
-                         *self.bg, self.d_ext, self.d_alpha, self.alpha_err, self.nsig], dtype=np.float64)
+                         *self.bg, self.d_ext, self.d_alpha, self.alpha_err, self.nsig, self.sh_degree],
+                        dtype=np.float64)
+
+
+def sh_basis(degree: int, dirs) -> np.ndarray:
+    """The view-dependent colour basis (Y[0] = 1, then real harmonics of degree 1..degree) on unit
+    directions [n,3]; returns [n, (degree + 1)^2]."""
+    d = _c(np.asarray(dirs).reshape(-1, 3), np.float64)
+    out = np.zeros((len(d), 16))
+    lib().gmro_sh_basis(int(degree), len(d), _p(d), _p(out))
+    return out[:, :(degree + 1) ** 2]
 
 
 def num_threads() -> int:
@@ -105,7 +128,8 @@ def num_threads() -> int:
 
 def convert(verts, faces, colors, cov_mode: int = 0):
     """Literal conversion of every face.  Returns mu [F,3], Sigma [F,3,3], colour [F,3], valid [F]."""
-    V, Fc, C = _c(verts, f32), _c(faces, np.int32), _c(colors, f32)
+    V, Fc = _c(verts, f32), _c(faces, np.int32)
+    C = _c(colors, f32)
     nf = len(Fc)
     mu = np.zeros((nf, 3)); S = np.zeros((nf, 9)); col = np.zeros((nf, 3)); valid = np.zeros(nf, np.uint8)
     lib().gmro_convert(len(V), _p(V), nf, _p(Fc), _p(C), cov_mode, _p(mu), _p(S), _p(col), _p(valid))
@@ -151,7 +175,8 @@ def project_one(mu, S, cam_arr, dilation=Params.dilation, nsig=3.0):
 def gaussians(verts, faces, colors, cam_arr, params: Params | None = None):
     """Per-face screen-space Gaussians for one view: array [F,12] = ok u v a b c rx ry depth r g b."""
     params = params or Params()
-    V, Fc, C = _c(verts, f32), _c(faces, np.int32), _c(colors, f32)
+    V, Fc = _c(verts, f32), _c(faces, np.int32)
+    C = _colours(colors, len(V), params)
     out = np.zeros((len(Fc), 12))
     lib().gmro_gaussians(len(V), _p(V), len(Fc), _p(Fc), _p(C), _p(_c(cam_arr, np.float64)),
                          _p(params.array()), _p(out))
@@ -173,7 +198,8 @@ def render_view(verts, faces, colors, cam_arr, params: Params | None = None, gid
     win = np.array(window if window is not None else (0, 0, W, H), dtype=np.int32)
     win = np.array([max(0, win[0]), max(0, win[1]), min(W, win[2]), min(H, win[3])], dtype=np.int32)
     w, h = max(0, int(win[2] - win[0])), max(0, int(win[3] - win[1]))
-    V, Fc, C = _c(verts, f32), _c(faces, np.int32), _c(colors, f32)
+    V, Fc = _c(verts, f32), _c(faces, np.int32)
+    C = _colours(colors, len(V), params)
     rgb = np.zeros((h, w, 3)); Tf = np.zeros((h, w)); nc = np.zeros((h, w), np.int32)
     mask = np.zeros((h, w), np.uint8)
     lh = np.zeros((h, w), np.uint64) if want_hash else None
@@ -186,17 +212,18 @@ def render_view(verts, faces, colors, cam_arr, params: Params | None = None, gid
 
 def adjoint_view(verts, faces, colors, cam_arr, g_rgb, g_alpha=None, params: Params | None = None,
                  gid_base: int = 0, window=None, want_screen_grads=False):
-    """Exact adjoint of render_view: returns (dV [V,3], dC [V,3]) (and the per-face screen-space
-    gradients [F,8] when want_screen_grads)."""
+    """Exact adjoint of render_view: returns (dV [V,3], dC shaped like colors) (and the per-face
+    screen-space gradients [F,8] when want_screen_grads)."""
     params = params or Params()
     cam_arr = _c(cam_arr, np.float64)
     W, H = int(cam_arr[16]), int(cam_arr[17])
     win = np.array(window if window is not None else (0, 0, W, H), dtype=np.int32)
     win = np.array([max(0, win[0]), max(0, win[1]), min(W, win[2]), min(H, win[3])], dtype=np.int32)
-    V, Fc, C = _c(verts, f32), _c(faces, np.int32), _c(colors, f32)
+    V, Fc = _c(verts, f32), _c(faces, np.int32)
+    C = _colours(colors, len(V), params)
     g_rgb = _c(g_rgb, np.float64)
     g_alpha = None if g_alpha is None else _c(g_alpha, np.float64)
-    dV = np.zeros((len(V), 3)); dC = np.zeros((len(V), 3))
+    dV = np.zeros((len(V), 3)); dC = np.zeros(C.shape)
     gG = np.zeros((len(Fc), 8)) if want_screen_grads else None
     lib().gmro_render_adjoint(len(V), _p(V), len(Fc), _p(Fc), _p(C), gid_base, _p(cam_arr),
                               _p(params.array()), _p(win), _p(g_rgb), _p(g_alpha), _p(dV), _p(dC), _p(gG))
@@ -213,7 +240,8 @@ def tile_lists_view(verts, faces, colors, cam_arr, tile_w, tile_h, params: Param
     cam_arr = _c(cam_arr, np.float64)
     W, H = int(cam_arr[16]), int(cam_arr[17])
     nt = ((W + tile_w - 1) // tile_w) * ((H + tile_h - 1) // tile_h)
-    V, Fc, C = _c(verts, f32), _c(faces, np.int32), _c(colors, f32)
+    V, Fc = _c(verts, f32), _c(faces, np.int32)
+    C = _colours(colors, len(V), params)
     off = np.zeros(nt + 1, np.int64)
     cap = 1 << 16
     while True:
@@ -229,11 +257,12 @@ def tile_lists_view(verts, faces, colors, cam_arr, tile_w, tile_h, params: Param
 # whole workloads (views laid out back to back, row-major, like the GPU output)
 # ------------------------------------------------------------------------------------------------
 
-def render_workload(wl, params: Params | None = None, verts=None, views=None):
+def render_workload(wl, params: Params | None = None, verts=None, views=None, colors=None):
     """Render every view of a workloads.Workload.  Returns flat (rgb [P,3], Tf [P], ncomp [P],
     mask [P]) with the views back to back."""
     params = params or Params()
     verts = wl.verts if verts is None else verts
+    colors = wl.colors if colors is None else colors
     views = range(wl.num_views) if views is None else views
     rgbs, tfs, ncs, masks = [], [], [], []
     cams = wl.cam_array()
@@ -241,18 +270,19 @@ def render_workload(wl, params: Params | None = None, verts=None, views=None):
         m = int(wl.view_mesh[v])
         v0, v1 = int(wl.vert_offsets[m]), int(wl.vert_offsets[m + 1])
         f0, f1 = int(wl.face_offsets[m]), int(wl.face_offsets[m + 1])
-        rgb, tf, nc, mk = render_view(verts[v0:v1], wl.faces[f0:f1] - v0, wl.colors[v0:v1], cams[v],
+        rgb, tf, nc, mk = render_view(verts[v0:v1], wl.faces[f0:f1] - v0, colors[v0:v1], cams[v],
                                       params, gid_base=f0)
         rgbs.append(rgb.reshape(-1, 3)); tfs.append(tf.reshape(-1)); ncs.append(nc.reshape(-1))
         masks.append(mk.reshape(-1))
     return np.concatenate(rgbs), np.concatenate(tfs), np.concatenate(ncs), np.concatenate(masks)
 
 
-def adjoint_workload(wl, g_rgb, g_alpha=None, params: Params | None = None, verts=None):
+def adjoint_workload(wl, g_rgb, g_alpha=None, params: Params | None = None, verts=None, colors=None):
     """Adjoint over every view of a workload; g_rgb [P,3] and g_alpha [P] in the flat layout."""
     params = params or Params()
     verts = wl.verts if verts is None else verts
-    dV = np.zeros((len(verts), 3)); dC = np.zeros((len(verts), 3))
+    colors = wl.colors if colors is None else colors
+    dV = np.zeros((len(verts), 3)); dC = np.zeros(np.shape(colors), np.float64)
     cams = wl.cam_array()
     po = wl.pixel_offsets()
     for v in range(wl.num_views):
@@ -262,7 +292,7 @@ def adjoint_workload(wl, g_rgb, g_alpha=None, params: Params | None = None, vert
         W, H = wl.cams[v].width, wl.cams[v].height
         gr = g_rgb[po[v]:po[v + 1]].reshape(H, W, 3)
         ga = None if g_alpha is None else g_alpha[po[v]:po[v + 1]].reshape(H, W)
-        dv, dc = adjoint_view(verts[v0:v1], wl.faces[f0:f1] - v0, wl.colors[v0:v1], cams[v], gr, ga, params,
+        dv, dc = adjoint_view(verts[v0:v1], wl.faces[f0:f1] - v0, colors[v0:v1], cams[v], gr, ga, params,
                               gid_base=f0)
         dV[v0:v1] += dv
         dC[v0:v1] += dc

@@ -23,6 +23,12 @@
 //     alpha cutoff 1/255, alpha clamp 0.99 and transmittance stop 1e-4 (all three as the
 //     float32-rounded constants the caller passes in), per pixel over that pixel's Gaussians
 //     ordered by (float32(depth), global id) -- no tiles;
+//   * view-dependent colour, the extension named with the colour assignment of Sec. 2.2: each
+//     vertex carries K = (degree + 1)^2 coefficients per channel; a face takes their mean (as in
+//     Eq. 16); per view its colour is max(0, c_0 + sum_{k >= 1} c_k Y_k(d)), d the unit direction
+//     from the camera centre to the Gaussian's mean and Y_k the real spherical harmonics of degree
+//     1-3 in the sign convention of 3DGS.  c_0 is the colour itself (the DC encode/decode cancel),
+//     so degree 0, or zero higher coefficients, is exactly Eq. 16;
 //   * the exact adjoint of that composite, chained to vertices and colours.  The chain through
 //     projection and conversion uses forward-mode dual numbers over the closed form
 //     Sigma = kappa/12 * sum_q q q^T + s_z^2 n n^T, which equals Eq. 13 exactly (pinned against
@@ -114,6 +120,42 @@ inline void cross3(const T* a, const T* b, T* c) {
 const double kPi = 3.14159265358979323846;
 const double kEps = 1e-14;   // Eq. 12 (epsilon on lambda1*lambda2)
 const double kSz = 1e-6;     // s_z, Sec. 2.2 after Eq. 12
+
+// ------------------------------------------------------------------------------------------------
+// Real spherical harmonics up to degree 3 on a unit direction d = (x, y, z): Y[0] = 1 (the colour
+// itself), then the orthonormal real harmonics with the normalisations sqrt((2l+1)/(4 pi) ...)
+// written out and the sign convention of 3DGS.
+// ------------------------------------------------------------------------------------------------
+template <class T>
+void sh_basis(int degree, const T* d, T* Y) {
+  const double c1 = std::sqrt(3.0 / (4.0 * kPi));
+  const double c2a = std::sqrt(15.0 / (4.0 * kPi)), c2b = std::sqrt(5.0 / (16.0 * kPi)),
+               c2c = std::sqrt(15.0 / (16.0 * kPi));
+  const double c3a = std::sqrt(35.0 / (32.0 * kPi)), c3b = std::sqrt(105.0 / (4.0 * kPi)),
+               c3c = std::sqrt(21.0 / (32.0 * kPi)), c3d = std::sqrt(7.0 / (16.0 * kPi)),
+               c3e = std::sqrt(105.0 / (16.0 * kPi));
+  const T x = d[0], y = d[1], z = d[2];
+  Y[0] = T(1.0);
+  if (degree < 1) return;
+  Y[1] = -c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = -c1 * x;
+  if (degree < 2) return;
+  const T xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = c2a * (x * y);
+  Y[5] = -c2a * (y * z);
+  Y[6] = c2b * (2.0 * zz - xx - yy);
+  Y[7] = -c2a * (x * z);
+  Y[8] = c2c * (xx - yy);
+  if (degree < 3) return;
+  Y[9] = -c3a * (y * (3.0 * xx - yy));
+  Y[10] = c3b * (x * y * z);
+  Y[11] = -c3c * (y * (4.0 * zz - xx - yy));
+  Y[12] = c3d * (z * (2.0 * zz - 3.0 * xx - 3.0 * yy));
+  Y[13] = -c3c * (x * (4.0 * zz - xx - yy));
+  Y[14] = c3e * (z * (xx - yy));
+  Y[15] = -c3a * (x * (xx - 3.0 * yy));
+}
 
 // ------------------------------------------------------------------------------------------------
 // Conversion, literal route of Sec. 2.2 (double only)
@@ -361,6 +403,7 @@ bool project(const T* mu, const T* S, const Cam& cam, double dilation, double ns
 
 struct Params {
   int cov_mode;
+  int sh_degree;     // 0: one colour per vertex (Eq. 16); 1-3: view-dependent colour
   double dilation, amin, amax, teps, bg[3];
   double d_ext;      // extent margin (px) within which the inside/outside decision counts as near
   double d_alpha;    // relative margin around the alpha cutoff and the alpha clamp
@@ -375,6 +418,7 @@ Params make_params(const double* a) {
   p.bg[0] = a[5]; p.bg[1] = a[6]; p.bg[2] = a[7];
   p.d_ext = a[8]; p.d_alpha = a[9]; p.alpha_err = a[10];
   p.nsig = a[11];
+  p.sh_degree = (int)a[12];
   return p;
 }
 
@@ -391,8 +435,38 @@ uint32_t f32bits(double x) {
   return b;
 }
 
+// Camera centre in world coordinates: -R^T t.
+void cam_centre(const Cam& cam, double* c) {
+  for (int i = 0; i < 3; ++i) c[i] = -(cam.R[i] * cam.t[0] + cam.R[3 + i] * cam.t[1] + cam.R[6 + i] * cam.t[2]);
+}
+
+// Mean colour coefficients of a face (Eq. 16 applied to every coefficient): coef[k][c].
+void face_coefs(const float* Cc, int K, const int32_t* id, double (*coef)[3]) {
+  for (int k = 0; k < K; ++k)
+    for (int c = 0; c < 3; ++c)
+      coef[k][c] = ((double)Cc[((size_t)id[0] * K + k) * 3 + c] + (double)Cc[((size_t)id[1] * K + k) * 3 + c] +
+                    (double)Cc[((size_t)id[2] * K + k) * 3 + c]) / 3.0;
+}
+
+// The face's colour in this view (before the clamp at 0), from its mean and coefficients.
+template <class T>
+void view_colour(int degree, const double (*coef)[3], const T* mu, const double* centre, T* raw, T* Y) {
+  const int K = (degree + 1) * (degree + 1);
+  T d[3] = {mu[0] - centre[0], mu[1] - centre[1], mu[2] - centre[2]};
+  T r = sqrt(dot3(d, d));
+  for (int i = 0; i < 3; ++i) d[i] = d[i] / r;
+  sh_basis(degree, d, Y);
+  for (int c = 0; c < 3; ++c) {
+    raw[c] = T(0.0);
+    for (int k = 0; k < K; ++k) raw[c] = raw[c] + coef[k][c] * Y[k];
+  }
+}
+
 void setup(long nv, const float* V, long nf, const int32_t* F, const float* Cc, long gid_base,
            const Cam& cam, const Params& P, std::vector<Gauss>& G) {
+  const int K = (P.sh_degree + 1) * (P.sh_degree + 1);
+  double centre[3];
+  cam_centre(cam, centre);
   G.assign(nf, Gauss{});
 #pragma omp parallel for schedule(static)
   for (long f = 0; f < nf; ++f) {
@@ -411,7 +485,15 @@ void setup(long nv, const float* V, long nf, const int32_t* F, const float* Cc, 
     g.u = pr.u; g.v = pr.v;
     g.a = pr.conic[0]; g.b = pr.conic[1]; g.c = pr.conic[2];
     g.rx = pr.rx; g.ry = pr.ry; g.depth = pr.depth;
-    for (int i = 0; i < 3; ++i) g.col[i] = ((double)Cc[3 * id[0] + i] + (double)Cc[3 * id[1] + i] + (double)Cc[3 * id[2] + i]) / 3.0;  // Eq. 16
+    double coef[16][3];
+    face_coefs(Cc, K, id, coef);  // Eq. 16
+    if (P.sh_degree == 0) {
+      for (int i = 0; i < 3; ++i) g.col[i] = coef[0][i];
+    } else {
+      double raw[3], Y[16];
+      view_colour(P.sh_degree, coef, st.mu, centre, raw, Y);
+      for (int i = 0; i < 3; ++i) g.col[i] = std::max(0.0, raw[i]);
+    }
     g.key = ((uint64_t)f32bits(pr.depth) << 32) | (uint64_t)(uint32_t)(gid_base + f);
   }
 }
@@ -598,6 +680,12 @@ int gmro_project_one(const double* mu, const double* S, const double* cam, doubl
   return 1;
 }
 
+// The colour basis on n unit directions: out[n][16] (entries past (degree + 1)^2 left untouched).
+long gmro_sh_basis(int degree, long n, const double* dirs, double* out) {
+  for (long i = 0; i < n; ++i) sh_basis(degree, dirs + 3 * i, out + 16 * i);
+  return n;
+}
+
 // Per-Gaussian screen-space record for one view: out[nf][12] = ok u v a b c rx ry depth r g b.
 long gmro_gaussians(long nv, const float* V, long nf, const int32_t* F, const float* C, const double* cam,
                     const double* prm, double* out) {
@@ -706,8 +794,12 @@ long gmro_render_adjoint(long nv, const float* V, long nf, const int32_t* F, con
       }
     }
   }
-  // Chain (u, v, a, b, c) -> vertices with dual numbers; colours by Eq. 16.
-  std::vector<double> dVl(3 * (size_t)nv, 0.0), dCl(3 * (size_t)nv, 0.0);
+  // Chain (u, v, a, b, c) -> vertices with dual numbers; colours by Eq. 16 (and, with view-dependent
+  // colour, through the coefficients and through the viewing direction's dependence on the mean).
+  const int K = (P.sh_degree + 1) * (P.sh_degree + 1);
+  double centre[3];
+  cam_centre(cm, centre);
+  std::vector<double> dVl(3 * (size_t)nv, 0.0), dCl(3 * (size_t)nv * K, 0.0);
   for (long f = 0; f < nf; ++f) {
     const double* gg = GG.data() + 8 * f;
     if (gG)
@@ -727,15 +819,30 @@ long gmro_render_adjoint(long nv, const float* V, long nf, const int32_t* F, con
     Proj<Dual> pr;
     if (!project(mu, S, cm, P.dilation, P.nsig, &pr)) continue;
     const Dual* outs[5] = {&pr.u, &pr.v, &pr.conic[0], &pr.conic[1], &pr.conic[2]};
+    double coef[16][3];
+    face_coefs(C, K, id, coef);
+    Dual raw[3], Y[16];
+    double gcol[3] = {gg[5], gg[6], gg[7]};  // dL/d(colour), zero where the clamp at 0 is active
+    if (P.sh_degree > 0) {
+      view_colour(P.sh_degree, coef, mu, centre, raw, Y);
+      for (int c = 0; c < 3; ++c)
+        if (!(val(raw[c]) > 0.0)) gcol[c] = 0.0;
+    }
     for (int k = 0; k < 3; ++k)
       for (int i = 0; i < 3; ++i) {
         double s = 0.0;
         for (int q = 0; q < 5; ++q) s += gg[q] * outs[q]->d[3 * k + i];
+        if (P.sh_degree > 0)
+          for (int c = 0; c < 3; ++c) s += gcol[c] * raw[c].d[3 * k + i];  // through the direction
         dVl[3 * (size_t)id[k] + i] += s;
-        dCl[3 * (size_t)id[k] + i] += gg[5 + i] / 3.0;
       }
+    for (int k = 0; k < 3; ++k)
+      for (int j = 0; j < K; ++j)
+        for (int c = 0; c < 3; ++c)
+          dCl[((size_t)id[k] * K + j) * 3 + c] += gcol[c] * (P.sh_degree > 0 ? val(Y[j]) : 1.0) / 3.0;
   }
-  for (long i = 0; i < 3 * nv; ++i) { dV[i] += dVl[i]; dC[i] += dCl[i]; }
+  for (long i = 0; i < 3 * nv; ++i) dV[i] += dVl[i];
+  for (long i = 0; i < 3 * nv * K; ++i) dC[i] += dCl[i];
   return np;
 }
 
