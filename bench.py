@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--raster-mode", type=int, default=None)
     ap.add_argument("--px-per-lane", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--lane-lists", type=int, default=None, choices=[0, 1])
+    ap.add_argument("--sh-degree", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="view-dependent colour: coefficient 0 = the workload's colours, the rest N(0, 0.1)")
     ap.add_argument("--cov-mode", type=int, default=0, choices=[0, 1, 2],
                     help="conversion: 0 Eq. 13, 1 Eq. 15, 2 the 3DGS-based edge-frame baseline")
     ap.add_argument("--no-graph", action="store_true", help="run the Adam loop eagerly (no HIP graph replay)")
@@ -155,6 +157,8 @@ def main():
     kw = {}
     if args.cov_mode:
         kw["cov_mode"] = args.cov_mode
+    if args.sh_degree:
+        kw["sh_degree"] = args.sh_degree
     if args.tile:
         tw, th = (int(x) for x in args.tile.lower().split("x"))
         kw.update(tile_w=tw, tile_h=th)
@@ -166,13 +170,20 @@ def main():
         kw["lane_lists"] = args.lane_lists
     r = gmr.Renderer(batch, W.faces, gmr.default_options(**kw))
     verts = torch.from_numpy(W.verts).cuda()
-    colors = torch.from_numpy(W.colors).cuda()
+    if args.sh_degree:
+        K = (args.sh_degree + 1) ** 2
+        C = np.zeros((len(W.verts), K, 3), np.float32)
+        C[:, 0] = W.colors
+        C[:, 1:] = np.random.default_rng(7).normal(0, 0.1, size=(len(W.verts), K - 1, 3))
+        colors = torch.from_numpy(C).cuda()
+    else:
+        colors = torch.from_numpy(W.colors).cuda()
     tverts = torch.from_numpy(W.target_verts).cuda()
     with torch.no_grad():
         target, _, _, _ = r.forward(tverts, colors, check=True)
     target = target.clone()
     tuned_ms = None
-    if not args.no_autotune and not any(k != "cov_mode" for k in kw):
+    if not args.no_autotune and not any(k not in ("cov_mode", "sh_degree") for k in kw):
         # more timed iterations where a step is short (the ranking of close candidates is noisy)
         _, tuned_ms = r.autotune(verts, colors, target, iters=10 if W.num_pixels < (1 << 23) else 3)
     recompute = args.config in (3, 5)
@@ -343,12 +354,17 @@ def main():
         Wsub = W if args.config in (1, 2) else wl._single(W.name, *W.mesh(int(W.view_mesh[0])), [W.cams[0]])
         tg_np = target[:sample_px].cpu().numpy().astype(np.float64) if args.config not in (1, 2) else \
             target.cpu().numpy().astype(np.float64)
+        # the same colour model and conversion as the timed GPU step
+        prm = oracle.Params(cov_mode=args.cov_mode, sh_degree=args.sh_degree)
+        m0 = int(W.view_mesh[0])
+        c_all = colors.cpu().numpy()
+        c_sub = c_all if args.config in (1, 2) else c_all[int(W.vert_offsets[m0]):int(W.vert_offsets[m0 + 1])]
         t_cpu, reps = 0.0, 0
         while t_cpu < args.cpu_seconds or reps == 0:
             t1 = time.perf_counter()
-            o_rgb, o_tf, _, _ = oracle.render_workload(Wsub)
+            o_rgb, o_tf, _, _ = oracle.render_workload(Wsub, prm, colors=c_sub)
             _, g = oracle.l2_loss(o_rgb, tg_np)
-            oracle.adjoint_workload(Wsub, g)
+            oracle.adjoint_workload(Wsub, g, None, prm, colors=c_sub)
             t_cpu += time.perf_counter() - t1
             reps += 1
         cpu = {"value": round(sample_px * reps / t_cpu / 1e6, 4), "unit": "Mpixel/s", "cores": oracle.num_threads(),
@@ -371,7 +387,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": W.name, "faces": F, "verts": V, "views": W.num_views, "pixels": P,
                    "instances": I, "tile": f"{r.opts.tile_w}x{r.opts.tile_h}", "px_per_lane": r.opts.px_per_lane,
-                   "lane_lists": r.opts.lane_lists, "cov_mode": r.opts.cov_mode,
+                   "lane_lists": r.opts.lane_lists, "cov_mode": r.opts.cov_mode, "sh_degree": r.opts.sh_degree,
                    "raster_mode": r.opts.raster_mode, "autotune_ms": tuned_ms,
                    "recompute_lists": recompute, "adam_graph": use_graph},
         "roofline": roofline,

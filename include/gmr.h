@@ -71,7 +71,14 @@ typedef struct gmr_options {
                                 built per staged batch with a 64 x 64 bit transpose) -- instead of
                                 every Gaussian meeting its block.  Images and saved states are
                                 bit-identical either way; the backward is unaffected.              */
-  int32_t reserved_opt;      /* [0] must be 0                                                      */
+  int32_t sh_degree;         /* [0] view-dependent colour, the extension named with Sec. 2.2's colour
+                                assignment: 0 = one colour per vertex (Eq. 16); 1..3 = colors_dev
+                                holds K = (sh_degree+1)^2 coefficients per channel, [V][K][3]
+                                (coefficient 0 is the colour itself), a face takes their mean and its
+                                colour in a view is max(0, c_0 + sum_k c_k Y_k(d)), d the unit
+                                direction from the camera centre to the face's mean, Y_k the real
+                                spherical harmonics (3DGS sign convention); d_colors_dev has the
+                                same layout                                                          */
   int64_t instance_capacity; /* [0] (Gaussian, tile) instances the workspace holds; must be > 0
                                 when sizing a workspace or rendering                               */
 } gmr_options;
@@ -150,7 +157,7 @@ gmr_status gmr_build_adjacency(const int32_t* faces_host, int64_t num_faces, int
 /* Forward pass of every view of the batch: per-face conversion (Sec. 2.2) fused with EWA
  * projection per view, instance emission, (tile | depth) radix sort, tile ranges, and per-tile
  * front-to-back compositing.
- *   verts_dev  [V][3] f32, faces_dev [F][3] i32 (global), colors_dev [V][3] f32
+ *   verts_dev  [V][3] f32, faces_dev [F][3] i32 (global), colors_dev [V][3] f32 ([V][K][3] with sh_degree)
  *   out_rgb_dev   [P][3] f32  composite + T_final * bg
  *   out_alpha_dev [P]    f32  1 - T_final (may be NULL)
  *   saved_dev     saved_bytes (T_final and the list position after the last composited
@@ -172,7 +179,7 @@ gmr_status gmr_render_fwd(gmr_handle h, const gmr_batch* batch, const gmr_option
  *   adj_off_dev [V + 1], adj_ent_dev [3F]  from gmr_build_adjacency (device copies)
  *   recompute_lists  0: ws_dev still holds the forward's lists (same inputs, untouched);
  *                    1: rebuild them (bit-identical to the forward's) inside ws_dev.
- *   d_verts_dev [V][3], d_colors_dev [V][3]  OVERWRITTEN with the gradients.
+ *   d_verts_dev [V][3], d_colors_dev (colors_dev's layout)  OVERWRITTEN with the gradients.
  * Culled faces (degenerate, behind the camera, off-screen) receive zero gradient. */
 gmr_status gmr_render_bwd(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table_dev,
                           const float* verts_dev, const int32_t* faces_dev, const float* colors_dev,

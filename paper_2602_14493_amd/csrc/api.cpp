@@ -79,7 +79,7 @@ gmr_status validate_options(const gmr_options* o) {
     return fail(GMR_ERR_INVALID_ARG, "px_per_lane must be 1, 2 or 4");
   if (o->tile_h % (kSub * o->px_per_lane) != 0) return fail(GMR_ERR_INVALID_ARG, "tile_h must be a multiple of 8*px_per_lane");
   if (o->lane_lists != 0 && o->lane_lists != 1) return fail(GMR_ERR_INVALID_ARG, "lane_lists must be 0 or 1");
-  if (o->reserved_opt != 0) return fail(GMR_ERR_INVALID_ARG, "reserved_opt must be 0");
+  if (o->sh_degree < 0 || o->sh_degree > 3) return fail(GMR_ERR_INVALID_ARG, "sh_degree must be in [0, 3]");
   return GMR_OK;
 }
 
@@ -206,6 +206,7 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   L.ranges = take((size_t)p.tiles_total * 8);
   L.dfv = take((size_t)p.fv_total * 32);
   L.fgrad = take((size_t)p.f_total * 48);
+  L.fsh = take(o->sh_degree > 0 ? (size_t)p.f_total * 12 * (o->sh_degree + 1) * (o->sh_degree + 1) : 0);
   L.statF = take((size_t)std::max(p.items_total, 1) * 8);
   L.statB = take((size_t)std::max(p.items_total, 1) * 16);
   L.statR = take((size_t)kLossReduceBlocks * 16);
@@ -248,6 +249,7 @@ KOpts kopts(const gmr_options* o) {
   k.bg0 = o->bg[0];
   k.bg1 = o->bg[1];
   k.bg2 = o->bg[2];
+  k.sh_degree = o->sh_degree;
   return k;
 }
 
@@ -270,6 +272,7 @@ struct WsPtrs {
   uint32_t* ranges;
   float* dfv;
   float4* fgrad;
+  float* fsh;
   unsigned long long* statF;
   float4* statB;
   unsigned long long* statR;
@@ -297,6 +300,7 @@ WsPtrs ws_ptrs(const Layout& L, void* ws) {
   w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
   w.dfv = reinterpret_cast<float*>(b + L.dfv);
   w.fgrad = reinterpret_cast<float4*>(b + L.fgrad);
+  w.fsh = reinterpret_cast<float*>(b + L.fsh);
   w.statF = reinterpret_cast<unsigned long long*>(b + L.statF);
   w.statB = reinterpret_cast<float4*>(b + L.statB);
   w.statR = reinterpret_cast<unsigned long long*>(b + L.statR);
@@ -429,11 +433,13 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   }
   {
     StageTimer t(h, s, kStFaceBwd);
-    launch_face_bwd(table, p.f_total, verts, faces, ko, reinterpret_cast<const float4*>(w.dfv), w.fgrad, s);
+    launch_face_bwd(table, p.f_total, verts, faces, colors, ko, reinterpret_cast<const float4*>(w.dfv), w.fgrad, w.fsh,
+                    s);
   }
   {
     StageTimer t(h, s, kStGather);
-    launch_vertex_gather(adj_off, adj_ent, reinterpret_cast<const float*>(w.fgrad), p.v_total, d_verts, d_colors, s);
+    launch_vertex_gather(adj_off, adj_ent, reinterpret_cast<const float*>(w.fgrad), w.fsh, opt->sh_degree, p.v_total,
+                         d_verts, d_colors, s);
   }
   return check_launch();
 }
@@ -461,8 +467,22 @@ gmr_status unique_edges(const int32_t* faces, int64_t nf, int64_t nv, std::vecto
   return GMR_OK;
 }
 
+// The caller's options with only the fields the autotuner chooses taken from `t` (everything else,
+// the colour model included, stays the caller's).
+gmr_options with_tuned(const gmr_options& base, const gmr_options& t) {
+  gmr_options o = base;
+  o.tile_w = t.tile_w;
+  o.tile_h = t.tile_h;
+  o.px_per_lane = t.px_per_lane;
+  o.raster_mode = t.raster_mode;
+  o.lane_lists = t.lane_lists;
+  o.instance_capacity = t.instance_capacity;
+  return o;
+}
+
 std::string tune_key(const Plan& p, const gmr_options* o) {
-  std::string k = std::to_string(p.nv) + ":" + std::to_string(p.f_total) + ":" + std::to_string(o->cov_mode);
+  std::string k = std::to_string(p.nv) + ":" + std::to_string(p.f_total) + ":" + std::to_string(o->cov_mode) + ":" +
+                  std::to_string(o->sh_degree);
   for (const ViewDev& v : p.views) k += ":" + std::to_string(v.W) + "x" + std::to_string(v.H);
   return k;
 }
@@ -486,7 +506,7 @@ gmr_options gmr_default_options(void) {
   o.raster_mode = 0;
   o.px_per_lane = 1;
   o.lane_lists = 1;
-  o.reserved_opt = 0;
+  o.sh_degree = 0;
   o.instance_capacity = 0;
   return o;
 }
@@ -791,7 +811,7 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
   const std::string key = tune_key(p0, &b);
   auto it = h->tune_cache.find(key);
   if (it != h->tune_cache.end()) {
-    *best_out = it->second.first;
+    *best_out = with_tuned(*base, it->second.first);
     if (ms_out) *ms_out = it->second.second;
     return GMR_OK;
   }
@@ -813,7 +833,9 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
   GMR_CHECK_HIP(hipMalloc(&rgb, sizeof(float) * 3 * p0.p_total));
   GMR_CHECK_HIP(hipMalloc(&saved, 8 * p0.p_total));
   GMR_CHECK_HIP(hipMalloc(&dv, sizeof(float) * 3 * p0.v_total));
-  GMR_CHECK_HIP(hipMalloc(&dc, sizeof(float) * 3 * p0.v_total));
+  // colour gradients have the colours' layout: (sh_degree + 1)^2 coefficients per channel
+  const size_t n_coef = (size_t)(b.sh_degree + 1) * (b.sh_degree + 1);
+  GMR_CHECK_HIP(hipMalloc(&dc, sizeof(float) * 3 * n_coef * p0.v_total));
   hipEvent_t e0, e1;
   GMR_CHECK_HIP(hipEventCreate(&e0));
   GMR_CHECK_HIP(hipEventCreate(&e1));
@@ -889,7 +911,7 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
   if (table) (void)hipFree(table);
   if (result != GMR_OK) return result;
   h->tune_cache[key] = {best, best_ms};
-  *best_out = best;
+  *best_out = with_tuned(*base, best);
   if (ms_out) *ms_out = best_ms;
   return GMR_OK;
 }

@@ -90,6 +90,7 @@ struct KOpts {
   int32_t cov_mode;
   float dilation, alpha_min, alpha_max, t_eps;
   float bg0, bg1, bg2;
+  int32_t sh_degree;  // view-dependent colour degree (0: Eq. 16)
 };
 
 // Where the per-item raster statistics live (recorded in the header by the build prologue).
@@ -104,7 +105,7 @@ constexpr int kLossReduceBlocks = 256;
 // Workspace layout, computed on the host (byte offsets) -------------------------------------------
 struct Layout {
   size_t hdr, rec, elA, elB, bsum, boff, instA, instB, keysF, valsF, hist, descF0, descF1, descI0, descI1,
-      ranges, dfv, fgrad, statF, statB, statR, total;
+      ranges, dfv, fgrad, fsh, statF, statB, statR, total;
   int64_t fv_total, faces_total, pixels_total, capacity;
   int32_t tiles_total, items_total, tile_bits, tile_passes, scan_blocks, parts_fv, parts_inst;
   int32_t scan_items;  // face-views per thread of the scan / emission blocks (scan_items_for)

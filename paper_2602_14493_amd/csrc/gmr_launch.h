@@ -46,11 +46,11 @@ void launch_raster_bwd(const void* table, int items, int persistent_blocks, int 
                        float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats,
                        hipStream_t s);
 
-void launch_face_bwd(const void* table, int64_t faces_total, const float* verts, const int32_t* faces, const KOpts& o,
-                     const float4* dfv, float4* fgrad, hipStream_t s);
+void launch_face_bwd(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
+                     const float* colors, const KOpts& o, const float4* dfv, float4* fgrad, float* fsh, hipStream_t s);
 
-void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* fgrad, int64_t nv, float* dV, float* dC,
-                          hipStream_t s);
+void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* fgrad, const float* fsh, int sh_degree,
+                          int64_t nv, float* dV, float* dC, hipStream_t s);
 
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                  int32_t* step, hipStream_t s);

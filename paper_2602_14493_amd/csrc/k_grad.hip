@@ -15,10 +15,15 @@
 //   clamped kappa = |A| / (pi sqrt(eps)), |A| = |m|/2: G_m += tr(G M)/36 / (pi sqrt(eps)) n / 2
 //   m = e1 x e2: G_e1 += e2 x G_m, G_e2 += G_m x e1; mu = (v_i + v_j + v_k)/3
 // and writes per-corner vertex gradients and the face's colour gradient (12 floats per face).
+// With view-dependent colour (degree SHD > 0) the colour of face-view (f, v) is
+// max(0, sum_k c_k Y_k(d_v)), d_v = (mu - centre_v) / r_v: the clamp passes dL/dcolour where the
+// sum is positive, G_c_k += dL/dcolour Y_k(d_v) (the face's coefficient gradients, 3K floats in
+// `fsh`), and G_mu += (I - d d^T) / r_v grad_d(sum_k w_k Y_k), w_k = sum_channels dL/dcolour c_k.
 // k_vertex_gather: one thread per vertex sums its corners through the (vertex -> face, corner)
 // CSR in a fixed order, so the vertex gradients do not depend on atomic ordering.
 #include "gmr_common.h"
 #include "gmr_launch.h"
+#include "gmr_sh.h"
 
 namespace gmr {
 
@@ -28,9 +33,12 @@ __device__ inline void sym3_from6(const double* s, double (&M)[3][3]) {
   M[2][0] = s[2]; M[2][1] = s[4]; M[2][2] = s[5];
 }
 
+template <int SHD>
 __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table, const float* __restrict__ verts,
-                                                  const int32_t* __restrict__ faces, KOpts o,
-                                                  const float4* __restrict__ dfv, float4* __restrict__ fgrad) {
+                                                  const int32_t* __restrict__ faces, const float* __restrict__ colors,
+                                                  KOpts o, const float4* __restrict__ dfv, float4* __restrict__ fgrad,
+                                                  float* __restrict__ fsh) {
+  constexpr int K = sh_count<SHD>();
   const TableHdr* th = static_cast<const TableHdr*>(table);
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= th->faces_total) return;
@@ -50,7 +58,15 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
   float4* out = fgrad + 3 * f;
   if (!face_convert(vi, vj, vk, o.cov_mode, g)) {
     out[0] = out[1] = out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (SHD > 0)
+      for (int k = 0; k < 3 * K; ++k) fsh[3 * K * f + k] = 0.f;
     return;
+  }
+  float coef[K][3], gsh[K][3];
+  if constexpr (SHD > 0) {
+    face_coefs<SHD>(colors, i0, i1, i2, coef);
+#pragma unroll
+    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
   }
   double Gmu[3] = {0.0, 0.0, 0.0};
   double GS[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
@@ -62,7 +78,38 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
     if (d0.x == 0.f && d0.y == 0.f && d0.z == 0.f && d0.w == 0.f && d1.x == 0.f && d1.y == 0.f && d1.z == 0.f &&
         d1.w == 0.f)
       continue;
-    gcol[0] += d1.y; gcol[1] += d1.z; gcol[2] += d1.w;
+    if constexpr (SHD == 0) {
+      gcol[0] += d1.y; gcol[1] += d1.z; gcol[2] += d1.w;
+    } else {
+      double cc[3];
+      view_centre(V.R, V.t, cc);
+      const double px = g.mu[0] - cc[0], py = g.mu[1] - cc[1], pz = g.mu[2] - cc[2];
+      const double ir = 1.0 / sqrt(px * px + py * py + pz * pz);
+      const double x = px * ir, y = py * ir, z = pz * ir;
+      double Y[K];
+      sh_basis<SHD>(x, y, z, Y);
+      double gc[3] = {d1.y, d1.z, d1.w};
+      for (int a = 0; a < 3; ++a) {
+        double raw = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) raw += (double)coef[k][a] * Y[k];
+        if (!(raw > 0.0)) gc[a] = 0.0;  // the clamp at 0
+      }
+      double w[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        gsh[k][0] += (float)(gc[0] * Y[k]);
+        gsh[k][1] += (float)(gc[1] * Y[k]);
+        gsh[k][2] += (float)(gc[2] * Y[k]);
+        w[k] = gc[0] * coef[k][0] + gc[1] * coef[k][1] + gc[2] * coef[k][2];
+      }
+      double gx, gy, gz;
+      sh_poly_grad<SHD>(x, y, z, w, gx, gy, gz);
+      const double dd = x * gx + y * gy + z * gz;
+      Gmu[0] += (gx - x * dd) * ir;
+      Gmu[1] += (gy - y * dd) * ir;
+      Gmu[2] += (gz - z * dd) * ir;
+    }
     ProjGeo q;
     if (!view_project(V, g.mu, g.S, (double)o.dilation, q)) continue;
     const double du = d0.x, dv = d0.y, da = d0.z, db = d0.w, dc = d1.x;
@@ -225,14 +272,26 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
   out[0] = make_float4(gv[0], gv[1], gv[2], gv[3]);
   out[1] = make_float4(gv[4], gv[5], gv[6], gv[7]);
   out[2] = make_float4(gv[8], gcol[0], gcol[1], gcol[2]);
+  if constexpr (SHD > 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      for (int a = 0; a < 3; ++a) fsh[3 * K * f + 3 * k + a] = gsh[k][a];
+  }
 }
 
+template <int SHD>
 __global__ __launch_bounds__(256) void k_vertex_gather(const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
-                                                       const float* __restrict__ fgrad, int64_t nv,
-                                                       float* __restrict__ dV, float* __restrict__ dC) {
+                                                       const float* __restrict__ fgrad, const float* __restrict__ fsh,
+                                                       int64_t nv, float* __restrict__ dV, float* __restrict__ dC) {
+  constexpr int K = sh_count<SHD>();
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   float gx = 0.f, gy = 0.f, gz = 0.f, cr = 0.f, cg = 0.f, cb = 0.f;
+  float cs[K][3];
+  if constexpr (SHD > 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) cs[k][0] = cs[k][1] = cs[k][2] = 0.f;
+  }
   for (int32_t e = off[v]; e < off[v + 1]; ++e) {
     const int32_t fc = ent[e];
     const int32_t f = fc / 3, corner = fc - 3 * f;
@@ -240,13 +299,29 @@ __global__ __launch_bounds__(256) void k_vertex_gather(const int32_t* __restrict
     gx += p[3 * corner];
     gy += p[3 * corner + 1];
     gz += p[3 * corner + 2];
-    cr += p[9];
-    cg += p[10];
-    cb += p[11];
+    if constexpr (SHD == 0) {
+      cr += p[9];
+      cg += p[10];
+      cb += p[11];
+    } else {
+      const float* q = fsh + (int64_t)3 * K * f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        cs[k][0] += q[3 * k];
+        cs[k][1] += q[3 * k + 1];
+        cs[k][2] += q[3 * k + 2];
+      }
+    }
   }
   const float third = 1.f / 3.f;
   dV[3 * v] = gx; dV[3 * v + 1] = gy; dV[3 * v + 2] = gz;
-  dC[3 * v] = cr * third; dC[3 * v + 1] = cg * third; dC[3 * v + 2] = cb * third;
+  if constexpr (SHD == 0) {
+    dC[3 * v] = cr * third; dC[3 * v + 1] = cg * third; dC[3 * v + 2] = cb * third;
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      for (int a = 0; a < 3; ++a) dC[((int64_t)v * K + k) * 3 + a] = cs[k][a] * third;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t n, float val) {
@@ -356,17 +431,28 @@ __global__ void k_adam_tick(int32_t* step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
 }
 
-void launch_face_bwd(const void* table, int64_t faces_total, const float* verts, const int32_t* faces, const KOpts& o,
-                     const float4* dfv, float4* fgrad, hipStream_t s) {
+void launch_face_bwd(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
+                     const float* colors, const KOpts& o, const float4* dfv, float4* fgrad, float* fsh, hipStream_t s) {
   if (faces_total <= 0) return;
-  hipLaunchKernelGGL(k_face_bwd, dim3((unsigned)((faces_total + 255) / 256)), dim3(256), 0, s, table, verts, faces, o, dfv,
-                     fgrad);
+  const dim3 grid((unsigned)((faces_total + 255) / 256));
+  switch (o.sh_degree) {
+    case 1: hipLaunchKernelGGL(k_face_bwd<1>, grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
+    case 2: hipLaunchKernelGGL(k_face_bwd<2>, grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
+    case 3: hipLaunchKernelGGL(k_face_bwd<3>, grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
+    default: hipLaunchKernelGGL(k_face_bwd<0>, grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
+  }
 }
 
-void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* fgrad, int64_t nv, float* dV, float* dC,
-                          hipStream_t s) {
+void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* fgrad, const float* fsh, int sh_degree,
+                          int64_t nv, float* dV, float* dC, hipStream_t s) {
   if (nv <= 0) return;
-  hipLaunchKernelGGL(k_vertex_gather, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, off, ent, fgrad, nv, dV, dC);
+  const dim3 grid((unsigned)((nv + 255) / 256));
+  switch (sh_degree) {
+    case 1: hipLaunchKernelGGL(k_vertex_gather<1>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC); break;
+    case 2: hipLaunchKernelGGL(k_vertex_gather<2>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC); break;
+    case 3: hipLaunchKernelGGL(k_vertex_gather<3>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC); break;
+    default: hipLaunchKernelGGL(k_vertex_gather<0>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC); break;
+  }
 }
 
 void launch_fill_f32(float* p, int64_t n, float val, hipStream_t s) {

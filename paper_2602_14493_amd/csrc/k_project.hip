@@ -14,9 +14,13 @@
 // x = 1920 carries ~1e-4 px of rounding, which alone would move alpha by ~1e-4.
 #include "gmr_common.h"
 #include "gmr_launch.h"
+#include "gmr_sh.h"
 
 namespace gmr {
 
+// SHD > 0: view-dependent colour of degree SHD (colours hold (SHD + 1)^2 coefficients per
+// channel and vertex); SHD = 0: Eq. 16.
+template <int SHD>
 __device__ inline void project_face(const TableHdr* th, const void* __restrict__ table, const float* __restrict__ verts,
                                     const int32_t* __restrict__ faces, const float* __restrict__ colors, const KOpts& o,
                                     float4* __restrict__ rec, uint4* __restrict__ el, uint32_t* s_h,
@@ -38,9 +42,14 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
   FaceGeo g;
   const bool ok = face_convert(vi, vj, vk, o.cov_mode, g);
   float col[3];
-  for (int a = 0; a < 3; ++a)
-    col[a] = (float)(((double)colors[3 * (int64_t)i0 + a] + (double)colors[3 * (int64_t)i1 + a] +
-                      (double)colors[3 * (int64_t)i2 + a]) * (1.0 / 3.0));
+  float coef[sh_count<SHD>()][3];
+  if constexpr (SHD == 0) {
+    for (int a = 0; a < 3; ++a)
+      col[a] = (float)(((double)colors[3 * (int64_t)i0 + a] + (double)colors[3 * (int64_t)i1 + a] +
+                        (double)colors[3 * (int64_t)i2 + a]) * (1.0 / 3.0));
+  } else {
+    face_coefs<SHD>(colors, i0, i1, i2, coef);
+  }
   const double kscale = sqrt(kHalfLog2e);
 
   for (int k = mvo[m]; k < mvo[m + 1]; ++k) {
@@ -58,6 +67,20 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
         const int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
         const int tx0 = ix0 / tw, tx1 = ix1 / tw, ty0 = iy0 / tht, ty1 = iy1 / tht;
         const int nx = tx1 - tx0 + 1, ny = ty1 - ty0 + 1;
+        if constexpr (SHD > 0) {  // colour in this view
+          double cc[3];
+          view_centre(V.R, V.t, cc);
+          const double px = g.mu[0] - cc[0], py = g.mu[1] - cc[1], pz = g.mu[2] - cc[2];
+          const double ir = 1.0 / sqrt(px * px + py * py + pz * pz);
+          double Y[sh_count<SHD>()];
+          sh_basis<SHD>(px * ir, py * ir, pz * ir, Y);
+          for (int a = 0; a < 3; ++a) {
+            double raw = 0.0;
+#pragma unroll
+            for (int k = 0; k < sh_count<SHD>(); ++k) raw += (double)coef[k][a] * Y[k];
+            col[a] = (float)fmax(raw, 0.0);
+          }
+        }
         const float uh = (float)q.u, vh = (float)q.v;
         const float ul = (float)(q.u - (double)uh), vl = (float)(q.v - (double)vh);
         // conic = L^T L, L = [[l11, l12], [0, l22]]; l22 = sqrt(det conic) / l11 = 1 / (l11 sqrt(det))
@@ -85,6 +108,7 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
   }
 }
 
+template <int SHD>
 __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table, const float* __restrict__ verts,
                                                  const int32_t* __restrict__ faces, const float* __restrict__ colors,
                                                  KOpts o, float4* __restrict__ rec, uint4* __restrict__ el,
@@ -96,7 +120,8 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
   const TableHdr* th = static_cast<const TableHdr*>(table);
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t kmin = 0xffffffffu, kmax = 0u;  // high 16 key bits of this thread's visible face-views
-  if (f < th->faces_total) project_face(th, table, verts, faces, colors, o, rec, el, s_h, kmin, kmax, dfv_zero, f);
+  if (f < th->faces_total)
+    project_face<SHD>(th, table, verts, faces, colors, o, rec, el, s_h, kmin, kmax, dfv_zero, f);
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) {
     kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, kWave));
@@ -145,8 +170,16 @@ void launch_project(const void* table, int64_t faces_total, const float* verts, 
   if (faces_total <= 0) return;
   const int bs = 256;
   const int64_t nb = (faces_total + bs - 1) / bs;
-  hipLaunchKernelGGL(k_project, dim3((unsigned)nb), dim3(bs), 0, s, table, verts, faces, colors, o, rec, el, hist, hdr,
-                     dfv_zero);
+#define GMR_PROJECT(D)                                                                                        \
+  hipLaunchKernelGGL(k_project<D>, dim3((unsigned)nb), dim3(bs), 0, s, table, verts, faces, colors, o, rec, el, hist, \
+                     hdr, dfv_zero)
+  switch (o.sh_degree) {
+    case 1: GMR_PROJECT(1); break;
+    case 2: GMR_PROJECT(2); break;
+    case 3: GMR_PROJECT(3); break;
+    default: GMR_PROJECT(0); break;
+  }
+#undef GMR_PROJECT
 }
 
 }  // namespace gmr

@@ -200,6 +200,13 @@ class Renderer:
         return Counters(int(c.instances), int(c.capacity), bool(c.overflow), int(c.pairs_fwd), int(c.pairs_bwd),
                         float(c.loss), float(c.loss_sil))
 
+    def check_colors(self, colors):
+        """Colours hold (sh_degree + 1)^2 x 3 floats per vertex ([V,3] at degree 0)."""
+        k = (int(self.opts.sh_degree) + 1) ** 2
+        if colors.numel() != self.batch.num_verts * 3 * k or colors.dtype != torch.float32:
+            raise ValueError(f"colors must be float32 with {k} x 3 values per vertex (sh_degree "
+                             f"{self.opts.sh_degree}), got {tuple(colors.shape)} {colors.dtype}")
+
     # -- raw calls (no capacity management) --------------------------------------------------------
     def fwd_raw(self, verts, colors, rgb, alpha, saved, ws):
         call("gmr_render_fwd", self.handle.ptr, ctypes.byref(self.batch.c), ctypes.byref(self.opts), _ptr(self.table),
@@ -238,6 +245,7 @@ class Renderer:
         capacity grows and the pass is redone."""
         verts = verts.contiguous()
         colors = colors.contiguous()
+        self.check_colors(colors)
         rgb, alpha, saved = self._alloc_outputs()
         if check is None:
             check = not self.capacity_checked

@@ -41,7 +41,7 @@ def test_default_options():
     import paper_2602_14493_amd as gmr
     o = gmr.default_options()
     assert o.cov_mode == 0 and o.tile_w == 16 and o.tile_h == 16 and o.raster_mode == 0 and o.px_per_lane == 1
-    assert o.lane_lists == 1 and o.reserved_opt == 0
+    assert o.lane_lists == 1 and o.sh_degree == 0
     assert ctypes.sizeof(o) == 64 and type(o).instance_capacity.offset == 56
     assert o.alpha_min == np.float32(1 / 255) and o.alpha_max == np.float32(0.99) and o.t_eps == np.float32(1e-4)
     assert o.dilation == np.float32(0.3) and tuple(o.bg) == (0.0, 0.0, 0.0)
@@ -72,7 +72,7 @@ def test_view_table_and_workspace_sizes():
 
 @pytest.mark.parametrize("field,value", [("cov_mode", 3), ("tile_w", 12), ("tile_h", 72), ("alpha_min", 0.0),
                                          ("t_eps", 1.5), ("raster_mode", 3), ("px_per_lane", 3),
-                                         ("lane_lists", 2), ("lane_lists", -1), ("reserved_opt", 1),
+                                         ("lane_lists", 2), ("lane_lists", -1), ("sh_degree", 4), ("sh_degree", -1),
                                          ("instance_capacity", 0), ("instance_capacity", 1 << 30)])
 def test_invalid_options_rejected(field, value):
     import paper_2602_14493_amd as gmr

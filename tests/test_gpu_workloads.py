@@ -78,6 +78,29 @@ def test_autotune(gpu):
            (best.tile_w, best.tile_h, best.px_per_lane, best.raster_mode)
 
 
+def test_autotune_view_dependent_colour(gpu):
+    """The autotuner with sh_degree 2 (colour gradients of 9 x 3 floats per vertex in its own
+    scratch) on the same handle as a degree-0 tuning: each keeps its colour model, and the tuned
+    degree-2 image equals the untuned one bit for bit."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    say("autotune sh_degree 2 cfg1")
+    W = wl.make_workload(1)
+    r0, verts, colors = gpu_setup(W)
+    base0, _, _, _ = r0.forward(verts, colors)
+    r0.autotune(verts, colors, torch.zeros_like(base0), iters=1)
+    r2 = gmr.Renderer(gmr.Batch.from_workload(W), W.faces, gmr.default_options(sh_degree=2), handle=r0.handle)
+    C = np.zeros((len(W.verts), 9, 3), np.float32)
+    C[:, 0] = W.colors
+    C[:, 1:] = np.random.default_rng(3).normal(0, 0.1, size=(len(W.verts), 8, 3))
+    c2 = torch.from_numpy(C).cuda()
+    base2, _, _, _ = r2.forward(verts, c2)
+    best, ms = r2.autotune(verts, c2, torch.zeros_like(base2), iters=1)
+    assert best.sh_degree == 2 and r0.opts.sh_degree == 0 and ms > 0
+    rgb, _, _, _ = r2.forward(verts, c2, check=True)
+    assert torch.equal(rgb, base2)
+
+
 def _window_submesh(G, faces_of, W, H, margin=2.0):
     """Pixel window covered by the faces in faces_of (from per-face screen records G) and the faces
     whose extents meet it."""
