@@ -35,15 +35,19 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # (tile, pixels per lane, raster mode, lane lists); `src` is the hash of the kernel's sources when the counters
 # were taken, and a changed source reports null.
 TRAFFIC = {
-    ("icosphere_s5_8x512", "raster_bwd", "32x32", 2, 0, 1):
-        {"fetch": 76340571, "write": 20475392, "src": "41e1ad69a92e722e"},
+    ("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1):
+        {"fetch": 77197247, "write": 27983672, "src": "9802c01cf7eef069"},
+    ("icosphere_s5_8x512", "raster_bwd", "32x16", 1, 0, 1):
+        {"fetch": 76685182, "write": 27984565, "src": "9802c01cf7eef069"},
+    ("icosphere_s5_8x512", "raster_bwd", "32x32", 1, 0, 1):
+        {"fetch": 76312504, "write": 27986834, "src": "9802c01cf7eef069"},
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 14628903483, "write": 1811400347, "src": "41e1ad69a92e722e"},
+        {"fetch": 16292717592, "write": 1784780500, "src": "9802c01cf7eef069"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
                 "project": "k_project.hip", "scan_emit": "k_bin.hip", "face_bwd": "k_grad.hip",
-                "vertex_gather": "k_grad.hip", "fill": "k_grad.hip"}
+                "vertex_gather": "k_grad.hip", "fill": "k_grad.hip", "loss_reduce": "k_grad.hip"}
 
 
 def source_hash(stage):
@@ -61,6 +65,25 @@ def measured_traffic(workload, stage, tile, px, mode, lanes):
     if e is None or e["src"] != source_hash(stage):
         return None
     return e["fetch"] + e["write"]
+
+
+def copy_peak_gbps(torch, mib: int = 1024, reps: int = 5) -> float:
+    """Streaming-copy bandwidth of this GPU (bytes read + written per second, HIP events), the
+    measured counterpart of the 8 TB/s vendor figure."""
+    n = (mib << 20) // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
 def copy_probe():
@@ -232,6 +255,16 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = e0.elapsed_time(e1) / args.steps
     value = P / (ms_step * 1e-3) / 1e6
+    # per-step spread (a second pass of the same steps, one event pair per step)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a_, b_ in ev:
+        a_.record()
+        step()
+        b_.record()
+    torch.cuda.synchronize()
+    per_step = np.array([a_.elapsed_time(b_) for a_, b_ in ev])
+    spread = {"p10": round(float(np.percentile(per_step, 10)), 4), "p50": round(float(np.median(per_step)), 4),
+              "p90": round(float(np.percentile(per_step, 90)), 4)}
     ws_ref = loop.ws_fwd if use_graph else ws
     cnt = r.counters(ws_ref)
     cnt_b = r.counters(loop.ws_bwd if use_graph else ws_b)
@@ -263,6 +296,13 @@ def main():
         if k in FLOPS_PER_PAIR:
             stages[k]["pairs"] = pairs[k]
             stages[k]["alg_TFLOPs"] = round(pairs[k] * FLOPS_PER_PAIR[k] / (avg * 1e-3) / 1e12, 2)
+    # model bytes of the whole step against the vendor peak and a measured streaming copy
+    model_bytes = sum(byte_model(k, F, FV, V, P, I, tiles) * n / args.steps for k, (ms, n) in prof.items() if n)
+    copy_gbps = copy_peak_gbps(torch)
+    hbm_model = {"bytes_per_step": int(model_bytes), "GBps": round(model_bytes / (ms_step * 1e-3) / 1e9, 1),
+                 "frac_vendor_peak": round(model_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "copy_GBps": round(copy_gbps, 1),
+                 "frac_copy_peak": round(model_bytes / (ms_step * 1e-3) / 1e9 / copy_gbps, 4)}
     dom = max(stages, key=lambda k: stages[k]["ms_per_step"])
     d = stages[dom]
     traffic = measured_traffic(W.name, dom, f"{r.opts.tile_w}x{r.opts.tile_h}", r.opts.px_per_lane,
@@ -380,6 +420,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_spread": spread,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -391,6 +432,7 @@ def main():
                    "raster_mode": r.opts.raster_mode, "autotune_ms": tuned_ms,
                    "recompute_lists": recompute, "adam_graph": use_graph},
         "roofline": roofline,
+        "hbm_model": hbm_model,
         "cpu_baseline": cpu,
         "per_view": per_view,
         "recon_step": recon_step,
