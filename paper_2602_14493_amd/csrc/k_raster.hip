@@ -523,32 +523,31 @@ __device__ inline float wave_reduce8_transpose(const float (&g)[8], int lane) {
 
 // One record's adjoint over a lane's PX pixels (summed into gr); `valid` = false is a no-op.
 // Returns (wave-uniformly) whether any pixel of the wavefront composited it.
+// cov[k]: the record's pixel-rectangle coverage of row group k (bit = lane), wave-uniform; the
+// lane masks stay on the scalar unit and reach the per-lane selects as masks (inverse ballot).
 template <int PX>
-__device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, const float4& a2, bool valid,
-                                         uint32_t prel, int x, float px, const int (&y)[PX], float amin, float amax,
+__device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, const float4& a2, const uint64_t (&cov)[PX],
+                                         uint32_t prel, float px, const int (&y)[PX], float amin, float amax,
                                          const float (&gc0)[PX], const float (&gc1)[PX], const float (&gc2)[PX],
                                          const float (&K)[PX], const uint32_t (&last)[PX], float (&T)[PX],
                                          float (&S)[PX], float (&gr)[8], unsigned long long& pairs) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) gr[i] = 0.f;
   bool contrib = false;  // wave-uniform: some pixel composited the Gaussian
-  const bool inx = valid && in_range(f2u(a1.w), x);
   const float dx = (a0.x - px) + a0.z;
-  const uint32_t ry = f2u(a2.w);
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
-    const bool act = prel < last[k] && inx && in_range(ry, y[k]);
     // wave-uniform skips: no pixel of the row group inside the extent (before its stop), or none
     // whose alpha reaches the cutoff -- then T, S and every partial are unchanged
-    const uint64_t actm = __ballot(act);
+    const uint64_t actm = cov[k] & __ballot(prel < last[k]);
     if (actm == 0ull) continue;
     const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
     float w1, w2;
     const float e = gauss_exp(a1, dx, dy, w1, w2);
     const float al = fminf(amax, e);
-    const bool ok = act && al >= amin;
     const uint64_t okm = actm & __ballot(al >= amin);  // ballot of the compare alone stays a scalar mask
     if (okm == 0ull) continue;
+    const bool ok = __builtin_amdgcn_inverse_ballot_w64(okm);
     contrib = true;
     pairs += (unsigned long long)__popcll(okm);  // wave-uniform, scalar unit
     const float rom = __builtin_amdgcn_rcpf(1.f - al);  // 1 - al >= 1 - alpha_max > 0
@@ -562,9 +561,9 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
     // d/d(l11, l12 | l22 rows of the scaled factor) and d/d(conic) partials, as FMAs into the sums:
     // -dpow 2 ln2 (l11 w1, l12 w1 + l22 w2) and -dpow / 2 (dx^2, 2 dx dy, dy^2)
     const float qn = dpow * -kTwoLn2;
+    const float h = -0.5f * dpow, t = h * dx;
     gr[0] = fmaf(qn, a1.x * w1, gr[0]);
     gr[1] = fmaf(qn, fmaf(a1.y, w1, a1.z * w2), gr[1]);
-    const float h = -0.5f * dpow, t = h * dx;
     gr[2] = fmaf(t, dx, gr[2]);
     gr[3] = fmaf(t + t, dy, gr[3]);
     gr[4] = fmaf(h * dy, dy, gr[4]);
@@ -576,9 +575,16 @@ __device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, con
 }
 
 struct BwdLds {
-  float4 (*rec)[kWave];  // [3][64] staged records
-  uint32_t* id;          // [64] their face-view ids
+  float4 (*rec)[kWave];   // [3][64] staged records
+  uint32_t* id;           // [64] their face-view ids
+  uint64_t (*cov)[kWave]; // [PX][64] their coverage of each row group of the block (bit = lane)
 };
+
+// A wave-uniform 64-bit value from LDS into scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
 
 // Block-uniform walk of one staged batch: every record is evaluated by the whole wavefront, two
 // per round, and its 8 partial sums are reduced across the wavefront.
@@ -599,10 +605,16 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
     const float4 a0 = s[0][j1], a1 = s[1][j1], a2 = s[2][j1];
     const float4 b0 = s[0][j2], b1 = s[1][j2], b2 = s[2][j2];
     const uint32_t id1 = L.id[j1], id2 = L.id[j2];
+    uint64_t cv1[PX], cv2[PX];
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      cv1[k] = uniform64(L.cov[k][j1]);
+      cv2[k] = has2 ? uniform64(L.cov[k][j2]) : 0ull;
+    }
     float gr[8], gq[8];
-    const bool c1 = bwd_eval<PX>(a0, a1, a2, true, (uint32_t)(hi - 1 - j1 - (int64_t)start), g.x, px, y, amin, amax,
+    const bool c1 = bwd_eval<PX>(a0, a1, a2, cv1, (uint32_t)(hi - 1 - j1 - (int64_t)start), px, y, amin, amax,
                                  gc0, gc1, gc2, K, last, T, S, gr, pairs);
-    const bool c2 = bwd_eval<PX>(b0, b1, b2, has2, (uint32_t)(hi - 1 - j2 - (int64_t)start), g.x, px, y, amin, amax,
+    const bool c2 = bwd_eval<PX>(b0, b1, b2, cv2, (uint32_t)(hi - 1 - j2 - (int64_t)start), px, y, amin, amax,
                                  gc0, gc1, gc2, K, last, T, S, gq, pairs);
     if (c1) {
       const float r = wave_reduce8_transpose(gr, lane);
@@ -621,7 +633,9 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return make_float4(0.f, 0.f, 0.f, 0.f);
   const int ly = lane >> 3;
-  const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
+  // the tile (and so its list) is the wavefront's own: keep the bounds in scalar registers
+  const uint32_t start = __builtin_amdgcn_readfirstlane(a.ranges[2 * (size_t)g.tile]);
+  const uint32_t end = __builtin_amdgcn_readfirstlane(a.ranges[2 * (size_t)g.tile + 1]);
   float gc0[PX], gc1[PX], gc2[PX], K[PX], T[PX], S[PX];
   uint32_t last[PX];
   int y[PX];
@@ -682,6 +696,7 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   }
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
+  mx = __builtin_amdgcn_readfirstlane(mx);
   if (mx == 0) return make_float4(loss, loss_sil, 0.f, 0.f);
   const float px = (float)g.x + 0.5f;
   const float amin = a.o.alpha_min, amax = a.o.alpha_max;
@@ -701,6 +716,9 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
     if (m == 0ull) continue;
     L.rec[0][lane] = r0; L.rec[1][lane] = r1; L.rec[2][lane] = r2;
     L.id[lane] = id;
+#pragma unroll
+    for (int k = 0; k < PX; ++k)
+      L.cov[k][lane] = ov ? block_coverage(f2u(r1.w), f2u(r2.w), g.bx0, g.by0 + kSub * k) : 0ull;
     wave_lds_sync();
     bwd_batch_uniform<PX>(a, L, m, hi, start, g, px, y, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
     wave_lds_sync();
@@ -712,10 +730,11 @@ template <int PX, bool kPersistent, bool kL2>
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   __shared__ float4 s_rec[256 / kWave][kRecF4][kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
+  __shared__ uint64_t s_cov[256 / kWave][PX][kWave];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
   const ViewDev* views = table_views(a.table);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const BwdLds L{s_rec[w], s_id[w]};
+  const BwdLds L{s_rec[w], s_id[w], s_cov[w]};
   const int items = th->items_total;
   if (kPersistent) {
     const int groups = (items + 3) / 4;  // grid-stride, as in the forward
