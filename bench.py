@@ -36,13 +36,13 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # were taken, and a changed source reports null.
 TRAFFIC = {
     ("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1):
-        {"fetch": 77197247, "write": 27983672, "src": "9802c01cf7eef069"},
+        {"fetch": 77166859, "write": 27982140, "src": "98b165faf507c583"},
     ("icosphere_s5_8x512", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 76685182, "write": 27984565, "src": "9802c01cf7eef069"},
+        {"fetch": 76662477, "write": 27981547, "src": "98b165faf507c583"},
     ("icosphere_s5_8x512", "raster_bwd", "32x32", 1, 0, 1):
-        {"fetch": 76312504, "write": 27986834, "src": "9802c01cf7eef069"},
+        {"fetch": 76290856, "write": 27983574, "src": "98b165faf507c583"},
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 16292717592, "write": 1784780500, "src": "9802c01cf7eef069"},
+        {"fetch": 16681155983, "write": 1787684279, "src": "98b165faf507c583"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
