@@ -235,3 +235,55 @@ def test_synthetic_reconstruction_converges(gpu):
     assert res["cd"] < 0.1 * res["cd_init"]
     assert res["nc"] > res["nc_init"]
     assert res["overflow_events"] == 0
+
+
+def test_recon_backward_with_recompute_and_options(gpu):
+    """The reconstruction backward rebuilding its lists equals the one reusing the forward's, with
+    view-dependent colour and with the baseline conversion (options compose with the loss)."""
+    import torch
+    W = wl.make_workload(2, scale=0.25)
+    tgt, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    target = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    mask = torch.from_numpy(_silhouette(W).astype(np.float32)).cuda()
+    for kw in ({"sh_degree": 2}, {"cov_mode": 2}):
+        say(f"recon backward, recompute vs saved lists, {kw}")
+        r, verts, colors = gpu_setup(W, **kw)
+        if "sh_degree" in kw:
+            C = np.zeros((len(W.verts), 9, 3), np.float32)
+            C[:, 0] = W.colors
+            C[:, 1:] = np.random.default_rng(5).normal(0, 0.1, size=(len(W.verts), 8, 3))
+            colors = torch.from_numpy(C).cuda()
+        rgb, alpha, saved, ws = r.forward(verts, colors)
+        dV0, dC0, l0 = r.backward_recon(verts, colors, rgb, target, mask, saved, ws, sil_weight=0.5)
+        dV1, dC1, l1 = r.backward_recon(verts, colors, rgb, target, mask, saved, None, sil_weight=0.5)
+        compare_grads(dV1, to_np(dV0), f"recompute vs saved dV {kw}", rel=1e-5)
+        compare_grads(dC1, to_np(dC0), f"recompute vs saved dC {kw}", rel=1e-5)
+        np.testing.assert_allclose(to_np(l1), to_np(l0), rtol=1e-6)
+
+
+def test_autograd_with_view_dependent_colour(gpu):
+    """torch.autograd through render() with sh_degree 1: the coefficient and vertex gradients equal
+    the explicit backward's, with the lists kept and rebuilt."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    W = wl.make_workload(1)
+    r, verts, _ = gpu_setup(W, sh_degree=1)
+    C = np.zeros((len(W.verts), 4, 3), np.float32)
+    C[:, 0] = W.colors
+    C[:, 1:] = np.random.default_rng(6).normal(0, 0.2, size=(len(W.verts), 3, 3))
+    grads = []
+    for save in (True, False):
+        v = verts.clone().requires_grad_()
+        c = torch.from_numpy(C).cuda().requires_grad_()
+        rgb, alpha = gmr.render(v, c, r, save_lists=save)
+        (rgb.square().mean() + 0.3 * alpha.mean()).backward()
+        grads.append((v.grad.clone(), c.grad.clone()))
+    assert grads[0][1].shape == (len(W.verts), 4, 3)
+    compare_grads(grads[1][0], to_np(grads[0][0]), "autograd sh1 recompute vs saved dV", rel=1e-5)
+    compare_grads(grads[1][1], to_np(grads[0][1]), "autograd sh1 recompute vs saved dC", rel=1e-5)
+    rgb, alpha, saved, ws = r.forward(verts, torch.from_numpy(C).cuda())
+    g = 2.0 * rgb / rgb.numel()
+    ga = torch.full_like(alpha, 0.3 / alpha.numel())
+    dV, dC = r.backward(verts, torch.from_numpy(C).cuda(), g, ga, saved, ws)
+    compare_grads(grads[0][0], to_np(dV), "autograd sh1 vs explicit dV", rel=1e-5)
+    compare_grads(grads[0][1], to_np(dC), "autograd sh1 vs explicit dC", rel=1e-5)
