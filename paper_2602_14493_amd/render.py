@@ -200,12 +200,19 @@ class Renderer:
         return Counters(int(c.instances), int(c.capacity), bool(c.overflow), int(c.pairs_fwd), int(c.pairs_bwd),
                         float(c.loss), float(c.loss_sil))
 
-    def check_colors(self, colors):
-        """Colours hold (sh_degree + 1)^2 x 3 floats per vertex ([V,3] at degree 0)."""
+    def check_colors(self, colors, verts=None):
+        """Colours hold (sh_degree + 1)^2 x 3 floats per vertex ([V,3] at degree 0); vertices [V,3];
+        both float32 on this renderer's device (the kernels index them by the batch's sizes)."""
         k = (int(self.opts.sh_degree) + 1) ** 2
         if colors.numel() != self.batch.num_verts * 3 * k or colors.dtype != torch.float32:
             raise ValueError(f"colors must be float32 with {k} x 3 values per vertex (sh_degree "
                              f"{self.opts.sh_degree}), got {tuple(colors.shape)} {colors.dtype}")
+        if verts is not None and (verts.numel() != self.batch.num_verts * 3 or verts.dtype != torch.float32):
+            raise ValueError(f"verts must be float32 [{self.batch.num_verts}, 3], got {tuple(verts.shape)} "
+                             f"{verts.dtype}")
+        for t in (colors, verts):
+            if t is not None and t.device != self.device:
+                raise ValueError(f"inputs must be on {self.device}, got {t.device}")
 
     # -- raw calls (no capacity management) --------------------------------------------------------
     def fwd_raw(self, verts, colors, rgb, alpha, saved, ws):
@@ -245,7 +252,7 @@ class Renderer:
         capacity grows and the pass is redone."""
         verts = verts.contiguous()
         colors = colors.contiguous()
-        self.check_colors(colors)
+        self.check_colors(colors, verts)
         rgb, alpha, saved = self._alloc_outputs()
         if check is None:
             check = not self.capacity_checked
@@ -271,6 +278,7 @@ class Renderer:
     def backward(self, verts, colors, d_rgb, d_alpha, saved, ws=None, recompute: bool = False):
         """dL/dverts, dL/dcolors from dL/drgb [P,3] (and dL/dalpha [P] or None).  With
         recompute=True (or no workspace) the sorted lists are rebuilt in a fresh workspace."""
+        self.check_colors(colors, verts)
         if ws is None:
             ws = self.new_workspace()
             recompute = True
@@ -282,6 +290,7 @@ class Renderer:
 
     def backward_l2(self, verts, colors, rgb, target, saved, ws=None, recompute=False, loss_weight=1.0,
                     want_loss=False):
+        self.check_colors(colors, verts)
         if ws is None:
             ws = self.new_workspace()
             recompute = True
@@ -296,6 +305,7 @@ class Renderer:
                        sil_weight=1.0):
         """Gradients of color_weight * MSE(rgb, target) + sil_weight * BCE(alpha, mask) (Sec. 3.1).
         Returns (dV, dC, losses [2] = colour, silhouette)."""
+        self.check_colors(colors, verts)
         if ws is None:
             ws = self.new_workspace()
             recompute = True

@@ -287,3 +287,19 @@ def test_autograd_with_view_dependent_colour(gpu):
     dV, dC = r.backward(verts, torch.from_numpy(C).cuda(), g, ga, saved, ws)
     compare_grads(grads[0][0], to_np(dV), "autograd sh1 vs explicit dV", rel=1e-5)
     compare_grads(grads[0][1], to_np(dC), "autograd sh1 vs explicit dC", rel=1e-5)
+
+
+def test_input_layout_checked_before_launch(gpu):
+    """Colours in the wrong layout for the colour model, or vertices of the wrong size, are refused
+    on the host before any kernel sees them."""
+    import torch
+    W = wl.make_workload(1)
+    r, verts, colors = gpu_setup(W, sh_degree=2)
+    with pytest.raises(ValueError):
+        r.forward(verts, colors)                           # [V,3] where [V,9,3] is expected
+    C = torch.zeros((len(W.verts), 9, 3), device=verts.device)
+    with pytest.raises(ValueError):
+        r.forward(verts[:-1], C)
+    rgb, alpha, saved, ws = r.forward(verts, C)
+    with pytest.raises(ValueError):
+        r.backward(verts, colors, torch.zeros_like(rgb), None, saved, ws)
