@@ -37,7 +37,7 @@ typedef enum gmr_status {
   GMR_ERR_INVALID_ARG = 1,   /* a size, pointer or option is out of range                       */
   GMR_ERR_WORKSPACE = 2,     /* the workspace / saved buffer is smaller than required            */
   GMR_ERR_CAPACITY = 3,      /* instance count exceeded the workspace's capacity (see counters)  */
-  GMR_ERR_UNSUPPORTED = 4,   /* valid request this build does not support                        */
+  GMR_ERR_UNSUPPORTED = 4,   /* valid request the library does not support                       */
   GMR_ERR_HIP = 5            /* a HIP runtime call failed                                        */
 } gmr_status;
 
