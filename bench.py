@@ -310,12 +310,12 @@ def main():
     if dom in FLOPS_PER_PAIR:   # compositing kernels: VALU-bound on LDS-broadcast data
         achieved = d["alg_TFLOPs"]
         roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_VECTOR_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_TFLOPS, 6), "traffic": traffic,
                     "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": pairs[dom]}
     else:
         achieved = d["alg_GBps"]
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+                    "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic}
 
     # ---- per-view launches (same work, one launch set per view) -------------------------------
     per_view = None

@@ -218,3 +218,30 @@ def test_cfg4_batched_equals_per_view_and_oracle(gpu):
         o_rgb, o_tf, _, o_mask = oracle.render_view(mv, mf, mc, cams[v], gid_base=int(W.face_offsets[m]))
         compare_images(to_np(rgb)[po[v]:po[v + 1]], to_np(alpha)[po[v]:po[v + 1]], o_rgb.reshape(-1, 3),
                        o_tf.reshape(-1), o_mask.reshape(-1), label=f"cfg4 view {v}")
+
+
+def test_bench_json_contract(gpu):
+    """bench.py prints one JSON line with the fields its contract names, on a small run."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cmd = [sys.executable, os.path.join(root, "bench.py"), "--config", "1", "--steps", "3", "--warmup", "1",
+           "--no-per-view", "--cpu-seconds", "0.5"]
+    say("bench contract: " + " ".join(cmd[1:]))
+    out = subprocess.run(cmd, capture_output=True, text=True, timeout=110)
+    assert out.returncode == 0, out.stderr[-2000:]
+    lines = [l for l in out.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 3 and d["warmup"] == 1 and d["value"] > 0
+    assert d["config"]["workload"] == "icosphere_s2_1x128"
+    rf = d["roofline"]
+    assert rf["bound"] in ("hbm", "alu") and rf["peak"] > 0
+    assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], rel=2e-2, abs=1e-6)
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
