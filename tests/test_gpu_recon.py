@@ -303,3 +303,50 @@ def test_input_layout_checked_before_launch(gpu):
     rgb, alpha, saved, ws = r.forward(verts, C)
     with pytest.raises(ValueError):
         r.backward(verts, colors, torch.zeros_like(rgb), None, saved, ws)
+
+
+def test_recon_and_view_dependent_colour_full_size(gpu):
+    """The 8-view 512^2 icosphere at full size, in the launch configuration the bench times: the
+    reconstruction backward (colour + silhouette) and, separately, sh_degree 3 colour against the
+    oracle's image and adjoint (pixels the oracle flags near a threshold are left out of the
+    upstream gradients)."""
+    import torch
+    W = wl.make_workload(2)
+    tgt, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    sil = _silhouette(W)
+    # reconstruction backward
+    r, verts, colors = gpu_setup(W)
+    target = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    mask = torch.from_numpy(sil.astype(np.float32)).cuda()
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W)
+    from gmr_testutil import compare_images
+    compare_images(rgb, alpha, o_rgb, o_tf, o_mask, label="cfg2 full")
+    keep = ~o_mask
+    _, g_rgb = oracle.l2_loss(o_rgb, tgt)
+    _, g_a = recon.silhouette_bce(1.0 - o_tf, sil, weight=0.5)
+    g_rgb, g_a = g_rgb * keep[:, None], g_a * keep
+    dV, dC = r.backward(verts, colors, torch.from_numpy(g_rgb.astype(np.float32)).cuda(),
+                        torch.from_numpy(g_a.astype(np.float32)).cuda(), saved, ws)
+    oV, oC = oracle.adjoint_workload(W, g_rgb, g_a)
+    compare_grads(dV, oV, "cfg2 full recon upstream dV")
+    compare_grads(dC, oC, "cfg2 full recon upstream dC")
+    dVf, dCf, losses = r.backward_recon(verts, colors, rgb, target, mask, saved, ws, sil_weight=0.5)
+    if not o_mask.any():
+        compare_grads(dVf, oV, "cfg2 full fused recon dV")
+    # view-dependent colour, degree 3
+    rs, _, _ = gpu_setup(W, sh_degree=3)
+    rng = np.random.default_rng(44)
+    C = np.zeros((len(W.verts), 16, 3), np.float32)
+    C[:, 0] = W.colors
+    C[:, 1:] = rng.normal(0, 0.15, size=(len(W.verts), 15, 3))
+    c3 = torch.from_numpy(C).cuda()
+    rgb, alpha, saved, ws = rs.forward(verts, c3)
+    P = oracle.Params(sh_degree=3)
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W, P, colors=C)
+    compare_images(rgb, alpha, o_rgb, o_tf, o_mask, label="cfg2 full sh3")
+    g = rng.normal(size=(W.num_pixels, 3)) * (~o_mask)[:, None] / W.num_pixels
+    dV, dC = rs.backward(verts, c3, torch.from_numpy(g.astype(np.float32)).cuda(), None, saved, ws)
+    oV, oC = oracle.adjoint_workload(W, g, None, P, colors=C)
+    compare_grads(dV, oV, "cfg2 full sh3 dV")
+    compare_grads(dC, oC, "cfg2 full sh3 dC")
