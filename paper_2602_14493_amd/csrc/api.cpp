@@ -184,8 +184,11 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   const int64_t scan_tile = (int64_t)kScanBlock * L.scan_items;
   L.scan_blocks = (int32_t)((p.fv_total + scan_tile - 1) / scan_tile);
   if (L.scan_blocks > 65536) return fail(GMR_ERR_INVALID_ARG, "too many face-views for the single-level scan");
-  L.parts_fv = (int32_t)((p.fv_total + kSortPart - 1) / kSortPart);
-  L.parts_inst = (int32_t)((cap + kSortPart - 1) / kSortPart);
+  L.sort_items_fv = sort_items_for(p.fv_total);
+  L.sort_items_inst = sort_items_for(cap);
+  const int64_t part_fv = (int64_t)kSortBlock * L.sort_items_fv, part_inst = (int64_t)kSortBlock * L.sort_items_inst;
+  L.parts_fv = (int32_t)((p.fv_total + part_fv - 1) / part_fv);
+  L.parts_inst = (int32_t)((cap + part_inst - 1) / part_inst);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t r = off; off = align_up(off + bytes); return r; };
   L.hdr = take(sizeof(WsHdr));
@@ -351,7 +354,7 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
     const bool odd = pass & 1;
     launch_sort_fv_pass(odd ? w.elB : w.elA, odd ? w.elA : w.elB, (uint32_t)p.fv_total, w.hist + pass * kHistStride,
                         odd ? w.descF1 : w.descF0, odd ? w.descF0 : w.descF1, fv_words, &w.hdr->part_ctr[pass], pass,
-                        w.hdr, s);
+                        w.hdr, L.sort_items_fv, s);
   }
   TilePasses tp;
   tp.n = L.tile_passes;
@@ -371,7 +374,8 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
     launch_sort_inst_pass(odd ? w.instB : w.instA, odd ? w.instA : w.instB, last ? w.keysF : nullptr,
                           last ? w.valsF : nullptr, &w.hdr->count, (uint32_t)L.capacity,
                           w.hist + (kTileRow0 + j) * kHistStride, odd ? w.descI1 : w.descI0, odd ? w.descI0 : w.descI1,
-                          last ? 0u : inst_words, &w.hdr->part_ctr[kTileRow0 + j], tp.shift[j], tp.mask[j], s);
+                          last ? 0u : inst_words, &w.hdr->part_ctr[kTileRow0 + j], tp.shift[j], tp.mask[j],
+                          L.sort_items_inst, s);
   }
   {
     StageTimer t(h, s, kStRanges);

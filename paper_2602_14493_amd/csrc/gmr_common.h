@@ -13,8 +13,15 @@ constexpr int kSub = 8;              // raster sub-block side: one 8x8 pixel blo
 constexpr int kRecF4 = 3;            // projected record = 3 x float4 = 48 B per face-view
 constexpr int kSortBlock = 512;      // onesweep workgroup (8 wavefronts)
 constexpr int kScanBlock = 256;
-constexpr int kSortItems = 8;        // elements per thread
-constexpr int kSortPart = kSortBlock * kSortItems;  // elements per partition
+// Onesweep elements per thread: 8 (4096-element partitions) amortises the per-partition work
+// (digit descriptors, look-back) on large inputs; an input that fills fewer than 64 such
+// partitions (a quarter of the CUs) takes 2 (1024), so four times as many workgroups share the
+// ranking and the latency of loads and stores.  (At ~500k elements the small partitions already
+// lose: their descriptors and look-back cost more than the wider spread saves.)
+constexpr int kSortItemsLarge = 8, kSortItemsSmall = 2;
+inline int sort_items_for(int64_t n) {
+  return n < (int64_t)64 * kSortBlock * kSortItemsLarge ? kSortItemsSmall : kSortItemsLarge;
+}
 // Face-views per thread of the scan / emission blocks: the large variant amortises per-workgroup
 // work on big inputs; inputs too small to give every CU a large block take the small one (4x the
 // workgroups).
@@ -109,6 +116,7 @@ struct Layout {
   int64_t fv_total, faces_total, pixels_total, capacity;
   int32_t tiles_total, items_total, tile_bits, tile_passes, scan_blocks, parts_fv, parts_inst;
   int32_t scan_items;  // face-views per thread of the scan / emission blocks (scan_items_for)
+  int32_t sort_items_fv, sort_items_inst;  // onesweep elements per thread (sort_items_for)
   int32_t tile_shift[kMaxPasses - kTileRow0], tile_mask[kMaxPasses - kTileRow0];
 };
 

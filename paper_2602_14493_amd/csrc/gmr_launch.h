@@ -21,10 +21,10 @@ void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t
 
 void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* hist, uint32_t* desc_cur,
                          uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int pass, const WsHdr* hdr,
-                         hipStream_t s);
+                         int items, hipStream_t s);
 void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
                            uint32_t cap, const uint32_t* hist, uint32_t* desc_cur, uint32_t* desc_next,
-                           uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, hipStream_t s);
+                           uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, int items, hipStream_t s);
 void launch_tile_ranges(const uint32_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int blocks, hipStream_t s);
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s);

@@ -12,10 +12,11 @@
 // (key >> 16) - min, which orders those bits exactly, and the fourth pass exits at once.
 //
 // k_onesweep (one launch per pass): each workgroup takes a partition ticket, so every earlier
-// partition is already resident; it loads its 4096 elements, ranks them stably in LDS with
-// wavefront ballots (one ballot per digit bit matches equal digits among 64 lanes), publishes its
-// digit counts, resolves its global offsets by decoupled look-back over the earlier partitions'
-// descriptors, stages the elements in LDS in digit order and writes them out in coalesced runs.
+// partition is already resident; it loads its partition (4096 elements, or 1024 for small inputs),
+// ranks them stably in LDS with wavefront ballots (one ballot per digit bit matches equal digits
+// among 64 lanes), publishes its digit counts, resolves its global offsets by decoupled look-back
+// over the earlier partitions' descriptors, stages the elements in LDS in digit order and writes
+// them out in coalesced runs.
 // Descriptor word: bits 31..30 = {0 empty, 1 aggregate, 2 inclusive prefix}, bits 29..0 = count,
 // so a single 32-bit atomic load observes flag and value together.  Each pass also clears its
 // share of the descriptor buffer the next pass will use, and scans its own digit histogram.
@@ -35,7 +36,8 @@ __device__ inline void desc_store(uint32_t* p, uint32_t v) {
 }
 
 // kSplit: write keys and values to separate uint32 arrays (the last instance pass).
-template <typename E, int kRadix, bool kSplit>
+// kItems: elements per thread; a partition holds kSortBlock * kItems elements.
+template <typename E, int kRadix, bool kSplit, int kItems>
 __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ in, E* __restrict__ out,
                                                          uint32_t* __restrict__ out_k, uint32_t* __restrict__ out_v,
                                                          const uint32_t* __restrict__ n_dev, uint32_t n_max,
@@ -45,7 +47,8 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
                                                          int depth_pass) {
   constexpr int kNW = kSortBlock / kWave;
   constexpr int kBits = kRadix == 256 ? 8 : 9;
-  __shared__ E s_el[kSortPart];
+  constexpr int kPart = kSortBlock * kItems;
+  __shared__ E s_el[kPart];
   __shared__ uint32_t s_wcnt[kNW][kRadix];
   __shared__ uint32_t s_bstart[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
@@ -84,24 +87,24 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   for (int ww = 0; ww < w; ++ww) dig_d += s_hsum[ww];
   const uint32_t n = n_dev ? min(*n_dev, n_max) : n_max;
   const uint32_t part = s_part;
-  const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
+  const uint32_t nparts = (n + kPart - 1) / kPart;
   if (part >= nparts) return;  // uniform across the workgroup
-  const uint32_t base = part * kSortPart;
+  const uint32_t base = part * kPart;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   // ---- load every element first (all loads in flight together)
-  E e[kSortItems];
+  E e[kItems];
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t idx = base + (uint32_t)w * (kSortItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t idx = base + (uint32_t)w * (kItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
     if (idx < n) e[i] = in[idx];
     else e[i] = E{};
   }
   // ---- stable ranking: wavefront w owns elements [w*ITEMS*64, (w+1)*ITEMS*64), 64 at a time
-  uint32_t rank[kSortItems];
+  uint32_t rank[kItems];
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t idx = base + (uint32_t)w * (kSortItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t idx = base + (uint32_t)w * (kItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
     const bool have = idx < n;
     const uint32_t d = ((elem_key(e[i]) >> shift) - sub) & mask;
     uint64_t peers = __ballot(have);
@@ -181,15 +184,15 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
 
   // ---- stage in digit order, then write out in coalesced runs
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const uint32_t idx = base + (uint32_t)w * (kSortItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t idx = base + (uint32_t)w * (kItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
     if (idx < n) {
       const uint32_t dd = ((elem_key(e[i]) >> shift) - sub) & mask;
       s_el[s_bstart[dd] + s_wcnt[w][dd] + rank[i]] = e[i];
     }
   }
   __syncthreads();
-  const uint32_t nb = min((uint32_t)kSortPart, n - base);
+  const uint32_t nb = min((uint32_t)kPart, n - base);
   for (uint32_t s = threadIdx.x; s < nb; s += kSortBlock) {
     const E x = s_el[s];
     const uint32_t dd = ((elem_key(x) >> shift) - sub) & mask;
@@ -246,36 +249,56 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)nb), dim3(256), 0, s, p, n, val);
 }
 
-void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* hist, uint32_t* desc_cur,
+template <int kItems>
+static void sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* hist, uint32_t* desc_cur,
                          uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int pass, const WsHdr* hdr,
                          hipStream_t s) {
-  const uint32_t parts = (n + kSortPart - 1) / kSortPart;
+  const uint32_t parts = (n + kSortBlock * kItems - 1) / (kSortBlock * kItems);
   if (parts == 0) return;
-  hipLaunchKernelGGL((k_onesweep<uint4, 256, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, nullptr, nullptr,
-                     nullptr, n, hist, desc_cur, desc_next, next_words, ticket, 8 * pass, 255u, hdr, pass);
+  hipLaunchKernelGGL((k_onesweep<uint4, 256, false, kItems>), dim3(parts), dim3(kSortBlock), 0, s, in, out, nullptr,
+                     nullptr, nullptr, n, hist, desc_cur, desc_next, next_words, ticket, 8 * pass, 255u, hdr, pass);
+}
+
+void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t* hist, uint32_t* desc_cur,
+                         uint32_t* desc_next, uint32_t next_words, uint32_t* ticket, int pass, const WsHdr* hdr,
+                         int items, hipStream_t s) {
+  if (items == kSortItemsSmall)
+    sort_fv_pass<kSortItemsSmall>(in, out, n, hist, desc_cur, desc_next, next_words, ticket, pass, hdr, s);
+  else
+    sort_fv_pass<kSortItemsLarge>(in, out, n, hist, desc_cur, desc_next, next_words, ticket, pass, hdr, s);
+}
+
+template <int kRadix, int kItems>
+static void sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
+                           uint32_t cap, const uint32_t* hist, uint32_t* desc_cur, uint32_t* desc_next,
+                           uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, hipStream_t s) {
+  const uint32_t parts = (cap + kSortBlock * kItems - 1) / (kSortBlock * kItems);
+  if (parts == 0) return;
+  if (out_k)
+    hipLaunchKernelGGL((k_onesweep<uint2, kRadix, true, kItems>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k,
+                       out_v, n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
+  else
+    hipLaunchKernelGGL((k_onesweep<uint2, kRadix, false, kItems>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k,
+                       out_v, n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
 }
 
 void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
                            uint32_t cap, const uint32_t* hist, uint32_t* desc_cur, uint32_t* desc_next,
-                           uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, hipStream_t s) {
-  const uint32_t parts = (cap + kSortPart - 1) / kSortPart;
-  if (parts == 0) return;
+                           uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, int items, hipStream_t s) {
   // digits of <= 8 bits use the 256-bin variant (fewer ballots, half the descriptors)
-  if (mask <= 255u) {
-    if (out_k)
-      hipLaunchKernelGGL((k_onesweep<uint2, 256, true>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
-                         n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
-    else
-      hipLaunchKernelGGL((k_onesweep<uint2, 256, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
-                         n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
-    return;
-  }
-  if (out_k)
-    hipLaunchKernelGGL((k_onesweep<uint2, 512, true>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v, n_dev,
-                       cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
+  const bool narrow = mask <= 255u, small = items == kSortItemsSmall;
+  if (narrow && small)
+    sort_inst_pass<256, kSortItemsSmall>(in, out, out_k, out_v, n_dev, cap, hist, desc_cur, desc_next, next_words,
+                                         ticket, shift, mask, s);
+  else if (narrow)
+    sort_inst_pass<256, kSortItemsLarge>(in, out, out_k, out_v, n_dev, cap, hist, desc_cur, desc_next, next_words,
+                                         ticket, shift, mask, s);
+  else if (small)
+    sort_inst_pass<512, kSortItemsSmall>(in, out, out_k, out_v, n_dev, cap, hist, desc_cur, desc_next, next_words,
+                                         ticket, shift, mask, s);
   else
-    hipLaunchKernelGGL((k_onesweep<uint2, 512, false>), dim3(parts), dim3(kSortBlock), 0, s, in, out, out_k, out_v,
-                       n_dev, cap, hist, desc_cur, desc_next, next_words, ticket, shift, mask, nullptr, -1);
+    sort_inst_pass<512, kSortItemsLarge>(in, out, out_k, out_v, n_dev, cap, hist, desc_cur, desc_next, next_words,
+                                         ticket, shift, mask, s);
 }
 
 // ranges[] was zeroed by the list-building prologue (tiles without instances stay [0, 0)).
