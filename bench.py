@@ -148,7 +148,7 @@ def byte_model(stage, F, FV, V, P, I, tiles):
     return {
         "project": F * (12 + 36 + 36) + FV * (48 + 16),        # gathers; records + sort elements
         "sort_fv_pass": FV * 32,                                # 16 B element read + written
-        "scan_emit": FV * 32 + I * 8,                           # elements read twice; instances written
+        "scan_emit": FV * 16 + I * 8,                           # elements read once; instances written
         "sort_pass": I * 16,                                    # {tile, face-view} read + written
         "tile_ranges": I * 4 + tiles * 8,
         "raster_fwd": I * (4 + 48) + tiles * 8 + P * (12 + 4 + 8),

@@ -183,7 +183,6 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   L.scan_items = scan_items_for(p.fv_total);
   const int64_t scan_tile = (int64_t)kScanBlock * L.scan_items;
   L.scan_blocks = (int32_t)((p.fv_total + scan_tile - 1) / scan_tile);
-  if (L.scan_blocks > 65536) return fail(GMR_ERR_INVALID_ARG, "too many face-views for the single-level scan");
   L.sort_items_fv = sort_items_for(p.fv_total);
   L.sort_items_inst = sort_items_for(cap);
   const int64_t part_fv = (int64_t)kSortBlock * L.sort_items_fv, part_inst = (int64_t)kSortBlock * L.sort_items_inst;
@@ -195,8 +194,7 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   L.rec = take((size_t)p.fv_total * kRecF4 * 16);
   L.elA = take((size_t)p.fv_total * 16);
   L.elB = take((size_t)p.fv_total * 16);
-  L.bsum = take((size_t)std::max(L.scan_blocks, 1) * 4);
-  L.boff = take((size_t)std::max(L.scan_blocks, 1) * 8);
+  L.bdesc = take((size_t)std::max(L.scan_blocks, 1) * 8);
   L.instA = take((size_t)cap * 8);
   L.instB = take((size_t)cap * 8);
   L.keysF = take((size_t)cap * 4);
@@ -261,8 +259,7 @@ struct WsPtrs {
   float4* rec;
   uint4* elA;
   uint4* elB;
-  uint32_t* bsum;
-  uint64_t* boff;
+  uint64_t* bdesc;
   uint2* instA;
   uint2* instB;
   uint32_t* keysF;
@@ -289,8 +286,7 @@ WsPtrs ws_ptrs(const Layout& L, void* ws) {
   w.rec = reinterpret_cast<float4*>(b + L.rec);
   w.elA = reinterpret_cast<uint4*>(b + L.elA);
   w.elB = reinterpret_cast<uint4*>(b + L.elB);
-  w.bsum = reinterpret_cast<uint32_t*>(b + L.bsum);
-  w.boff = reinterpret_cast<uint64_t*>(b + L.boff);
+  w.bdesc = reinterpret_cast<uint64_t*>(b + L.bdesc);
   w.instA = reinterpret_cast<uint2*>(b + L.instA);
   w.instB = reinterpret_cast<uint2*>(b + L.instB);
   w.keysF = reinterpret_cast<uint32_t*>(b + L.keysF);
@@ -346,7 +342,7 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
     const StatsInfo si{(uint32_t)p.items_total, (unsigned long long)L.statF, (unsigned long long)L.statB};
     launch_project(table, p.f_total, verts, faces, colors, ko, w.rec, w.elA, w.hist,
                    zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.hdr, w.descF0, fv_words, w.ranges,
-                   2 * p.tiles_total, si, s);
+                   2 * p.tiles_total, w.bdesc, L.scan_blocks, (uint32_t)L.capacity, si, s);
   }
   // depth digits on the face-view elements: 4 passes, A -> B -> A -> B -> A
   for (int pass = 0; pass < kDepthPasses; ++pass) {
@@ -364,7 +360,7 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   }
   {
     StageTimer t(h, s, kStScanEmit);
-    launch_bin(table, w.elA, w.elB, p.fv_total, L.scan_items, w.bsum, w.boff, L.scan_blocks, w.hdr, (uint32_t)L.capacity,
+    launch_bin(table, w.elA, w.elB, p.fv_total, L.scan_items, w.bdesc, L.scan_blocks, w.hdr, (uint32_t)L.capacity,
                w.instA, w.hist, tp, w.descI0, inst_words, s);
   }
   // tile digits on the instances: A -> B -> A ..., the last pass writes keysF / valsF

@@ -77,7 +77,8 @@ struct WsHdr {                 // 256 B at the start of the workspace
   float loss_sil;                  // its silhouette loss
   uint32_t red_ticket;             // last-block ticket of that sum (left at 0)
   uint32_t key_hi_min, key_hi_max; // range of the high 16 depth-key bits over visible face-views
-  uint32_t pad1[41];
+  uint32_t emit_ctr;               // block tickets of the one-pass scan + emission
+  uint32_t pad1[40];
 };
 static_assert(sizeof(WsHdr) == 256, "ws header");
 
@@ -111,7 +112,7 @@ constexpr int kLossReduceBlocks = 256;
 
 // Workspace layout, computed on the host (byte offsets) -------------------------------------------
 struct Layout {
-  size_t hdr, rec, elA, elB, bsum, boff, instA, instB, keysF, valsF, hist, descF0, descF1, descI0, descI1,
+  size_t hdr, rec, elA, elB, bdesc, instA, instB, keysF, valsF, hist, descF0, descF1, descI0, descI1,
       ranges, dfv, fgrad, fsh, statF, statB, statR, total;
   int64_t fv_total, faces_total, pixels_total, capacity;
   int32_t tiles_total, items_total, tile_bits, tile_passes, scan_blocks, parts_fv, parts_inst;

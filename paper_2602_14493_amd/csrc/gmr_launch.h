@@ -8,14 +8,16 @@
 
 namespace gmr {
 
-// Clears the per-build counters, histograms and first depth-pass descriptors, then converts and
-// projects every face into every view of its mesh.
+// Clears the per-build counters, histograms, first depth-pass descriptors and the emission's
+// block descriptors, then converts and projects every face into every view of its mesh.
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
                     const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
                     WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, uint32_t* ranges, int64_t ranges_words,
-                    const StatsInfo& si, hipStream_t s);
+                    uint64_t* bdesc, int64_t bdesc_n, uint32_t cap, const StatsInfo& si, hipStream_t s);
 
-void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
+// One-pass scan of tiles-touched and emission of the instances (nb blocks of kScanBlock * items
+// face-views); writes the instance count and overflow flag.
+void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t n, int items, uint64_t* bdesc, int nb,
                 WsHdr* hdr, uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0,
                 uint32_t desc0_words, hipStream_t s);
 

@@ -4,9 +4,13 @@
 // (tile, depth, id) order.  The emitter also accumulates the histograms of the tile digits and
 // clears the first tile pass's descriptors.
 //
-// Scan: reduce (per 4096 elements) -> single-block scan of the block sums -> emit, which redoes the
-// block-local scan on wavefront shuffles.  Element t of block b, wave w, round i, lane l is
-// b*4096 + w*1024 + i*64 + l: every load is a coalesced 64-wide run.
+// One pass: each workgroup takes a ticket b (so every earlier block is already resident), counts
+// the instances of its face-views, publishes that aggregate, finds its exclusive offset by
+// decoupled look-back over the earlier blocks' descriptors (one wavefront reads 64 of them at a
+// time) and emits.  Element t of block b, wave w, round i, lane l is b*256*I + w*64*I + i*64 + l
+// (I face-views per thread): every load is a coalesced 64-wide run.  Descriptor (64-bit): bits
+// 63..62 = {0 empty, 1 aggregate, 2 inclusive prefix}, bits 61..0 = count; the list-building
+// prologue clears them.  The last block writes the instance total and the overflow flag.
 #include "gmr_common.h"
 #include "gmr_launch.h"
 
@@ -29,78 +33,56 @@ __device__ inline uint32_t wave_sum(uint32_t x) {
   return x;
 }
 
-template <int kItems>
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint4* __restrict__ el_a,
-                                                            const uint4* __restrict__ el_b, const WsHdr* __restrict__ hdr,
-                                                            int64_t n, uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t s_w[kScanBlock / kWave];
-  const uint4* __restrict__ el = depth_keys_narrow(hdr) ? el_b : el_a;  // where the depth passes ended
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int64_t base = (int64_t)blockIdx.x * (kScanBlock * kItems) + (int64_t)w * (kItems * kWave) + lane;
-  uint32_t acc = 0;
+__device__ inline uint64_t wave_sum64(uint64_t x) {
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    const int64_t idx = base + (int64_t)i * kWave;
-    if (idx < n) acc += el_count(el[idx]);
-  }
-  acc = wave_sum(acc);
-  if (lane == 0) s_w[w] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int k = 0; k < kScanBlock / kWave; ++k) t += s_w[k];
-    bsum[blockIdx.x] = t;
-  }
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
 }
 
-// Single workgroup: exclusive scan of the block sums (64-bit), instance total and overflow flag.
-__global__ __launch_bounds__(1024) void k_scan_top(const uint32_t* __restrict__ bsum, int nb, uint64_t* __restrict__ boff,
-                                                   WsHdr* hdr, uint32_t cap) {
-  __shared__ uint64_t s_part[1024 / kWave];
-  __shared__ uint64_t s_carry;
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  if (threadIdx.x == 0) s_carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nb; base += 1024) {
-    const int idx = base + threadIdx.x;
-    const uint64_t x = idx < nb ? bsum[idx] : 0;
-    uint64_t inc = x;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      uint64_t y = __shfl_up(inc, d, kWave);
-      if (lane >= d) inc += y;
-    }
-    if (lane == kWave - 1) s_part[w] = inc;
-    __syncthreads();
-    uint64_t before = s_carry;
-    for (int k = 0; k < w; ++k) before += s_part[k];
-    if (idx < nb) boff[idx] = before + inc - x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint64_t t = 0;
-      for (int k = 0; k < 1024 / kWave; ++k) t += s_part[k];
-      s_carry += t;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const uint64_t total = s_carry;
-    hdr->capacity = cap;
-    hdr->count = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
-    hdr->overflow = total > cap ? 1u : 0u;
+constexpr uint64_t kBinAgg = 1ull << 62, kBinInc = 2ull << 62, kBinVal = (1ull << 62) - 1ull;
+
+__device__ inline uint64_t bdesc_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void bdesc_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wavefront 0 of block b (b > 0): the sum of the counts of blocks [0, b).  Lane l reads the
+// descriptor of block j - l; the nearest inclusive prefix ends the walk, and an empty descriptor
+// (its block has not published yet) ends the window, to be read again.
+__device__ inline uint64_t bin_lookback(const uint64_t* desc, uint32_t b, int lane) {
+  uint64_t excl = 0;
+  int64_t j = (int64_t)b - 1;
+  while (true) {
+    const int64_t q = j - lane;
+    // below block 0 nothing is read: block 0 publishes an inclusive prefix, which ends the walk first
+    const uint64_t x = q >= 0 ? bdesc_load(desc + q) : kBinInc;
+    const uint64_t inc_m = __ballot((x & ~kBinVal) == kBinInc);
+    const uint64_t stop = inc_m | __ballot((x & ~kBinVal) == 0ull);
+    const int f = stop ? __builtin_ctzll(stop) : kWave;  // nearest lane that is not a plain aggregate
+    const bool inclusive = f < kWave && ((inc_m >> f) & 1ull);
+    const int upto = inclusive ? f + 1 : f;
+    excl += wave_sum64(lane < upto ? (x & kBinVal) : 0ull);
+    if (inclusive) return excl;
+    j -= f;
+    if (f < kWave) __builtin_amdgcn_s_sleep(1);
   }
 }
 
 template <int kItems>
 __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ table, const uint4* __restrict__ el_a,
-                                                     const uint4* __restrict__ el_b, int64_t n,
-                                                     const uint64_t* __restrict__ boff, const WsHdr* __restrict__ hdr,
+                                                     const uint4* __restrict__ el_b, int64_t n, uint32_t nb,
+                                                     uint64_t* bdesc, WsHdr* hdr, uint32_t cap32,
                                                      uint2* __restrict__ inst, uint32_t* __restrict__ hist, TilePasses tp,
                                                      uint32_t* __restrict__ desc0, uint32_t desc0_words) {
   const uint4* __restrict__ el = depth_keys_narrow(hdr) ? el_b : el_a;  // where the depth passes ended
   __shared__ uint32_t s_w[kScanBlock / kWave];
   __shared__ uint32_t s_h[kMaxPasses - kTileRow0][kHistStride];
+  __shared__ uint32_t s_b;
+  __shared__ uint64_t s_excl;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (threadIdx.x == 0) s_b = atomicAdd(&hdr->emit_ctr, 1u);
   const ViewDev* views = table_views(table);
   const int nv = static_cast<const TableHdr*>(table)->num_views;
   for (int i = threadIdx.x; i < tp.n * kHistStride; i += kScanBlock) (&s_h[0][0])[i] = 0u;
@@ -110,7 +92,9 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
     const uint32_t b1 = min(desc0_words, b0 + chunk);
     for (uint32_t i = b0 + threadIdx.x; i < b1; i += kScanBlock) desc0[i] = 0u;
   }
-  const int64_t base = (int64_t)blockIdx.x * (kScanBlock * kItems) + (int64_t)w * (kItems * kWave) + lane;
+  __syncthreads();  // s_b (and the cleared histogram)
+  const uint32_t b = s_b;
+  const int64_t base = (int64_t)b * (kScanBlock * kItems) + (int64_t)w * (kItems * kWave) + lane;
   uint32_t c[kItems];
   uint32_t wtot = 0;
 #pragma unroll
@@ -122,9 +106,25 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
   wtot = wave_sum(wtot);
   if (lane == 0) s_w[w] = wtot;
   __syncthreads();
-  uint64_t off = boff[blockIdx.x];
+  if (w == 0) {
+    uint64_t tot = 0;
+    for (int k = 0; k < kScanBlock / kWave; ++k) tot += s_w[k];
+    if (lane == 0) bdesc_store(bdesc + b, (b == 0 ? kBinInc : kBinAgg) | tot);
+    const uint64_t excl = b > 0 ? bin_lookback(bdesc, b, lane) : 0ull;
+    if (lane == 0) {
+      if (b > 0) bdesc_store(bdesc + b, kBinInc | (excl + tot));
+      s_excl = excl;
+      if (b + 1 == nb) {
+        const uint64_t total = excl + tot;
+        hdr->count = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
+        hdr->overflow = total > cap32 ? 1u : 0u;
+      }
+    }
+  }
+  __syncthreads();
+  uint64_t off = s_excl;
   for (int k = 0; k < w; ++k) off += s_w[k];
-  const uint64_t cap = hdr->capacity;
+  const uint64_t cap = cap32;
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     const uint32_t inc = wave_incl_scan(c[i], lane);
@@ -150,23 +150,16 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
     if ((&s_h[0][0])[i]) atomicAdd(&hist[kTileRow0 * kHistStride + i], (&s_h[0][0])[i]);
 }
 
-void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t n, int items, uint32_t* bsum, uint64_t* boff, int nb,
+void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t n, int items, uint64_t* bdesc, int nb,
                 WsHdr* hdr, uint32_t cap, uint2* inst, uint32_t* hist, const TilePasses& tp, uint32_t* desc0,
                 uint32_t desc0_words, hipStream_t s) {
-  const bool large = items == kScanItemsLarge;
-  if (nb > 0) {
-    if (large) hipLaunchKernelGGL(k_scan_reduce<kScanItemsLarge>, dim3(nb), dim3(kScanBlock), 0, s, el_a, el_b, hdr, n, bsum);
-    else hipLaunchKernelGGL(k_scan_reduce<kScanItemsSmall>, dim3(nb), dim3(kScanBlock), 0, s, el_a, el_b, hdr, n, bsum);
-  }
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, boff, hdr, cap);
-  if (nb > 0) {
-    if (large)
-      hipLaunchKernelGGL(k_emit<kScanItemsLarge>, dim3(nb), dim3(kScanBlock), 0, s, table, el_a, el_b, n, boff, hdr, inst, hist,
-                         tp, desc0, desc0_words);
-    else
-      hipLaunchKernelGGL(k_emit<kScanItemsSmall>, dim3(nb), dim3(kScanBlock), 0, s, table, el_a, el_b, n, boff, hdr, inst, hist,
-                         tp, desc0, desc0_words);
-  }
+  if (nb <= 0) return;  // the prologue left count = 0, overflow = 0
+  if (items == kScanItemsLarge)
+    hipLaunchKernelGGL(k_emit<kScanItemsLarge>, dim3(nb), dim3(kScanBlock), 0, s, table, el_a, el_b, n, (uint32_t)nb,
+                       bdesc, hdr, cap, inst, hist, tp, desc0, desc0_words);
+  else
+    hipLaunchKernelGGL(k_emit<kScanItemsSmall>, dim3(nb), dim3(kScanBlock), 0, s, table, el_a, el_b, n, (uint32_t)nb,
+                       bdesc, hdr, cap, inst, hist, tp, desc0, desc0_words);
 }
 
 }  // namespace gmr

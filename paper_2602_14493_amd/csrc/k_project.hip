@@ -136,19 +136,26 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
     if (s_h[i]) atomicAdd(&hist[(i >> 8) * kHistStride + (i & 255)], s_h[i]);
 }
 
-// Clears the per-build counters, every histogram row and the first depth pass's descriptors, and
+// Clears the per-build counters, every histogram row, the first depth pass's descriptors and the
+// emission's block descriptors, sets the instance capacity (count 0 until the emission) and
 // records where the raster kernels' per-item statistics live.
 __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restrict__ hist,
                                                   uint32_t* __restrict__ desc0, int64_t desc0_words,
                                                   uint32_t* __restrict__ ranges, int64_t ranges_words,
+                                                  uint64_t* __restrict__ bdesc, int64_t bdesc_n, uint32_t cap,
                                                   StatsInfo si) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t; i < desc0_words; i += stride) desc0[i] = 0u;
   for (int64_t i = t; i < ranges_words; i += stride) ranges[i] = 0u;  // empty tiles keep [0, 0)
+  for (int64_t i = t; i < bdesc_n; i += stride) bdesc[i] = 0ull;
   for (int64_t i = t; i < kMaxPasses * kHistStride; i += stride) hist[i] = 0u;
   if (t == 0) {
     for (int p = 0; p < kMaxPasses; ++p) hdr->part_ctr[p] = 0u;
+    hdr->emit_ctr = 0u;
+    hdr->count = 0u;  // the emission's last block overwrites both
+    hdr->overflow = 0u;
+    hdr->capacity = cap;
     hdr->stats_items = si.items;
     hdr->bwd_stats = 0u;
     hdr->stats_fwd_off = si.fwd_off;
@@ -162,11 +169,11 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
                     const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
                     WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, uint32_t* ranges, int64_t ranges_words,
-                    const StatsInfo& si, hipStream_t s) {
-  int64_t pb = (std::max(desc0_words, ranges_words) + 255) / 256;
+                    uint64_t* bdesc, int64_t bdesc_n, uint32_t cap, const StatsInfo& si, hipStream_t s) {
+  int64_t pb = (std::max(std::max(desc0_words, ranges_words), bdesc_n) + 255) / 256;
   pb = pb < 1 ? 1 : (pb > 4096 ? 4096 : pb);
   hipLaunchKernelGGL(k_prologue, dim3((unsigned)pb), dim3(256), 0, s, hdr, hist, desc0, desc0_words, ranges,
-                     ranges_words, si);
+                     ranges_words, bdesc, bdesc_n, cap, si);
   if (faces_total <= 0) return;
   const int bs = 256;
   const int64_t nb = (faces_total + bs - 1) / bs;
