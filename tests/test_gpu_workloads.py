@@ -220,6 +220,54 @@ def test_cfg4_batched_equals_per_view_and_oracle(gpu):
                        o_tf.reshape(-1), o_mask.reshape(-1), label=f"cfg4 view {v}")
 
 
+@pytest.mark.parametrize("cfg", [3, 4])
+def test_tile_lists_bit_exact_large_inputs(gpu, cfg):
+    """Every tile list of the UV sphere (1.6M face-views) and of the 16-mesh batch (64 views)
+    against the oracle's, at full size in the bench's default tiling.  These inputs take the
+    large-input paths the 8-view icosphere does not: 4096-face-view blocks of the one-pass
+    scan + emission (look-back over hundreds of blocks), 4096-element onesweep partitions for the
+    depth and tile digits."""
+    from gmr_testutil import fv_to_face, workspace_lists
+    W = wl.make_workload(cfg)
+    r, verts, colors = gpu_setup(W, tile_w=16, tile_h=16)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    cnt = r.counters(ws)
+    fv = sum(int(W.face_offsets[m + 1] - W.face_offsets[m]) for m in W.view_mesh)
+    say(f"cfg{cfg}: {fv} face-views, {cnt.instances} instances")
+    assert not cnt.overflow
+    assert fv >= (1 << 20) and cnt.instances >= (1 << 18), "the workload must take the large-input paths"
+    ranges, vals = workspace_lists(r, ws)
+    vv_all, gl_all = fv_to_face(W)(vals[:cnt.instances])
+    cams = W.cam_array()
+    tbase, checked = 0, 0
+    for v in range(W.num_views):
+        m = int(W.view_mesh[v])
+        mv, mf, mc = W.mesh(m)
+        f0 = int(W.face_offsets[m])
+        off, ids, amb = oracle.tile_lists_view(mv, mf, mc, cams[v], 16, 16, gid_base=f0)
+        nt = len(off) - 1
+        rv = ranges[tbase:tbase + nt].astype(np.int64)
+        ne = rv[:, 1] > rv[:, 0]
+        if ne.any():  # tile ids are view-major: view v's instances are one run
+            assert (vv_all[rv[ne, 0].min():rv[ne, 1].max()] == v).all(), f"view {v}"
+        for t in range(nt):
+            s, e = rv[t]
+            gl = gl_all[s:e]
+            o_ids, o_amb = ids[off[t]:off[t + 1]], amb[off[t]:off[t + 1]]
+            if not o_amb.any():  # no entry near an extent margin: the lists must be identical
+                assert np.array_equal(gl, o_ids), f"view {v} tile {t}"
+                checked += len(o_ids)
+                continue
+            ambiguous = set(o_ids[o_amb != 0].tolist())
+            want = [i for i, a in zip(o_ids.tolist(), o_amb.tolist()) if a == 0]
+            assert [i for i in gl.tolist() if i not in ambiguous] == want, f"view {v} tile {t}"
+            assert set(gl.tolist()) <= set(o_ids.tolist()), f"view {v} tile {t}"
+            checked += len(want)
+        tbase += nt
+    say(f"checked {checked} list entries")
+    assert checked >= cnt.instances // 2
+
+
 def test_bench_json_contract(gpu):
     """bench.py prints one JSON line with the fields its contract names, on a small run."""
     import json
