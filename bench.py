@@ -47,7 +47,7 @@ TRAFFIC = {
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
                 "project": "k_project.hip", "scan_emit": "k_bin.hip", "face_bwd": "k_grad.hip",
-                "vertex_gather": "k_grad.hip", "fill": "k_grad.hip", "loss_reduce": "k_grad.hip"}
+                "vertex_gather": "k_grad.hip", "fill": "k_grad.hip"}
 
 
 def source_hash(stage):

@@ -241,8 +241,8 @@ gmr_status gmr_profile_enable(gmr_handle h, int32_t enable);
 /* Waits for the recorded events and returns, per stage, its name (names: max_stages x 32 chars),
  * the summed milliseconds and the number of timed launch groups; then discards the records.
  * Stages: project, scan_emit, sort_fv_pass (the depth passes over face-views), sort_pass (the
- * instance passes), tile_ranges, raster_fwd, fill, raster_bwd, face_bwd, vertex_gather,
- * loss_reduce (the fused-loss backwards' fixed-order loss sum).  max_stages must be >= 11. */
+ * instance passes), tile_ranges, raster_fwd, fill, raster_bwd, face_bwd, vertex_gather (with the
+ * fused-loss backwards' fixed-order loss sum).  max_stages must be >= 10. */
 gmr_status gmr_profile_read(gmr_handle h, int32_t max_stages, char* names, float* ms_total, int32_t* launches,
                             int32_t* n_stages);
 

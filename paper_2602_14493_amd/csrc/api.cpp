@@ -18,10 +18,10 @@ using namespace gmr;
 
 // Stages timed by gmr_profile_* (HIP events around each launch group on the call's stream).
 enum Stage { kStProject, kStScanEmit, kStSortFv, kStSortPass, kStRanges, kStRasterFwd, kStFill, kStRasterBwd,
-             kStFaceBwd, kStGather, kStLoss, kNumStages };
+             kStFaceBwd, kStGather, kNumStages };
 static const char* kStageNames[kNumStages] = {"project",     "scan_emit",  "sort_fv_pass", "sort_pass",
                                               "tile_ranges", "raster_fwd", "fill",         "raster_bwd",
-                                              "face_bwd",    "vertex_gather", "loss_reduce"};
+                                              "face_bwd",    "vertex_gather"};
 
 struct gmr_ctx {
   int device = 0;
@@ -427,10 +427,9 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
                       saved_n, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
                       mask, (float)(sil_weight / (double)p.p_total), w.dfv, w.statB, s);
   }
-  if (target) {  // fused loss: fixed-order sum of the per-item slots into the header (and loss_dev)
-    StageTimer t(h, s, kStLoss);
-    launch_loss_reduce(w.statB, p.items_total, w.statR, w.hdr, loss_dev, n_losses, s);
-  }
+  // fused loss: fixed-order sum of the per-item slots into the header (and loss_dev), carried by
+  // the vertex gather's first blocks
+  const LossRed red{w.statB, p.items_total, w.statR, w.hdr, loss_dev, n_losses, 0};
   {
     StageTimer t(h, s, kStFaceBwd);
     launch_face_bwd(table, p.f_total, verts, faces, colors, ko, reinterpret_cast<const float4*>(w.dfv), w.fgrad, w.fsh,
@@ -439,7 +438,7 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   {
     StageTimer t(h, s, kStGather);
     launch_vertex_gather(adj_off, adj_ent, reinterpret_cast<const float*>(w.fgrad), w.fsh, opt->sh_degree, p.v_total,
-                         d_verts, d_colors, s);
+                         d_verts, d_colors, target ? &red : nullptr, s);
   }
   return check_launch();
 }

@@ -34,8 +34,18 @@ void launch_fill_f32(float* p, int64_t n, float val, hipStream_t s);
 // zeroes the backward counters of hdr and dfv[0, n)
 void launch_bwd_prologue(WsHdr* hdr, float* dfv, int64_t n, hipStream_t s);
 
-void launch_loss_reduce(const float4* stats, int items, unsigned long long* part, WsHdr* hdr, float* out, int n_out,
-                        hipStream_t s);
+// The fused-loss backward's fixed-order sum of the per-item loss slots: into hdr->loss / loss_sil
+// and, when out is given, out[0..n_out).  part holds kLossReduceBlocks (a, b) partials.
+struct LossRed {
+  const float4* stats;
+  int items;
+  unsigned long long* part;
+  WsHdr* hdr;
+  float* out;
+  int n_out;
+  int nb;  // blocks taking part (set by the launchers)
+};
+void launch_loss_reduce(const LossRed& r, hipStream_t s);
 
 void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists, const uint32_t* ranges,
                        const uint32_t* vals,
@@ -51,8 +61,9 @@ void launch_raster_bwd(const void* table, int items, int persistent_blocks, int 
 void launch_face_bwd(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
                      const float* colors, const KOpts& o, const float4* dfv, float4* fgrad, float* fsh, hipStream_t s);
 
+// With red != NULL the gather's first blocks also perform the loss sum (one launch fewer).
 void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* fgrad, const float* fsh, int sh_degree,
-                          int64_t nv, float* dV, float* dC, hipStream_t s);
+                          int64_t nv, float* dV, float* dC, const LossRed* red, hipStream_t s);
 
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                  int32_t* step, hipStream_t s);

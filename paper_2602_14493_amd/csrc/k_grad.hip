@@ -20,7 +20,8 @@
 // sum is positive, G_c_k += dL/dcolour Y_k(d_v) (the face's coefficient gradients, 3K floats in
 // `fsh`), and G_mu += (I - d d^T) / r_v grad_d(sum_k w_k Y_k), w_k = sum_channels dL/dcolour c_k.
 // k_vertex_gather: one thread per vertex sums its corners through the (vertex -> face, corner)
-// CSR in a fixed order, so the vertex gradients do not depend on atomic ordering.
+// CSR in a fixed order, so the vertex gradients do not depend on atomic ordering.  With a fused
+// loss its first blocks also sum the per-item loss slots (one launch fewer per backward).
 #include "gmr_common.h"
 #include "gmr_launch.h"
 #include "gmr_sh.h"
@@ -279,13 +280,77 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
   }
 }
 
+namespace {
+// Sum of (a, b) over the 256 threads of a block in a fixed order; valid in thread 0.
+__device__ inline void block_sum2(double& a, double& b, double* s_a, double* s_b) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    a += __shfl_xor(a, d, kWave);
+    b += __shfl_xor(b, d, kWave);
+  }
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) { s_a[w] = a; s_b[w] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = s_a[0]; b = s_b[0];
+    for (int i = 1; i < 256 / kWave; ++i) { a += s_a[i]; b += s_b[i]; }
+  }
+  __syncthreads();
+}
+__device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
+__device__ inline double bitsd(unsigned long long x) { return __longlong_as_double((long long)x); }
+}  // namespace
+
+// Fused-loss backward: the colour and silhouette losses as a deterministic sum of the per-item
+// slots.  Block b < r.nb sums a contiguous chunk; the block that takes the last ticket sums the
+// block results in block order and writes the header (and `out`, n_out floats, when given).
+// Every thread of the block calls it (it synchronises the block).
+__device__ inline void loss_reduce_block(const LossRed& r, int b) {
+  __shared__ double s_a[256 / kWave], s_b[256 / kWave];
+  __shared__ bool s_last;
+  const int nb = r.nb;
+  const int chunk = (r.items + nb - 1) / nb;
+  const int lo = b * chunk, hi = min(r.items, lo + chunk);
+  double l = 0.0, ls = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += 256) {
+    const float4 v = r.stats[i];
+    l += (double)v.x;
+    ls += (double)v.y;
+  }
+  block_sum2(l, ls, s_a, s_b);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&r.part[2 * b], dbits(l), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&r.part[2 * b + 1], dbits(ls), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t t = __hip_atomic_fetch_add(&r.hdr->red_ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = t == (uint32_t)nb - 1u;
+  }
+  __syncthreads();
+  if (!s_last) return;  // uniform across the block
+  __threadfence();
+  l = 0.0; ls = 0.0;
+  if ((int)threadIdx.x < nb) {
+    l = bitsd(__hip_atomic_load(&r.part[2 * threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    ls = bitsd(__hip_atomic_load(&r.part[2 * threadIdx.x + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  }
+  block_sum2(l, ls, s_a, s_b);
+  if (threadIdx.x == 0) {
+    r.hdr->loss = (float)l;
+    r.hdr->loss_sil = (float)ls;
+    if (r.out) {
+      r.out[0] = (float)l;
+      if (r.n_out > 1) r.out[1] = (float)ls;
+    }
+    r.hdr->red_ticket = 0u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_loss_reduce(LossRed r) { loss_reduce_block(r, (int)blockIdx.x); }
+
 template <int SHD>
-__global__ __launch_bounds__(256) void k_vertex_gather(const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
-                                                       const float* __restrict__ fgrad, const float* __restrict__ fsh,
-                                                       int64_t nv, float* __restrict__ dV, float* __restrict__ dC) {
+__device__ inline void gather_vertex(const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
+                                     const float* __restrict__ fgrad, const float* __restrict__ fsh, int64_t v,
+                                     float* __restrict__ dV, float* __restrict__ dC) {
   constexpr int K = sh_count<SHD>();
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
   float gx = 0.f, gy = 0.f, gz = 0.f, cr = 0.f, cg = 0.f, cb = 0.f;
   float cs[K][3];
   if constexpr (SHD > 0) {
@@ -324,6 +389,16 @@ __global__ __launch_bounds__(256) void k_vertex_gather(const int32_t* __restrict
   }
 }
 
+template <int SHD>
+__global__ __launch_bounds__(256) void k_vertex_gather(const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
+                                                       const float* __restrict__ fgrad, const float* __restrict__ fsh,
+                                                       int64_t nv, float* __restrict__ dV, float* __restrict__ dC,
+                                                       LossRed red) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nv) gather_vertex<SHD>(off, ent, fgrad, fsh, v, dV, dC);
+  if (red.stats && (int)blockIdx.x < red.nb) loss_reduce_block(red, (int)blockIdx.x);  // block-uniform
+}
+
 __global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t n, float val) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = val;
 }
@@ -341,75 +416,6 @@ __global__ __launch_bounds__(256) void k_bwd_prologue(WsHdr* __restrict__ hdr, f
   }
 }
 
-namespace {
-// Sum of (a, b) over the 256 threads of a block in a fixed order; valid in thread 0.
-__device__ inline void block_sum2(double& a, double& b, double* s_a, double* s_b) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    a += __shfl_xor(a, d, kWave);
-    b += __shfl_xor(b, d, kWave);
-  }
-  const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) { s_a[w] = a; s_b[w] = b; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a = s_a[0]; b = s_b[0];
-    for (int i = 1; i < 256 / kWave; ++i) { a += s_a[i]; b += s_b[i]; }
-  }
-  __syncthreads();
-}
-__device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
-__device__ inline double bitsd(unsigned long long x) { return __longlong_as_double((long long)x); }
-}  // namespace
-
-// Fused-loss backward: the colour and silhouette losses as a deterministic sum of the per-item
-// slots.  Block b sums a contiguous chunk; the block that takes the last ticket sums the block
-// results in block order and writes the header (and `out`, n_out floats, when given).
-__global__ __launch_bounds__(256) void k_loss_reduce(const float4* __restrict__ stats, int items,
-                                                     unsigned long long* part, WsHdr* hdr, float* out, int n_out) {
-  __shared__ double s_a[256 / kWave], s_b[256 / kWave];
-  __shared__ bool s_last;
-  const int nb = (int)gridDim.x;
-  const int chunk = (items + nb - 1) / nb;
-  const int lo = (int)blockIdx.x * chunk, hi = min(items, lo + chunk);
-  double l = 0.0, ls = 0.0;
-  for (int i = lo + (int)threadIdx.x; i < hi; i += 256) {
-    const float4 v = stats[i];
-    l += (double)v.x;
-    ls += (double)v.y;
-  }
-  block_sum2(l, ls, s_a, s_b);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&part[2 * blockIdx.x], dbits(l), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&part[2 * blockIdx.x + 1], dbits(ls), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t t = __hip_atomic_fetch_add(&hdr->red_ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = t == (uint32_t)nb - 1u;
-  }
-  __syncthreads();
-  if (!s_last) return;  // uniform across the block
-  __threadfence();
-  l = 0.0; ls = 0.0;
-  if ((int)threadIdx.x < nb) {
-    l = bitsd(__hip_atomic_load(&part[2 * threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    ls = bitsd(__hip_atomic_load(&part[2 * threadIdx.x + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  }
-  block_sum2(l, ls, s_a, s_b);
-  if (threadIdx.x == 0) {
-    hdr->loss = (float)l;
-    hdr->loss_sil = (float)ls;
-    if (out) {
-      out[0] = (float)l;
-      if (n_out > 1) out[1] = (float)ls;
-    }
-    hdr->red_ticket = 0u;
-  }
-}
-
-void launch_loss_reduce(const float4* stats, int items, unsigned long long* part, WsHdr* hdr, float* out, int n_out,
-                        hipStream_t s) {
-  const int nb = std::max(1, std::min(kLossReduceBlocks, (items + 2047) / 2048));
-  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)nb), dim3(256), 0, s, stats, items, part, hdr, out, n_out);
-}
 
 // Adam with bias correction; t = step + 1 is read from the device (advanced by k_adam_tick).
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -443,15 +449,30 @@ void launch_face_bwd(const void* table, int64_t faces_total, const float* verts,
   }
 }
 
+void launch_loss_reduce(const LossRed& r, hipStream_t s) {
+  LossRed q = r;
+  q.nb = std::max(1, std::min(kLossReduceBlocks, (r.items + 2047) / 2048));
+  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)q.nb), dim3(256), 0, s, q);
+}
+
 void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* fgrad, const float* fsh, int sh_degree,
-                          int64_t nv, float* dV, float* dC, hipStream_t s) {
-  if (nv <= 0) return;
-  const dim3 grid((unsigned)((nv + 255) / 256));
+                          int64_t nv, float* dV, float* dC, const LossRed* red, hipStream_t s) {
+  if (nv <= 0) {
+    if (red) launch_loss_reduce(*red, s);
+    return;
+  }
+  const int64_t blocks = (nv + 255) / 256;
+  LossRed q{};
+  if (red) {
+    q = *red;
+    q.nb = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(kLossReduceBlocks, (red->items + 2047) / 2048), blocks));
+  }
+  const dim3 grid((unsigned)blocks);
   switch (sh_degree) {
-    case 1: hipLaunchKernelGGL(k_vertex_gather<1>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC); break;
-    case 2: hipLaunchKernelGGL(k_vertex_gather<2>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC); break;
-    case 3: hipLaunchKernelGGL(k_vertex_gather<3>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC); break;
-    default: hipLaunchKernelGGL(k_vertex_gather<0>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC); break;
+    case 1: hipLaunchKernelGGL(k_vertex_gather<1>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC, q); break;
+    case 2: hipLaunchKernelGGL(k_vertex_gather<2>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC, q); break;
+    case 3: hipLaunchKernelGGL(k_vertex_gather<3>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC, q); break;
+    default: hipLaunchKernelGGL(k_vertex_gather<0>, grid, dim3(256), 0, s, off, ent, fgrad, fsh, nv, dV, dC, q); break;
   }
 }
 
