@@ -36,13 +36,13 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # were taken, and a changed source reports null.
 TRAFFIC = {
     ("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1):
-        {"fetch": 77166859, "write": 27982140, "src": "98b165faf507c583"},
+        {"fetch": 77168323, "write": 27984535, "src": "7e2177358af4399e"},
     ("icosphere_s5_8x512", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 76662477, "write": 27981547, "src": "98b165faf507c583"},
+        {"fetch": 76662396, "write": 27986965, "src": "7e2177358af4399e"},
     ("icosphere_s5_8x512", "raster_bwd", "32x32", 1, 0, 1):
-        {"fetch": 76290856, "write": 27983574, "src": "98b165faf507c583"},
+        {"fetch": 76290850, "write": 27989195, "src": "7e2177358af4399e"},
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 16681155983, "write": 1787684279, "src": "98b165faf507c583"},
+        {"fetch": 16687148933, "write": 1787675529, "src": "7e2177358af4399e"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
