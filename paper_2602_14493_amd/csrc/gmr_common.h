@@ -25,7 +25,7 @@ inline int sort_items_for(int64_t n) {
 // Face-views per thread of the scan / emission blocks: the large variant amortises per-workgroup
 // work on big inputs; inputs too small to give every CU a large block take the small one (4x the
 // workgroups).
-constexpr int kScanItemsLarge = 16, kScanItemsSmall = 4;
+constexpr int kScanItemsLarge = 8, kScanItemsSmall = 4;
 inline int scan_items_for(int64_t n) { return n >= (int64_t{1} << 20) ? kScanItemsLarge : kScanItemsSmall; }
 constexpr int kMaxPasses = 8;        // histogram rows: 0..3 depth digits (face-views), 4..7 tile digits
 constexpr int kDepthPasses = 4;      // 32 depth bits in 8-bit digits

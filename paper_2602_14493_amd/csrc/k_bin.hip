@@ -7,8 +7,11 @@
 // One pass: each workgroup takes a ticket b (so every earlier block is already resident), counts
 // the instances of its face-views, publishes that aggregate, finds its exclusive offset by
 // decoupled look-back over the earlier blocks' descriptors (one wavefront reads 64 of them at a
-// time) and emits.  Element t of block b, wave w, round i, lane l is b*256*I + w*64*I + i*64 + l
-// (I face-views per thread): every load is a coalesced 64-wide run.  Descriptor (64-bit): bits
+// time) and emits, from the elements it kept in registers.  Large inputs: the wavefront writes the
+// runs of its 64 face-views 64 instances at a time (coalesced stores, every lane busy); small,
+// latency-bound inputs: each lane writes its own face-view's run.  Element t of block b, wave w,
+// round i, lane l is b*256*I + w*64*I + i*64 + l (I face-views per thread): every load is a
+// coalesced 64-wide run.  Descriptor (64-bit): bits
 // 63..62 = {0 empty, 1 aggregate, 2 inclusive prefix}, bits 61..0 = count; the list-building
 // prologue clears them.  The last block writes the instance total and the overflow flag.
 #include "gmr_common.h"
@@ -16,7 +19,14 @@
 
 namespace gmr {
 
-__device__ inline uint32_t el_count(const uint4& e) { return (e.w & 0xffffu) * (e.w >> 16); }
+// Instances of a face-view from its packed tile extent nx | ny << 16.
+__device__ inline uint32_t wh_count(uint32_t wh) { return (wh & 0xffffu) * (wh >> 16); }
+
+// Per-wavefront staging of one round's 64 face-views for the cooperative emission.
+struct EmitLds {
+  uint32_t fv[kWave], t0[kWave], nxtx[kWave], ex[kWave];  // face-view, first tile, nx | tiles_x << 16, run start
+  int32_t mark[kWave];                                     // source lane of the run starting at a window slot
+};
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
 #pragma unroll
@@ -81,6 +91,7 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
   __shared__ uint32_t s_h[kMaxPasses - kTileRow0][kHistStride];
   __shared__ uint32_t s_b;
   __shared__ uint64_t s_excl;
+  __shared__ EmitLds s_lds[kScanBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   if (threadIdx.x == 0) s_b = atomicAdd(&hdr->emit_ctr, 1u);
   const ViewDev* views = table_views(table);
@@ -95,13 +106,19 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
   __syncthreads();  // s_b (and the cleared histogram)
   const uint32_t b = s_b;
   const int64_t base = (int64_t)b * (kScanBlock * kItems) + (int64_t)w * (kItems * kWave) + lane;
-  uint32_t c[kItems];
+  // the elements stay in registers from the count to the emission: {face-view, first tile, nx | ny << 16}
+  uint32_t ef[kItems], et[kItems], ew[kItems];
   uint32_t wtot = 0;
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
     const int64_t idx = base + (int64_t)i * kWave;
-    c[i] = idx < n ? el_count(el[idx]) : 0u;
-    wtot += c[i];
+    ew[i] = 0u;
+    ef[i] = et[i] = 0u;
+    if (idx < n) {
+      const uint4 e = el[idx];
+      ef[i] = e.y; et[i] = e.z; ew[i] = e.w;
+    }
+    wtot += wh_count(ew[i]);
   }
   wtot = wave_sum(wtot);
   if (lane == 0) s_w[w] = wtot;
@@ -125,24 +142,75 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
   uint64_t off = s_excl;
   for (int k = 0; k < w; ++k) off += s_w[k];
   const uint64_t cap = cap32;
+  if constexpr (kItems == kScanItemsSmall) {
+    // small inputs (latency-bound): each lane writes its own face-view's run
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    const uint32_t inc = wave_incl_scan(c[i], lane);
-    const uint64_t my = off + inc - c[i];
-    off += __shfl(inc, kWave - 1, kWave);
-    if (c[i] == 0) continue;
-    const uint4 e = el[base + (int64_t)i * kWave];
-    const uint32_t nx = e.w & 0xffffu, ny = e.w >> 16;
-    const uint32_t tiles_x = (uint32_t)views[find_view_by_fv(views, nv, (int64_t)e.y)].tiles_x;
-    uint64_t pos = my;
-    for (uint32_t ty = 0; ty < ny; ++ty) {
-      for (uint32_t tx = 0; tx < nx; ++tx, ++pos) {
-        if (pos < cap) {
-          const uint32_t tile = e.z + ty * tiles_x + tx;
-          inst[pos] = make_uint2(tile, e.y);
-          for (int p = 0; p < tp.n; ++p) atomicAdd(&s_h[p][(tile >> tp.shift[p]) & tp.mask[p]], 1u);
+    for (int i = 0; i < kItems; ++i) {
+      const uint32_t c = wh_count(ew[i]);
+      const uint32_t inc = wave_incl_scan(c, lane);
+      uint64_t pos = off + inc - c;
+      off += __shfl(inc, kWave - 1, kWave);
+      if (c == 0u) continue;
+      const uint32_t nx = ew[i] & 0xffffu, ny = ew[i] >> 16;
+      const uint32_t tiles_x = (uint32_t)views[find_view_by_fv(views, nv, (int64_t)ef[i])].tiles_x;
+      for (uint32_t ty = 0; ty < ny; ++ty) {
+        for (uint32_t tx = 0; tx < nx; ++tx, ++pos) {
+          if (pos < cap) {
+            const uint32_t tile = et[i] + ty * tiles_x + tx;
+            inst[pos] = make_uint2(tile, ef[i]);
+            for (int q = 0; q < tp.n; ++q) atomicAdd(&s_h[q][(tile >> tp.shift[q]) & tp.mask[q]], 1u);
+          }
         }
       }
+    }
+  } else {
+    EmitLds& L = s_lds[w];
+    const uint64_t le_mask = (2ull << lane) - 1ull;  // slots 0..lane
+    // Large inputs: each round's 64 face-views own consecutive runs of the output, and the wavefront
+    // writes them 64 instances at a time (coalesced, every lane busy): slot t of a window holds
+    // output j0 + t, whose face-view is the one whose run starts at the last marked slot <= t (each
+    // run marks its first slot in the window).
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const uint32_t c = wh_count(ew[i]);
+      const uint32_t inc = wave_incl_scan(c, lane);
+      const uint32_t total = __shfl(inc, kWave - 1, kWave);
+      if (total == 0u) continue;  // wave-uniform
+      const uint32_t excl = inc - c;
+      const uint32_t nx = ew[i] & 0xffffu;
+      const uint32_t tiles_x = c ? (uint32_t)views[find_view_by_fv(views, nv, (int64_t)ef[i])].tiles_x : 0u;
+      L.fv[lane] = ef[i];
+      L.t0[lane] = et[i];
+      L.nxtx[lane] = nx | (tiles_x << 16);
+      L.ex[lane] = excl;
+      for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
+        L.mark[lane] = -1;
+        wave_lds_sync();
+        if (c > 0u && excl < j0 + kWave && excl + c > j0) L.mark[excl > j0 ? excl - j0 : 0u] = lane;
+        wave_lds_sync();
+        const int mk = L.mark[lane];
+        const uint64_t heads = __ballot(mk >= 0) & le_mask;  // slot 0 is always marked
+        const int ps = 63 - __builtin_clzll(heads);
+        const int src = ps == lane ? mk : L.mark[ps];
+        const uint32_t j = j0 + (uint32_t)lane;
+        if (j < total) {
+          const uint32_t k = j - L.ex[src];
+          const uint32_t nt = L.nxtx[src], nxs = nt & 0xffffu;
+          // k / nxs: a float estimate (k < 2^24 is exact in float), then exact integer correction
+          uint32_t ty = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)nxs));
+          int32_t r = (int32_t)(k - ty * nxs);
+          while (r < 0) { --ty; r += (int32_t)nxs; }
+          while (r >= (int32_t)nxs) { ++ty; r -= (int32_t)nxs; }
+          const uint64_t pos = off + j;
+          if (pos < cap) {
+            const uint32_t tile = L.t0[src] + ty * (nt >> 16) + (uint32_t)r;
+            inst[pos] = make_uint2(tile, L.fv[src]);
+            for (int q = 0; q < tp.n; ++q) atomicAdd(&s_h[q][(tile >> tp.shift[q]) & tp.mask[q]], 1u);
+          }
+        }
+        wave_lds_sync();  // the next window (or round) rewrites the slots
+      }
+      off += total;
     }
   }
   __syncthreads();
