@@ -73,6 +73,32 @@ __device__ inline bool rect_meets_block(uint32_t rx, uint32_t ry, int bx0, int b
   return ix0 <= bx0 + kSub - 1 && ix1 >= bx0 && iy0 <= by0 + bh - 1 && iy1 >= by0;
 }
 
+// Whether the record's Gaussian can reach the alpha cutoff anywhere in the pixel-centre box of the
+// block [bx0 + 1/2, bx0 + 7.5] x [by0 + 1/2, by0 + bh - 1/2]: the minimum over that box of its
+// power (w1^2 + w2^2 of gauss_exp, a convex quadratic in the offset) against pmax.  The minimum is 0
+// when the mean is inside the box, else it lies on an edge, where the quadratic is minimised in
+// closed form and clamped to the edge.  The box holds every pixel centre of the block, so a record
+// rejected here composites at none of them (pmax carries a margin over the cutoff's power).
+__device__ inline bool ellipse_meets_block(const float4& r0, const float4& r1, int bx0, int by0, int bh, float pmax) {
+  const float cx = r0.x + r0.z, cy = r0.y + r0.w;
+  const float lox = ((float)bx0 + 0.5f) - cx, hix = ((float)bx0 + (float)(kSub - 1) + 0.5f) - cx;
+  const float loy = ((float)by0 + 0.5f) - cy, hiy = ((float)(by0 + bh - 1) + 0.5f) - cy;
+  if (lox <= 0.f && hix >= 0.f && loy <= 0.f && hiy >= 0.f) return true;
+  const float l11 = r1.x, l12 = r1.y, l22 = r1.z;
+  const float cyy = fmaf(l12, l12, l22 * l22);  // coefficient of dy^2
+  auto power = [&](float dx, float dy) {
+    const float w1 = fmaf(l11, dx, l12 * dy), w2 = l22 * dy;
+    return fmaf(w1, w1, w2 * w2);
+  };
+  // edges dx = const: minimiser dy = -l11 l12 dx / cyy; edges dy = const: dx = -l12 dy / l11
+  const float ky = -(l11 * l12) / cyy, kx = -l12 / l11;
+  const float p1 = power(lox, fminf(fmaxf(ky * lox, loy), hiy));
+  const float p2 = power(hix, fminf(fmaxf(ky * hix, loy), hiy));
+  const float p3 = power(fminf(fmaxf(kx * loy, lox), hix), loy);
+  const float p4 = power(fminf(fmaxf(kx * hiy, lox), hix), hiy);
+  return fminf(fminf(p1, p2), fminf(p3, p4)) <= pmax;
+}
+
 __device__ inline bool in_range(uint32_t r, int x) {
   const int lo = (int)(r & 0xffffu), hi = (int)(r >> 16);
   return (uint32_t)(x - lo) <= (uint32_t)(hi - lo);
@@ -700,6 +726,8 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   if (mx == 0) return make_float4(loss, loss_sil, 0.f, 0.f);
   const float px = (float)g.x + 0.5f;
   const float amin = a.o.alpha_min, amax = a.o.alpha_max;
+  // power above which exp2(-power) < alpha_min, with a 2 % margin for rounding
+  const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;
   unsigned long long pairs = 0;  // wave-uniform count
   for (int64_t hi = (int64_t)start + mx; hi > (int64_t)start; hi -= kWave) {
     const int64_t pos = hi - 1 - lane;
@@ -710,7 +738,8 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
       id = a.vals[pos];
       const float4* rp = a.rec + (size_t)kRecF4 * id;
       r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
-      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX);
+      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX) &&
+           ellipse_meets_block(r0, r1, g.bx0, g.by0, kSub * PX, pmax);
     }
     const uint64_t m = __ballot(ov);
     if (m == 0ull) continue;
