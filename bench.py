@@ -36,13 +36,13 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # were taken, and a changed source reports null.
 TRAFFIC = {
     ("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1):
-        {"fetch": 77168323, "write": 27984535, "src": "7e2177358af4399e"},
+        {"fetch": 77197872, "write": 27982993, "src": "323e8803a966b853"},
     ("icosphere_s5_8x512", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 76662396, "write": 27986965, "src": "7e2177358af4399e"},
+        {"fetch": 76693987, "write": 27986035, "src": "323e8803a966b853"},
     ("icosphere_s5_8x512", "raster_bwd", "32x32", 1, 0, 1):
-        {"fetch": 76290850, "write": 27989195, "src": "7e2177358af4399e"},
+        {"fetch": 76322847, "write": 27988105, "src": "323e8803a966b853"},
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 16687148933, "write": 1787675529, "src": "7e2177358af4399e"},
+        {"fetch": 16428218613, "write": 1787915133, "src": "323e8803a966b853"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
