@@ -304,15 +304,19 @@ gmr_status gmr_vector_adam_step(float* param_dev, const float* grad_dev, float* 
  * outside graph capture.
  * ------------------------------------------------------------------------------------------- */
 
-/* Times forward + L2 backward for each candidate tile shape and raster mode on the given inputs
- * (iters timed launches each, after one warm-up) and writes the fastest options to best_out
- * (instance_capacity set with 25% headroom over the measured count).  Results are cached in the
- * handle per (image sizes, face count, views); a cached entry is returned without timing.
- * ms_out (may be NULL) receives the best time per forward+backward. */
+/* Times forward + L2 backward for each candidate tile shape, block shape, raster mode and forward
+ * list walk on the given inputs (iters timed steps each, after one warm-up step), times the three
+ * fastest once more and writes the options with the best of their two timings to best_out
+ * (instance_capacity set with 25% headroom over the measured count).  recompute = 1 times the
+ * backward with the tile lists rebuilt (as gmr_render_bwd_l2 with recompute = 1 runs it: the list
+ * building then counts twice per step); 0 reuses the forward's lists.  Results are cached in the
+ * handle per (image sizes, face count, views, cov_mode, sh_degree, recompute); a cached entry is
+ * returned without timing.  ms_out (may be NULL) receives the best time per forward+backward.
+ * Returns GMR_ERR_INVALID_ARG for a NULL pointer, iters < 1 or recompute not 0 / 1. */
 gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options* base,
                         const float* verts_dev, const int32_t* faces_dev, const float* colors_dev,
                         const float* target_dev, const int32_t* adj_off_dev, const int32_t* adj_ent_dev,
-                        int32_t iters, gmr_options* best_out, float* ms_out, void* stream);
+                        int32_t iters, int32_t recompute, gmr_options* best_out, float* ms_out, void* stream);
 
 #ifdef __cplusplus
 }

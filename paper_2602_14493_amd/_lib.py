@@ -77,7 +77,7 @@ _SIGS = {
     "gmr_vector_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_float, c_float, c_float,
                                        c_float, c_void_p, c_void_p]),
     "gmr_autotune": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p, c_void_p,
-                               c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(gmr_options),
+                               c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.POINTER(gmr_options),
                                ctypes.POINTER(c_float), c_void_p]),
 }
 

@@ -316,13 +316,15 @@ class Renderer:
                            mask.contiguous(), sil_weight, saved, ws, recompute, dV, dC, losses)
         return dV, dC, losses
 
-    def autotune(self, verts, colors, target, iters: int = 3):
-        """gmr_autotune over tile shapes and raster modes; adopts and returns the best options."""
+    def autotune(self, verts, colors, target, iters: int = 3, recompute: bool = False):
+        """gmr_autotune over tile shapes and raster modes; adopts and returns the best options.
+        recompute=True times the backward with the lists rebuilt (the form GraphAdamLoop and
+        render(save_lists=False) run)."""
         best = gmr_options()
         ms = ctypes.c_float()
         call("gmr_autotune", self.handle.ptr, ctypes.byref(self.batch.c), ctypes.byref(self.opts), _ptr(verts),
              _ptr(self.faces), _ptr(colors), _ptr(target), _ptr(self.adj_off), _ptr(self.adj_ent), int(iters),
-             ctypes.byref(best), ctypes.byref(ms), _stream(self.device))
+             int(bool(recompute)), ctypes.byref(best), ctypes.byref(ms), _stream(self.device))
         self.set_options(best)
         return best, float(ms.value)
 

@@ -76,6 +76,20 @@ def test_autotune(gpu):
     best2, ms2 = r.autotune(verts, colors, target, iters=2)  # cached
     assert (best2.tile_w, best2.tile_h, best2.px_per_lane, best2.raster_mode) == \
            (best.tile_w, best.tile_h, best.px_per_lane, best.raster_mode)
+    # timed with the lists rebuilt in the backward: its own cache entry, a valid configuration whose
+    # recompute backward equals the saved-lists backward of the default configuration
+    r3, _, _ = gpu_setup(W)
+    g = torch.randn_like(base)
+    _, _, s0, ws0 = r3.forward(verts, colors)
+    dV0, dC0 = r3.backward(verts, colors, g, None, s0, ws0)
+    best3, ms3 = r3.autotune(verts, colors, target, iters=1, recompute=True)
+    say(f"recompute: best tile {best3.tile_w}x{best3.tile_h} px {best3.px_per_lane}: {ms3:.3f} ms")
+    assert ms3 > 0 and best3.instance_capacity > 0
+    rgb3, _, s3, ws3 = r3.forward(verts, colors, check=True)
+    assert torch.equal(rgb3, base)
+    dV3, dC3 = r3.backward(verts, colors, g, None, s3, r3.new_workspace(), recompute=True)
+    compare_grads(dV3, to_np(dV0), "autotuned recompute dV", rel=1e-5)
+    compare_grads(dC3, to_np(dC0), "autotuned recompute dC", rel=1e-5)
 
 
 def test_autotune_view_dependent_colour(gpu):
