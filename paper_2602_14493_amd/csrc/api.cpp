@@ -890,7 +890,7 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
       o.instance_capacity = std::min<int64_t>((1ll << 30) - 1, (int64_t)(c.instances * 1.25) + 1024);
       return GMR_OK;
     }
-    return fail(GMR_ERR_CAPACITY, "autotune: instance count kept growing");
+    return GMR_ERR_CAPACITY;  // more instances than a workspace can hold: the candidate is skipped
   };
   // round 1: every candidate once; round 2: the three fastest again, each scored by the better of
   // its two timings (a candidate slowed once by interference is not lost, and a lucky first
@@ -906,9 +906,12 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
     o.lane_lists = cd.lanes;
     o.instance_capacity = std::max<int64_t>(b.instance_capacity, 1 << 20);
     float ms = 0.f;
-    if ((result = time_cand(o, ms)) != GMR_OK) break;
+    const gmr_status r = time_cand(o, ms);
+    if (r == GMR_ERR_CAPACITY) continue;
+    if ((result = r) != GMR_OK) break;
     timed.push_back({ms, o});
   }
+  if (result == GMR_OK && timed.empty()) result = fail(GMR_ERR_CAPACITY, "autotune: no candidate fits 2^30 instances");
   gmr_options best = b;
   float best_ms = 1e30f;
   if (result == GMR_OK) {
@@ -916,7 +919,7 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
     for (size_t i = 0; i < timed.size() && i < 3 && result == GMR_OK; ++i) {
       gmr_options o = timed[i].o;
       float ms = 0.f;
-      if ((result = time_cand(o, ms)) != GMR_OK) break;
+      if ((result = time_cand(o, ms)) != GMR_OK) break;  // it fitted in round 1, so it fits again
       const float score = std::min(ms, timed[i].ms);
       if (score < best_ms) {
         best_ms = score;
