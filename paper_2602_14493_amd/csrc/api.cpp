@@ -820,7 +820,8 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
   // candidates: binning tile, pixels per lane (block shape), raster mode
   struct Cand { int tw, th, px, mode, lanes; };
   std::vector<Cand> cands;
-  const int shapes[][2] = {{8, 8}, {16, 16}, {32, 16}, {32, 32}, {64, 32}};
+  // 64 x 64 lets a small batch sort its tile ids in one pass (512 tiles: 8 views of 512^2)
+  const int shapes[][2] = {{8, 8}, {16, 16}, {32, 16}, {32, 32}, {64, 32}, {64, 64}};
   for (const auto& sh : shapes)
     for (int px : {1, 2, 4})
       if (sh[1] % (kSub * px) == 0)
