@@ -827,8 +827,21 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
       if (sh[1] % (kSub * px) == 0)
         for (int mode = 0; mode < 2; ++mode)
           for (int lanes = 0; lanes < 2; ++lanes) cands.push_back({sh[0], sh[1], px, mode, lanes});
-  float *rgb = nullptr, *dv = nullptr, *dc = nullptr;
-  void *saved = nullptr, *ws = nullptr, *table = nullptr;
+  // the search's own scratch, released on every return path
+  struct Scratch {
+    float *rgb = nullptr, *dv = nullptr, *dc = nullptr;
+    void *saved = nullptr, *ws = nullptr, *table = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Scratch() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      for (void* q : {(void*)rgb, (void*)dv, (void*)dc, saved, ws, table})
+        if (q) (void)hipFree(q);
+    }
+  } sc;
+  float *&rgb = sc.rgb, *&dv = sc.dv, *&dc = sc.dc;
+  void *&saved = sc.saved, *&ws = sc.ws, *&table = sc.table;
+  hipEvent_t &e0 = sc.e0, &e1 = sc.e1;
   size_t ws_cap = 0, table_cap = 0;
   GMR_CHECK_HIP(hipMalloc(&rgb, sizeof(float) * 3 * p0.p_total));
   GMR_CHECK_HIP(hipMalloc(&saved, 8 * p0.p_total));
@@ -836,7 +849,6 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
   // colour gradients have the colours' layout: (sh_degree + 1)^2 coefficients per channel
   const size_t n_coef = (size_t)(b.sh_degree + 1) * (b.sh_degree + 1);
   GMR_CHECK_HIP(hipMalloc(&dc, sizeof(float) * 3 * n_coef * p0.v_total));
-  hipEvent_t e0, e1;
   GMR_CHECK_HIP(hipEventCreate(&e0));
   GMR_CHECK_HIP(hipEventCreate(&e1));
   gmr_status result = GMR_OK;
@@ -928,14 +940,6 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipFree(rgb);
-  (void)hipFree(saved);
-  (void)hipFree(dv);
-  (void)hipFree(dc);
-  if (ws) (void)hipFree(ws);
-  if (table) (void)hipFree(table);
   if (result != GMR_OK) return result;
   h->tune_cache[key] = {best, best_ms};
   *best_out = with_tuned(*base, best);
