@@ -32,17 +32,17 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # Measured HBM bytes per launch of the dominant kernels: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch, averaged over the dispatches of one run), each scaled by what the same counter
 # reads for the plain copy of --copy-probe.  Keyed by workload, kernel and launch configuration
-# (tile, pixels per lane, raster mode, lane lists); `src` is the hash of the kernel's sources when the counters
-# were taken, and a changed source reports null.
+# (tile, pixels per lane, raster mode, lane lists); `src` is source_hash of the kernel's code when the
+# counters were taken, and changed code reports null.
 TRAFFIC = {
     ("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1):
-        {"fetch": 77197872, "write": 27982993, "src": "323e8803a966b853"},
+        {"fetch": 77197872, "write": 27982993, "src": "375ba62408c1c45b"},
     ("icosphere_s5_8x512", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 76693987, "write": 27986035, "src": "323e8803a966b853"},
+        {"fetch": 76693987, "write": 27986035, "src": "375ba62408c1c45b"},
     ("icosphere_s5_8x512", "raster_bwd", "32x32", 1, 0, 1):
-        {"fetch": 76322847, "write": 27988105, "src": "323e8803a966b853"},
+        {"fetch": 76322847, "write": 27988105, "src": "375ba62408c1c45b"},
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 16428218613, "write": 1787915133, "src": "323e8803a966b853"},
+        {"fetch": 16428218613, "write": 1787915133, "src": "375ba62408c1c45b"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
@@ -51,12 +51,17 @@ STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sor
 
 
 def source_hash(stage):
+    """Hash of the code (comments and trailing blanks stripped) of a stage's source file and the
+    shared header: a change of code makes stored counters stale, a reworded comment does not."""
     import hashlib
+    import re
     csrc = os.path.join(ROOT, "paper_2602_14493_amd", "csrc")
     h = hashlib.sha256()
     for f in (STAGE_SOURCE[stage], "gmr_common.h"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            code = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        code = "\n".join(line.split("//", 1)[0].rstrip() for line in code.splitlines())
+        h.update(re.sub(r"\n+", "\n", code).encode())
     return h.hexdigest()[:16]
 
 

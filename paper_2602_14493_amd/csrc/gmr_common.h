@@ -22,9 +22,9 @@ constexpr int kSortItemsLarge = 8, kSortItemsSmall = 2;
 inline int sort_items_for(int64_t n) {
   return n < (int64_t)64 * kSortBlock * kSortItemsLarge ? kSortItemsSmall : kSortItemsLarge;
 }
-// Face-views per thread of the scan / emission blocks: the large variant amortises per-workgroup
-// work on big inputs; inputs too small to give every CU a large block take the small one (4x the
-// workgroups).
+// Face-views per thread of the scan / emission blocks: inputs of 1M face-views or more take 8
+// (2048 per block, the elements kept in registers, windowed emission); smaller ones take 4 (1024
+// per block, twice the workgroups, per-lane emission).
 constexpr int kScanItemsLarge = 8, kScanItemsSmall = 4;
 inline int scan_items_for(int64_t n) { return n >= (int64_t{1} << 20) ? kScanItemsLarge : kScanItemsSmall; }
 constexpr int kMaxPasses = 8;        // histogram rows: 0..3 depth digits (face-views), 4..7 tile digits
