@@ -140,6 +140,29 @@ def test_bench_refuses_several_gpus():
     assert r.returncode != 0 and "one GPU" in r.stderr
 
 
+def test_bench_traffic_hash_tracks_code_not_comments(tmp_path, monkeypatch):
+    """The stored HBM-byte counters stay valid across a reworded comment and go stale (null) when
+    the kernel's code changes."""
+    import shutil
+    import bench
+    src = os.path.join(ROOT, "paper_2602_14493_amd", "csrc")
+    fake = tmp_path / "paper_2602_14493_amd" / "csrc"
+    fake.mkdir(parents=True)
+    for f in ("k_raster.hip", "gmr_common.h"):
+        shutil.copy(os.path.join(src, f), fake / f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.source_hash("raster_bwd")
+    assert h0 == bench.TRAFFIC[("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1)]["src"]
+    with open(fake / "k_raster.hip", "a") as f:
+        f.write("\n// a reworded note\n/* and a block\n   comment */\n")
+    assert bench.source_hash("raster_bwd") == h0
+    assert bench.measured_traffic("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1) is not None
+    with open(fake / "k_raster.hip", "a") as f:
+        f.write("static int added_code = 1;\n")
+    assert bench.source_hash("raster_bwd") != h0
+    assert bench.measured_traffic("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1) is None
+
+
 def test_status_strings():
     from paper_2602_14493_amd import _lib
     L = _lib.load()
