@@ -57,6 +57,7 @@ struct Plan {
   int32_t tile_w = 16, tile_h = 16;
   std::vector<ViewDev> views;
   std::vector<int32_t> mfo, mvo, mvs;
+  int32_t max_views = 0;  // most views bound to one mesh
   Layout L{};
   size_t table_bytes = 0;
 };
@@ -152,6 +153,7 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   p.mvs.clear();
   for (int m = 0; m < p.nm; ++m) {
     p.mvo[m + 1] = p.mvo[m] + (int32_t)per_mesh[m].size();
+    p.max_views = std::max(p.max_views, (int32_t)per_mesh[m].size());
     for (int32_t v : per_mesh[m]) p.mvs.push_back(v);
   }
   p.table_bytes = sizeof(TableHdr) + sizeof(ViewDev) * p.nv + sizeof(int32_t) * (2 * (p.nm + 1) + p.nv);
@@ -433,7 +435,7 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   {
     StageTimer t(h, s, kStFaceBwd);
     launch_face_bwd(table, p.f_total, verts, faces, colors, ko, reinterpret_cast<const float4*>(w.dfv), w.fgrad, w.fsh,
-                    s);
+                    p.max_views, s);
   }
   {
     StageTimer t(h, s, kStGather);

@@ -59,7 +59,8 @@ void launch_raster_bwd(const void* table, int items, int persistent_blocks, int 
                        hipStream_t s);
 
 void launch_face_bwd(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
-                     const float* colors, const KOpts& o, const float4* dfv, float4* fgrad, float* fsh, hipStream_t s);
+                     const float* colors, const KOpts& o, const float4* dfv, float4* fgrad, float* fsh, int max_views,
+                     hipStream_t s);
 
 // With red != NULL the gather's first blocks also perform the loss sum (one launch fewer).
 void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* fgrad, const float* fsh, int sh_degree,

@@ -34,15 +34,22 @@ __device__ inline void sym3_from6(const double* s, double (&M)[3][3]) {
   M[2][0] = s[2]; M[2][1] = s[4]; M[2][2] = s[5];
 }
 
-template <int SHD>
+// LPF lanes per face (1 or 8, consecutive lanes of a wavefront): with LPF > 1 lane u of a face's
+// group takes views u, u + LPF, ... of its mesh, the group sums its per-view partials in a fixed
+// tree order, and the group's first lane differentiates the conversion -- small batches then run
+// LPF times as many wavefronts, each with a shorter chain of dependent FP64 work.
+template <int SHD, int LPF>
 __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table, const float* __restrict__ verts,
                                                   const int32_t* __restrict__ faces, const float* __restrict__ colors,
                                                   KOpts o, const float4* __restrict__ dfv, float4* __restrict__ fgrad,
                                                   float* __restrict__ fsh) {
+  static_assert(LPF == 1 || (SHD == 0 && (LPF & (LPF - 1)) == 0 && LPF <= kWave), "LPF: 1, or a power of two without SH");
   constexpr int K = sh_count<SHD>();
   const TableHdr* th = static_cast<const TableHdr*>(table);
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= th->faces_total) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t f = t / LPF;
+  const int u = (int)(t - f * LPF);
+  if (f >= th->faces_total) return;  // the whole group (same face)
   const int32_t* mfo = table_i32(table, th->mesh_face_off);
   const int32_t* mvo = table_i32(table, th->mesh_view_off);
   const int32_t* mvs = table_i32(table, th->mesh_views_off);
@@ -57,10 +64,12 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
   }
   FaceGeo g;
   float4* out = fgrad + 3 * f;
-  if (!face_convert(vi, vj, vk, o.cov_mode, g)) {
-    out[0] = out[1] = out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if constexpr (SHD > 0)
-      for (int k = 0; k < 3 * K; ++k) fsh[3 * K * f + k] = 0.f;
+  if (!face_convert(vi, vj, vk, o.cov_mode, g)) {  // uniform over the face's group
+    if (u == 0) {
+      out[0] = out[1] = out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (SHD > 0)
+        for (int k = 0; k < 3 * K; ++k) fsh[3 * K * f + k] = 0.f;
+    }
     return;
   }
   float coef[K][3], gsh[K][3];
@@ -72,7 +81,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
   double Gmu[3] = {0.0, 0.0, 0.0};
   double GS[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   float gcol[3] = {0.f, 0.f, 0.f};
-  for (int k = mvo[m]; k < mvo[m + 1]; ++k) {
+  for (int k = mvo[m] + u; k < mvo[m + 1]; k += LPF) {
     const ViewDev& V = views[mvs[k]];
     const int64_t fv = V.fv_offset + (f - V.face_begin);
     const float4 d0 = dfv[2 * fv], d1 = dfv[2 * fv + 1];
@@ -154,6 +163,19 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
     Gp[2] = GJm[0][0] * (-fx * iz * iz) + GJm[0][2] * (2.0 * fx * x * iz * iz * iz) + GJm[1][1] * (-fy * iz * iz) +
             GJm[1][2] * (2.0 * fy * y * iz * iz * iz) - du * fx * x * iz * iz - dv * fy * y * iz * iz;
     for (int r = 0; r < 3; ++r) Gmu[r] += R[0][r] * Gp[0] + R[1][r] * Gp[1] + R[2][r] * Gp[2];
+  }
+  if constexpr (LPF > 1) {
+#pragma unroll
+    for (int d = LPF / 2; d > 0; d >>= 1) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        Gmu[r] += __shfl_xor(Gmu[r], d, kWave);
+        gcol[r] += __shfl_xor(gcol[r], d, kWave);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) GS[r][cc] += __shfl_xor(GS[r][cc], d, kWave);
+      }
+    }
+    if (u != 0) return;
   }
   // symmetrise (G_Sigma is symmetric up to rounding)
   for (int r = 0; r < 3; ++r)
@@ -438,14 +460,22 @@ __global__ void k_adam_tick(int32_t* step) {
 }
 
 void launch_face_bwd(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
-                     const float* colors, const KOpts& o, const float4* dfv, float4* fgrad, float* fsh, hipStream_t s) {
+                     const float* colors, const KOpts& o, const float4* dfv, float4* fgrad, float* fsh, int max_views,
+                     hipStream_t s) {
   if (faces_total <= 0) return;
-  const dim3 grid((unsigned)((faces_total + 255) / 256));
+  // 8 lanes per face when the faces alone would leave most of the GPU idle (fewer than 256 per CU)
+  const bool split = o.sh_degree == 0 && max_views > 1 && faces_total < 256 * 256;
+  const int lpf = split ? 8 : 1;
+  const dim3 grid((unsigned)((faces_total * lpf + 255) / 256));
+  if (split) {
+    hipLaunchKernelGGL((k_face_bwd<0, 8>), grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh);
+    return;
+  }
   switch (o.sh_degree) {
-    case 1: hipLaunchKernelGGL(k_face_bwd<1>, grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
-    case 2: hipLaunchKernelGGL(k_face_bwd<2>, grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
-    case 3: hipLaunchKernelGGL(k_face_bwd<3>, grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
-    default: hipLaunchKernelGGL(k_face_bwd<0>, grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
+    case 1: hipLaunchKernelGGL((k_face_bwd<1, 1>), grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
+    case 2: hipLaunchKernelGGL((k_face_bwd<2, 1>), grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
+    case 3: hipLaunchKernelGGL((k_face_bwd<3, 1>), grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
+    default: hipLaunchKernelGGL((k_face_bwd<0, 1>), grid, dim3(256), 0, s, table, verts, faces, colors, o, dfv, fgrad, fsh); break;
   }
 }
 
