@@ -392,6 +392,53 @@ def test_edge_cases(gpu):
         oV, oC = oracle.adjoint_workload(Wk, g)
         if np.abs(oV).max() > 0:
             compare_grads(dV, oV, f"edge{k} dV")
+    # the four views in one batch: a face's views are then split over 8 lanes in the face backward
+    # (a small batch with several views per mesh), the degenerate face included
+    say("edge cases, all views in one batch")
+    Wa = wl._single("edge_all", V, F, C, cams)
+    r, verts, colors = gpu_setup(Wa)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(Wa)
+    g = rng.normal(size=(Wa.num_pixels, 3)) * (~o_mask)[:, None]
+    dV, dC = r.backward(verts, colors, torch.from_numpy(g.astype(np.float32)).cuda(), None, saved, ws)
+    d = to_np(dV)
+    assert np.isfinite(d).all() and (d[3:6] == 0).all()
+    oV, oC = oracle.adjoint_workload(Wa, g)
+    compare_grads(dV, oV, "edge all views dV")
+    compare_grads(dC, oC, "edge all views dC")
+
+
+def test_small_two_mesh_batch_images_and_grads(gpu):
+    """Two small meshes, one with three views and one with a single view, interleaved in the view
+    order: the face backward splits each face's views over 8 lanes (a mesh with fewer views leaves
+    lanes idle); images and gradients against the oracle."""
+    import torch
+    say("small two-mesh batch")
+    rng = np.random.default_rng(11)
+    va, fa = wl.icosphere(2)
+    vb, fb = wl.torus(14, 9, R=0.5, r=0.2)
+    va = va * 0.8 + rng.normal(0, 0.01, size=va.shape)
+    vb = vb + np.array([0.1, -0.05, 0.0]) + rng.normal(0, 0.01, size=vb.shape)
+    verts = np.concatenate([va, vb]).astype(np.float32)
+    faces = np.concatenate([fa, fb + len(va)]).astype(np.int32)
+    colors = rng.uniform(size=verts.shape).astype(np.float32)
+    cams = [wl.look_at_camera((0.0, 0.0, 3.0), width=96, height=80),
+            wl.look_at_camera((1.5, 1.0, 1.2), width=72, height=72),
+            wl.look_at_camera((-2.0, 0.5, 2.0), width=64, height=96),
+            wl.look_at_camera((0.3, -2.5, 1.0), width=80, height=64)]
+    W = wl.Workload(name="two_mesh_small", verts=verts, faces=faces, colors=colors,
+                    vert_offsets=np.array([0, len(va), len(verts)], dtype=np.int64),
+                    face_offsets=np.array([0, len(fa), len(faces)], dtype=np.int64),
+                    view_mesh=np.array([0, 1, 0, 0], dtype=np.int32), cams=cams)
+    r, v_d, c_d = gpu_setup(W)
+    rgb, alpha, saved, ws = r.forward(v_d, c_d)
+    o_rgb, o_tf, _, o_mask = oracle.render_workload(W)
+    compare_images(rgb, alpha, o_rgb, o_tf, o_mask, label="two-mesh")
+    g = rng.normal(size=(W.num_pixels, 3)) * (~o_mask)[:, None] / W.num_pixels
+    dV, dC = r.backward(v_d, c_d, torch.from_numpy(g.astype(np.float32)).cuda(), None, saved, ws)
+    oV, oC = oracle.adjoint_workload(W, g)
+    compare_grads(dV, oV, "two-mesh dV")
+    compare_grads(dC, oC, "two-mesh dC")
 
 
 def test_autograd_recompute_equals_saved(gpu):
