@@ -20,7 +20,8 @@
 // sum is positive, G_c_k += dL/dcolour Y_k(d_v) (the face's coefficient gradients, 3K floats in
 // `fsh`), and G_mu += (I - d d^T) / r_v grad_d(sum_k w_k Y_k), w_k = sum_channels dL/dcolour c_k.
 // k_vertex_gather: one thread per vertex sums its corners through the (vertex -> face, corner)
-// CSR in a fixed order, so the vertex gradients do not depend on atomic ordering.  With a fused
+// CSR in a fixed order, so the vertex gradients do not depend on atomic ordering (a vertex with
+// more than 32 corners is summed by its whole wavefront, lane-strided, in a fixed tree order).  With a fused
 // loss its first blocks also sum the per-item loss slots (one launch fewer per backward).
 #include "gmr_common.h"
 #include "gmr_launch.h"
@@ -368,48 +369,51 @@ __device__ inline void loss_reduce_block(const LossRed& r, int b) {
 
 __global__ __launch_bounds__(256) void k_loss_reduce(LossRed r) { loss_reduce_block(r, (int)blockIdx.x); }
 
+// Corner sums of one vertex: x[0..3) position gradient, x[3 + 3k + channel] colour (coefficient k)
+// gradient.
 template <int SHD>
-__device__ inline void gather_vertex(const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
-                                     const float* __restrict__ fgrad, const float* __restrict__ fsh, int64_t v,
-                                     float* __restrict__ dV, float* __restrict__ dC) {
+struct VertexAcc {
+  static constexpr int n = 3 + 3 * sh_count<SHD>();
+  float x[n];
+};
+
+// Adds the corners e0, e0 + step, ... < e1 of the (vertex -> face, corner) CSR to a.
+template <int SHD>
+__device__ inline void gather_corners(const int32_t* __restrict__ ent, const float* __restrict__ fgrad,
+                                      const float* __restrict__ fsh, int32_t e0, int32_t e1, int32_t step,
+                                      VertexAcc<SHD>& a) {
   constexpr int K = sh_count<SHD>();
-  float gx = 0.f, gy = 0.f, gz = 0.f, cr = 0.f, cg = 0.f, cb = 0.f;
-  float cs[K][3];
-  if constexpr (SHD > 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) cs[k][0] = cs[k][1] = cs[k][2] = 0.f;
-  }
-  for (int32_t e = off[v]; e < off[v + 1]; ++e) {
+  for (int32_t e = e0; e < e1; e += step) {
     const int32_t fc = ent[e];
     const int32_t f = fc / 3, corner = fc - 3 * f;
     const float* p = fgrad + 12 * (int64_t)f;
-    gx += p[3 * corner];
-    gy += p[3 * corner + 1];
-    gz += p[3 * corner + 2];
+    a.x[0] += p[3 * corner];
+    a.x[1] += p[3 * corner + 1];
+    a.x[2] += p[3 * corner + 2];
     if constexpr (SHD == 0) {
-      cr += p[9];
-      cg += p[10];
-      cb += p[11];
+      a.x[3] += p[9];
+      a.x[4] += p[10];
+      a.x[5] += p[11];
     } else {
       const float* q = fsh + (int64_t)3 * K * f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        cs[k][0] += q[3 * k];
-        cs[k][1] += q[3 * k + 1];
-        cs[k][2] += q[3 * k + 2];
-      }
+      for (int k = 0; k < 3 * K; ++k) a.x[3 + k] += q[k];
     }
   }
-  const float third = 1.f / 3.f;
-  dV[3 * v] = gx; dV[3 * v + 1] = gy; dV[3 * v + 2] = gz;
-  if constexpr (SHD == 0) {
-    dC[3 * v] = cr * third; dC[3 * v + 1] = cg * third; dC[3 * v + 2] = cb * third;
-  } else {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      for (int a = 0; a < 3; ++a) dC[((int64_t)v * K + k) * 3 + a] = cs[k][a] * third;
-  }
 }
+
+template <int SHD>
+__device__ inline void write_vertex(const VertexAcc<SHD>& a, int64_t v, float* __restrict__ dV, float* __restrict__ dC) {
+  constexpr int K = sh_count<SHD>();
+  const float third = 1.f / 3.f;
+  dV[3 * v] = a.x[0]; dV[3 * v + 1] = a.x[1]; dV[3 * v + 2] = a.x[2];
+#pragma unroll
+  for (int k = 0; k < 3 * K; ++k) dC[(int64_t)v * 3 * K + k] = a.x[3 + k] * third;
+}
+
+// Vertices with more corners than this (the poles of a UV sphere have hundreds) are gathered by a
+// whole wavefront, so no lane serialises a long run of dependent loads while the others wait.
+constexpr int32_t kCoopCorners = 32;
 
 template <int SHD>
 __global__ __launch_bounds__(256) void k_vertex_gather(const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
@@ -417,7 +421,33 @@ __global__ __launch_bounds__(256) void k_vertex_gather(const int32_t* __restrict
                                                        int64_t nv, float* __restrict__ dV, float* __restrict__ dC,
                                                        LossRed red) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < nv) gather_vertex<SHD>(off, ent, fgrad, fsh, v, dV, dC);
+  const int lane = threadIdx.x & (kWave - 1);
+  int32_t e0 = 0, e1 = 0;
+  if (v < nv) {
+    e0 = off[v];
+    e1 = off[v + 1];
+  }
+  const bool coop = e1 - e0 > kCoopCorners;
+  if (v < nv && !coop) {
+    VertexAcc<SHD> a{};
+    gather_corners<SHD>(ent, fgrad, fsh, e0, e1, 1, a);
+    write_vertex<SHD>(a, v, dV, dC);
+  }
+  // high-degree vertices, one at a time: lane l takes corners l, l + 64, ..., then a fixed-order
+  // tree sum over the wavefront (deterministic)
+  uint64_t m = __ballot(coop);
+  while (m) {
+    const int l = __builtin_ctzll(m);
+    m &= m - 1;
+    const int32_t b0 = __shfl(e0, l, kWave), b1 = __shfl(e1, l, kWave);
+    VertexAcc<SHD> a{};
+    gather_corners<SHD>(ent, fgrad, fsh, b0 + lane, b1, kWave, a);
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1)
+#pragma unroll
+      for (int i = 0; i < VertexAcc<SHD>::n; ++i) a.x[i] += __shfl_xor(a.x[i], d, kWave);
+    if (lane == 0) write_vertex<SHD>(a, (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane) + l, dV, dC);
+  }
   if (red.stats && (int)blockIdx.x < red.nb) loss_reduce_block(red, (int)blockIdx.x);  // block-uniform
 }
 
