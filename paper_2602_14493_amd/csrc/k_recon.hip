@@ -10,7 +10,8 @@
 //
 // Gradients are formed without atomics: one kernel writes each edge's gradient vector and each
 // vertex's normalised Laplacian, and a gather over the vertex -> incident-edge CSR adds them to
-// the vertex gradient in a fixed order, so the result is deterministic.  The loss values are
+// the vertex gradient in a fixed order, so the result is deterministic (vertices of more than 32
+// edges are summed by their wavefront in a fixed tree order).  The loss values are
 // per-block partial sums reduced by one block in block order (deterministic as well).
 #include "gmr_common.h"
 #include "gmr_launch.h"
@@ -33,6 +34,17 @@ __device__ inline void block_sum_store(double x, double* dst) {
     for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += s_w[i];
     *dst = t;
   }
+}
+
+// Vertices with more incident edges than this (UV-sphere poles have hundreds) are summed by their
+// whole wavefront: lane l takes entries l, l + 64, ..., then a fixed-order tree sum, so no lane
+// serialises a long run of dependent loads while the rest of the wavefront waits.
+constexpr int32_t kCoopDegree = 32;
+
+__device__ inline float wave_sum_f(float x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
 }
 
 }  // namespace
@@ -62,15 +74,35 @@ __global__ __launch_bounds__(256) void k_lap_terms(const float* __restrict__ ver
                                                    int64_t V, float scale, float4* __restrict__ lu,
                                                    double* __restrict__ part) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float l = 0.f;
+  const int lane = threadIdx.x & (kWave - 1);
+  int32_t b = 0, n = 0;
   if (i < V) {
-    const int32_t b = voff[i], n = voff[i + 1] - b;
-    float sx = 0.f, sy = 0.f, sz = 0.f;
+    b = voff[i];
+    n = voff[i + 1] - b;
+  }
+  const bool coop = n > kCoopDegree;
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+  if (i < V && !coop) {
     for (int32_t k = 0; k < n; ++k) {
       const int32_t t = vent[b + k];
       const float3 q = ld3(verts, edges[2 * (t >> 1) + (1 - (t & 1))]);
       sx += q.x; sy += q.y; sz += q.z;
     }
+  }
+  for (uint64_t m = __ballot(coop); m; m &= m - 1) {  // high-degree vertices of this wavefront
+    const int o = __builtin_ctzll(m);
+    const int32_t bb = __shfl(b, o, kWave), nn = __shfl(n, o, kWave);
+    float px = 0.f, py = 0.f, pz = 0.f;
+    for (int32_t k = lane; k < nn; k += kWave) {
+      const int32_t t = vent[bb + k];
+      const float3 q = ld3(verts, edges[2 * (t >> 1) + (1 - (t & 1))]);
+      px += q.x; py += q.y; pz += q.z;
+    }
+    px = wave_sum_f(px); py = wave_sum_f(py); pz = wave_sum_f(pz);
+    if (lane == o) { sx = px; sy = py; sz = pz; }
+  }
+  float l = 0.f;
+  if (i < V) {
     float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
     if (n > 0) {
       const float inv = 1.f / (float)n;
@@ -115,26 +147,48 @@ __global__ __launch_bounds__(256) void k_reg_gather(const int32_t* __restrict__ 
                                                     const float4* __restrict__ ge, const float4* __restrict__ lu,
                                                     float* __restrict__ grad) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= V) return;
-  const float4 own = lu ? lu[k] : make_float4(0.f, 0.f, 0.f, 0.f);
-  float gx = -own.x, gy = -own.y, gz = -own.z;
-  const int32_t b = voff[k], n = voff[k + 1] - b;
-  for (int32_t j = 0; j < n; ++j) {
-    const int32_t t = vent[b + j];
-    const int32_t e = t >> 1;
-    if (ge) {
-      const float4 g = ge[e];
-      const float sg = (t & 1) ? -1.f : 1.f;  // side 0 = first end of the edge
-      gx = fmaf(sg, g.x, gx); gy = fmaf(sg, g.y, gy); gz = fmaf(sg, g.z, gz);
-    }
-    if (lu) {
-      const float4 q = lu[edges[2 * e + (1 - (t & 1))]];
-      gx = fmaf(q.x, q.w, gx); gy = fmaf(q.y, q.w, gy); gz = fmaf(q.z, q.w, gz);
-    }
+  const int lane = threadIdx.x & (kWave - 1);
+  int32_t b = 0, n = 0;
+  if (k < V) {
+    b = voff[k];
+    n = voff[k + 1] - b;
   }
-  grad[3 * k] += gx;
-  grad[3 * k + 1] += gy;
-  grad[3 * k + 2] += gz;
+  // incident-edge terms of entries j0, j0 + step, ... < n of the CSR row at b
+  auto add_row = [&](int32_t bb, int32_t j0, int32_t nn, int32_t step, float& gx, float& gy, float& gz) {
+    for (int32_t j = j0; j < nn; j += step) {
+      const int32_t t = vent[bb + j];
+      const int32_t e = t >> 1;
+      if (ge) {
+        const float4 g = ge[e];
+        const float sg = (t & 1) ? -1.f : 1.f;  // side 0 = first end of the edge
+        gx = fmaf(sg, g.x, gx); gy = fmaf(sg, g.y, gy); gz = fmaf(sg, g.z, gz);
+      }
+      if (lu) {
+        const float4 q = lu[edges[2 * e + (1 - (t & 1))]];
+        gx = fmaf(q.x, q.w, gx); gy = fmaf(q.y, q.w, gy); gz = fmaf(q.z, q.w, gz);
+      }
+    }
+  };
+  const bool coop = n > kCoopDegree;
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  if (k < V) {
+    const float4 own = lu ? lu[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+    gx = -own.x; gy = -own.y; gz = -own.z;
+    if (!coop) add_row(b, 0, n, 1, gx, gy, gz);
+  }
+  for (uint64_t m = __ballot(coop); m; m &= m - 1) {  // high-degree vertices of this wavefront
+    const int o = __builtin_ctzll(m);
+    const int32_t bb = __shfl(b, o, kWave), nn = __shfl(n, o, kWave);
+    float px = 0.f, py = 0.f, pz = 0.f;
+    add_row(bb, lane, nn, kWave, px, py, pz);
+    px = wave_sum_f(px); py = wave_sum_f(py); pz = wave_sum_f(pz);
+    if (lane == o) { gx += px; gy += py; gz += pz; }
+  }
+  if (k < V) {
+    grad[3 * k] += gx;
+    grad[3 * k + 1] += gy;
+    grad[3 * k + 2] += gz;
+  }
 }
 
 // VectorAdam on V 3-vectors; t = *step + 1 (advanced by k_adam_tick after the update).
