@@ -201,7 +201,7 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   L.instB = take((size_t)cap * 8);
   L.keysF = take((size_t)cap * 4);
   L.valsF = take((size_t)cap * 4);
-  L.hist = take(kMaxPasses * kHistStride * 4);
+  L.hist = take((size_t)kHistCopies * kHistWords * 4);
   L.descF0 = take((size_t)std::max(L.parts_fv, 1) * 256 * 4);
   L.descF1 = take((size_t)std::max(L.parts_fv, 1) * 256 * 4);
   L.descI0 = take((size_t)L.parts_inst * 512 * 4);

@@ -31,6 +31,11 @@ constexpr int kMaxPasses = 8;        // histogram rows: 0..3 depth digits (face-
 constexpr int kDepthPasses = 4;      // 32 depth bits in 8-bit digits
 constexpr int kTileRow0 = 4;
 constexpr int kHistStride = 512;     // one histogram row holds up to 512 bins
+constexpr int kHistWords = kMaxPasses * kHistStride;
+// The digit histograms are kept in 8 copies: workgroup b adds its counts to copy b mod 8, and a
+// sort pass sums the copies of its row, so the atomics of many workgroups on few bins spread over
+// 8 times as many addresses.
+constexpr int kHistCopies = 8;
 constexpr uint32_t kFlagAgg = 1u << 30;   // onesweep partition descriptor: aggregate published
 constexpr uint32_t kFlagInc = 2u << 30;   // inclusive prefix published
 constexpr uint32_t kValMask = (1u << 30) - 1u;

@@ -215,7 +215,8 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
   }
   __syncthreads();
   for (int i = threadIdx.x; i < tp.n * kHistStride; i += kScanBlock)
-    if ((&s_h[0][0])[i]) atomicAdd(&hist[kTileRow0 * kHistStride + i], (&s_h[0][0])[i]);
+    if ((&s_h[0][0])[i])
+      atomicAdd(&hist[(blockIdx.x % kHistCopies) * kHistWords + kTileRow0 * kHistStride + i], (&s_h[0][0])[i]);
 }
 
 void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t n, int items, uint64_t* bdesc, int nb,

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kDepthPasses * 256; i += blockDim.x)
-    if (s_h[i]) atomicAdd(&hist[(i >> 8) * kHistStride + (i & 255)], s_h[i]);
+    if (s_h[i]) atomicAdd(&hist[(blockIdx.x % kHistCopies) * kHistWords + (i >> 8) * kHistStride + (i & 255)], s_h[i]);
 }
 
 // Clears the per-build counters, every histogram row, the first depth pass's descriptors and the
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
   for (int64_t i = t; i < desc0_words; i += stride) desc0[i] = 0u;
   for (int64_t i = t; i < ranges_words; i += stride) ranges[i] = 0u;  // empty tiles keep [0, 0)
   for (int64_t i = t; i < bdesc_n; i += stride) bdesc[i] = 0ull;
-  for (int64_t i = t; i < kMaxPasses * kHistStride; i += stride) hist[i] = 0u;
+  for (int64_t i = t; i < kHistCopies * kHistWords; i += stride) hist[i] = 0u;
   if (t == 0) {
     for (int p = 0; p < kMaxPasses; ++p) hdr->part_ctr[p] = 0u;
     hdr->emit_ctr = 0u;

@@ -74,7 +74,12 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   for (int i = threadIdx.x; i < kNW * kRadix; i += kSortBlock) (&s_wcnt[0][0])[i] = 0u;
   // global start of this thread's digit: exclusive scan of the pass's digit histogram
   const int d = threadIdx.x;
-  const uint32_t hcount = d < kRadix ? hist[sub ? ((uint32_t)d + sub) & 0xffu : (uint32_t)d] : 0u;
+  uint32_t hcount = 0u;
+  if (d < kRadix) {
+    const uint32_t bin = sub ? ((uint32_t)d + sub) & 0xffu : (uint32_t)d;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) hcount += hist[c * kHistWords + bin];
+  }
   uint32_t hinc = hcount;
 #pragma unroll
   for (int s = 1; s < kWave; s <<= 1) {

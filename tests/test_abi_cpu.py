@@ -152,11 +152,12 @@ def test_bench_traffic_hash_tracks_code_not_comments(tmp_path, monkeypatch):
         shutil.copy(os.path.join(src, f), fake / f)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     h0 = bench.source_hash("raster_bwd")
-    assert h0 == bench.TRAFFIC[("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1)]["src"]
+    key = ("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1)
+    monkeypatch.setitem(bench.TRAFFIC, key, {"fetch": 3, "write": 4, "src": h0})  # counters of this code
     with open(fake / "k_raster.hip", "a") as f:
         f.write("\n// a reworded note\n/* and a block\n   comment */\n")
     assert bench.source_hash("raster_bwd") == h0
-    assert bench.measured_traffic("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1) is not None
+    assert bench.measured_traffic("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1) == 7
     with open(fake / "k_raster.hip", "a") as f:
         f.write("static int added_code = 1;\n")
     assert bench.source_hash("raster_bwd") != h0
