@@ -81,9 +81,11 @@ struct WsHdr {                 // 256 B at the start of the workspace
   float loss;                      // colour loss of the last fused backward (fixed-order sum of the slots)
   float loss_sil;                  // its silhouette loss
   uint32_t red_ticket;             // last-block ticket of that sum (left at 0)
-  uint32_t key_hi_min, key_hi_max; // range of the high 16 depth-key bits over visible face-views
+  // range of the high 16 depth-key bits over visible face-views, in kKeyCopies copies (projection
+  // workgroup b folds its range into copy b mod kKeyCopies; readers combine the copies)
+  uint32_t key_hi_min[8], key_hi_max[8];
   uint32_t emit_ctr;               // block tickets of the one-pass scan + emission
-  uint32_t pad1[40];
+  uint32_t pad1[26];
 };
 static_assert(sizeof(WsHdr) == 256, "ws header");
 
@@ -94,8 +96,19 @@ constexpr float kBceEps = 1e-6f;
 // third depth pass sorts on (key >> 16) - key_hi_min (one 8-bit digit that orders them exactly)
 // and the fourth pass is skipped; the sorted elements then end in the second element buffer.
 // Culled face-views (key 0xffffffff, no instances) may land anywhere: they emit nothing.
+constexpr int kKeyCopies = 8;
+__device__ inline uint32_t key_hi_min(const WsHdr* h) {
+  uint32_t m = h->key_hi_min[0];
+#pragma unroll
+  for (int c = 1; c < kKeyCopies; ++c) m = min(m, h->key_hi_min[c]);
+  return m;
+}
 __device__ inline bool depth_keys_narrow(const WsHdr* h) {
-  return h->key_hi_max >= h->key_hi_min && h->key_hi_max - h->key_hi_min < 256u;
+  uint32_t mx = h->key_hi_max[0];
+#pragma unroll
+  for (int c = 1; c < kKeyCopies; ++c) mx = max(mx, h->key_hi_max[c]);
+  const uint32_t mn = key_hi_min(h);
+  return mx >= mn && mx - mn < 256u;
 }
 
 // Kernel-side options (plain values) ---------------------------------------------------------------

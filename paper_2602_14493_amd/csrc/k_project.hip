@@ -115,6 +115,7 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
                                                  uint32_t* __restrict__ hist, WsHdr* __restrict__ hdr,
                                                  float4* __restrict__ dfv_zero) {
   __shared__ uint32_t s_h[kDepthPasses * 256];
+  __shared__ uint32_t s_kmin[256 / kWave], s_kmax[256 / kWave];
   for (int i = threadIdx.x; i < kDepthPasses * 256; i += blockDim.x) s_h[i] = 0u;
   __syncthreads();
   const TableHdr* th = static_cast<const TableHdr*>(table);
@@ -127,11 +128,23 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ table,
     kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, kWave));
     kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d, kWave));
   }
-  if ((threadIdx.x & (kWave - 1)) == 0 && kmin <= kmax) {
-    atomicMin(&hdr->key_hi_min, kmin);
-    atomicMax(&hdr->key_hi_max, kmax);
+  // one atomic pair per workgroup, into copy b mod kKeyCopies: same-address atomics serialise, and
+  // one pair per wavefront on a single address had set the projection's time
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    s_kmin[threadIdx.x / kWave] = kmin;
+    s_kmax[threadIdx.x / kWave] = kmax;
   }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
+      kmin = min(kmin, s_kmin[w]);
+      kmax = max(kmax, s_kmax[w]);
+    }
+    if (kmin <= kmax) {
+      atomicMin(&hdr->key_hi_min[blockIdx.x % kKeyCopies], kmin);
+      atomicMax(&hdr->key_hi_max[blockIdx.x % kKeyCopies], kmax);
+    }
+  }
   for (int i = threadIdx.x; i < kDepthPasses * 256; i += blockDim.x)
     if (s_h[i]) atomicAdd(&hist[(blockIdx.x % kHistCopies) * kHistWords + (i >> 8) * kHistStride + (i & 255)], s_h[i]);
 }
@@ -161,8 +174,10 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
     hdr->stats_fwd_off = si.fwd_off;
     hdr->stats_bwd_off = si.bwd_off;
     hdr->red_ticket = 0u;
-    hdr->key_hi_min = 0xffffffffu;
-    hdr->key_hi_max = 0u;
+    for (int c = 0; c < kKeyCopies; ++c) {
+      hdr->key_hi_min[c] = 0xffffffffu;
+      hdr->key_hi_max[c] = 0u;
+    }
   }
 }
 

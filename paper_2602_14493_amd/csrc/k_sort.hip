@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
   uint32_t sub = 0u;
   if (range_hdr && depth_pass >= 2 && depth_keys_narrow(range_hdr)) {
     if (depth_pass == 3) return;
-    sub = range_hdr->key_hi_min;
+    sub = key_hi_min(range_hdr);
   }
   // clear this workgroup's slice of the next pass's descriptors (every workgroup, before any exit)
   {
