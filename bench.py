@@ -36,13 +36,13 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # counters were taken, and changed code reports null.
 TRAFFIC = {
     ("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1):
-        {"fetch": 77197872, "write": 27982993, "src": "7e8702e5034eae2e"},
+        {"fetch": 77195673, "write": 27981786, "src": "80be7ac0ca925fd5"},
     ("icosphere_s5_8x512", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 76693987, "write": 27986035, "src": "7e8702e5034eae2e"},
+        {"fetch": 76693617, "write": 27985865, "src": "80be7ac0ca925fd5"},
     ("icosphere_s5_8x512", "raster_bwd", "32x32", 1, 0, 1):
-        {"fetch": 76322847, "write": 27988105, "src": "7e8702e5034eae2e"},
+        {"fetch": 76322635, "write": 27989156, "src": "80be7ac0ca925fd5"},
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 16428218613, "write": 1787915133, "src": "7e8702e5034eae2e"},
+        {"fetch": 16435307360, "write": 1787913690, "src": "80be7ac0ca925fd5"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
