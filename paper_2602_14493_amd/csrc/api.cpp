@@ -907,7 +907,7 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
     }
     return GMR_ERR_CAPACITY;  // more instances than a workspace can hold: the candidate is skipped
   };
-  // round 1: every candidate once; round 2: the three fastest again, each scored by the better of
+  // first pass: every candidate once; second pass: the three fastest again, each scored by the better of
   // its two timings (a candidate slowed once by interference is not lost, and a lucky first
   // timing is checked)
   struct Timed { float ms; gmr_options o; };
@@ -934,7 +934,7 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
     for (size_t i = 0; i < timed.size() && i < 3 && result == GMR_OK; ++i) {
       gmr_options o = timed[i].o;
       float ms = 0.f;
-      if ((result = time_cand(o, ms)) != GMR_OK) break;  // it fitted in round 1, so it fits again
+      if ((result = time_cand(o, ms)) != GMR_OK) break;  // it fitted in the first pass, so it fits again
       const float score = std::min(ms, timed[i].ms);
       if (score < best_ms) {
         best_ms = score;
