@@ -344,7 +344,7 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
     const StatsInfo si{(uint32_t)p.items_total, (unsigned long long)L.statF, (unsigned long long)L.statB};
     launch_project(table, p.f_total, verts, faces, colors, ko, w.rec, w.elA, w.hist,
                    zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.hdr, w.descF0, fv_words, w.ranges,
-                   2 * p.tiles_total, w.bdesc, L.scan_blocks, (uint32_t)L.capacity, si, s);
+                   2 * p.tiles_total, w.bdesc, L.scan_blocks, (uint32_t)L.capacity, si, p.max_views, s);
   }
   // depth digits on the face-view elements: 4 passes, A -> B -> A -> B -> A
   for (int pass = 0; pass < kDepthPasses; ++pass) {

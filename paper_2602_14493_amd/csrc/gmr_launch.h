@@ -13,7 +13,8 @@ namespace gmr {
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
                     const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
                     WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, uint32_t* ranges, int64_t ranges_words,
-                    uint64_t* bdesc, int64_t bdesc_n, uint32_t cap, const StatsInfo& si, hipStream_t s);
+                    uint64_t* bdesc, int64_t bdesc_n, uint32_t cap, const StatsInfo& si, int max_views,
+                    hipStream_t s);
 
 // One-pass scan of tiles-touched and emission of the instances (nb blocks of kScanBlock * items
 // face-views); writes the instance count and overflow flag.

@@ -24,7 +24,8 @@ template <int SHD>
 __device__ inline void project_face(const TableHdr* th, const void* __restrict__ table, const float* __restrict__ verts,
                                     const int32_t* __restrict__ faces, const float* __restrict__ colors, const KOpts& o,
                                     float4* __restrict__ rec, uint4* __restrict__ el, uint32_t* s_h,
-                                    uint32_t& kmin, uint32_t& kmax, float4* __restrict__ dfv_zero, int64_t f) {
+                                    uint32_t& kmin, uint32_t& kmax, float4* __restrict__ dfv_zero, int64_t f,
+                                    int u, int lpf) {
   const int32_t* mfo = table_i32(table, th->mesh_face_off);
   const int32_t* mvo = table_i32(table, th->mesh_view_off);
   const int32_t* mvs = table_i32(table, th->mesh_views_off);
@@ -52,7 +53,7 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
   }
   const double kscale = sqrt(kHalfLog2e);
 
-  for (int k = mvo[m]; k < mvo[m + 1]; ++k) {
+  for (int k = mvo[m] + u; k < mvo[m + 1]; k += lpf) {
     const ViewDev& V = views[mvs[k]];
     const int64_t fv = V.fv_offset + (f - V.face_begin);
     uint4 e = make_uint4(0xffffffffu, (uint32_t)fv, 0u, 0u);
@@ -108,21 +109,27 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
   }
 }
 
-template <int SHD>
-__global__ __launch_bounds__(256) void k_project(const void* __restrict__ table, const float* __restrict__ verts,
+// LPF lanes per face (1, or 8 with 1024-thread workgroups): lane u of a face's group converts the
+// face and projects it into views u, u + LPF, ... of its mesh -- small batches then run LPF times as
+// many wavefronts, each with a shorter FP64 chain, while a workgroup still covers 256 face-views'
+// worth of histogram flushes per 256 threads.
+template <int SHD, int LPF>
+__global__ __launch_bounds__(256 * (LPF > 1 ? 4 : 1)) void k_project(const void* __restrict__ table, const float* __restrict__ verts,
                                                  const int32_t* __restrict__ faces, const float* __restrict__ colors,
                                                  KOpts o, float4* __restrict__ rec, uint4* __restrict__ el,
                                                  uint32_t* __restrict__ hist, WsHdr* __restrict__ hdr,
                                                  float4* __restrict__ dfv_zero) {
   __shared__ uint32_t s_h[kDepthPasses * 256];
-  __shared__ uint32_t s_kmin[256 / kWave], s_kmax[256 / kWave];
+  __shared__ uint32_t s_kmin[1024 / kWave], s_kmax[1024 / kWave];
   for (int i = threadIdx.x; i < kDepthPasses * 256; i += blockDim.x) s_h[i] = 0u;
   __syncthreads();
   const TableHdr* th = static_cast<const TableHdr*>(table);
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t f = t / LPF;
+  const int u = (int)(t - f * LPF);
   uint32_t kmin = 0xffffffffu, kmax = 0u;  // high 16 key bits of this thread's visible face-views
   if (f < th->faces_total)
-    project_face<SHD>(th, table, verts, faces, colors, o, rec, el, s_h, kmin, kmax, dfv_zero, f);
+    project_face<SHD>(th, table, verts, faces, colors, o, rec, el, s_h, kmin, kmax, dfv_zero, f, u, LPF);
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) {
     kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, kWave));
@@ -184,17 +191,25 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,
                     const float* colors, const KOpts& o, float4* rec, uint4* el, uint32_t* hist, float4* dfv_zero,
                     WsHdr* hdr, uint32_t* desc0, int64_t desc0_words, uint32_t* ranges, int64_t ranges_words,
-                    uint64_t* bdesc, int64_t bdesc_n, uint32_t cap, const StatsInfo& si, hipStream_t s) {
+                    uint64_t* bdesc, int64_t bdesc_n, uint32_t cap, const StatsInfo& si, int max_views,
+                    hipStream_t s) {
   int64_t pb = (std::max(std::max(desc0_words, ranges_words), bdesc_n) + 255) / 256;
   pb = pb < 1 ? 1 : (pb > 4096 ? 4096 : pb);
   hipLaunchKernelGGL(k_prologue, dim3((unsigned)pb), dim3(256), 0, s, hdr, hist, desc0, desc0_words, ranges,
                      ranges_words, bdesc, bdesc_n, cap, si);
   if (faces_total <= 0) return;
+  // 8 lanes per face when the faces alone would leave most of the GPU idle (fewer than 256 per CU)
+  if (o.sh_degree == 0 && max_views > 1 && faces_total < 256 * 256) {
+    const int64_t nb = (faces_total * 8 + 1023) / 1024;
+    hipLaunchKernelGGL((k_project<0, 8>), dim3((unsigned)nb), dim3(1024), 0, s, table, verts, faces, colors, o, rec, el,
+                       hist, hdr, dfv_zero);
+    return;
+  }
   const int bs = 256;
   const int64_t nb = (faces_total + bs - 1) / bs;
 #define GMR_PROJECT(D)                                                                                        \
-  hipLaunchKernelGGL(k_project<D>, dim3((unsigned)nb), dim3(bs), 0, s, table, verts, faces, colors, o, rec, el, hist, \
-                     hdr, dfv_zero)
+  hipLaunchKernelGGL((k_project<D, 1>), dim3((unsigned)nb), dim3(bs), 0, s, table, verts, faces, colors, o, rec, el, \
+                     hist, hdr, dfv_zero)
   switch (o.sh_degree) {
     case 1: GMR_PROJECT(1); break;
     case 2: GMR_PROJECT(2); break;
