@@ -215,8 +215,8 @@ def main():
     if not args.no_autotune and not any(k not in ("cov_mode", "sh_degree") for k in kw):
         # more timed iterations where a step is short (the ranking of close candidates is noisy);
         # the tuner times the backward in the form this workload runs (lists rebuilt or reused)
-        _, tuned_ms = r.autotune(verts, colors, target, iters=10 if W.num_pixels < (1 << 23) else 3,
-                                 recompute=recompute)
+        iters = 10 if W.num_pixels < (1 << 23) else (5 if W.num_pixels < (1 << 25) else 3)
+        _, tuned_ms = r.autotune(verts, colors, target, iters=iters, recompute=recompute)
     use_graph = args.config == 5
     P = W.num_pixels
 
