@@ -525,7 +525,8 @@ void launch_vertex_gather(const int32_t* off, const int32_t* ent, const float* f
   LossRed q{};
   if (red) {
     q = *red;
-    q.nb = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(kLossReduceBlocks, (red->items + 2047) / 2048), blocks));
+    // every gather block up to kLossReduceBlocks takes a share (shorter chunks, shorter tail)
+    q.nb = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kLossReduceBlocks, red->items), blocks));
   }
   const dim3 grid((unsigned)blocks);
   switch (sh_degree) {
