@@ -1,6 +1,7 @@
 """FP64 oracle of the reconstruction step around the renderer (Sec. 3.1, Implementation Details
 and Loss Functions): silhouette binary cross-entropy on the rendered alpha, edge-length and
-Laplacian-smoothing regularisers on the mesh, and the VectorAdam update of the vertices.
+Laplacian-smoothing regularisers on the mesh, the VectorAdam update of the vertices, and the plain
+Adam step of the torus optimisation workload.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  The paper names these terms without
 formulas or weights; the readings taken here are:
@@ -17,6 +18,9 @@ formulas or weights; the readings taken here are:
   gradient (so the update of a vertex is equivariant under rotations of the gradients):
   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) |g|^2,
   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+* Adam (the optimiser of the 2M-face torus workload: vertices only, lr 1e-3, betas (0.9, 0.999),
+  eps 1e-8): the same update with the second moment kept per coordinate, v = b2 v + (1 - b2) g^2,
+  in the bias-corrected form of Kingma & Ba's Adam (ICLR 2015, Algorithm 1).
 Each function returns the loss and its gradient in float64.
 """
 from __future__ import annotations
@@ -106,3 +110,19 @@ def vector_adam_step(p, g, m, v, t: int, lr: float, b1: float = 0.9, b2: float =
     mh = m / (1.0 - b1 ** t)
     vh = v / (1.0 - b2 ** t)
     return p - lr * mh / (np.sqrt(vh)[:, None] + eps), m, v
+
+
+def adam_step(p, g, m, v, t: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """One Adam step at step number t >= 1 (the first step has t = 1), elementwise over arrays of
+    any shape: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2, then the bias-corrected moments
+    m / (1 - b1^t) and v / (1 - b2^t) give p - lr m_hat / (sqrt(v_hat) + eps).  Returns the new
+    (p, m, v)."""
+    if t < 1:
+        raise ValueError("Adam's step number starts at 1")
+    p = np.asarray(p, np.float64)
+    g = np.asarray(g, np.float64)
+    m = b1 * np.asarray(m, np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, np.float64) + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

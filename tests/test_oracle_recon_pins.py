@@ -142,3 +142,77 @@ def test_vector_adam_rotation_equivariance():
         pa, ma, va = recon.vector_adam_step(pa, g, ma, va, t, lr=0.1)
         pb, mb, vb = recon.vector_adam_step(pb, g @ q.T, mb, vb, t, lr=0.1)
     assert np.allclose(pb, pa @ q.T, atol=1e-12)                     # rotated gradients, rotated path
+
+
+# ---- Adam (the torus workload's optimiser) ------------------------------------------------------
+
+def test_adam_first_step_closed_form():
+    """Bias correction makes the first step's moments g and g^2: p moves by lr g / (|g| + eps)."""
+    rng = np.random.default_rng(7)
+    p = rng.normal(size=(12, 3)); g = rng.normal(size=(12, 3))
+    p1, m1, v1 = recon.adam_step(p, g, np.zeros_like(p), np.zeros_like(p), 1, lr=0.01)
+    assert np.allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8), atol=1e-15)
+    assert np.allclose(m1, 0.1 * g, atol=1e-16) and np.allclose(v1, 0.001 * g * g, atol=1e-16)
+
+
+def test_adam_two_steps_hand_computed():
+    """g = 1 then g = -2 from p = 0 with lr 0.1, betas (0.9, 0.999), eps 0.  By hand: m1 = 0.1,
+    v1 = 0.001, step 1 moves by -lr (m1 / 0.1) / sqrt(v1 / 0.001) = -0.1; m2 = 0.09 - 0.2 = -0.11,
+    v2 = 0.000999 + 0.004 = 0.004999, m2 / (1 - 0.81) = -11/19, v2 / (1 - 0.998001) = 4999/1999, so
+    p2 = -0.1 + (11/190) sqrt(1999/4999) = -0.0633896472964154434717... (40-digit decimal)."""
+    p, m, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    p, m, v = recon.adam_step(p, [1.0], m, v, 1, lr=0.1, eps=0.0)
+    assert p[0] == pytest.approx(-0.1, abs=1e-15)
+    p, m, v = recon.adam_step(p, [-2.0], m, v, 2, lr=0.1, eps=0.0)
+    assert m[0] == pytest.approx(-0.11, abs=1e-15) and v[0] == pytest.approx(0.004999, abs=1e-17)
+    assert p[0] == pytest.approx(-0.06338964729641544347, abs=1e-15)
+
+
+def test_adam_zero_gradient_and_constant_gradient():
+    """A coordinate that never receives a gradient never moves (eps > 0 keeps 0 / 0 away); a
+    constant gradient moves its coordinate by exactly lr sign(g) on every step when eps = 0, since
+    both bias-corrected moments are then exact (m_hat = g, v_hat = g^2 for every t)."""
+    g = np.array([0.0, 3.0, -0.25, 1e-3])
+    p0 = np.array([0.5, -1.0, 2.0, 0.0])
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    q = p0[1:].copy(); mq, vq = np.zeros(3), np.zeros(3)
+    for t in range(1, 8):
+        p, m, v = recon.adam_step(p, g, m, v, t, lr=0.05)
+        assert p[0] == p0[0] and m[0] == 0.0 and v[0] == 0.0
+        q, mq, vq = recon.adam_step(q, g[1:], mq, vq, t, lr=0.05, eps=0.0)
+        assert np.allclose(q, p0[1:] - 0.05 * t * np.sign(g[1:]), atol=1e-13)
+
+
+def test_adam_scale_and_sign_invariance():
+    """With eps = 0 the update is invariant to a positive scale of every gradient and odd under a
+    sign flip of every gradient; with eps > 0 a scale of 1e6 changes it by a negligible amount."""
+    rng = np.random.default_rng(8)
+    gs = [rng.normal(size=20) for _ in range(6)]
+    runs = {}
+    for key, c, eps in (("one", 1.0, 0.0), ("big", 1e6, 0.0), ("neg", -1.0, 0.0), ("eps", 1e6, 1e-8)):
+        p, m, v = np.zeros(20), np.zeros(20), np.zeros(20)
+        for t, g in enumerate(gs, start=1):
+            p, m, v = recon.adam_step(p, c * g, m, v, t, lr=0.02, eps=eps)
+        runs[key] = p
+    assert np.allclose(runs["big"], runs["one"], rtol=1e-12, atol=1e-15)
+    assert np.allclose(runs["neg"], -runs["one"], rtol=1e-12, atol=1e-15)
+    assert np.allclose(runs["eps"], runs["one"], rtol=1e-9, atol=1e-12)
+
+
+def test_adam_equals_vector_adam_on_one_axis():
+    """VectorAdam's second moment is |g|^2 per vertex; with gradients on the x axis only, that is
+    g_x^2 and the two optimisers take the same steps (a cross-check of two independent forms)."""
+    rng = np.random.default_rng(9)
+    gs = [np.stack([rng.normal(size=6), np.zeros(6), np.zeros(6)], axis=1) for _ in range(4)]
+    pa, ma, va = np.zeros((6, 3)), np.zeros((6, 3)), np.zeros((6, 3))
+    pb, mb, vb = np.zeros((6, 3)), np.zeros((6, 3)), np.zeros(6)
+    for t, g in enumerate(gs, start=1):
+        pa, ma, va = recon.adam_step(pa, g, ma, va, t, lr=0.03)
+        pb, mb, vb = recon.vector_adam_step(pb, g, mb, vb, t, lr=0.03)
+    assert np.allclose(pa, pb, atol=1e-15)
+    assert np.allclose(va[:, 0], vb, atol=1e-18)
+
+
+def test_adam_rejects_step_zero():
+    with pytest.raises(ValueError):
+        recon.adam_step(np.zeros(2), np.ones(2), np.zeros(2), np.zeros(2), 0, lr=0.1)
