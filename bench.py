@@ -8,6 +8,9 @@ workload also runs the captured Adam step with the lists rebuilt in the backward
 synthetic and resident in HBM before timing.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--config {1..5}] [--gpus 1]
+
+The default workload is the largest single-GPU one: the 2M-face torus, 32 views at 1920x1080, the
+100-step Adam vertex optimisation captured as a HIP graph with the lists rebuilt in the backward.
 """
 from __future__ import annotations
 
@@ -21,7 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
-FP32_VECTOR_TFLOPS = 157.3     # MI355X vector FP32, published (packed FP32; the build disables packed ops)
+FP32_VECTOR_TFLOPS_PUBLISHED = 157.3   # MI355X vector FP32, published: packed FP32 (two FMAs per lane)
+# What the build can reach: it disables packed FP32, so a lane issues one FMA per clock:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s
+FP32_VECTOR_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Arithmetic per (pixel, Gaussian) pair, counting an FMA as 2: forward = offsets 4, w1/w2 4,
 # squared radius 3, exp2 2, clamp/cutoff 2, transmittance 3, weight 1, colour 6 -> 25;
 # backward = the forward's 19 up to the cutoff + rcp, T_k, c.g (5), dL/dalpha (4), weight, S (2),
@@ -111,7 +117,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--adam-steps", type=int, default=100,
+                    help="length of the timed optimisation runs of the Adam workload (each from the start)")
+    ap.add_argument("--adam-runs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile / block shape")
     ap.add_argument("--tile", type=str, default=None, help="WxH binning tile, e.g. 16x16")
     ap.add_argument("--raster-mode", type=int, default=None)
@@ -121,7 +130,7 @@ def parse():
                     help="view-dependent colour: coefficient 0 = the workload's colours, the rest N(0, 0.1)")
     ap.add_argument("--cov-mode", type=int, default=0, choices=[0, 1, 2],
                     help="conversion: 0 Eq. 13, 1 Eq. 15, 2 the 3DGS-based edge-frame baseline")
-    ap.add_argument("--no-graph", action="store_true", help="run the Adam loop eagerly (no HIP graph replay)")
+    ap.add_argument("--no-graph", action="store_true", help="launch the step eagerly (no HIP graph replay)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     ap.add_argument("--no-per-view", action="store_true")
@@ -129,6 +138,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
+
+
+def progress(msg):
+    """One line on stderr per finished phase (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def stage_profile(r):
@@ -181,6 +195,7 @@ def main():
 
     torch.cuda.set_device(0)
     W = wl.make_workload(args.config)
+    progress(f"workload {W.name}: {W.num_views} views, {W.num_pixels} px")
     batch = gmr.Batch.from_workload(W)
     kw = {}
     if args.cov_mode:
@@ -217,18 +232,39 @@ def main():
         # the tuner times the backward in the form this workload runs (lists rebuilt or reused)
         iters = 10 if W.num_pixels < (1 << 23) else (5 if W.num_pixels < (1 << 25) else 3)
         _, tuned_ms = r.autotune(verts, colors, target, iters=iters, recompute=recompute)
+        progress(f"autotuned: tile {r.opts.tile_w}x{r.opts.tile_h}, {tuned_ms:.3f} ms/step")
     use_graph = args.config == 5
     P = W.num_pixels
 
     # ---- batched form ------------------------------------------------------------------------
+    adam_runs = None
     if use_graph:
-        # lr 1e-4: Adam moves a coordinate by about lr per step, so the 100 steps of the workload
-        # move a vertex by about the noise amplitude (0.01) it is meant to remove
-        loop = gmr.GraphAdamLoop(r, verts, colors, target, lr=1e-4, recompute=True)
-        if args.no_graph:
-            loop._step_body()
+        # the workload's optimiser: Adam on the vertices, lr 1e-3, betas (0.9, 0.999), eps 1e-8.
+        # The whole optimisation run goes once, untimed, to size the instance capacity: the peak
+        # counter covers every list build of the run; on overflow the capacity grows to the peak
+        # plus headroom and the step is captured again
+        for attempt in range(4):
+            loop = gmr.GraphAdamLoop(r, verts, colors, target, lr=1e-3, recompute=True)
+            if not args.no_graph:
+                loop.capture()
+            start = [t.clone() for t in loop._state()]
+            loop.overflow()          # restarts the peak counter
+            for _ in range(args.adam_steps):
+                loop._step_body() if args.no_graph else loop.graph.replay()
+            c = r.counters(loop.ws)
+            adam_peak = c.peak_instances
+            progress(f"sizing run of {args.adam_steps} optimisation steps: peak {c.peak_instances} instances, "
+                     f"capacity {c.capacity}")
+            if not (c.overflow or c.overflow_any):
+                break
+            r.opts.instance_capacity = min((1 << 30) - 1, int(c.peak_instances * r.headroom) + 1024)
+            del loop
         else:
-            loop.capture()
+            raise RuntimeError("instance capacity did not converge over the optimisation run")
+
+        def reset():
+            for t, t0 in zip(loop._state(), start):
+                t.copy_(t0)
 
         def step():
             if args.no_graph:
@@ -238,19 +274,21 @@ def main():
 
         def step_profiled():
             loop._step_body()
+
+        reset()
     else:
-        rgb, alpha, saved, ws = r.forward(verts, colors, check=True)
-        ws_b = r.new_workspace() if recompute else ws
-        dV = torch.empty_like(verts)
-        dC = torch.empty_like(colors)
-
-        def step():
-            r.fwd_raw(verts, colors, rgb, alpha, saved, ws)
-            r.bwd_l2_raw(verts, colors, rgb, target, 1.0, saved, ws_b, 1 if recompute else 0, dV, dC)
-
-        step_profiled = step
+        # forward + fused L2 backward (with recompute the backward rebuilds the lists into the
+        # forward's workspace), captured as one HIP graph (--no-graph: launched eagerly)
+        gstep = gmr.GraphStep(r, verts, colors, target, recompute=recompute)
+        if not args.no_graph:
+            gstep.capture()
+        ws = gstep.ws
+        step = gstep._step_body if args.no_graph else gstep.graph.replay
+        step_profiled = gstep._step_body
     for _ in range(args.warmup):
         step()
+    if use_graph:
+        reset()       # the timed steps are the first steps of the optimisation run
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -272,13 +310,47 @@ def main():
     per_step = np.array([a_.elapsed_time(b_) for a_, b_ in ev])
     spread = {"p10": round(float(np.percentile(per_step, 10)), 4), "p50": round(float(np.median(per_step)), 4),
               "p90": round(float(np.percentile(per_step, 90)), 4)}
-    ws_ref = loop.ws_fwd if use_graph else ws
+    # the same step launched eagerly (what the graph saves in per-launch cost)
+    ms_eager = None
+    if not use_graph and not args.no_graph:
+        for _ in range(2):
+            step_profiled()
+        e0.record()
+        for _ in range(args.steps):
+            step_profiled()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_eager = round(e0.elapsed_time(e1) / args.steps, 4)
+    ws_ref = loop.ws if use_graph else ws
     cnt = r.counters(ws_ref)
-    cnt_b = r.counters(loop.ws_bwd if use_graph else ws_b)
-    if cnt.overflow or cnt_b.overflow:
+    if cnt.overflow or cnt.overflow_any:
         raise RuntimeError("instance capacity overflowed during the timed steps")
     I = cnt.instances
-    pairs = {"raster_fwd": cnt.pairs_fwd, "raster_bwd": cnt_b.pairs_bwd}
+    pairs = {"raster_fwd": cnt.pairs_fwd, "raster_bwd": cnt.pairs_bwd}
+    progress(f"timed {args.steps} steps: {ms_step:.4f} ms/step")
+    if use_graph:
+        # the workload's own protocol: the whole optimisation run from its start, replayed several
+        # times; ms/step = replay time / steps
+        runs = []
+        for _ in range(args.adam_runs):
+            reset()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.adam_steps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            runs.append(e0.elapsed_time(e1) / args.adam_steps)
+        c = r.counters(loop.ws)
+        if c.overflow or c.overflow_any:
+            raise RuntimeError("instance capacity overflowed during the optimisation runs")
+        progress(f"optimisation runs: {[round(x, 4) for x in runs]} ms/step")
+        adam_runs = {"steps": args.adam_steps, "runs": args.adam_runs,
+                     "ms_per_step": [round(x, 4) for x in runs], "ms_per_step_median": round(float(np.median(runs)), 4),
+                     "Mpixel_per_s_median": round(P / (float(np.median(runs)) * 1e-3) / 1e6, 2),
+                     "loss_final": float(loop.loss.item()), "peak_instances": int(max(adam_peak, c.peak_instances)),
+                     "capacity": int(c.capacity), "lr": 1e-3, "graph": not args.no_graph}
+        reset()
 
     # ---- per-stage timing (HIP events on the library's stream), same steps ----------------------
     from paper_2602_14493_amd import _lib
@@ -287,6 +359,7 @@ def main():
         step_profiled()
     torch.cuda.synchronize()
     prof = stage_profile(r)
+    progress("per-stage profile done")
     _lib.call("gmr_profile_enable", r.handle.ptr, 0)
     F, V = batch.num_faces, batch.num_verts
     FV = int(sum(int(W.face_offsets[m + 1] - W.face_offsets[m]) for m in W.view_mesh))
@@ -316,9 +389,13 @@ def main():
                                r.opts.raster_mode, r.opts.lane_lists)
     if dom in FLOPS_PER_PAIR:   # compositing kernels: VALU-bound on LDS-broadcast data
         achieved = d["alg_TFLOPs"]
-        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_VECTOR_TFLOPS,
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": round(FP32_VECTOR_TFLOPS, 2),
                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_TFLOPS, 6), "traffic": traffic,
-                    "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": pairs[dom]}
+                    "peak_note": "unpacked FP32 (packed FP32 is disabled in this build)",
+                    "peak_published": FP32_VECTOR_TFLOPS_PUBLISHED,
+                    "frac_published": round(achieved / FP32_VECTOR_TFLOPS_PUBLISHED, 6),
+                    "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": pairs[dom],
+                    "hbm_alg_GBps": d["alg_GBps"], "hbm_frac": round(d["alg_GBps"] / HBM_PEAK_GBS, 4)}
     else:
         achieved = d["alg_GBps"]
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -338,13 +415,12 @@ def main():
             po = int(W.pixel_offsets()[v])
             tg = target[po:po + npx].contiguous()
             o_rgb, o_a, o_s, o_ws = rv.forward(vv, cc, check=True)
-            o_wsb = rv.new_workspace() if recompute else o_ws
-            rs.append((rv, vv, cc, tg, o_rgb, o_a, o_s, o_ws, o_wsb, torch.empty_like(vv), torch.empty_like(cc)))
+            rs.append((rv, vv, cc, tg, o_rgb, o_a, o_s, o_ws, torch.empty_like(vv), torch.empty_like(cc)))
 
         def step_pv():
-            for (rv, vv, cc, tg, o_rgb, o_a, o_s, o_ws, o_wsb, dv, dc) in rs:
+            for (rv, vv, cc, tg, o_rgb, o_a, o_s, o_ws, dv, dc) in rs:
                 rv.fwd_raw(vv, cc, o_rgb, o_a, o_s, o_ws)
-                rv.bwd_l2_raw(vv, cc, o_rgb, tg, 1.0, o_s, o_wsb, 1 if recompute else 0, dv, dc)
+                rv.bwd_l2_raw(vv, cc, o_rgb, tg, 1.0, o_s, o_ws, 1 if recompute else 0, dv, dc)
         for _ in range(args.warmup):
             step_pv()
         torch.cuda.synchronize()
@@ -354,6 +430,7 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_pv = e0.elapsed_time(e1) / args.steps
+        progress(f"per-view launches: {ms_pv:.4f} ms/step")
         per_view = {"ms_per_step": round(ms_pv, 4), "Mpixel_per_s": round(P / (ms_pv * 1e-3) / 1e6, 2),
                     "batched_speedup": round(ms_pv / ms_step, 3)}
 
@@ -364,7 +441,7 @@ def main():
         with torch.no_grad():
             _, t_alpha, _, _ = r.forward(tverts, colors)
         sil = (t_alpha > 0.5).float()
-        rl = gmr.ReconLoop(r, verts, colors, target, sil, lr=1e-4, recompute=recompute)
+        rl = gmr.ReconLoop(r, verts, colors, target, sil, lr=1e-3, recompute=recompute)
         rl.capture()
         for _ in range(args.warmup):
             rl.graph.replay()
@@ -386,6 +463,7 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_tail = e0.elapsed_time(e1) / args.steps
+        progress(f"reconstruction step: {ms_rc:.4f} ms/step")
         recon_step = {"ms_per_step": round(ms_rc, 4), "Mpixel_per_s": round(P / (ms_rc * 1e-3) / 1e6, 2),
                       "overhead_vs_hot_path": round(ms_rc / ms_step, 3),
                       "regularizers_vector_adam_ms": round(ms_tail, 4),
@@ -414,6 +492,7 @@ def main():
             oracle.adjoint_workload(Wsub, g, None, prm, colors=c_sub)
             t_cpu += time.perf_counter() - t1
             reps += 1
+            progress(f"oracle rep {reps}: {t_cpu:.1f} s")
         cpu = {"value": round(sample_px * reps / t_cpu / 1e6, 4), "unit": "Mpixel/s", "cores": oracle.num_threads(),
                "kind": "oracle",
                "sample": f"{'all' if args.config in (1, 2) else 'view 0 of'} {W.num_views} views, "
@@ -428,6 +507,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
         "ms_per_step_spread": spread,
+        "ms_per_step_eager_launches": ms_eager,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -437,11 +517,12 @@ def main():
                    "instances": I, "tile": f"{r.opts.tile_w}x{r.opts.tile_h}", "px_per_lane": r.opts.px_per_lane,
                    "lane_lists": r.opts.lane_lists, "cov_mode": r.opts.cov_mode, "sh_degree": r.opts.sh_degree,
                    "raster_mode": r.opts.raster_mode, "autotune_ms": tuned_ms,
-                   "recompute_lists": recompute, "adam_graph": use_graph},
+                   "recompute_lists": recompute, "adam_graph": use_graph, "hip_graph": not args.no_graph},
         "roofline": roofline,
         "hbm_model": hbm_model,
         "cpu_baseline": cpu,
         "per_view": per_view,
+        "adam_optimisation": adam_runs,
         "recon_step": recon_step,
         "stages": stages,
         "wall_s": round(wall, 3),

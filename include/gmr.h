@@ -100,11 +100,13 @@ typedef struct gmr_counters {
   int64_t instances;   /* (Gaussian, tile) instances the last pass generated                  */
   int64_t capacity;    /* capacity of the workspace                                           */
   int32_t overflow;    /* 1 if instances > capacity (outputs of that pass are incomplete)    */
-  int32_t reserved;
+  int32_t overflow_any;/* 1 if any list build since the previous read overflowed             */
   int64_t pairs_fwd;   /* (pixel, Gaussian) pairs the last forward evaluated inside extents   */
   int64_t pairs_bwd;   /* pairs the last backward differentiated (composited ones)           */
   float loss;          /* colour loss of the last fused backward (L2 or reconstruction)       */
   float loss_sil;      /* silhouette loss of the last gmr_render_bwd_recon (0 otherwise)      */
+  int64_t peak_instances; /* largest instance count of any list build since the previous read
+                             (e.g. over the replays of a captured optimisation loop)          */
 } gmr_counters;
 
 typedef struct gmr_ctx* gmr_handle;
@@ -140,7 +142,9 @@ gmr_status gmr_view_table_fill(const gmr_batch* batch, const gmr_options* opt, v
 /* Workspace bytes for one forward+backward of this batch at opt->instance_capacity.  The
  * workspace holds the per face-view projected records, the instance keys/values (double
  * buffered), the sort state, the tile ranges and the backward's gradient accumulators.
- * `saved_bytes` is the per-pixel state render_fwd leaves for render_bwd (8 bytes per pixel). */
+ * `saved_bytes` is the per-pixel state render_fwd leaves for render_bwd (8 bytes per pixel).
+ * The workspace needs no initialisation, except that zeroing its first 256 bytes once after
+ * allocation arms the peak instance counter gmr_read_counters reports. */
 gmr_status gmr_workspace_size(const gmr_batch* batch, const gmr_options* opt, size_t* ws_bytes, size_t* saved_bytes);
 
 /* CSR of (vertex -> face*3 + corner), entries ascending per vertex: the deterministic gather the
@@ -226,7 +230,10 @@ gmr_status gmr_render_bwd_recon(gmr_handle h, const gmr_batch* batch, const gmr_
 gmr_status gmr_workspace_view(const gmr_batch* batch, const gmr_options* opt, size_t* ranges_off, size_t* vals_off,
                               size_t* rec_off, size_t* keys_off);
 
-/* Reads the workspace's device counters (synchronises `stream`).  Not capturable. */
+/* Reads the workspace's device counters (synchronises `stream`).  Not capturable.
+ * peak_instances / overflow_any cover every list build since the previous read (the read restarts
+ * them); they are meaningful from the first read on only if the caller zeroed the workspace's
+ * first 256 bytes after allocating it (the other counters need no initialisation). */
 gmr_status gmr_read_counters(const void* ws_dev, size_t ws_bytes, gmr_counters* out_host, void* stream);
 
 /* ---------------------------------------------------------------------------------------------

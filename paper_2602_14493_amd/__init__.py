@@ -13,9 +13,9 @@ from ._lib import GMRError, gmr_options
 
 _lib.load()
 
-from .render import (Batch, GraphAdamLoop, Handle, MeshGraph, ReconLoop, ReconWeights, Renderer,  # noqa: E402
+from .render import (Batch, GraphAdamLoop, GraphStep, Handle, MeshGraph, ReconLoop, ReconWeights, Renderer,  # noqa: E402
                      adam_step, copy_options, default_options, options_dict, render, vector_adam_step)
 
-__all__ = ["Batch", "GraphAdamLoop", "Handle", "MeshGraph", "ReconLoop", "ReconWeights", "Renderer", "adam_step",
+__all__ = ["Batch", "GraphAdamLoop", "GraphStep", "Handle", "MeshGraph", "ReconLoop", "ReconWeights", "Renderer", "adam_step",
            "copy_options", "default_options", "options_dict", "render", "vector_adam_step", "GMRError",
            "gmr_options"]

@@ -33,8 +33,9 @@ class gmr_batch(ctypes.Structure):
 
 
 class gmr_counters(ctypes.Structure):
-    _fields_ = [("instances", c_int64), ("capacity", c_int64), ("overflow", c_int32), ("reserved", c_int32),
-                ("pairs_fwd", c_int64), ("pairs_bwd", c_int64), ("loss", c_float), ("loss_sil", c_float)]
+    _fields_ = [("instances", c_int64), ("capacity", c_int64), ("overflow", c_int32), ("overflow_any", c_int32),
+                ("pairs_fwd", c_int64), ("pairs_bwd", c_int64), ("loss", c_float), ("loss_sil", c_float),
+                ("peak_instances", c_int64)]
 
 
 # name -> (restype, argtypes)

@@ -767,7 +767,14 @@ gmr_status gmr_read_counters(const void* ws, size_t ws_bytes, gmr_counters* out,
   out->instances = hdr.count;
   out->capacity = hdr.capacity;
   out->overflow = (int32_t)hdr.overflow;
-  out->reserved = 0;
+  out->peak_instances = hdr.peak_count;
+  out->overflow_any = hdr.peak_count > hdr.capacity ? 1 : 0;
+  {  // restart the peak: the next read covers the builds after this one
+    const uint32_t zero = 0u;
+    GMR_CHECK_HIP(hipMemcpyAsync(static_cast<char*>(const_cast<void*>(ws)) + offsetof(WsHdr, peak_count), &zero,
+                                 sizeof zero, hipMemcpyHostToDevice, s));
+    GMR_CHECK_HIP(hipStreamSynchronize(s));
+  }
   // pair counts: sums of the raster kernels' per-item slots
   out->pairs_fwd = 0;
   out->pairs_bwd = 0;

@@ -85,7 +85,9 @@ struct WsHdr {                 // 256 B at the start of the workspace
   // workgroup b folds its range into copy b mod kKeyCopies; readers combine the copies)
   uint32_t key_hi_min[8], key_hi_max[8];
   uint32_t emit_ctr;               // block tickets of the one-pass scan + emission
-  uint32_t pad1[26];
+  uint32_t peak_count;             // largest instance count of any list build since it was last reset
+                                   // (by gmr_read_counters; zeroed with the header by the caller)
+  uint32_t pad1[25];
 };
 static_assert(sizeof(WsHdr) == 256, "ws header");
 

@@ -135,6 +135,7 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
         const uint64_t total = excl + tot;
         hdr->count = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
         hdr->overflow = total > cap32 ? 1u : 0u;
+        hdr->peak_count = max(hdr->peak_count, hdr->count);
       }
     }
   }

@@ -129,6 +129,8 @@ class Counters:
     pairs_bwd: int = 0
     loss: float = 0.0
     loss_sil: float = 0.0
+    peak_instances: int = 0      # largest count of any list build since the previous read
+    overflow_any: bool = False   # any of those builds overflowed
 
 
 class Renderer:
@@ -188,7 +190,9 @@ class Renderer:
 
     def new_workspace(self) -> torch.Tensor:
         ws, _ = self.sizes()
-        return torch.empty(ws, dtype=torch.uint8, device=self.device)
+        w = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        w[:256].zero_()   # arms the peak instance counter (the rest needs no initialisation)
+        return w
 
     def new_saved(self) -> torch.Tensor:
         _, saved = self.sizes()
@@ -198,7 +202,7 @@ class Renderer:
         c = gmr_counters()
         call("gmr_read_counters", _ptr(ws), ws.numel(), ctypes.byref(c), _stream(self.device))
         return Counters(int(c.instances), int(c.capacity), bool(c.overflow), int(c.pairs_fwd), int(c.pairs_bwd),
-                        float(c.loss), float(c.loss_sil))
+                        float(c.loss), float(c.loss_sil), int(c.peak_instances), bool(c.overflow_any))
 
     def check_colors(self, colors, verts=None):
         """Colours hold (sh_degree + 1)^2 x 3 floats per vertex ([V,3] at degree 0); vertices [V,3];
@@ -459,34 +463,45 @@ class ReconLoop:
         self.v = torch.zeros((self.verts.shape[0],), dtype=torch.float32, device=dev)
         self.step_count = torch.zeros((1,), dtype=torch.int32, device=dev)
         self.lr, self.betas, self.eps, self.recompute = lr, betas, eps, recompute
+        # eager warm-up sizes the instance capacity (with headroom) before capture; with
+        # recompute the backward rebuilds the lists into the same workspace (one list buffer)
         rgb, alpha, saved, ws = renderer.forward(self.verts, self.colors, check=True)
-        self.ws_fwd = ws
-        self.ws_bwd = renderer.new_workspace() if recompute else ws
+        self.ws = ws
         self.rgb, self.alpha, self.saved = rgb, alpha, saved
         self.dV = torch.empty_like(self.verts)
         self.dC = torch.empty_like(self.colors)
         self.losses = torch.zeros((4,), dtype=torch.float32, device=dev)
         self.graph = None
 
+    def _state(self):
+        return (self.verts, self.m, self.v, self.step_count)
+
     def _step_body(self):
         r, w = self.r, self.w
-        r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws_fwd)
+        r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws)
         r.bwd_recon_raw(self.verts, self.colors, self.rgb, self.target, w.color, self.mask, w.silhouette, self.saved,
-                        self.ws_bwd, 1 if self.recompute else 0, self.dV, self.dC, self.losses[0:2])
+                        self.ws, 1 if self.recompute else 0, self.dV, self.dC, self.losses[0:2])
         self.graph_mesh.regularizers_raw(self.verts, self.dV, self.losses[2:4], w.edge_length, w.edge, w.laplacian)
         vector_adam_step(self.verts, self.dV, self.m, self.v, self.step_count, self.lr, self.betas[0],
                          self.betas[1], self.eps)
 
     def capture(self):
+        """Captures one step as a HIP graph.  An eager step runs first (on a side stream, as graph
+        capture requires); the optimiser state it advanced is restored afterwards, so the first
+        replay is the first step."""
+        state = [t.clone() for t in self._state()]
         s = torch.cuda.Stream(self.r.device)
         s.wait_stream(torch.cuda.current_stream(self.r.device))
         with torch.cuda.stream(s):
-            self._step_body()  # one eager step on the side stream before capture
+            self._step_body()
         torch.cuda.current_stream(self.r.device).wait_stream(s)
         torch.cuda.synchronize(self.r.device)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self._step_body()
+        for t, saved in zip(self._state(), state):
+            t.copy_(saved)
+        torch.cuda.synchronize(self.r.device)
         return self
 
     def run(self, steps: int):
@@ -500,7 +515,59 @@ class ReconLoop:
             self._step_body()
 
     def overflow(self) -> bool:
-        return self.r.counters(self.ws_fwd).overflow or self.r.counters(self.ws_bwd).overflow
+        """True if any list build since the previous check overflowed the instance capacity
+        (synchronises; reading restarts the peak counter)."""
+        c = self.r.counters(self.ws)
+        return c.overflow or c.overflow_any
+
+
+class GraphStep:
+    """One forward + fused L2 backward (the lists reused, or rebuilt with recompute=True) captured
+    once as a HIP graph and replayed: every launch of the step goes to the GPU in one submission,
+    which on small batches removes the host's per-launch cost.  Outputs (rgb, alpha, dV, dC, loss)
+    are this object's buffers, overwritten by each replay."""
+
+    def __init__(self, renderer: Renderer, verts: torch.Tensor, colors: torch.Tensor, target: torch.Tensor,
+                 recompute: bool = False):
+        self.r = renderer
+        self.verts = verts.detach().contiguous()
+        self.colors = colors.detach().contiguous()
+        self.target = target.detach().contiguous()
+        self.recompute = bool(recompute)
+        # eager warm-up sizes the instance capacity (with headroom) before capture
+        self.rgb, self.alpha, self.saved, self.ws = renderer.forward(self.verts, self.colors, check=True)
+        self.dV = torch.empty_like(self.verts)
+        self.dC = torch.empty_like(self.colors)
+        self.loss = torch.zeros((1,), dtype=torch.float32, device=renderer.device)
+        self.graph = None
+
+    def _step_body(self):
+        r = self.r
+        r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws)
+        r.bwd_l2_raw(self.verts, self.colors, self.rgb, self.target, 1.0, self.saved, self.ws,
+                     1 if self.recompute else 0, self.dV, self.dC, self.loss)
+
+    def capture(self):
+        s = torch.cuda.Stream(self.r.device)
+        s.wait_stream(torch.cuda.current_stream(self.r.device))
+        with torch.cuda.stream(s):
+            self._step_body()  # one eager step on a side stream before capture
+        torch.cuda.current_stream(self.r.device).wait_stream(s)
+        torch.cuda.synchronize(self.r.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step_body()
+        return self
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+
+    def overflow(self) -> bool:
+        """True if any list build since the previous check overflowed (synchronises)."""
+        c = self.r.counters(self.ws)
+        return c.overflow or c.overflow_any
 
 
 class GraphAdamLoop:
@@ -518,34 +585,44 @@ class GraphAdamLoop:
         self.v = torch.zeros_like(self.verts)
         self.step_count = torch.zeros((1,), dtype=torch.int32, device=dev)
         self.lr, self.betas, self.eps, self.recompute = lr, betas, eps, recompute
-        # eager warm-up sizes the instance capacity (with headroom) before capture
+        # eager warm-up sizes the instance capacity (with headroom) before capture; with
+        # recompute the backward rebuilds the lists into the same workspace (one list buffer)
         rgb, alpha, saved, ws = renderer.forward(self.verts, self.colors, check=True)
-        self.ws_fwd = ws
-        self.ws_bwd = renderer.new_workspace() if recompute else ws
+        self.ws = ws
         self.rgb, self.alpha, self.saved = rgb, alpha, saved
         self.dV = torch.empty_like(self.verts)
         self.dC = torch.empty_like(self.colors)
         self.loss = torch.zeros((1,), dtype=torch.float32, device=dev)
         self.graph = None
 
+    def _state(self):
+        return (self.verts, self.m, self.v, self.step_count)
+
     def _step_body(self):
         r = self.r
-        r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws_fwd)
-        r.bwd_l2_raw(self.verts, self.colors, self.rgb, self.target, 1.0, self.saved, self.ws_bwd,
+        r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws)
+        r.bwd_l2_raw(self.verts, self.colors, self.rgb, self.target, 1.0, self.saved, self.ws,
                      1 if self.recompute else 0, self.dV, self.dC, self.loss)
         adam_step(self.verts, self.dV, self.m, self.v, self.step_count, self.lr, self.betas[0], self.betas[1],
                   self.eps)
 
     def capture(self):
+        """Captures one step as a HIP graph.  An eager step runs first (on a side stream, as graph
+        capture requires); the optimiser state it advanced is restored afterwards, so the first
+        replay is the first step."""
+        state = [t.clone() for t in self._state()]
         s = torch.cuda.Stream(self.r.device)
         s.wait_stream(torch.cuda.current_stream(self.r.device))
         with torch.cuda.stream(s):
-            self._step_body()  # one eager step on the side stream before capture
+            self._step_body()
         torch.cuda.current_stream(self.r.device).wait_stream(s)
         torch.cuda.synchronize(self.r.device)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self._step_body()
+        for t, saved in zip(self._state(), state):
+            t.copy_(saved)
+        torch.cuda.synchronize(self.r.device)
         return self
 
     def run(self, steps: int):
@@ -559,4 +636,7 @@ class GraphAdamLoop:
             self._step_body()
 
     def overflow(self) -> bool:
-        return self.r.counters(self.ws_fwd).overflow or self.r.counters(self.ws_bwd).overflow
+        """True if any list build since the previous check overflowed the instance capacity
+        (synchronises; reading restarts the peak counter)."""
+        c = self.r.counters(self.ws)
+        return c.overflow or c.overflow_any

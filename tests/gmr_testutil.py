@@ -40,6 +40,19 @@ def compare_images(rgb_gpu, alpha_gpu, rgb_orc, tf_orc, mask, tol=IMG_ATOL, labe
     return e_rgb, e_a
 
 
+def flagged_pixels_agree(rgb_gpu, alpha_gpu, rgb_orc, tf_orc, mask, tol=IMG_ATOL):
+    """Whether the GPU image equals the oracle's within the image tolerance on the pixels the oracle
+    flags as near a decision threshold: then both sides took the same decisions there, and a
+    gradient fed from those pixels can be compared with the oracle's adjoint."""
+    m = np.asarray(mask).reshape(-1)
+    if not m.any():
+        return True
+    d_rgb = np.abs(to_np(rgb_gpu).reshape(-1, 3).astype(np.float64) - rgb_orc.reshape(-1, 3))[m].max()
+    d_a = np.abs(to_np(alpha_gpu).reshape(-1).astype(np.float64) - (1.0 - tf_orc.reshape(-1)))[m].max()
+    print(f"{int(m.sum())} flagged pixels: max|drgb|={d_rgb:.3e} max|dalpha|={d_a:.3e}", flush=True)
+    return d_rgb <= tol and d_a <= tol
+
+
 def compare_grads(g_gpu, g_ref, label="", rel=GRAD_REL):
     g = to_np(g_gpu).astype(np.float64).reshape(-1)
     r = np.asarray(g_ref, np.float64).reshape(-1)

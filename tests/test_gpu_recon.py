@@ -201,8 +201,7 @@ def test_recon_loop_graph_matches_eager_and_descends(gpu):
     eager = gmr.ReconLoop(r, verts, colors, target, mask, w, lr=1e-3)
     graph = gmr.ReconLoop(r, verts, colors, target, mask, w, lr=1e-3)
     graph.capture()
-    graph.verts.copy_(verts)
-    graph.m.zero_(); graph.v.zero_(); graph.step_count.zero_()
+    assert torch.equal(graph.verts, verts) and int(graph.step_count.item()) == 0   # capture keeps the state
     for k in range(5):
         eager.run_eager(1)
         graph.graph.replay()
@@ -220,6 +219,93 @@ def test_recon_loop_graph_matches_eager_and_descends(gpu):
     say(f"objective after 5 steps {first:.6e}, after 65 {last:.6e}")
     assert np.isfinite(last) and last < first
     assert not graph.overflow()
+
+
+def _vector_adam_update_tolerance(p, g, m, v, t, hp, rel):
+    """How far VectorAdam's new vertices can move when each gradient element moves within the
+    gradient tolerance: the largest deviation over the 8 sign patterns of that bound per vertex."""
+    bound = np.where(g == 0.0, 0.0, rel * np.abs(g) + 1e-5 * np.abs(g).max())
+    base, _, _ = recon.vector_adam_step(p, g, m, v, t, **hp)
+    tol = np.zeros_like(p)
+    for sx in (-1, 1):
+        for sy in (-1, 1):
+            for sz in (-1, 1):
+                q, _, _ = recon.vector_adam_step(p, g + bound * np.array([sx, sy, sz]), m, v, t, **hp)
+                tol = np.maximum(tol, np.abs(q - base))
+    return base, tol
+
+
+def test_recon_loop_steps_vs_oracle_chain(gpu):
+    """Icosphere subdiv 2 at 128^2: three replays of the captured reconstruction step (colour MSE
+    1, silhouette BCE 0.1, edge length 0.01, Laplacian 0.01; VectorAdam lr 1e-3).  Before each
+    replay the GPU state is read; the oracle takes the same step from it: render -> both image
+    losses and their adjoint -> + the regulariser gradients -> VectorAdam.  Checked per step: the
+    four losses, the gradient the step applied (the loop's dV buffer), the update given the GPU's
+    gradient (tight) and the update given the oracle's (within what the gradient tolerance
+    allows)."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    from gmr_testutil import GRAD_REL, flagged_pixels_agree
+    say("recon loop vs oracle chain, cfg1")
+    W = wl.make_workload(1)
+    r, verts, colors = gpu_setup(W)
+    tgt, _, _, _ = oracle.render_workload(W, verts=W.target_verts)
+    sil = _silhouette(W)
+    target = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    mask = torch.from_numpy(sil.astype(np.float32)).cuda()
+    w = gmr.ReconWeights(color=1.0, silhouette=0.1, edge=0.01, laplacian=0.01)
+    lr = 1e-3
+    hp = dict(lr=float(np.float32(lr)), b1=float(np.float32(0.9)), b2=float(np.float32(0.999)),
+              eps=float(np.float32(1e-8)))
+    loop = gmr.ReconLoop(r, verts, colors, target, mask, w, lr=lr)
+    loop.capture()
+    edges = recon.mesh_edges(W.faces)
+    nb = recon.neighbours(len(W.verts), edges)
+    loose_total, compared = 0, 0
+    for t in range(1, 4):
+        p0 = to_np(loop.verts).astype(np.float64)
+        m0 = to_np(loop.m).astype(np.float64)
+        v0 = to_np(loop.v).astype(np.float64)
+        loop.graph.replay()
+        torch.cuda.synchronize()
+        assert int(loop.step_count.item()) == t and not loop.overflow()
+        dV = to_np(loop.dV).astype(np.float64)
+        pg, mg, vg = recon.vector_adam_step(p0, dV, m0, v0, t, **hp)
+        p1 = to_np(loop.verts).astype(np.float64)
+        e = np.abs(p1 - pg).max()
+        say(f"  step {t}: |p - vector_adam(p0, dV_gpu)| max {e:.3e}")
+        assert e <= 1e-6
+        np.testing.assert_allclose(to_np(loop.m), mg, rtol=1e-5, atol=1e-6 * np.abs(mg).max())
+        np.testing.assert_allclose(to_np(loop.v), vg, rtol=1e-5, atol=1e-6 * np.abs(vg).max())
+        o_rgb, o_tf, _, o_mask = oracle.render_workload(W, verts=p0.astype(np.float32))
+        # a pixel near a decision threshold counts only where both sides took the same decisions
+        # (its image value); else the oracle comparison of this step is skipped
+        if not flagged_pixels_agree(loop.rgb, loop.alpha, o_rgb, o_tf, o_mask):
+            say(f"  step {t}: flagged pixels disagree, oracle comparison skipped")
+            continue
+        compared += 1
+        Lc, g_rgb = oracle.l2_loss(o_rgb, tgt)
+        Ls, g_a = recon.silhouette_bce(1.0 - o_tf, sil, weight=w.silhouette)
+        Le, ge = recon.edge_length(p0, edges, l0=w.edge_length, weight=w.edge)
+        Ll, gl = recon.laplacian_smoothing(p0, nb, weight=w.laplacian)
+        lg = to_np(loop.losses).astype(np.float64)
+        say(f"  step {t}: losses gpu {lg} oracle {[w.color * Lc, Ls, Le, Ll]}")
+        assert lg[0] == pytest.approx(w.color * Lc, rel=1e-5)
+        assert lg[1] == pytest.approx(Ls, rel=1e-5)
+        assert lg[2] == pytest.approx(Le, rel=1e-4)
+        assert lg[3] == pytest.approx(Ll, rel=1e-4)
+        oV, _ = oracle.adjoint_workload(W, w.color * g_rgb, g_a, verts=p0.astype(np.float32))
+        oV = oV + ge + gl
+        compare_grads(dV, oV, f"step {t} dV (renderer + regularisers)")
+        po, tol = _vector_adam_update_tolerance(p0, oV, m0, v0, t, hp, GRAD_REL)
+        d = np.abs(p1 - po)
+        assert (d <= tol + 1e-6).all(), np.argwhere(d > tol + 1e-6)[:5]
+        loose = (tol > 0.1 * lr).any(axis=1)
+        loose_total += int(loose.sum())
+        say(f"  step {t}: |p - vector_adam(p0, dV_oracle)| max {d.max():.3e}; {int(loose.sum())} vertices "
+            f"whose gradient is within its tolerance of zero")
+    assert compared >= 2, "the oracle comparison ran on fewer than two of the three steps"
+    assert loose_total <= 0.05 * 3 * len(W.verts)
 
 
 def test_synthetic_reconstruction_converges(gpu):

@@ -234,6 +234,61 @@ def test_cfg4_batched_equals_per_view_and_oracle(gpu):
                        o_tf.reshape(-1), o_mask.reshape(-1), label=f"cfg4 view {v}")
 
 
+def test_cfg4_batched_grads_two_meshes(gpu):
+    """16-mesh batch (64 views) in one launch set, bench tiling (32 x 16): vertex and colour
+    gradients of a random upstream gradient (colour and alpha) on a 64 x 64 crop of one view of the
+    smallest mesh and one of the largest, vs the oracle's adjoint of those views.  The batch's
+    vertices are global indices into one CSR gather: every other mesh's gradient must be zero."""
+    import torch
+    say("cfg4 16 meshes / 64 views: batched gradients of two meshes")
+    W = wl.make_workload(4)
+    r, verts, colors = gpu_setup(W, tile_w=32, tile_h=16)
+    rgb, alpha, saved, ws = r.forward(verts, colors)
+    F = np.diff(W.face_offsets)
+    ms = sorted(set(int(m) for m in W.view_mesh))
+    m_small, m_large = min(ms, key=lambda m: F[m]), max(ms, key=lambda m: F[m])
+    views = [int(np.flatnonzero(W.view_mesh == m_small)[0]), int(np.flatnonzero(W.view_mesh == m_large)[-1])]
+    po = W.pixel_offsets()
+    cams = W.cam_array()
+    rng = np.random.default_rng(44)
+    g = np.zeros((W.num_pixels, 3), np.float32)
+    ga = np.zeros(W.num_pixels, np.float32)
+    oV, oC = np.zeros(W.verts.shape), np.zeros(W.colors.shape)
+    for v in views:
+        m = int(W.view_mesh[v])
+        mv, mf, mc = W.mesh(m)
+        v0, v1, f0 = int(W.vert_offsets[m]), int(W.vert_offsets[m + 1]), int(W.face_offsets[m])
+        Wv, Hv = W.cams[v].width, W.cams[v].height
+        o_rgb, o_tf, _, o_mask = oracle.render_view(mv, mf, mc, cams[v], gid_base=f0)
+        cov = (1.0 - o_tf) > 0.5
+        # the 64 x 64 window (16-px grid) nearest the centre whose coverage is closest to 3/4
+        best = min(((abs(cov[y:y + 64, x:x + 64].mean() - 0.75), (y - Hv / 2) ** 2 + (x - Wv / 2) ** 2, y, x)
+                    for y in range(0, Hv - 63, 16) for x in range(0, Wv - 63, 16)))
+        _, _, y, x = best
+        keep = ~o_mask[y:y + 64, x:x + 64]
+        gr = (rng.normal(size=(64, 64, 3)) * keep[..., None]).astype(np.float32)
+        gal = (0.1 * rng.normal(size=(64, 64)) * keep).astype(np.float32)
+        say(f"view {v} (mesh {m}, {F[m]} faces, {Wv}x{Hv}): crop at ({x}, {y}), "
+            f"coverage {cov[y:y + 64, x:x + 64].mean():.2f}")
+        rows = po[v] + (np.arange(y, y + 64)[:, None] * Wv + np.arange(x, x + 64)[None, :]).reshape(-1)
+        g[rows] = gr.reshape(-1, 3)
+        ga[rows] = gal.reshape(-1)
+        dv, dc = oracle.adjoint_view(mv, mf, mc, cams[v], gr.astype(np.float64), gal.astype(np.float64),
+                                     gid_base=f0, window=(x, y, x + 64, y + 64))
+        oV[v0:v1] += dv
+        oC[v0:v1] += dc
+    dV, dC = r.backward(verts, colors, torch.from_numpy(g).cuda(), torch.from_numpy(ga).cuda(), saved, ws)
+    for m in (m_small, m_large):
+        v0, v1 = int(W.vert_offsets[m]), int(W.vert_offsets[m + 1])
+        compare_grads(dV[v0:v1], oV[v0:v1], f"cfg4 mesh {m} dV")
+        compare_grads(dC[v0:v1], oC[v0:v1], f"cfg4 mesh {m} dC")
+    others = np.ones(len(W.verts), bool)
+    for m in (m_small, m_large):
+        others[int(W.vert_offsets[m]):int(W.vert_offsets[m + 1])] = False
+    assert float(dV[torch.from_numpy(others).cuda()].abs().max()) == 0.0
+    assert float(dC[torch.from_numpy(others).cuda()].abs().max()) == 0.0
+
+
 @pytest.mark.parametrize("cfg", [3, 4])
 def test_tile_lists_bit_exact_large_inputs(gpu, cfg):
     """Every tile list of the UV sphere (1.6M face-views) and of the 16-mesh batch (64 views)
