@@ -176,6 +176,26 @@ gmr_status gmr_render_fwd(gmr_handle h, const gmr_batch* batch, const gmr_option
                           float* out_rgb_dev, float* out_alpha_dev, void* saved_dev,
                           void* ws_dev, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gmr_render_fwd with the workspace taken from a static
+ * device array of GMR_NOALLOC_WORKSPACE_BYTES that the library holds on every GPU it runs on until
+ * the process ends.  The call allocates and frees nothing, synchronises nothing and is capturable.
+ * Arguments as gmr_render_fwd, without ws_dev / ws_bytes, plus
+ *   counters_dev  [2] uint32 (may be NULL): {instance count, overflow flag} of this call's list
+ *                 build, copied on the stream (gmr_read_counters cannot see the static workspace).
+ * Errors (returned before anything is enqueued): GMR_ERR_WORKSPACE when the batch's workspace
+ * (gmr_workspace_size for these options) exceeds GMR_NOALLOC_WORKSPACE_BYTES -- lower
+ * instance_capacity or use gmr_render_fwd; the other errors of gmr_render_fwd.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's contents (each call
+ * clears what it needs): calls that overlap on one GPU (several streams or threads) race, and the
+ * lists a call leaves there cannot be handed to gmr_render_bwd -- its backward rebuilds them
+ * (recompute_lists = 1) in a caller workspace. */
+#define GMR_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+gmr_status gmr_render_fwd_noalloc(gmr_handle h, const gmr_batch* batch, const gmr_options* opt,
+                                  const void* table_dev, const float* verts_dev, const int32_t* faces_dev,
+                                  const float* colors_dev, float* out_rgb_dev, float* out_alpha_dev,
+                                  void* saved_dev, uint32_t* counters_dev, void* stream);
+
 /* Backward pass: reverse-order adjoint of the compositing per pixel, chained through the EWA
  * projection and the conversion to vertex positions and colours.
  *   d_rgb_dev   [P][3] f32  dL/d rgb;  d_alpha_dev [P] f32 dL/d alpha (may be NULL)

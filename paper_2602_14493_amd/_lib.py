@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libgmr.so")
 c_float, c_int32, c_int64, c_size_t, c_void_p = ctypes.c_float, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
 
 GMR_OK, GMR_ERR_INVALID_ARG, GMR_ERR_WORKSPACE, GMR_ERR_CAPACITY, GMR_ERR_UNSUPPORTED, GMR_ERR_HIP = range(6)
+NOALLOC_WORKSPACE_BYTES = 64 << 20   # GMR_NOALLOC_WORKSPACE_BYTES of gmr.h
 
 
 class gmr_camera(ctypes.Structure):
@@ -53,6 +54,9 @@ _SIGS = {
     "gmr_render_fwd": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                  c_void_p]),
+    "gmr_render_fwd_noalloc": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p,
+                                         c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                         c_void_p]),
     "gmr_render_bwd": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),

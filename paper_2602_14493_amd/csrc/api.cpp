@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,15 +27,25 @@ static const char* kStageNames[kNumStages] = {"project",     "scan_emit",  "sort
 struct gmr_ctx {
   int device = 0;
   int num_cus = 256;
+  void* scratch = nullptr;  // this device's copy of the static workspace of gmr_render_fwd_noalloc
   std::map<std::string, std::pair<gmr_options, float>> tune_cache;
   bool prof = false;
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> recs;
 };
 
+// Workspace of gmr_render_fwd_noalloc: one static device array, of which every GPU the library
+// runs on holds its own copy, at its own address, until the process ends.  Host code never passes
+// the array's name to a kernel or a copy (on the host it names a stand-in, not device memory): the
+// device address is resolved once per device with hipGetSymbolAddress and used from then on.
+static __device__ __align__(256) unsigned char scratch[GMR_NOALLOC_WORKSPACE_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;  // per device: the address of `scratch`, or NULL before resolving
 
 gmr_status fail(gmr_status s, const std::string& msg) {
   g_err = msg;
@@ -334,13 +345,15 @@ struct StageTimer {
 
 // Conversion + projection + binning + sort (+ optionally zeroing the face-view gradients).
 void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* table, const float* verts,
-                 const int32_t* faces, const float* colors, const WsPtrs& w, bool zero_dfv, hipStream_t s) {
+                 const int32_t* faces, const float* colors, const WsPtrs& w, bool zero_dfv, hipStream_t s,
+                 bool timed = true) {
+  gmr_ctx* const th = timed ? h : nullptr;  // stage timing records events; untimed calls create none
   const KOpts ko = kopts(o);
   const Layout& L = p.L;
   const uint32_t fv_words = (uint32_t)std::max(L.parts_fv, 1) * 256u;
   const uint32_t inst_words = (uint32_t)L.parts_inst * 512u;
   {
-    StageTimer t(h, s, kStProject);
+    StageTimer t(th, s, kStProject);
     const StatsInfo si{(uint32_t)p.items_total, (unsigned long long)L.statF, (unsigned long long)L.statB};
     launch_project(table, p.f_total, verts, faces, colors, ko, w.rec, w.elA, w.hist,
                    zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.hdr, w.descF0, fv_words, w.ranges,
@@ -348,7 +361,7 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   }
   // depth digits on the face-view elements: 4 passes, A -> B -> A -> B -> A
   for (int pass = 0; pass < kDepthPasses; ++pass) {
-    StageTimer t(h, s, kStSortFv);
+    StageTimer t(th, s, kStSortFv);
     const bool odd = pass & 1;
     launch_sort_fv_pass(odd ? w.elB : w.elA, odd ? w.elA : w.elB, (uint32_t)p.fv_total, w.hist + pass * kHistStride,
                         odd ? w.descF1 : w.descF0, odd ? w.descF0 : w.descF1, fv_words, &w.hdr->part_ctr[pass], pass,
@@ -361,13 +374,13 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
     tp.mask[j] = j < tp.n ? (uint32_t)L.tile_mask[j] : 0u;
   }
   {
-    StageTimer t(h, s, kStScanEmit);
+    StageTimer t(th, s, kStScanEmit);
     launch_bin(table, w.elA, w.elB, p.fv_total, L.scan_items, w.bdesc, L.scan_blocks, w.hdr, (uint32_t)L.capacity,
                w.instA, w.hist, tp, w.descI0, inst_words, s);
   }
   // tile digits on the instances: A -> B -> A ..., the last pass writes keysF / valsF
   for (int j = 0; j < tp.n; ++j) {
-    StageTimer t(h, s, kStSortPass);
+    StageTimer t(th, s, kStSortPass);
     const bool odd = j & 1, last = j + 1 == tp.n;
     launch_sort_inst_pass(odd ? w.instB : w.instA, odd ? w.instA : w.instB, last ? w.keysF : nullptr,
                           last ? w.valsF : nullptr, &w.hdr->count, (uint32_t)L.capacity,
@@ -376,7 +389,7 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
                           L.sort_items_inst, s);
   }
   {
-    StageTimer t(h, s, kStRanges);
+    StageTimer t(th, s, kStRanges);
     launch_tile_ranges(w.keysF, w.hdr, w.ranges, hist_blocks(h), s);
   }
 }
@@ -533,9 +546,27 @@ gmr_status gmr_create(gmr_handle* out, int device) {
   if (device < 0 || device >= n) return fail(GMR_ERR_INVALID_ARG, "device out of range");
   hipDeviceProp_t prop;
   GMR_CHECK_HIP(hipGetDeviceProperties(&prop, device));
+  // the device address of the static workspace, resolved once per device with that device current
+  void* sp = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_dev.size() < n) g_scratch_dev.resize(n, nullptr);
+    if (!g_scratch_dev[device]) {
+      int prev = 0;
+      GMR_CHECK_HIP(hipGetDevice(&prev));
+      GMR_CHECK_HIP(hipSetDevice(device));
+      const hipError_t e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+      (void)hipSetDevice(prev);
+      if (e != hipSuccess || !sp)
+        return fail(GMR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      g_scratch_dev[device] = sp;
+    }
+    sp = g_scratch_dev[device];
+  }
   gmr_ctx* c = new gmr_ctx;
   c->device = device;
   c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->scratch = sp;
   *out = c;
   return GMR_OK;
 }
@@ -590,6 +621,24 @@ gmr_status gmr_build_adjacency(const int32_t* faces, int64_t nf, int64_t nv, int
   return GMR_OK;
 }
 
+namespace {
+// The forward's launches into workspace ws (validated by the caller).
+void fwd_impl(gmr_ctx* h, const Plan& p, const gmr_options* opt, const void* table, const float* verts,
+              const int32_t* faces, const float* colors, float* out_rgb, float* out_alpha, void* saved, void* ws,
+              bool timed, hipStream_t s) {
+  const WsPtrs w = ws_ptrs(p.L, ws);
+  build_lists(h, p, opt, table, verts, faces, colors, w, false, s, timed);
+  float* saved_T = static_cast<float*>(saved);
+  uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
+  {
+    StageTimer t(timed ? h : nullptr, s, kStRasterFwd);
+    launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0, w.ranges,
+                      w.sorted_vals, w.rec, kopts(opt),
+                      out_rgb, out_alpha, saved_T, saved_n, w.statF, s);
+  }
+}
+}  // namespace
+
 gmr_status gmr_render_fwd(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
                           const float* verts, const int32_t* faces, const float* colors, float* out_rgb, float* out_alpha,
                           void* saved, void* ws, size_t ws_bytes, void* stream) {
@@ -599,17 +648,33 @@ gmr_status gmr_render_fwd(gmr_handle h, const gmr_batch* batch, const gmr_option
   st = common_checks(h, table, ws, ws_bytes, p);
   if (st != GMR_OK) return st;
   if (!verts || !faces || !colors || !out_rgb || !saved) return fail(GMR_ERR_INVALID_ARG, "a required device pointer is NULL");
+  fwd_impl(h, p, opt, table, verts, faces, colors, out_rgb, out_alpha, saved, ws, true, static_cast<hipStream_t>(stream));
+  return check_launch();
+}
+
+gmr_status gmr_render_fwd_noalloc(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
+                                  const float* verts, const int32_t* faces, const float* colors, float* out_rgb,
+                                  float* out_alpha, void* saved, uint32_t* counters, void* stream) {
+  Plan p;
+  gmr_status st = make_plan(batch, opt, true, p);
+  if (st != GMR_OK) return st;
+  if (!h) return fail(GMR_ERR_INVALID_ARG, "handle is NULL");
+  if (!h->scratch) return fail(GMR_ERR_HIP, "the static workspace of this device was not resolved");
+  if (p.L.total > GMR_NOALLOC_WORKSPACE_BYTES)
+    return fail(GMR_ERR_WORKSPACE, "this batch needs " + std::to_string(p.L.total) +
+                                       " workspace bytes; the static workspace holds " +
+                                       std::to_string((size_t)GMR_NOALLOC_WORKSPACE_BYTES) +
+                                       " (use gmr_render_fwd with a caller workspace, or a smaller instance_capacity)");
+  st = common_checks(h, table, h->scratch, GMR_NOALLOC_WORKSPACE_BYTES, p);
+  if (st != GMR_OK) return st;
+  if (!verts || !faces || !colors || !out_rgb || !saved) return fail(GMR_ERR_INVALID_ARG, "a required device pointer is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const WsPtrs w = ws_ptrs(p.L, ws);
-  build_lists(h, p, opt, table, verts, faces, colors, w, false, s);
-  float* saved_T = static_cast<float*>(saved);
-  uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
-  {
-    StageTimer t(h, s, kStRasterFwd);
-    launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0, w.ranges,
-                      w.sorted_vals, w.rec, kopts(opt),
-                      out_rgb, out_alpha, saved_T, saved_n, w.statF, s);
-  }
+  // every region the forward reads is written earlier in the same call (its prologue clears the
+  // counters, tickets, descriptors, histograms and tile ranges), so the previous call's contents
+  // need no clearing here
+  fwd_impl(h, p, opt, table, verts, faces, colors, out_rgb, out_alpha, saved, h->scratch, false, s);
+  if (counters)  // {instance count, overflow flag}: the first two words of the workspace header
+    GMR_CHECK_HIP(hipMemcpyAsync(counters, h->scratch, 2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   return check_launch();
 }
 

@@ -169,3 +169,10 @@ def test_status_strings():
     L = _lib.load()
     assert L.gmr_status_string(0) == b"ok"
     assert b"workspace" in L.gmr_status_string(2)
+
+
+def test_noalloc_workspace_limit_matches_header():
+    from paper_2602_14493_amd import _lib
+    txt = open(os.path.join(ROOT, "include", "gmr.h")).read()
+    m = re.search(r"#define GMR_NOALLOC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_WORKSPACE_BYTES
