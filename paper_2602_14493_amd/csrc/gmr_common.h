@@ -317,8 +317,9 @@ __device__ inline bool view_project(const ViewDev& V, const double* mu, const do
 }
 
 // exp(power) = exp2(-(k w)^2) with w = L (dx, dy), L^T L = conic, k^2 = log2(e) / 2.
-constexpr double kHalfLog2e = 0.72134752044448170368;   // log2(e) / 2
-constexpr float kTwoLn2 = 1.3862943611198906f;           // 1 / k^2
+constexpr double kHalfLog2e = 0.72134752044448170368;    // log2(e) / 2
+constexpr double kRasterScale = 0.84932180028801904272;  // k = sqrt(log2(e) / 2), the records' scale of L
+constexpr double kLn2 = 0.69314718055994530942;
 
 // Pixel-centre predicate of the 3-sigma extent, per axis: the pixels i with |i + 0.5 - u| <= r
 // are ceil(u - r - 0.5) .. floor(u + r - 0.5) (computed in double by the projection).

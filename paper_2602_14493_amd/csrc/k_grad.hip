@@ -1,9 +1,10 @@
 // Backward of the EWA projection and of the conversion, then the per-vertex gather.
 //
 // k_face_bwd: one thread per face (double precision).  For every view of the face's mesh it reads
-// the face-view's screen-space gradient {du, dv, da, db, dc, dr, dg, db}, re-derives the
-// projection and accumulates dL/dmu and dL/dSigma over views (gradients as full symmetric
-// matrices: dL = tr(G dX)):
+// the face-view's gradient sums {A, B, C, D, E, dr, dg, db} (the rasteriser's sums in the scaled
+// Cholesky frame of the conic, turned into {du, dv, da, db, dc} below), re-derives the projection
+// and accumulates dL/dmu and dL/dSigma over views (gradients as full symmetric matrices:
+// dL = tr(G dX)):
 //   conic Q = Sigma'^-1:           G_Sigma' = -Q Gq Q, Gq = [[da, db/2], [db/2, dc]]
 //   Sigma' = J W J^T + d I:        G_W = J^T G_Sigma' J,  G_J = 2 G_Sigma' J W
 //   W = R Sigma R^T:               G_Sigma = R^T G_W R
@@ -123,7 +124,20 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
     }
     ProjGeo q;
     if (!view_project(V, g.mu, g.S, (double)o.dilation, q)) continue;
-    const double du = d0.x, dv = d0.y, da = d0.z, db = d0.w, dc = d1.x;
+    // the rasteriser's sums over the face-view's pixels, {A, B, C, D, E} = sum of gq {w1, w2,
+    // w1 dx, w1 dy, w2 dy} with gq = dL/d(ln alpha) and w = k L (dx, dy), L the conic's Cholesky
+    // factor (k^2 = log2(e) / 2, the record's scale): exp2(-|w|^2) = exp(-d^T Q d / 2), so
+    // dL/d(u, v) = -2 ln2 k (L^T (A, B)) and the sums of gq dx^2, gq dx dy, gq dy^2 follow from
+    // the triangular system C = k (l11 Sxx + l12 Sxy), D = k (l11 Sxy + l12 Syy), E = k l22 Syy;
+    // dL/d(a, b, c) = -(Sxx / 2, Sxy, Syy / 2)
+    const double l11 = sqrt(q.a), l12 = q.b / l11, l22 = 1.0 / (l11 * sqrt(q.det));
+    const double kl11 = kRasterScale * l11, kl12 = kRasterScale * l12, kl22 = kRasterScale * l22;
+    const double sA = d0.x, sB = d0.y, sC = d0.z, sD = d0.w, sE = d1.x;
+    const double Syy = sE / kl22;
+    const double Sxy = (sD - kl12 * Syy) / kl11;
+    const double Sxx = (sC - kl12 * Sxy) / kl11;
+    const double du = -2.0 * kLn2 * kl11 * sA, dv = -2.0 * kLn2 * (kl12 * sA + kl22 * sB);
+    const double da = -0.5 * Sxx, db = -Sxy, dc = -0.5 * Syy;
     // G_Sigma' = -Q Gq Q
     const double a = q.a, b = q.b, c = q.c;
     const double m00 = a * da + b * 0.5 * db, m01 = a * 0.5 * db + b * dc;

@@ -51,7 +51,7 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
   } else {
     face_coefs<SHD>(colors, i0, i1, i2, coef);
   }
-  const double kscale = sqrt(kHalfLog2e);
+  const double kscale = kRasterScale;
 
   for (int k = mvo[m] + u; k < mvo[m + 1]; k += lpf) {
     const ViewDev& V = views[mvs[k]];

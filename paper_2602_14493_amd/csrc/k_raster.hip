@@ -104,11 +104,45 @@ __device__ inline bool in_range(uint32_t r, int x) {
   return (uint32_t)(x - lo) <= (uint32_t)(hi - lo);
 }
 
-// Shared by forward and backward so both take bit-identical decisions.
-__device__ inline float gauss_exp(const float4& r1, float dx, float dy, float& w1, float& w2) {
-  w1 = fmaf(r1.x, dx, r1.y * dy);
-  w2 = r1.z * dy;
+// Shared by forward and backward so both take bit-identical decisions: w = k L (dx, dy) with the
+// record's scaled Cholesky factor (l11, l12, l22), exp(power) = exp2(-(w1^2 + w2^2)).
+__device__ inline float gauss_exp(float l11, float l12, float l22, float dx, float dy, float& w1, float& w2) {
+  w1 = fmaf(l11, dx, l12 * dy);
+  w2 = l22 * dy;
   return __builtin_amdgcn_exp2f(-fmaf(w1, w1, w2 * w2));
+}
+
+// A record as a wavefront stages it for its block: the mean as offsets from the centre of an
+// 8 x 8 block's top-left pixel (origin bx0 or yb), with the mean's low half folded in, so that
+// pixel (bx0 + c, yb + r) of that block takes dx = ox - c and dy = oy - r.  Forward and backward
+// stage and subtract the same way, so they take the same decisions; the offsets depend on the
+// 8 x 8 block alone (never on the tile shape or the pixels per lane), so neither do images.
+// LDS slot j: s[0] = {ox, oy of row group 0, l11, l12}, s[1] = {l22, r, g, b} and, with PX > 1
+// row groups, s[2] = {oy of row groups 1, 2, 3, 0}.
+__device__ inline float block_off(float hi, float lo, int origin) { return (hi - ((float)origin + 0.5f)) + lo; }
+
+template <int PX>
+__device__ inline void stage_record(float4 (*s)[kWave], int slot, const float4& r0, const float4& r1,
+                                    const float4& r2, int bx0, int by0) {
+  s[0][slot] = make_float4(block_off(r0.x, r0.z, bx0), block_off(r0.y, r0.w, by0), r1.x, r1.y);
+  s[1][slot] = make_float4(r1.z, r2.x, r2.y, r2.z);
+  if constexpr (PX > 1)
+    s[2][slot] = make_float4(block_off(r0.y, r0.w, by0 + kSub), PX > 2 ? block_off(r0.y, r0.w, by0 + 2 * kSub) : 0.f,
+                             PX > 2 ? block_off(r0.y, r0.w, by0 + 3 * kSub) : 0.f, 0.f);
+}
+
+// The row-group offsets oy of staged slot j (a = s[0][j]).
+template <int PX>
+__device__ __forceinline__ void staged_oy(const float4 (*s)[kWave], int j, const float4& a, float (&oy)[PX]) {
+  oy[0] = a.y;
+  if constexpr (PX > 1) {
+    const float4 c = s[2][j];
+    oy[1] = c.x;
+    if constexpr (PX > 2) {
+      oy[2] = c.y;
+      oy[3] = c.z;
+    }
+  }
 }
 
 // DPP controls (GFX9 encoding): quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror, row_ror:8,
@@ -200,24 +234,23 @@ struct FwdArgs {
   unsigned long long* stats;  // [items] pairs evaluated per item (summed on the host when read)
 };
 
-// One record against a lane's PX pixels; `valid` = false makes it a no-op (predicated).
+// One record against a lane's PX pixels; `valid` = false makes it a no-op (predicated).  a = s[0][j],
+// b = s[1][j]; cov[k]: the record's pixel-rectangle coverage of row group k (bit = lane), uniform.
 template <int PX>
-__device__ __forceinline__ void fwd_eval(const float4& a0, const float4& a1, const float4& a2, bool valid,
-                                         uint32_t pos_next, int x, float px, const int (&y)[PX], float amin,
-                                         float amax, float teps, float (&T)[PX], float (&C0)[PX], float (&C1)[PX],
-                                         float (&C2)[PX], uint32_t (&last)[PX], bool (&done)[PX],
-                                         unsigned long long& pairs) {
-  const bool inx = valid && in_range(f2u(a1.w), x);
-  const float dx = (a0.x - px) + a0.z;
-  const uint32_t ry = f2u(a2.w);
+__device__ __forceinline__ void fwd_eval(const float4& a, const float4& b, const float (&oy)[PX],
+                                         const uint64_t (&cov)[PX], bool valid, uint32_t pos_next, float lxf,
+                                         float lyf, float amin, float amax, float teps, float (&T)[PX],
+                                         float (&C0)[PX], float (&C1)[PX], float (&C2)[PX], uint32_t (&last)[PX],
+                                         bool (&done)[PX], unsigned long long& pairs) {
+  const float dx = a.x - lxf;
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
-    const bool act = !done[k] && inx && in_range(ry, y[k]);
+    const bool act = valid && !done[k] && __builtin_amdgcn_inverse_ballot_w64(cov[k]);
     if (PX > 1 && __ballot(act) == 0ull) continue;  // wave-uniform: no lane's row k meets it
-    const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
+    const float dy = oy[k] - lyf;
     float w1, w2;
-    const float e = gauss_exp(a1, dx, dy, w1, w2);
-    const float al = fminf(amax, e);
+    const float e = gauss_exp(a.z, a.w, b.x, dx, dy, w1, w2);
+    const float al = __builtin_amdgcn_fmed3f(e, 0.f, amax);  // min(e, amax): e is in [0, 1]
     const bool ok = act && al >= amin;
     const float Tn = T[k] * (1.f - al);
     const bool stop = ok && Tn < teps;
@@ -225,22 +258,28 @@ __device__ __forceinline__ void fwd_eval(const float4& a0, const float4& a1, con
     pairs += (unsigned long long)__popcll(__ballot(act));  // wave-uniform, scalar unit
     done[k] = done[k] || stop;
     const float wt = al * T[k];
-    C0[k] = comp ? fmaf(a2.x, wt, C0[k]) : C0[k];
-    C1[k] = comp ? fmaf(a2.y, wt, C1[k]) : C1[k];
-    C2[k] = comp ? fmaf(a2.z, wt, C2[k]) : C2[k];
+    C0[k] = comp ? fmaf(b.y, wt, C0[k]) : C0[k];
+    C1[k] = comp ? fmaf(b.z, wt, C1[k]) : C1[k];
+    C2[k] = comp ? fmaf(b.w, wt, C2[k]) : C2[k];
     T[k] = comp ? Tn : T[k];
     last[k] = comp ? pos_next : last[k];
   }
 }
 
+// A wave-uniform 64-bit value from LDS into scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 // Returns the item's pair count (wave-uniform).
 template <int PX>
 __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const TableHdr* th, const ViewDev* views,
-                                                     int item, int lane, float4 (*s)[kWave]) {
+                                                     int item, int lane, float4 (*s)[kWave], uint64_t (*scov)[kWave]) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return 0ull;
   const int ly = lane >> 3;
-  const float px = (float)g.x + 0.5f;
+  const float lxf = (float)(lane & 7), lyf = (float)ly;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
   float T[PX], C0[PX], C1[PX], C2[PX];
@@ -271,7 +310,9 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
     }
     uint64_t m = __ballot(ov);
     if (m == 0ull) continue;
-    s[0][lane] = r0; s[1][lane] = r1; s[2][lane] = r2;
+    stage_record<PX>(s, lane, r0, r1, r2, g.bx0, g.by0);
+#pragma unroll
+    for (int k = 0; k < PX; ++k) scov[k][lane] = ov ? block_coverage(f2u(r1.w), f2u(r2.w), g.bx0, g.by0 + kSub * k) : 0ull;
     wave_lds_sync();
     // consume the kept records in list order, two per round: both broadcast reads are issued
     // before either is evaluated, and the second evaluation is predicated (not branched) when the
@@ -282,12 +323,21 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
       const bool has2 = m != 0ull;
       const int j2 = has2 ? __builtin_ctzll(m) : j1;
       m &= m - (has2 ? 1ull : 0ull);
-      const float4 a0 = s[0][j1], a1 = s[1][j1], a2 = s[2][j1];
-      const float4 b0 = s[0][j2], b1 = s[1][j2], b2 = s[2][j2];
-      fwd_eval<PX>(a0, a1, a2, true, cb + (uint32_t)j1 - start + 1u, g.x, px, y, amin, amax, teps, T, C0, C1, C2,
-                   last, done, pairs);
-      fwd_eval<PX>(b0, b1, b2, has2, cb + (uint32_t)j2 - start + 1u, g.x, px, y, amin, amax, teps, T, C0, C1, C2,
-                   last, done, pairs);
+      const float4 a0 = s[0][j1], a1 = s[1][j1];
+      const float4 b0 = s[0][j2], b1 = s[1][j2];
+      float oy1[PX], oy2[PX];
+      staged_oy<PX>(s, j1, a0, oy1);
+      staged_oy<PX>(s, j2, b0, oy2);
+      uint64_t cv1[PX], cv2[PX];
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        cv1[k] = uniform64(scov[k][j1]);
+        cv2[k] = uniform64(scov[k][j2]);
+      }
+      fwd_eval<PX>(a0, a1, oy1, cv1, true, cb + (uint32_t)j1 - start + 1u, lxf, lyf, amin, amax, teps, T, C0, C1,
+                   C2, last, done, pairs);
+      fwd_eval<PX>(b0, b1, oy2, cv2, has2, cb + (uint32_t)j2 - start + 1u, lxf, lyf, amin, amax, teps, T, C0, C1,
+                   C2, last, done, pairs);
       bool live2 = false;
 #pragma unroll
       for (int k = 0; k < PX; ++k) live2 |= !done[k];
@@ -317,18 +367,18 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
 // lane walks only those, in slot order.  Every (pixel, Gaussian) pair takes the same arithmetic as
 // in raster_fwd_item, so images are bit-identical.
 template <int PX>
-__device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const uint32_t* s_pos, uint32_t n,
-                                               const ItemGeo& g, float px, const int (&y)[PX], float amin, float amax,
-                                               float teps, float (&T)[PX], float (&C0)[PX], float (&C1)[PX],
-                                               float (&C2)[PX], uint32_t (&last)[PX], bool (&done)[PX],
-                                               uint32_t& pairs, int lane) {
+__device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const uint32_t* s_pos, const uint2* s_rect,
+                                               uint32_t n, const ItemGeo& g, float lxf, float lyf, float amin,
+                                               float amax, float teps, float (&T)[PX], float (&C0)[PX],
+                                               float (&C1)[PX], float (&C2)[PX], uint32_t (&last)[PX],
+                                               bool (&done)[PX], uint32_t& pairs, int lane) {
   uint64_t mine[PX];
   {
     const bool own = (uint32_t)lane < n;
-    const uint32_t rx = own ? f2u(s[1][lane].w) : 0u, ry = own ? f2u(s[2][lane].w) : 0u;
+    const uint2 rr = own ? s_rect[lane] : make_uint2(0u, 0u);
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
-      const uint64_t cov = own ? block_coverage(rx, ry, g.bx0, g.by0 + kSub * k) : 0ull;
+      const uint64_t cov = own ? block_coverage(rr.x, rr.y, g.bx0, g.by0 + kSub * k) : 0ull;
       mine[k] = transpose64(cov, lane);
     }
   }
@@ -337,7 +387,6 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
     const uint64_t mk = done[k] ? 0ull : mine[k];
     // every slot of the lane's list is evaluated unless the pixel stops first (subtracted below)
     pairs += (uint32_t)__popcll(mk);
-    const float py = (float)y[k] + 0.5f;
     // the two 32-slot halves are walked with 32-bit masks (one find-first-set per step)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -345,12 +394,20 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
       while (m) {
         const int j = 32 * h + __builtin_ctz(m);
         m &= m - 1u;
-        const float4 a0 = s[0][j], a1 = s[1][j], a2 = s[2][j];
-        const float dx = (a0.x - px) + a0.z;
-        const float dy = (a0.y - py) + a0.w;
+        const float4 a = s[0][j], b = s[1][j];
+        float oy;
+        if constexpr (PX == 1) {
+          oy = a.y;
+        } else {
+          float o4[PX];
+          staged_oy<PX>(s, j, a, o4);
+          oy = o4[k];
+        }
+        const float dx = a.x - lxf;
+        const float dy = oy - lyf;
         float w1, w2;
-        const float e = gauss_exp(a1, dx, dy, w1, w2);
-        const float al = fminf(amax, e);
+        const float e = gauss_exp(a.z, a.w, b.x, dx, dy, w1, w2);
+        const float al = __builtin_amdgcn_fmed3f(e, 0.f, amax);  // min(e, amax): e is in [0, 1]
         if (al >= amin) {
           const float Tn = T[k] * (1.f - al);
           if (Tn < teps) {
@@ -359,9 +416,9 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
             m = 0u;
           } else {
             const float wt = al * T[k];
-            C0[k] = fmaf(a2.x, wt, C0[k]);
-            C1[k] = fmaf(a2.y, wt, C1[k]);
-            C2[k] = fmaf(a2.z, wt, C2[k]);
+            C0[k] = fmaf(b.y, wt, C0[k]);
+            C1[k] = fmaf(b.z, wt, C1[k]);
+            C2[k] = fmaf(b.w, wt, C2[k]);
             T[k] = Tn;
             last[k] = s_pos[j];
           }
@@ -377,11 +434,12 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
 // transpose serves 64 kept Gaussians however sparse they are in the list.
 template <int PX>
 __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* th, const ViewDev* views,
-                                                           int item, int lane, float4 (*s)[kWave], uint32_t* s_pos) {
+                                                           int item, int lane, float4 (*s)[kWave], uint32_t* s_pos,
+                                                           uint2* s_rect) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return 0ull;
   const int ly = lane >> 3;
-  const float px = (float)g.x + 0.5f;
+  const float lxf = (float)(lane & 7), lyf = (float)ly;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
@@ -419,26 +477,29 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
     if (m == 0ull) continue;
     const uint32_t cnt = (uint32_t)__popcll(m), slot = nk + (uint32_t)__popcll(m & below);
     if (ov && slot < (uint32_t)kWave) {
-      s[0][slot] = r0; s[1][slot] = r1; s[2][slot] = r2;
+      stage_record<PX>(s, (int)slot, r0, r1, r2, g.bx0, g.by0);
       s_pos[slot] = pos - start + 1u;  // list position after this Gaussian
+      s_rect[slot] = make_uint2(f2u(r1.w), f2u(r2.w));
     }
     if (nk + cnt < (uint32_t)kWave) {
       nk += cnt;
       continue;
     }
     wave_lds_sync();
-    fwd_walk_lanes<PX>(s, s_pos, (uint32_t)kWave, g, px, y, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
+    fwd_walk_lanes<PX>(s, s_pos, s_rect, (uint32_t)kWave, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done,
+                       pairs, lane);
     wave_lds_sync();
     if (ov && slot >= (uint32_t)kWave) {  // the overflow starts the next 64
       const uint32_t t = slot - (uint32_t)kWave;
-      s[0][t] = r0; s[1][t] = r1; s[2][t] = r2;
+      stage_record<PX>(s, (int)t, r0, r1, r2, g.bx0, g.by0);
       s_pos[t] = pos - start + 1u;
+      s_rect[t] = make_uint2(f2u(r1.w), f2u(r2.w));
     }
     nk = nk + cnt - (uint32_t)kWave;
   }
   if (nk > 0) {
     wave_lds_sync();
-    fwd_walk_lanes<PX>(s, s_pos, nk, g, px, y, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
+    fwd_walk_lanes<PX>(s, s_pos, s_rect, nk, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
   }
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
@@ -462,19 +523,28 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
 
 // Every item writes its own statistics slot (no atomics on a shared counter: one float or 64-bit
 // atomic per wavefront on one address serialises at the L2 and bounded these kernels).
+// LDS of one forward wavefront: the staged records, and per slot either its list position and
+// pixel rectangle (per-lane lists) or its coverage of each row group (block-uniform walk).
+template <int PX, bool kLanes>
+struct FwdLds {
+  float4 rec[PX > 1 ? 3 : 2][kWave];
+  uint32_t pos[kLanes ? kWave : 1];
+  uint2 rect[kLanes ? kWave : 1];
+  uint64_t cov[kLanes ? 1 : PX][kWave];
+};
+
 template <int PX, bool kPersistent, bool kLanes>
 __device__ __forceinline__ void raster_fwd_any(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
-                                               int lane, float4 (*s)[kWave], uint32_t* s_pos) {
+                                               int lane, FwdLds<PX, kLanes>& L) {
   unsigned long long pairs;
-  if constexpr (kLanes) pairs = raster_fwd_item_lanes<PX>(a, th, views, item, lane, s, s_pos);
-  else pairs = raster_fwd_item<PX>(a, th, views, item, lane, s);
+  if constexpr (kLanes) pairs = raster_fwd_item_lanes<PX>(a, th, views, item, lane, L.rec, L.pos, L.rect);
+  else pairs = raster_fwd_item<PX>(a, th, views, item, lane, L.rec, L.cov);
   if (lane == 0) a.stats[item] = pairs;
 }
 
 template <int PX, bool kPersistent, bool kLanes>
 __global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
-  __shared__ float4 s_rec[256 / kWave][kRecF4][kWave];
-  __shared__ uint32_t s_pos[kLanes ? 256 / kWave : 1][kWave];
+  __shared__ FwdLds<PX, kLanes> s_lds[256 / kWave];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
   const ViewDev* views = table_views(a.table);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -485,12 +555,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
     const int groups = (items + 3) / 4;
     for (int v = (int)blockIdx.x; v < groups; v += (int)gridDim.x) {
       const int item = xcd_remap(v, groups) * 4 + w;
-      if (item < items)
-        raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w], s_pos[kLanes ? w : 0]);
+      if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_lds[w]);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
-    if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_rec[w], s_pos[kLanes ? w : 0]);
+    if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_lds[w]);
   }
 }
 
@@ -547,89 +616,97 @@ __device__ inline float wave_reduce8_transpose(const float (&g)[8], int lane) {
   return r;  // lanes with (lane & 7) == 0 hold the sum of g[lane >> 3]
 }
 
-// One record's adjoint over a lane's PX pixels (summed into gr); `valid` = false is a no-op.
-// Returns (wave-uniformly) whether any pixel of the wavefront composited it.
+// One record's adjoint over a lane's PX pixels, summed into gr.  Returns (wave-uniformly) whether
+// any pixel of the wavefront composited it.  a = s[0][j], b = s[1][j].
 // cov[k]: the record's pixel-rectangle coverage of row group k (bit = lane), wave-uniform; the
 // lane masks stay on the scalar unit and reach the per-lane selects as masks (inverse ballot).
+// Per composited pixel, with q = dL/d(ln alpha) (0 where alpha is clamped at alpha_max) and the
+// record's w = k L (dx, dy), the geometry sums are {q w1, q w2, q w1 dx, q w1 dy, q w2 dy}: the
+// factors constant over the Gaussian (L, -2 ln 2) are applied once per face-view by the face
+// backward, which turns these sums into the mean and conic gradients.  Then the colour sums
+// alpha T g_C.
 template <int PX>
-__device__ __forceinline__ bool bwd_eval(const float4& a0, const float4& a1, const float4& a2, const uint64_t (&cov)[PX],
-                                         uint32_t prel, float px, const int (&y)[PX], float amin, float amax,
-                                         const float (&gc0)[PX], const float (&gc1)[PX], const float (&gc2)[PX],
-                                         const float (&K)[PX], const uint32_t (&last)[PX], float (&T)[PX],
-                                         float (&S)[PX], float (&gr)[8], unsigned long long& pairs) {
-#pragma unroll
-  for (int i = 0; i < 8; ++i) gr[i] = 0.f;
+__device__ __forceinline__ bool bwd_eval(const float4& a, const float4& b, const float (&oy)[PX],
+                                         const uint64_t (&cov)[PX], uint32_t prel, float lxf, float lyf, float amin,
+                                         float amax, const float (&gc0)[PX], const float (&gc1)[PX],
+                                         const float (&gc2)[PX], const float (&K)[PX], const uint32_t (&last)[PX],
+                                         float (&T)[PX], float (&S)[PX], float (&gr)[8], unsigned long long& pairs) {
   bool contrib = false;  // wave-uniform: some pixel composited the Gaussian
-  const float dx = (a0.x - px) + a0.z;
+  const float dx = a.x - lxf;
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     // wave-uniform skips: no pixel of the row group inside the extent (before its stop), or none
     // whose alpha reaches the cutoff -- then T, S and every partial are unchanged
     const uint64_t actm = cov[k] & __ballot(prel < last[k]);
     if (actm == 0ull) continue;
-    const float dy = (a0.y - ((float)y[k] + 0.5f)) + a0.w;
+    const float dy = oy[k] - lyf;
     float w1, w2;
-    const float e = gauss_exp(a1, dx, dy, w1, w2);
-    const float al = fminf(amax, e);
+    const float e = gauss_exp(a.z, a.w, b.x, dx, dy, w1, w2);
+    const float al = __builtin_amdgcn_fmed3f(e, 0.f, amax);  // min(e, amax): e is in [0, 1]
     const uint64_t okm = actm & __ballot(al >= amin);  // ballot of the compare alone stays a scalar mask
     if (okm == 0ull) continue;
     const bool ok = __builtin_amdgcn_inverse_ballot_w64(okm);
-    contrib = true;
     pairs += (unsigned long long)__popcll(okm);  // wave-uniform, scalar unit
     const float rom = __builtin_amdgcn_rcpf(1.f - al);  // 1 - al >= 1 - alpha_max > 0
     const float Tk = T[k] * rom;
-    const float cg = fmaf(a2.x, gc0[k], fmaf(a2.y, gc1[k], a2.z * gc2[k]));
+    const float cg = fmaf(b.y, gc0[k], fmaf(b.z, gc1[k], b.w * gc2[k]));
     const float dal = Tk * cg - (S[k] + K[k]) * rom;
     const float wt = ok ? al * Tk : 0.f;
     S[k] = fmaf(wt, cg, S[k]);
     T[k] = ok ? Tk : T[k];
-    const float dpow = (ok && e < amax) ? e * dal : 0.f;
-    // d/d(l11, l12 | l22 rows of the scaled factor) and d/d(conic) partials, as FMAs into the sums:
-    // -dpow 2 ln2 (l11 w1, l12 w1 + l22 w2) and -dpow / 2 (dx^2, 2 dx dy, dy^2)
-    const float qn = dpow * -kTwoLn2;
-    const float h = -0.5f * dpow, t = h * dx;
-    gr[0] = fmaf(qn, a1.x * w1, gr[0]);
-    gr[1] = fmaf(qn, fmaf(a1.y, w1, a1.z * w2), gr[1]);
-    gr[2] = fmaf(t, dx, gr[2]);
-    gr[3] = fmaf(t + t, dy, gr[3]);
-    gr[4] = fmaf(h * dy, dy, gr[4]);
-    gr[5] = fmaf(wt, gc0[k], gr[5]);
-    gr[6] = fmaf(wt, gc1[k], gr[6]);
-    gr[7] = fmaf(wt, gc2[k], gr[7]);
+    const float q = (ok && e < amax) ? e * dal : 0.f;
+    const float qw1 = q * w1, qw2 = q * w2;
+    if constexpr (PX == 1) {  // one pixel per lane: the partials are the values (gr enters as 0)
+      gr[0] = qw1;
+      gr[1] = qw2;
+      gr[2] = qw1 * dx;
+      gr[3] = qw1 * dy;
+      gr[4] = qw2 * dy;
+      gr[5] = wt * gc0[k];
+      gr[6] = wt * gc1[k];
+      gr[7] = wt * gc2[k];
+    } else {
+      gr[0] += qw1;
+      gr[1] += qw2;
+      gr[2] = fmaf(qw1, dx, gr[2]);
+      gr[3] = fmaf(qw1, dy, gr[3]);
+      gr[4] = fmaf(qw2, dy, gr[4]);
+      gr[5] = fmaf(wt, gc0[k], gr[5]);
+      gr[6] = fmaf(wt, gc1[k], gr[6]);
+      gr[7] = fmaf(wt, gc2[k], gr[7]);
+    }
+    contrib = true;
   }
   return contrib;
 }
 
 struct BwdLds {
-  float4 (*rec)[kWave];   // [3][64] staged records
+  float4 (*rec)[kWave];   // [3][64] staged records (stage_record)
   uint32_t* id;           // [64] their face-view ids
   uint64_t (*cov)[kWave]; // [PX][64] their coverage of each row group of the block (bit = lane)
 };
-
-// A wave-uniform 64-bit value from LDS into scalar registers.
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return (uint64_t)lo | ((uint64_t)hi << 32);
-}
 
 // Block-uniform walk of one staged batch: every record is evaluated by the whole wavefront, two
 // per round, and its 8 partial sums are reduced across the wavefront.
 template <int PX>
 __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds& L, uint64_t m, int64_t hi,
-                                                  uint32_t start, const ItemGeo& g, float px, const int (&y)[PX],
-                                                  float amin, float amax, const float (&gc0)[PX],
-                                                  const float (&gc1)[PX], const float (&gc2)[PX], const float (&K)[PX],
+                                                  uint32_t start, float lxf, float lyf, float amin, float amax,
+                                                  const float (&gc0)[PX], const float (&gc1)[PX],
+                                                  const float (&gc2)[PX], const float (&K)[PX],
                                                   const uint32_t (&last)[PX], float (&T)[PX], float (&S)[PX],
                                                   unsigned long long& pairs, int lane) {
-  float4 (*s)[kWave] = L.rec;
+  const float4 (*s)[kWave] = L.rec;
   while (m) {
     const int j1 = __builtin_ctzll(m);
     m &= m - 1;
     const bool has2 = m != 0ull;
     const int j2 = has2 ? __builtin_ctzll(m) : j1;
     m &= m - (has2 ? 1ull : 0ull);
-    const float4 a0 = s[0][j1], a1 = s[1][j1], a2 = s[2][j1];
-    const float4 b0 = s[0][j2], b1 = s[1][j2], b2 = s[2][j2];
+    const float4 a1 = s[0][j1], b1 = s[1][j1];
+    const float4 a2 = s[0][j2], b2 = s[1][j2];
+    float oy1[PX], oy2[PX];
+    staged_oy<PX>(s, j1, a1, oy1);
+    staged_oy<PX>(s, j2, a2, oy2);
     const uint32_t id1 = L.id[j1], id2 = L.id[j2];
     uint64_t cv1[PX], cv2[PX];
 #pragma unroll
@@ -638,9 +715,11 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
       cv2[k] = has2 ? uniform64(L.cov[k][j2]) : 0ull;
     }
     float gr[8], gq[8];
-    const bool c1 = bwd_eval<PX>(a0, a1, a2, cv1, (uint32_t)(hi - 1 - j1 - (int64_t)start), px, y, amin, amax,
+#pragma unroll
+    for (int i = 0; i < 8; ++i) gr[i] = gq[i] = 0.f;
+    const bool c1 = bwd_eval<PX>(a1, b1, oy1, cv1, (uint32_t)(hi - 1 - j1 - (int64_t)start), lxf, lyf, amin, amax,
                                  gc0, gc1, gc2, K, last, T, S, gr, pairs);
-    const bool c2 = bwd_eval<PX>(b0, b1, b2, cv2, (uint32_t)(hi - 1 - j2 - (int64_t)start), px, y, amin, amax,
+    const bool c2 = bwd_eval<PX>(a2, b2, oy2, cv2, (uint32_t)(hi - 1 - j2 - (int64_t)start), lxf, lyf, amin, amax,
                                  gc0, gc1, gc2, K, last, T, S, gq, pairs);
     if (c1) {
       const float r = wave_reduce8_transpose(gr, lane);
@@ -724,7 +803,7 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   for (int d = kWave / 2; d > 0; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
   mx = __builtin_amdgcn_readfirstlane(mx);
   if (mx == 0) return make_float4(loss, loss_sil, 0.f, 0.f);
-  const float px = (float)g.x + 0.5f;
+  const float lxf = (float)(lane & 7), lyf = (float)ly;
   const float amin = a.o.alpha_min, amax = a.o.alpha_max;
   // power above which exp2(-power) < alpha_min, with a 2 % margin for rounding
   const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;
@@ -743,13 +822,13 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
     }
     const uint64_t m = __ballot(ov);
     if (m == 0ull) continue;
-    L.rec[0][lane] = r0; L.rec[1][lane] = r1; L.rec[2][lane] = r2;
+    stage_record<PX>(L.rec, lane, r0, r1, r2, g.bx0, g.by0);
     L.id[lane] = id;
 #pragma unroll
     for (int k = 0; k < PX; ++k)
       L.cov[k][lane] = ov ? block_coverage(f2u(r1.w), f2u(r2.w), g.bx0, g.by0 + kSub * k) : 0ull;
     wave_lds_sync();
-    bwd_batch_uniform<PX>(a, L, m, hi, start, g, px, y, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
+    bwd_batch_uniform<PX>(a, L, m, hi, start, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
     wave_lds_sync();
   }
   return make_float4(loss, loss_sil, u2f((uint32_t)pairs), u2f((uint32_t)(pairs >> 32)));
@@ -757,7 +836,7 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
 
 template <int PX, bool kPersistent, bool kL2>
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
-  __shared__ float4 s_rec[256 / kWave][kRecF4][kWave];
+  __shared__ float4 s_rec[256 / kWave][PX > 1 ? 3 : 2][kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
   __shared__ uint64_t s_cov[256 / kWave][PX][kWave];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
