@@ -41,19 +41,13 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # (tile, pixels per lane, raster mode, lane lists); `src` is source_hash of the kernel's code when the
 # counters were taken, and changed code reports null.
 TRAFFIC = {
-    ("icosphere_s5_8x512", "raster_bwd", "16x16", 1, 0, 1):
-        {"fetch": 77195673, "write": 27981786, "src": "80be7ac0ca925fd5"},
-    ("icosphere_s5_8x512", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 76693617, "write": 27985865, "src": "80be7ac0ca925fd5"},
-    ("icosphere_s5_8x512", "raster_bwd", "32x32", 1, 0, 1):
-        {"fetch": 76322635, "write": 27989156, "src": "80be7ac0ca925fd5"},
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 16435307360, "write": 1787913690, "src": "80be7ac0ca925fd5"},
+        {"fetch": 16542268098, "write": 1800893756, "src": "0b34306c2db47733"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
                 "project": "k_project.hip", "scan_emit": "k_bin.hip", "face_bwd": "k_grad.hip",
-                "vertex_gather": "k_grad.hip", "fill": "k_grad.hip"}
+                "vertex_gather": "k_grad.hip", "fill": "k_grad.hip", "build_small": "k_project.hip"}
 
 
 def source_hash(stage):
@@ -176,6 +170,8 @@ def byte_model(stage, F, FV, V, P, I, tiles):
         "face_bwd": F * (12 + 36 + 48) + FV * 32,
         "vertex_gather": V * 4 + 3 * F * (4 + 12 + 12) + V * 24,
         "fill": FV * 32,
+        # the one-launch build of small batches: projection writes, then keys, values and ranges
+        "build_small": F * (12 + 36 + 36) + FV * (48 + 16 + 16) + I * 8 + tiles * 8,
     }.get(stage, 0)
 
 
