@@ -269,7 +269,8 @@ gmr_status gmr_profile_enable(gmr_handle h, int32_t enable);
  * the summed milliseconds and the number of timed launch groups; then discards the records.
  * Stages: project, scan_emit, sort_fv_pass (the depth passes over face-views), sort_pass (the
  * instance passes), tile_ranges, raster_fwd, fill, raster_bwd, face_bwd, vertex_gather (with the
- * fused-loss backwards' fixed-order loss sum).  max_stages must be >= 10. */
+ * fused-loss backwards' fixed-order loss sum), build_small (the one-launch list build of small
+ * batches, in place of the first five).  max_stages must be >= 11. */
 gmr_status gmr_profile_read(gmr_handle h, int32_t max_stages, char* names, float* ms_total, int32_t* launches,
                             int32_t* n_stages);
 

@@ -19,10 +19,10 @@ using namespace gmr;
 
 // Stages timed by gmr_profile_* (HIP events around each launch group on the call's stream).
 enum Stage { kStProject, kStScanEmit, kStSortFv, kStSortPass, kStRanges, kStRasterFwd, kStFill, kStRasterBwd,
-             kStFaceBwd, kStGather, kNumStages };
+             kStFaceBwd, kStGather, kStBuildSmall, kNumStages };
 static const char* kStageNames[kNumStages] = {"project",     "scan_emit",  "sort_fv_pass", "sort_pass",
                                               "tile_ranges", "raster_fwd", "fill",         "raster_bwd",
-                                              "face_bwd",    "vertex_gather"};
+                                              "face_bwd",    "vertex_gather", "build_small"};
 
 struct gmr_ctx {
   int device = 0;
@@ -350,6 +350,14 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   gmr_ctx* const th = timed ? h : nullptr;  // stage timing records events; untimed calls create none
   const KOpts ko = kopts(o);
   const Layout& L = p.L;
+  if (small_build_fits(p.fv_total, p.tiles_total, L.capacity, o->sh_degree)) {  // one launch builds it all
+    StageTimer t(th, s, kStBuildSmall);
+    const StatsInfo si{(uint32_t)p.items_total, (unsigned long long)L.statF, (unsigned long long)L.statB};
+    launch_build_small(table, verts, faces, colors, ko, w.rec, w.elA, w.hdr,
+                       zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.ranges, 2 * p.tiles_total, w.keysF,
+                       w.valsF, (uint32_t)L.capacity, si, s);
+    return;
+  }
   const uint32_t fv_words = (uint32_t)std::max(L.parts_fv, 1) * 256u;
   const uint32_t inst_words = (uint32_t)L.parts_inst * 512u;
   {
@@ -930,7 +938,8 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
   // recompute = 1), iters timed steps after a warm-up step.  On return o.instance_capacity holds
   // the measured count with 25 % headroom.
   auto time_cand = [&](gmr_options& o, float& ms_out_c) -> gmr_status {
-    for (int attempt = 0; attempt < 3; ++attempt) {
+    bool tightened = false;
+    for (int attempt = 0; attempt < 4; ++attempt) {
       Plan p;
       gmr_status r;
       if ((r = make_plan(batch, &o, true, p)) != GMR_OK) return r;
@@ -954,6 +963,14 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
         return r;
       gmr_counters c;
       if ((r = gmr_read_counters(ws, ws_cap, &c, s)) != GMR_OK) return r;
+      const int64_t tight = std::min<int64_t>((1ll << 30) - 1, (int64_t)(c.instances * 1.25) + 1024);
+      if (!c.overflow && !tightened && tight < o.instance_capacity) {
+        // time the candidate at the capacity it will run with (a small batch then takes the
+        // one-launch list build): plan again with the measured count plus headroom
+        o.instance_capacity = tight;
+        tightened = true;
+        continue;
+      }
       if (c.overflow) {
         o.instance_capacity = std::min<int64_t>((1ll << 30) - 1, (int64_t)(c.instances * 1.25) + 1024);
         continue;

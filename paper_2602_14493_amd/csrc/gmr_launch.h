@@ -16,6 +16,13 @@ void launch_project(const void* table, int64_t faces_total, const float* verts, 
                     uint64_t* bdesc, int64_t bdesc_n, uint32_t cap, const StatsInfo& si, int max_views,
                     hipStream_t s);
 
+// One-workgroup list build (small batches; see small_build_fits): projection, keys, sort, ranges.
+bool small_build_fits(int64_t fv_total, int64_t tiles_total, int64_t capacity, int sh_degree);
+void launch_build_small(const void* table, const float* verts, const int32_t* faces, const float* colors,
+                        const KOpts& o, float4* rec, uint4* el, WsHdr* hdr, float4* dfv_zero, uint32_t* ranges,
+                        int64_t ranges_words, uint32_t* keys, uint32_t* vals, uint32_t cap, const StatsInfo& si,
+                        hipStream_t s);
+
 // One-pass scan of tiles-touched and emission of the instances (nb blocks of kScanBlock * items
 // face-views); writes the instance count and overflow flag.
 void launch_bin(const void* table, const uint4* el_a, const uint4* el_b, int64_t n, int items, uint64_t* bdesc, int nb,

@@ -206,7 +206,19 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
           if (pos < cap) {
             const uint32_t tile = L.t0[src] + ty * (nt >> 16) + (uint32_t)r;
             inst[pos] = make_uint2(tile, L.fv[src]);
-            for (int q = 0; q < tp.n; ++q) atomicAdd(&s_h[q][(tile >> tp.shift[q]) & tp.mask[q]], 1u);
+            for (int q = 0; q < tp.n; ++q) {
+              const uint32_t dg = (tile >> tp.shift[q]) & tp.mask[q];
+              if (q == 0) {  // the low digit of a run of neighbouring tiles: spread over the bins
+                atomicAdd(&s_h[q][dg], 1u);
+              } else {
+                // higher digits: the window's tiles mostly share them, and same-address LDS atomics
+                // serialise -- the lanes holding the first active lane's digit add once
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+                const uint64_t same = __ballot(dg == d0);
+                if (dg != d0) atomicAdd(&s_h[q][dg], 1u);
+                else if (lane == __builtin_ctzll(same)) atomicAdd(&s_h[q][d0], (uint32_t)__popcll(same));
+              }
+            }
           }
         }
         wave_lds_sync();  // the next window (or round) rewrites the slots

@@ -18,6 +18,10 @@
 
 namespace gmr {
 
+// One-workgroup list build for small batches: at most kSmallThreads * kSmallPer face-views and
+// kSmallInst instances, keys (tile | depth | face-view) with the face-view in kSmallFvBits bits.
+constexpr int kSmallThreads = 1024, kSmallPer = 4, kSmallInst = 8192, kSmallFvBits = 14;
+
 // SHD > 0: view-dependent colour of degree SHD (colours hold (SHD + 1)^2 coefficients per
 // channel and vertex); SHD = 0: Eq. 16.
 template <int SHD>
@@ -100,8 +104,23 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
       }
     }
     el[fv] = e;
+    if (s_h) {  // the sort's digit histograms (the one-workgroup build below needs none)
 #pragma unroll
-    for (int p = 0; p < kDepthPasses; ++p) atomicAdd(&s_h[p * 256 + ((e.x >> (8 * p)) & 255u)], 1u);
+      for (int p = 0; p < kDepthPasses; ++p) {
+        const uint32_t dg = (e.x >> (8 * p)) & 255u;
+        if (p < 2) {  // low digits: spread over the bins
+          atomicAdd(&s_h[p * 256 + dg], 1u);
+        } else {
+          // high digits: neighbouring faces share them, and same-address LDS atomics serialise --
+          // the lanes holding the first active lane's digit add once, with their count
+          const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+          const uint64_t same = __ballot(dg == d0);
+          if (dg != d0) atomicAdd(&s_h[p * 256 + dg], 1u);
+          else if ((__lane_id() & (kWave - 1)) == (uint32_t)__builtin_ctzll(same))
+            atomicAdd(&s_h[p * 256 + d0], (uint32_t)__popcll(same));
+        }
+      }
+    }
     if (dfv_zero) {
       dfv_zero[2 * fv] = make_float4(0.f, 0.f, 0.f, 0.f);
       dfv_zero[2 * fv + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -186,6 +205,134 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
       hdr->key_hi_max[c] = 0u;
     }
   }
+}
+
+// One-workgroup list build for small batches (every face-view and instance fits the workgroup's
+// LDS): the same projection, then the instances' (tile | depth | face-view) keys -- tile id in the
+// top kSmallTileBits bits, the float32 depth bits, the face-view in the low kSmallFvBits bits --
+// sorted in LDS by a bitonic network, and the tile ranges.  Sorting that key orders the instances
+// by (tile, depth, face-view), the order the radix sort of the large path produces, so the lists
+// are identical; one launch replaces the prologue, the projection, the depth passes, the emission,
+// the tile passes and the ranges, whose launch latencies dominate a small batch.  More instances
+// than cap: the overflow flag is set (count = the true total) and no list is written.
+__global__ __launch_bounds__(kSmallThreads) void k_build_small(const void* __restrict__ table,
+                                                               const float* __restrict__ verts,
+                                                               const int32_t* __restrict__ faces,
+                                                               const float* __restrict__ colors, KOpts o,
+                                                               float4* __restrict__ rec, uint4* __restrict__ el,
+                                                               WsHdr* __restrict__ hdr, float4* __restrict__ dfv_zero,
+                                                               uint32_t* __restrict__ ranges, int64_t ranges_words,
+                                                               uint32_t* __restrict__ keys_out,
+                                                               uint32_t* __restrict__ vals_out, uint32_t cap,
+                                                               StatsInfo si) {
+  __shared__ uint64_t s_key[kSmallInst];
+  __shared__ uint32_t s_wsum[kSmallThreads / kWave];
+  const TableHdr* th = static_cast<const TableHdr*>(table);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int64_t nfv = th->fv_total;
+  for (int64_t i = tid; i < ranges_words; i += kSmallThreads) ranges[i] = 0u;  // empty tiles keep [0, 0)
+  if (tid == 0) {
+    hdr->capacity = cap;
+    hdr->stats_items = si.items;
+    hdr->bwd_stats = 0u;
+    hdr->stats_fwd_off = si.fwd_off;
+    hdr->stats_bwd_off = si.bwd_off;
+    hdr->red_ticket = 0u;
+  }
+  // 1. projection: records to the workspace, elements {depth bits, fv, first tile, nx | ny << 16}
+  {
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+    for (int64_t f = tid; f < th->faces_total; f += kSmallThreads)
+      project_face<0>(th, table, verts, faces, colors, o, rec, el, nullptr, kmin, kmax, dfv_zero, f, 0, 1);
+  }
+  __syncthreads();  // the elements (global, written by this workgroup) are visible to it
+  // 2. instance offsets: thread t owns face-views [t * kSmallPer, (t + 1) * kSmallPer)
+  uint4 e[kSmallPer];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int i = 0; i < kSmallPer; ++i) {
+    const int64_t fv = (int64_t)tid * kSmallPer + i;
+    e[i] = fv < nfv ? el[fv] : make_uint4(0xffffffffu, 0u, 0u, 0u);
+    cnt += (e[i].w & 0xffffu) * (e[i].w >> 16);
+  }
+  uint32_t inc = cnt;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, kWave);
+    if (lane >= d) inc += y;
+  }
+  if (lane == kWave - 1) s_wsum[w] = inc;
+  __syncthreads();
+  uint32_t base = inc - cnt, total = 0;
+  for (int k = 0; k < kSmallThreads / kWave; ++k) {
+    if (k < w) base += s_wsum[k];
+    total += s_wsum[k];
+  }
+  if (tid == 0) {
+    hdr->count = total;
+    hdr->overflow = total > cap ? 1u : 0u;
+    hdr->peak_count = max(hdr->peak_count, total);
+  }
+  if (total > cap) return;  // uniform: the host grows the capacity and builds again
+  // 3. keys
+  const ViewDev* views = table_views(table);
+#pragma unroll
+  for (int i = 0; i < kSmallPer; ++i) {
+    const uint32_t nx = e[i].w & 0xffffu, ny = e[i].w >> 16;
+    if (nx * ny == 0u) continue;
+    const uint32_t fv = e[i].y;
+    const uint32_t tiles_x = (uint32_t)views[find_view_by_fv(views, th->num_views, (int64_t)fv)].tiles_x;
+    const uint64_t low = ((uint64_t)e[i].x << kSmallFvBits) | fv;
+    for (uint32_t ty = 0; ty < ny; ++ty)
+      for (uint32_t tx = 0; tx < nx; ++tx)
+        s_key[base++] = ((uint64_t)(e[i].z + ty * tiles_x + tx) << (32 + kSmallFvBits)) | low;
+  }
+  uint32_t n2 = 64;  // the network's width: the next power of two >= total
+  while (n2 < total) n2 <<= 1;
+  for (uint32_t i = total + tid; i < n2; i += kSmallThreads) s_key[i] = ~0ull;
+  __syncthreads();
+  // 4. bitonic sort of s_key[0, n2): thread t compares pairs t, t + T, ... (T = kSmallThreads).  A
+  // stage of distance j <= 64 keeps every wavefront inside its own 128-key runs (keys 128 (w + 16 r)
+  // onwards), so two such stages in a row need only the wavefront in step; any stage that crosses
+  // runs, or is followed by one that does, ends with a workgroup barrier
+  for (uint32_t k = 2; k <= n2; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < n2 / 2; i += kSmallThreads) {
+        const uint32_t lo = ((i & ~(j - 1u)) << 1) | (i & (j - 1u)), hi = lo + j;
+        const uint64_t a = s_key[lo], b = s_key[hi];
+        if ((a > b) == ((lo & k) == 0u)) {
+          s_key[lo] = b;
+          s_key[hi] = a;
+        }
+      }
+      const uint32_t next_j = j > 1u ? j >> 1 : k;  // the next stage's distance (k: the next round's first)
+      if (j > (uint32_t)kWave || next_j > (uint32_t)kWave) __syncthreads();
+      else wave_lds_sync();
+    }
+  }
+  __syncthreads();
+  // 5. keys, values and the tile ranges
+  for (uint32_t i = tid; i < total; i += kSmallThreads) {
+    const uint64_t key = s_key[i];
+    const uint32_t tile = (uint32_t)(key >> (32 + kSmallFvBits));
+    keys_out[i] = tile;
+    vals_out[i] = (uint32_t)key & ((1u << kSmallFvBits) - 1u);
+    if (i == 0 || (uint32_t)(s_key[i - 1] >> (32 + kSmallFvBits)) != tile) ranges[2 * (size_t)tile] = i;
+    if (i + 1 == total || (uint32_t)(s_key[i + 1] >> (32 + kSmallFvBits)) != tile) ranges[2 * (size_t)tile + 1] = i + 1;
+  }
+}
+
+bool small_build_fits(int64_t fv_total, int64_t tiles_total, int64_t capacity, int sh_degree) {
+  return sh_degree == 0 && fv_total <= (int64_t)kSmallThreads * kSmallPer && fv_total < (1ll << kSmallFvBits) &&
+         tiles_total <= (1ll << (32 - kSmallFvBits)) && capacity <= kSmallInst;
+}
+
+void launch_build_small(const void* table, const float* verts, const int32_t* faces, const float* colors,
+                        const KOpts& o, float4* rec, uint4* el, WsHdr* hdr, float4* dfv_zero, uint32_t* ranges,
+                        int64_t ranges_words, uint32_t* keys, uint32_t* vals, uint32_t cap, const StatsInfo& si,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_build_small, dim3(1), dim3(kSmallThreads), 0, s, table, verts, faces, colors, o, rec, el, hdr,
+                     dfv_zero, ranges, ranges_words, keys, vals, cap, si);
 }
 
 void launch_project(const void* table, int64_t faces_total, const float* verts, const int32_t* faces,

@@ -112,13 +112,18 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
     const uint32_t idx = base + (uint32_t)w * (kItems * kWave) + (uint32_t)i * kWave + (uint32_t)lane;
     const bool have = idx < n;
     const uint32_t d = ((elem_key(e[i]) >> shift) - sub) & mask;
-    uint64_t peers = __ballot(have);
+    // lanes whose digit equals this lane's: per bit, keep the lanes whose bit agrees with ours --
+    // peers &= ~(ballot(bit) ^ (bit ? ~0 : 0)), on the two 32-bit halves (m = the bit sign-extended)
+    const uint64_t h = __ballot(have);
+    uint32_t plo = (uint32_t)h, phi = (uint32_t)(h >> 32);
 #pragma unroll
     for (int b = 0; b < kBits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
+      const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);
+      const uint64_t bb = __ballot(m != 0u);
+      plo &= ~((uint32_t)bb ^ m);
+      phi &= ~((uint32_t)(bb >> 32) ^ m);
     }
+    const uint64_t peers = (uint64_t)plo | ((uint64_t)phi << 32);
     const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
     uint32_t old = 0;
     if (have) old = s_wcnt[w][d];

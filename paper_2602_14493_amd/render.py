@@ -159,7 +159,9 @@ class Renderer:
         self.adj_ent = torch.from_numpy(ent).to(self.device)
         self._set_table()
         if self.opts.instance_capacity <= 0:
-            self.opts.instance_capacity = max(1 << 16, 4 * batch.num_faces * max(1, batch.c.num_views))
+            # a small first guess keeps small batches on the one-launch list build (the first
+            # forward measures the count and grows the capacity if it was too small)
+            self.opts.instance_capacity = max(1 << 12, 4 * batch.num_faces * max(1, batch.c.num_views))
             self.opts.instance_capacity = min(self.opts.instance_capacity, 1 << 26)
         self.capacity_checked = False
         self.ws = None

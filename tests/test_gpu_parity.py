@@ -273,6 +273,61 @@ def test_tile_lists_bit_exact(gpu, tile):
     assert checked > 100000
 
 
+def _two_mesh_small():
+    """Two small meshes, one with three views and one with a single view, interleaved in the view
+    order (1,212 face-views)."""
+    rng = np.random.default_rng(11)
+    va, fa = wl.icosphere(2)
+    vb, fb = wl.torus(14, 9, R=0.5, r=0.2)
+    va = va * 0.8 + rng.normal(0, 0.01, size=va.shape)
+    vb = vb + np.array([0.1, -0.05, 0.0]) + rng.normal(0, 0.01, size=vb.shape)
+    verts = np.concatenate([va, vb]).astype(np.float32)
+    faces = np.concatenate([fa, fb + len(va)]).astype(np.int32)
+    colors = rng.uniform(size=verts.shape).astype(np.float32)
+    cams = [wl.look_at_camera((0.0, 0.0, 3.0), width=96, height=80),
+            wl.look_at_camera((1.5, 1.0, 1.2), width=72, height=72),
+            wl.look_at_camera((-2.0, 0.5, 2.0), width=64, height=96),
+            wl.look_at_camera((0.3, -2.5, 1.0), width=80, height=64)]
+    return wl.Workload(name="two_mesh_small", verts=verts, faces=faces, colors=colors,
+                       vert_offsets=np.array([0, len(va), len(verts)], dtype=np.int64),
+                       face_offsets=np.array([0, len(fa), len(faces)], dtype=np.int64),
+                       view_mesh=np.array([0, 1, 0, 0], dtype=np.int32), cams=cams)
+
+
+@pytest.mark.parametrize("case", ["cfg1-8", "cfg1-16", "cfg1-32", "two-mesh"])
+def test_small_build_matches_radix_build(gpu, case):
+    """Small batches build their lists in one launch (an LDS bitonic sort of (tile | depth |
+    face-view) keys); with a capacity above that path's limit the same batch takes the radix-sort
+    path.  Both must give the same tile lists (bit for bit), the same images and saved state, and
+    the same gradients (up to the order of the raster backward's float atomics); a capacity far
+    too small overflows on the one-launch path and the protocol grows it."""
+    import torch
+    import paper_2602_14493_amd as gmr
+    if case == "two-mesh":
+        W, tw = _two_mesh_small(), 16
+    else:
+        W, tw = wl.make_workload(1), int(case.split("-")[1])
+    say(f"one-launch vs radix list build: {case}")
+    r_s, verts, colors = gpu_setup(W, tile_w=tw, tile_h=tw, instance_capacity=256)
+    r_b, _, _ = gpu_setup(W, tile_w=tw, tile_h=tw, instance_capacity=1 << 16)
+    a = r_s.forward(verts, colors, check=True)      # overflows at 256 and grows
+    b = r_b.forward(verts, colors, check=True)
+    cs, cb = r_s.counters(a[3]), r_b.counters(b[3])
+    say(f"instances {cs.instances} (capacity {cs.capacity}) vs {cb.instances} (capacity {cb.capacity})")
+    assert cs.capacity <= 8192 < cb.capacity and cs.instances == cb.instances and not cs.overflow
+    ls, lb = workspace_lists(r_s, a[3]), workspace_lists(r_b, b[3])
+    assert np.array_equal(ls[0], lb[0])
+    n = cs.instances
+    assert np.array_equal(ls[1][:n], lb[1][:n])
+    for x, y in zip(a[:3], b[:3]):
+        assert torch.equal(x, y)
+    g = torch.randn_like(a[0])
+    dV1, dC1 = r_s.backward(verts, colors, g, None, a[2], a[3], recompute=True)
+    dV2, dC2 = r_b.backward(verts, colors, g, None, b[2], b[3], recompute=True)
+    compare_grads(dV1, to_np(dV2), f"{case} dV", rel=1e-5)
+    compare_grads(dC1, to_np(dC2), f"{case} dC", rel=1e-5)
+
+
 def test_tile_lists_and_image_wide_depth_range(gpu):
     """A camera 0.3 units from the surface and one at radius 3: the visible depths span 0.3 .. 4,
     more than the 256 values of the high 16 key bits that let the depth sort take three passes, so
