@@ -616,6 +616,24 @@ __device__ inline float wave_reduce8_transpose(const float (&g)[8], int lane) {
   return r;  // lanes with (lane & 7) == 0 hold the sum of g[lane >> 3]
 }
 
+// The same sum through the wavefront's 8 x 64 LDS scratch: row i takes value i of every lane, lane l
+// adds the eight entries of row l >> 3 that lanes 8 (l & 7) .. 8 (l & 7) + 7 wrote, and three DPP
+// steps add the eight lanes of each row group: 8 stores, 2 loads and 10 adds where the exchanges
+// cost 7 lane swaps, 7 adds and 2 selects.
+__device__ inline float wave_reduce8_lds(const float (&g)[8], int lane, float* red) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) red[i * kWave + lane] = g[i];
+  wave_lds_sync();
+  const float4* p = reinterpret_cast<const float4*>(red + (lane >> 3) * kWave + 8 * (lane & 7));
+  const float4 x = p[0], y = p[1];
+  wave_lds_sync();  // a later reduction's stores stay behind these loads
+  float r = ((x.x + x.y) + (x.z + x.w)) + ((y.x + y.y) + (y.z + y.w));
+  r = add_dpp<kDppXor1>(r, r);        // lane ^ 1
+  r = add_dpp<kDppXor2>(r, r);        // lane ^ 2
+  r = add_dpp<kDppHalfMirror>(r, r);  // the other quad of the eight
+  return r;  // lanes 8i .. 8i + 7 hold the sum of g[i]
+}
+
 // One record's adjoint over a lane's PX pixels, summed into gr.  Returns (wave-uniformly) whether
 // any pixel of the wavefront composited it.  a = s[0][j], b = s[1][j].
 // cov[k]: the record's pixel-rectangle coverage of row group k (bit = lane), wave-uniform; the
@@ -625,12 +643,17 @@ __device__ inline float wave_reduce8_transpose(const float (&g)[8], int lane) {
 // factors constant over the Gaussian (L, -2 ln 2) are applied once per face-view by the face
 // backward, which turns these sums into the mean and conic gradients.  Then the colour sums
 // alpha T g_C.
-template <int PX>
-__device__ __forceinline__ bool bwd_eval(const float4& a, const float4& b, const float (&oy)[PX],
+template <int PX, typename Emit>
+__device__ __forceinline__ void bwd_eval(const float4& a, const float4& b, const float (&oy)[PX],
                                          const uint64_t (&cov)[PX], uint32_t prel, float lxf, float lyf, float amin,
                                          float amax, const float (&gc0)[PX], const float (&gc1)[PX],
                                          const float (&gc2)[PX], const float (&K)[PX], const uint32_t (&last)[PX],
-                                         float (&T)[PX], float (&S)[PX], float (&gr)[8], unsigned long long& pairs) {
+                                         float (&T)[PX], float (&S)[PX], unsigned long long& pairs, Emit&& emit) {
+  float gr[8];
+  if constexpr (PX > 1) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) gr[i] = 0.f;
+  }
   bool contrib = false;  // wave-uniform: some pixel composited the Gaussian
   const float dx = a.x - lxf;
 #pragma unroll
@@ -665,6 +688,7 @@ __device__ __forceinline__ bool bwd_eval(const float4& a, const float4& b, const
       gr[5] = wt * gc0[k];
       gr[6] = wt * gc1[k];
       gr[7] = wt * gc2[k];
+      emit(gr);  // on this path only: a skipped record leaves nothing to reduce
     } else {
       gr[0] += qw1;
       gr[1] += qw2;
@@ -677,13 +701,16 @@ __device__ __forceinline__ bool bwd_eval(const float4& a, const float4& b, const
     }
     contrib = true;
   }
-  return contrib;
+  if constexpr (PX > 1) {
+    if (contrib) emit(gr);
+  }
 }
 
 struct BwdLds {
   float4 (*rec)[kWave];   // [3][64] staged records (stage_record)
   uint32_t* id;           // [64] their face-view ids
   uint64_t (*cov)[kWave]; // [PX][64] their coverage of each row group of the block (bit = lane)
+  float* red;             // [8 * 64] the gradient reduction's scratch
 };
 
 // Block-uniform walk of one staged batch: every record is evaluated by the whole wavefront, two
@@ -701,7 +728,7 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
     m &= m - 1;
     const bool has2 = m != 0ull;
     const int j2 = has2 ? __builtin_ctzll(m) : j1;
-    m &= m - (has2 ? 1ull : 0ull);
+    m &= m - 1;  // m = 0 stays 0
     const float4 a1 = s[0][j1], b1 = s[1][j1];
     const float4 a2 = s[0][j2], b2 = s[1][j2];
     float oy1[PX], oy2[PX];
@@ -714,21 +741,17 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
       cv1[k] = uniform64(L.cov[k][j1]);
       cv2[k] = has2 ? uniform64(L.cov[k][j2]) : 0ull;
     }
-    float gr[8], gq[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) gr[i] = gq[i] = 0.f;
-    const bool c1 = bwd_eval<PX>(a1, b1, oy1, cv1, (uint32_t)(hi - 1 - j1 - (int64_t)start), lxf, lyf, amin, amax,
-                                 gc0, gc1, gc2, K, last, T, S, gr, pairs);
-    const bool c2 = bwd_eval<PX>(a2, b2, oy2, cv2, (uint32_t)(hi - 1 - j2 - (int64_t)start), lxf, lyf, amin, amax,
-                                 gc0, gc1, gc2, K, last, T, S, gq, pairs);
-    if (c1) {
-      const float r = wave_reduce8_transpose(gr, lane);
-      if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id1 + (lane >> 3), r);
-    }
-    if (c2) {
-      const float r = wave_reduce8_transpose(gq, lane);
-      if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id2 + (lane >> 3), r);
-    }
+    // a composited record's 8 sums, reduced over the wavefront: lanes 8i hold sum i
+    auto emit = [&](uint32_t id) {
+      return [&, id](const float (&g)[8]) {
+        const float r = wave_reduce8_lds(g, lane, L.red);
+        if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id + (lane >> 3), r);
+      };
+    };
+    bwd_eval<PX>(a1, b1, oy1, cv1, (uint32_t)(hi - 1 - j1 - (int64_t)start), lxf, lyf, amin, amax, gc0, gc1, gc2, K,
+                 last, T, S, pairs, emit(id1));
+    bwd_eval<PX>(a2, b2, oy2, cv2, (uint32_t)(hi - 1 - j2 - (int64_t)start), lxf, lyf, amin, amax, gc0, gc1, gc2, K,
+                 last, T, S, pairs, emit(id2));
   }
 }
 
@@ -839,10 +862,11 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   __shared__ float4 s_rec[256 / kWave][PX > 1 ? 3 : 2][kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
   __shared__ uint64_t s_cov[256 / kWave][PX][kWave];
+  __shared__ float s_red[256 / kWave][8 * kWave];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
   const ViewDev* views = table_views(a.table);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const BwdLds L{s_rec[w], s_id[w], s_cov[w]};
+  const BwdLds L{s_rec[w], s_id[w], s_cov[w], s_red[w]};
   const int items = th->items_total;
   if (kPersistent) {
     const int groups = (items + 3) / 4;  // grid-stride, as in the forward
