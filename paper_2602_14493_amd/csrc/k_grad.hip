@@ -64,15 +64,23 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
     vj[a] = verts[3 * (int64_t)i1 + a];
     vk[a] = verts[3 * (int64_t)i2 + a];
   }
-  FaceGeo g;
   float4* out = fgrad + 3 * f;
-  if (!face_convert(vi, vj, vk, o.cov_mode, g)) {  // uniform over the face's group
-    if (u == 0) {
-      out[0] = out[1] = out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if constexpr (SHD > 0)
-        for (int k = 0; k < 3 * K; ++k) fsh[3 * K * f + k] = 0.f;
+  // only the mean and covariance stay live through the view loop; the rest of the conversion is
+  // recomputed after it (fewer registers held across the loop's FP64 work)
+  double mu[3], Sg[6];
+  {
+    FaceGeo g0;
+    const bool ok = face_convert(vi, vj, vk, o.cov_mode, g0);
+    for (int a = 0; a < 3; ++a) mu[a] = g0.mu[a];
+    for (int a = 0; a < 6; ++a) Sg[a] = g0.S[a];
+    if (!ok) {  // uniform over the face's group
+      if (u == 0) {
+        out[0] = out[1] = out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (SHD > 0)
+          for (int k = 0; k < 3 * K; ++k) fsh[3 * K * f + k] = 0.f;
+      }
+      return;
     }
-    return;
   }
   float coef[K][3], gsh[K][3];
   if constexpr (SHD > 0) {
@@ -81,7 +89,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
     for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
   }
   double Gmu[3] = {0.0, 0.0, 0.0};
-  double GS[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  double GS6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // G_Sigma (symmetric): xx xy xz yy yz zz
   float gcol[3] = {0.f, 0.f, 0.f};
   for (int k = mvo[m] + u; k < mvo[m + 1]; k += LPF) {
     const ViewDev& V = views[mvs[k]];
@@ -95,7 +103,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
     } else {
       double cc[3];
       view_centre(V.R, V.t, cc);
-      const double px = g.mu[0] - cc[0], py = g.mu[1] - cc[1], pz = g.mu[2] - cc[2];
+      const double px = mu[0] - cc[0], py = mu[1] - cc[1], pz = mu[2] - cc[2];
       const double ir = 1.0 / sqrt(px * px + py * py + pz * pz);
       const double x = px * ir, y = py * ir, z = pz * ir;
       double Y[K];
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
       Gmu[2] += (gz - z * dd) * ir;
     }
     ProjGeo q;
-    if (!view_project(V, g.mu, g.S, (double)o.dilation, q)) continue;
+    if (!view_project(V, mu, Sg, (double)o.dilation, q)) continue;
     // the rasteriser's sums over the face-view's pixels, {A, B, C, D, E} = sum of gq {w1, w2,
     // w1 dx, w1 dy, w2 dy} with gq = dL/d(ln alpha) and w = k L (dx, dy), L the conic's Cholesky
     // factor (k^2 = log2(e) / 2, the record's scale): exp2(-|w|^2) = exp(-d^T Q d / 2), so
@@ -167,8 +175,10 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
     double GWR[3][3];
     for (int r = 0; r < 3; ++r)
       for (int cc = 0; cc < 3; ++cc) GWR[r][cc] = GW[r][0] * R[0][cc] + GW[r][1] * R[1][cc] + GW[r][2] * R[2][cc];
-    for (int r = 0; r < 3; ++r)
-      for (int cc = 0; cc < 3; ++cc) GS[r][cc] += R[0][r] * GWR[0][cc] + R[1][r] * GWR[1][cc] + R[2][r] * GWR[2][cc];
+    // R^T G_W R is symmetric (G_W is): its upper triangle
+    for (int r = 0, i6 = 0; r < 3; ++r)
+      for (int cc = r; cc < 3; ++cc, ++i6)
+        GS6[i6] += R[0][r] * GWR[0][cc] + R[1][r] * GWR[1][cc] + R[2][r] * GWR[2][cc];
     // G_p from J(p) and (u, v)(p)
     const double x = q.p[0], y = q.p[1], iz = 1.0 / q.p[2];
     const double fx = V.fx, fy = V.fy;
@@ -186,18 +196,24 @@ __global__ __launch_bounds__(256) void k_face_bwd(const void* __restrict__ table
       for (int r = 0; r < 3; ++r) {
         Gmu[r] += __shfl_xor(Gmu[r], d, kWave);
         gcol[r] += __shfl_xor(gcol[r], d, kWave);
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) GS[r][cc] += __shfl_xor(GS[r][cc], d, kWave);
       }
+#pragma unroll
+      for (int i6 = 0; i6 < 6; ++i6) GS6[i6] += __shfl_xor(GS6[i6], d, kWave);
     }
     if (u != 0) return;
   }
-  // symmetrise (G_Sigma is symmetric up to rounding)
-  for (int r = 0; r < 3; ++r)
-    for (int cc = r + 1; cc < 3; ++cc) {
-      const double s = 0.5 * (GS[r][cc] + GS[cc][r]);
-      GS[r][cc] = GS[cc][r] = s;
+  double GS[3][3];
+  sym3_from6(GS6, GS);
+  // the conversion again, from the vertices (read back: they were not kept in registers)
+  FaceGeo g;
+  {
+    for (int a = 0; a < 3; ++a) {
+      vi[a] = verts[3 * (int64_t)i0 + a];
+      vj[a] = verts[3 * (int64_t)i1 + a];
+      vk[a] = verts[3 * (int64_t)i2 + a];
     }
+    face_convert(vi, vj, vk, o.cov_mode, g);
+  }
   const double* e1 = g.e1;
   const double* e2 = g.e2;
   double Ge1[3], Ge2[3];

@@ -207,6 +207,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(const E* __restrict__ i
     const E x = s_el[s];
     const uint32_t dd = ((elem_key(x) >> shift) - sub) & mask;
     const uint32_t g = s_gbase[dd] + (s - s_bstart[dd]);
+    if (g >= n) continue;  // only if the histogram disagreed with n: never write past the input's size
     if constexpr (kSplit) {
       out_k[g] = elem_key(x);
       out_v[g] = reinterpret_cast<const uint32_t*>(&x)[1];

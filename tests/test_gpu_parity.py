@@ -458,6 +458,53 @@ def test_overflow_protocol(gpu):
     assert torch.equal(out, ref)
 
 
+def test_overflow_radix_lists_are_valid(gpu):
+    """Overflow on the radix path with two tile passes and a 512-bin first tile digit (8 views of
+    1024 x 1024, 8 x 8 tiles: 17 tile bits): what the build writes within the capacity is a valid
+    tile-sorted list of real instances with consistent ranges, i.e. the later passes sort exactly
+    the instances the emission placed and nothing lands past the capacity."""
+    import ctypes
+    import paper_2602_14493_amd as gmr
+    say("overflow on the radix path, cfg2 at 1024^2, 8x8 tiles")
+    W = wl.make_workload(2, scale=2.0)
+    r_full, verts, colors = gpu_setup(W, tile_w=8, tile_h=8)
+    _, _, _, ws_full = r_full.forward(verts, colors, check=True)
+    N = r_full.counters(ws_full).instances
+    C = N // 3
+    r, _, _ = gpu_setup(W, tile_w=8, tile_h=8, instance_capacity=C)
+    rgb, alpha, saved = r._alloc_outputs()
+    ws = r.new_workspace()
+    r.fwd_raw(verts, colors, rgb, alpha, saved, ws)
+    c = r.counters(ws)
+    say(f"  {N} instances, capacity {C}")
+    assert c.overflow and c.instances == N and c.capacity == C
+    ranges, vals = workspace_lists(r, ws)
+    nz = ranges[:, 1] > ranges[:, 0]
+    tiles = np.nonzero(nz)[0]
+    starts, ends = ranges[nz, 0].astype(np.int64), ranges[nz, 1].astype(np.int64)
+    # the non-empty ranges tile [0, C) in tile order
+    assert starts[0] == 0 and ends[-1] == C and np.array_equal(starts[1:], ends[:-1])
+    # every (tile, face-view) pair is an instance: the face-view's pixel rectangle meets the tile,
+    # in the tile's view; no pair twice
+    key = np.repeat(tiles, ends - starts).astype(np.int64)
+    fv = vals[:C].astype(np.int64)
+    assert fv.max() < W.num_views * len(W.faces)
+    ro, vo, rc, bo = (ctypes.c_size_t() for _ in range(4))
+    gmr._lib.call("gmr_workspace_view", ctypes.byref(r.batch.c), ctypes.byref(r.opts), ctypes.byref(ro),
+                  ctypes.byref(vo), ctypes.byref(rc), ctypes.byref(bo))
+    w = ws.cpu().numpy()
+    rec = w[rc.value:rc.value + 48 * W.num_views * len(W.faces)].view(np.uint32).reshape(-1, 12)
+    xr, yr = rec[fv, 7].astype(np.int64), rec[fv, 11].astype(np.int64)
+    per_view = 128 * 128
+    view_of_tile, local = key // per_view, key % per_view
+    ty, tx = local // 128, local % 128
+    v_fv, _ = fv_to_face(W)(fv)
+    assert np.array_equal(v_fv, view_of_tile)
+    assert np.all((xr & 0xFFFF) <= 8 * tx + 7) and np.all((xr >> 16) >= 8 * tx)
+    assert np.all((yr & 0xFFFF) <= 8 * ty + 7) and np.all((yr >> 16) >= 8 * ty)
+    assert len(np.unique(key * (1 << 32) + fv)) == C
+
+
 def test_edge_cases(gpu):
     """Camera looking away (no instances), odd image sizes, 1x1 image, a degenerate face (zero
     gradient), a mesh partly behind the camera."""
