@@ -42,7 +42,7 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # counters were taken, and changed code reports null.
 TRAFFIC = {
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 16542268098, "write": 1800893756, "src": "0b34306c2db47733"},
+        {"fetch": 16477506789, "write": 1800464237, "src": "f7b0ca731d6c0d7e"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
