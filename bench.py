@@ -47,7 +47,8 @@ TRAFFIC = {
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
                 "project": "k_project.hip", "scan_emit": "k_bin.hip", "face_bwd": "k_grad.hip",
-                "vertex_gather": "k_grad.hip", "fill": "k_grad.hip", "build_small": "k_project.hip"}
+                "vertex_gather": "k_grad.hip", "fill": "k_grad.hip", "build_small": "k_project.hip",
+                "raster_step": "k_raster.hip"}
 
 
 def source_hash(stage):
@@ -130,6 +131,8 @@ def parse():
                     help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-recon", action="store_true", help="skip timing the full reconstruction step")
+    ap.add_argument("--no-fused-step", action="store_true",
+                    help="skip timing the optimisation rendered with gmr_render_step_l2 (one list build per step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
@@ -235,6 +238,7 @@ def main():
 
     # ---- batched form ------------------------------------------------------------------------
     adam_runs = None
+    fused_step = None
     if use_graph:
         # the workload's optimiser: Adam on the vertices, lr 1e-3, betas (0.9, 0.999), eps 1e-8.
         # The whole optimisation run goes once, untimed, to size the instance capacity: the peak
@@ -347,6 +351,48 @@ def main():
                      "loss_final": float(loop.loss.item()), "peak_instances": int(max(adam_peak, c.peak_instances)),
                      "capacity": int(c.capacity), "lr": 1e-3, "graph": not args.no_graph}
         reset()
+        if not args.no_fused_step:
+            # the same optimisation rendered with gmr_render_step_l2: one list build per step, the
+            # compositing and its adjoint in one launch; first K steps from the start and the whole
+            # run, as above (reported beside the headline, which rebuilds the lists in the backward)
+            floop = gmr.GraphAdamLoop(r, verts, colors, target, lr=1e-3, recompute=True, fused=True)
+            if not args.no_graph:
+                floop.capture()
+            fstart = [t.clone() for t in floop._state()]
+
+            def freset():
+                for t, t0 in zip(floop._state(), fstart):
+                    t.copy_(t0)
+
+            def fstep():
+                floop._step_body() if args.no_graph else floop.graph.replay()
+            floop.overflow()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                fstep()
+            e1.record()
+            torch.cuda.synchronize()
+            ms_fk = e0.elapsed_time(e1) / args.steps
+            fruns = []
+            for _ in range(args.adam_runs):
+                freset()
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(args.adam_steps):
+                    fstep()
+                e1.record()
+                torch.cuda.synchronize()
+                fruns.append(e0.elapsed_time(e1) / args.adam_steps)
+            if floop.overflow():
+                raise RuntimeError("instance capacity overflowed during the fused-step runs")
+            fused_step = {"ms_per_step": round(ms_fk, 4), "Mpixel_per_s": round(P / (ms_fk * 1e-3) / 1e6, 2),
+                          "adam_ms_per_step_median": round(float(np.median(fruns)), 4),
+                          "loss_final": float(floop.loss.item()), "list_builds_per_step": 1,
+                          "entry_point": "gmr_render_step_l2", "graph": not args.no_graph}
+            progress(f"fused step: {ms_fk:.4f} ms/step (first {args.steps}), runs {[round(x, 4) for x in fruns]}")
+            del floop
+            reset()
 
     # ---- per-stage timing (HIP events on the library's stream), same steps ----------------------
     # (the Adam workload's state was reset to its start: these are again its first steps)
@@ -527,6 +573,7 @@ def main():
         "cpu_baseline": cpu,
         "per_view": per_view,
         "adam_optimisation": adam_runs,
+        "fused_step": fused_step,
         "recon_step": recon_step,
         "stages": stages,
         "wall_s": round(wall, 3),

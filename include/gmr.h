@@ -222,6 +222,23 @@ gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_opt
                              int32_t recompute_lists, float* d_verts_dev, float* d_colors_dev, float* loss_dev,
                              void* ws_dev, size_t ws_bytes, void* stream);
 
+/* One training step's rendering for the colour loss of Sec. 3.1, fused: gmr_render_fwd followed by
+ * gmr_render_bwd_l2 with one list build instead of the forward's and the backward's (the sorted
+ * lists live only inside this call, as with recompute_lists = 1, so nothing is saved for a later
+ * backward).  The compositing of Sec. 2.1 and its reverse-order adjoint run in one launch: each
+ * 8 x 8 pixel block composites its pixels and then differentiates them, since a pixel's L2
+ * upstream gradient needs only its own colour (px_per_lane 1 and the plain grid schedule; other
+ * options run the two compositing launches in turn after the one build).
+ * Writes out_rgb_dev, out_alpha_dev (may be NULL) and saved_dev as gmr_render_fwd does (bit for
+ * bit), and d_verts_dev, d_colors_dev and loss_dev (may be NULL) as gmr_render_bwd_l2 does (equal up
+ * to the order of the float atomics that sum each face-view's gradient).  Errors as those calls. */
+gmr_status gmr_render_step_l2(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table_dev,
+                              const float* verts_dev, const int32_t* faces_dev, const float* colors_dev,
+                              const float* target_dev, float loss_weight, float* out_rgb_dev, float* out_alpha_dev,
+                              void* saved_dev, const int32_t* adj_off_dev, const int32_t* adj_ent_dev,
+                              float* d_verts_dev, float* d_colors_dev, float* loss_dev, void* ws_dev,
+                              size_t ws_bytes, void* stream);
+
 /* The reconstruction objective's image terms (Sec. 3.1, Loss Functions): gmr_render_bwd_l2's colour
  * loss (weight color_weight) plus the silhouette loss, color_weight * MSE(rgb, target) +
  * sil_weight * mean over every pixel of every view of -(s log a + (1 - s) log(1 - a)), with
@@ -270,7 +287,8 @@ gmr_status gmr_profile_enable(gmr_handle h, int32_t enable);
  * Stages: project, scan_emit, sort_fv_pass (the depth passes over face-views), sort_pass (the
  * instance passes), tile_ranges, raster_fwd, fill, raster_bwd, face_bwd, vertex_gather (with the
  * fused-loss backwards' fixed-order loss sum), build_small (the one-launch list build of small
- * batches, in place of the first five).  max_stages must be >= 11. */
+ * batches, in place of the first five), raster_step (gmr_render_step_l2's compositing and adjoint in
+ * one launch).  max_stages must be >= 12. */
 gmr_status gmr_profile_read(gmr_handle h, int32_t max_stages, char* names, float* ms_total, int32_t* launches,
                             int32_t* n_stages);
 

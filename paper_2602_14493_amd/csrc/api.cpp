@@ -19,10 +19,10 @@ using namespace gmr;
 
 // Stages timed by gmr_profile_* (HIP events around each launch group on the call's stream).
 enum Stage { kStProject, kStScanEmit, kStSortFv, kStSortPass, kStRanges, kStRasterFwd, kStFill, kStRasterBwd,
-             kStFaceBwd, kStGather, kStBuildSmall, kNumStages };
+             kStFaceBwd, kStGather, kStBuildSmall, kStRasterStep, kNumStages };
 static const char* kStageNames[kNumStages] = {"project",     "scan_emit",  "sort_fv_pass", "sort_pass",
                                               "tile_ranges", "raster_fwd", "fill",         "raster_bwd",
-                                              "face_bwd",    "vertex_gather", "build_small"};
+                                              "face_bwd",    "vertex_gather", "build_small", "raster_step"};
 
 struct gmr_ctx {
   int device = 0;
@@ -419,6 +419,23 @@ gmr_status common_checks(gmr_handle h, const void* table, const void* ws, size_t
   return GMR_OK;
 }
 
+// The backward after the compositing adjoint: face-view sums -> face gradients -> vertex gradients
+// (with the fused loss's fixed-order sum when red is given).
+void bwd_tail(gmr_ctx* h, const Plan& p, const gmr_options* opt, const void* table, const float* verts,
+              const int32_t* faces, const float* colors, const WsPtrs& w, const int32_t* adj_off,
+              const int32_t* adj_ent, float* d_verts, float* d_colors, const LossRed* red, hipStream_t s) {
+  {
+    StageTimer t(h, s, kStFaceBwd);
+    launch_face_bwd(table, p.f_total, verts, faces, colors, kopts(opt), reinterpret_cast<const float4*>(w.dfv), w.fgrad,
+                    w.fsh, p.max_views, s);
+  }
+  {
+    StageTimer t(h, s, kStGather);
+    launch_vertex_gather(adj_off, adj_ent, reinterpret_cast<const float*>(w.fgrad), w.fsh, opt->sh_degree, p.v_total,
+                         d_verts, d_colors, red, s);
+  }
+}
+
 gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table, const float* verts,
                     const int32_t* faces, const float* colors, const float* d_rgb, const float* d_alpha, const float* rgb,
                     const float* target, float loss_weight, const float* mask, float sil_weight, const void* saved,
@@ -453,16 +470,7 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   // fused loss: fixed-order sum of the per-item slots into the header (and loss_dev), carried by
   // the vertex gather's first blocks
   const LossRed red{w.statB, p.items_total, w.statR, w.hdr, loss_dev, n_losses, 0};
-  {
-    StageTimer t(h, s, kStFaceBwd);
-    launch_face_bwd(table, p.f_total, verts, faces, colors, ko, reinterpret_cast<const float4*>(w.dfv), w.fgrad, w.fsh,
-                    p.max_views, s);
-  }
-  {
-    StageTimer t(h, s, kStGather);
-    launch_vertex_gather(adj_off, adj_ent, reinterpret_cast<const float*>(w.fgrad), w.fsh, opt->sh_degree, p.v_total,
-                         d_verts, d_colors, target ? &red : nullptr, s);
-  }
+  bwd_tail(h, p, opt, table, verts, faces, colors, w, adj_off, adj_ent, d_verts, d_colors, target ? &red : nullptr, s);
   return check_launch();
 }
 
@@ -738,6 +746,53 @@ gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_opt
   if (!std::isfinite(loss_weight)) return fail(GMR_ERR_INVALID_ARG, "loss_weight must be finite");
   return bwd_impl(h, batch, opt, table, verts, faces, colors, nullptr, nullptr, rgb, target, loss_weight, nullptr, 0.f,
                   saved, adj_off, adj_ent, recompute, d_verts, d_colors, loss_dev, 1, ws, ws_bytes, stream);
+}
+
+gmr_status gmr_render_step_l2(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
+                              const float* verts, const int32_t* faces, const float* colors, const float* target,
+                              float loss_weight, float* out_rgb, float* out_alpha, void* saved, const int32_t* adj_off,
+                              const int32_t* adj_ent, float* d_verts, float* d_colors, float* loss_dev, void* ws,
+                              size_t ws_bytes, void* stream) {
+  Plan p;
+  gmr_status st = make_plan(batch, opt, true, p);
+  if (st != GMR_OK) return st;
+  st = common_checks(h, table, ws, ws_bytes, p);
+  if (st != GMR_OK) return st;
+  if (!verts || !faces || !colors || !target || !out_rgb || !saved || !adj_off || !adj_ent || !d_verts || !d_colors)
+    return fail(GMR_ERR_INVALID_ARG, "a required device pointer is NULL");
+  if (!std::isfinite(loss_weight)) return fail(GMR_ERR_INVALID_ARG, "loss_weight must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const WsPtrs w = ws_ptrs(p.L, ws);
+  const KOpts ko = kopts(opt);
+  build_lists(h, p, opt, table, verts, faces, colors, w, true, s);  // the projection also clears dfv
+  {
+    StageTimer t(h, s, kStFill);
+    launch_bwd_prologue(w.hdr, w.dfv, 0, s);
+  }
+  float* saved_T = static_cast<float*>(saved);
+  uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
+  const double n3 = 3.0 * (double)p.p_total;
+  const float gs = (float)(2.0 * loss_weight / n3), ls = (float)(loss_weight / n3);
+  if (opt->px_per_lane == 1 && persistent_blocks(h, opt) == 0) {  // one launch composites and differentiates
+    StageTimer t(h, s, kStRasterStep);
+    launch_raster_step(table, p.items_total, opt->lane_lists != 0, w.ranges, w.sorted_vals, w.rec, ko, out_rgb,
+                       out_alpha, saved_T, saved_n, w.statF, target, gs, ls, w.dfv, w.statB, s);
+  } else {
+    {
+      StageTimer t(h, s, kStRasterFwd);
+      launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0,
+                        w.ranges, w.sorted_vals, w.rec, ko, out_rgb, out_alpha, saved_T, saved_n, w.statF, s);
+    }
+    {
+      StageTimer t(h, s, kStRasterBwd);
+      launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals,
+                        w.rec, ko, saved_T, saved_n, nullptr, nullptr, out_rgb, target, gs, ls, nullptr, 0.f, w.dfv,
+                        w.statB, s);
+    }
+  }
+  const LossRed red{w.statB, p.items_total, w.statR, w.hdr, loss_dev, 1, 0};
+  bwd_tail(h, p, opt, table, verts, faces, colors, w, adj_off, adj_ent, d_verts, d_colors, &red, s);
+  return check_launch();
 }
 
 gmr_status gmr_render_bwd_recon(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,

@@ -886,6 +886,42 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   }
 }
 
+// One training step's compositing for the fused L2 loss (one pixel per lane): each wavefront
+// composites its 8 x 8 block front to back (per-lane or block-uniform walk, as k_raster_fwd),
+// writes the image, alpha and the saved per-pixel state, and then runs the same block's
+// reverse-order adjoint (as k_raster_bwd): the L2 upstream gradient of a pixel needs only that
+// pixel's colour, which each lane reads back from its own stores, so no grid-wide wait separates
+// the two and one list build serves both.  The two walks share the wavefront's LDS slots.
+template <bool kLanes>
+__global__ __launch_bounds__(256) void k_raster_step(FwdArgs fa, BwdArgs ba) {
+  __shared__ FwdLds<1, kLanes> s_f[256 / kWave];
+  __shared__ uint32_t s_id[256 / kWave][kWave];
+  __shared__ float s_red[256 / kWave][8 * kWave];
+  const TableHdr* th = static_cast<const TableHdr*>(fa.table);
+  const ViewDev* views = table_views(fa.table);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
+  if (item >= th->items_total) return;
+  raster_fwd_any<1, false, kLanes>(fa, th, views, item, lane, s_f[w]);
+  wave_lds_sync();  // the backward restages the slots
+  const BwdLds Lb{s_f[w].rec, s_id[w], s_f[w].cov, s_red[w]};
+  const float4 st = raster_bwd_item<1, true>(ba, th, views, item, lane, Lb);
+  if (lane == 0) ba.stats[item] = st;
+}
+
+void launch_raster_step(const void* table, int items, bool lane_lists, const uint32_t* ranges, const uint32_t* vals,
+                        const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
+                        uint32_t* saved_n, unsigned long long* stats_fwd, const float* target, float l2_grad_scale,
+                        float l2_loss_scale, float* dfv, float4* stats_bwd, hipStream_t s) {
+  if (items <= 0) return;
+  const FwdArgs fa{table, ranges, vals, rec, o, out_rgb, out_alpha, saved_T, saved_n, stats_fwd};
+  const BwdArgs ba{table,  ranges,        vals,          rec,     o,   saved_T, saved_n, nullptr, nullptr,
+                   out_rgb, target, l2_grad_scale, l2_loss_scale, nullptr, 0.f, dfv, stats_bwd};
+  const dim3 grid((unsigned)((items + 3) / 4));
+  if (lane_lists) hipLaunchKernelGGL((k_raster_step<true>), grid, dim3(256), 0, s, fa, ba);
+  else hipLaunchKernelGGL((k_raster_step<false>), grid, dim3(256), 0, s, fa, ba);
+}
+
 template <int PX, bool kLanes>
 static void fwd_dispatch(const FwdArgs& a, int items, int persistent_blocks, hipStream_t s) {
   if (persistent_blocks > 0)

@@ -226,6 +226,13 @@ class Renderer:
              _ptr(verts), _ptr(self.faces), _ptr(colors), _ptr(rgb), _ptr(alpha), _ptr(saved), _ptr(ws), ws.numel(),
              _stream(self.device))
 
+    def step_l2_raw(self, verts, colors, target, loss_weight, rgb, alpha, saved, ws, d_verts, d_colors, loss=None):
+        """gmr_render_step_l2: forward + fused L2 backward from one list build (see the header)."""
+        call("gmr_render_step_l2", self.handle.ptr, ctypes.byref(self.batch.c), ctypes.byref(self.opts),
+             _ptr(self.table), _ptr(verts), _ptr(self.faces), _ptr(colors), _ptr(target), float(loss_weight),
+             _ptr(rgb), _ptr(alpha), _ptr(saved), _ptr(self.adj_off), _ptr(self.adj_ent), _ptr(d_verts),
+             _ptr(d_colors), _ptr(loss), _ptr(ws), ws.numel(), _stream(self.device))
+
     def bwd_raw(self, verts, colors, d_rgb, d_alpha, saved, ws, recompute, d_verts, d_colors):
         call("gmr_render_bwd", self.handle.ptr, ctypes.byref(self.batch.c), ctypes.byref(self.opts), _ptr(self.table),
              _ptr(verts), _ptr(self.faces), _ptr(colors), _ptr(d_rgb), _ptr(d_alpha), _ptr(saved), _ptr(self.adj_off),
@@ -574,10 +581,12 @@ class GraphStep:
 
 class GraphAdamLoop:
     """One optimisation step -- forward, fused L2 backward with the sorted lists rebuilt, Adam on
-    the vertices -- captured once as a HIP graph and replayed."""
+    the vertices -- captured once as a HIP graph and replayed.  fused=True renders the step with
+    gmr_render_step_l2 (one list build, compositing and adjoint in one launch)."""
 
     def __init__(self, renderer: Renderer, verts: torch.Tensor, colors: torch.Tensor, target: torch.Tensor,
-                 lr=1e-3, betas=(0.9, 0.999), eps=1e-8, recompute=True):
+                 lr=1e-3, betas=(0.9, 0.999), eps=1e-8, recompute=True, fused=False):
+        self.fused = fused
         self.r = renderer
         dev = renderer.device
         self.verts = verts.detach().clone().contiguous()
@@ -602,9 +611,13 @@ class GraphAdamLoop:
 
     def _step_body(self):
         r = self.r
-        r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws)
-        r.bwd_l2_raw(self.verts, self.colors, self.rgb, self.target, 1.0, self.saved, self.ws,
-                     1 if self.recompute else 0, self.dV, self.dC, self.loss)
+        if self.fused:
+            r.step_l2_raw(self.verts, self.colors, self.target, 1.0, self.rgb, self.alpha, self.saved, self.ws,
+                          self.dV, self.dC, self.loss)
+        else:
+            r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws)
+            r.bwd_l2_raw(self.verts, self.colors, self.rgb, self.target, 1.0, self.saved, self.ws,
+                         1 if self.recompute else 0, self.dV, self.dC, self.loss)
         adam_step(self.verts, self.dV, self.m, self.v, self.step_count, self.lr, self.betas[0], self.betas[1],
                   self.eps)
 
