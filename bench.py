@@ -323,6 +323,32 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_graph = round(e0.elapsed_time(e1) / args.steps, 4)
+    if not use_graph and not args.no_fused_step:
+        # the same step rendered with gmr_render_step_l2 (one list build, compositing and adjoint
+        # in one launch), launched eagerly, reported beside the headline
+        rgb_f, alpha_f, saved_f = r._alloc_outputs()
+        ws_f = r.new_workspace()
+        dv_f, dc_f = torch.empty_like(verts), torch.empty_like(colors)
+        loss_f = torch.zeros((1,), dtype=torch.float32, device="cuda")
+
+        def fstep():
+            r.step_l2_raw(verts, colors, target, 1.0, rgb_f, alpha_f, saved_f, ws_f, dv_f, dc_f, loss_f)
+        for _ in range(args.warmup):
+            fstep()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            fstep()
+        e1.record()
+        torch.cuda.synchronize()
+        cf = r.counters(ws_f)
+        if cf.overflow or cf.overflow_any:
+            raise RuntimeError("instance capacity overflowed during the fused-step timing")
+        ms_f = e0.elapsed_time(e1) / args.steps
+        fused_step = {"ms_per_step": round(ms_f, 4), "Mpixel_per_s": round(P / (ms_f * 1e-3) / 1e6, 2),
+                      "list_builds_per_step": 1, "entry_point": "gmr_render_step_l2", "graph": False}
+        progress(f"fused step: {ms_f:.4f} ms/step")
+        del ws_f
     ws_ref = loop.ws if use_graph else ws
     cnt = r.counters(ws_ref)
     if cnt.overflow or cnt.overflow_any:
@@ -518,6 +544,25 @@ def main():
                       "regularizers_vector_adam_ms": round(ms_tail, 4),
                       "edges": rl.graph_mesh.num_edges, "graph": True,
                       "losses": [round(float(x), 6) for x in rl.losses.cpu().tolist()]}
+        del rl
+        if not args.no_fused_step:
+            # the same step rendered with gmr_render_step_recon (one list build, one compositing launch)
+            rf = gmr.ReconLoop(r, verts, colors, target, sil, lr=1e-3, recompute=recompute, fused=True)
+            rf.capture()
+            for _ in range(args.warmup):
+                rf.graph.replay()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                rf.graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            if rf.overflow():
+                raise RuntimeError("instance capacity overflowed during the fused reconstruction steps")
+            ms_rf = e0.elapsed_time(e1) / args.steps
+            recon_step["fused_ms_per_step"] = round(ms_rf, 4)
+            progress(f"fused reconstruction step: {ms_rf:.4f} ms/step")
+            del rf
 
     # ---- CPU baseline: the FP64 oracle, forward + adjoint -------------------------------------
     cpu = None

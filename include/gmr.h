@@ -256,6 +256,18 @@ gmr_status gmr_render_bwd_recon(gmr_handle h, const gmr_batch* batch, const gmr_
                                 float* d_verts_dev, float* d_colors_dev, float* losses_dev, void* ws_dev,
                                 size_t ws_bytes, void* stream);
 
+/* gmr_render_step_l2 for the reconstruction objective's image terms: gmr_render_fwd followed by
+ * gmr_render_bwd_recon (colour loss with weight color_weight plus the silhouette loss against
+ * mask_dev with weight sil_weight, Sec. 3.1) from one list build, the compositing and its adjoint in
+ * one launch.  losses_dev (may be NULL) receives the two weighted losses.  Outputs and errors as
+ * gmr_render_step_l2; mask_dev must not be NULL. */
+gmr_status gmr_render_step_recon(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table_dev,
+                                 const float* verts_dev, const int32_t* faces_dev, const float* colors_dev,
+                                 const float* target_dev, float color_weight, const float* mask_dev, float sil_weight,
+                                 float* out_rgb_dev, float* out_alpha_dev, void* saved_dev,
+                                 const int32_t* adj_off_dev, const int32_t* adj_ent_dev, float* d_verts_dev,
+                                 float* d_colors_dev, float* losses_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Where the forward's tile lists live inside a workspace laid out for (batch, opt): byte offsets
  * of the tile ranges (uint32 [tiles][2] = start, end into the sorted instances), the sorted
  * instance values (uint32 [instance_capacity] face-view indices, sorted by (tile, float32 depth,

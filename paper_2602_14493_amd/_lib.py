@@ -66,6 +66,10 @@ _SIGS = {
     "gmr_render_step_l2": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gmr_render_step_recon": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p,
+                                        c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_float, c_void_p,
+                                        c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_size_t, c_void_p]),
     "gmr_render_bwd_recon": (c_int32, [c_void_p, ctypes.POINTER(gmr_batch), ctypes.POINTER(gmr_options), c_void_p,
                                        c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_float,
                                        c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -346,13 +346,14 @@ struct StageTimer {
 // Conversion + projection + binning + sort (+ optionally zeroing the face-view gradients).
 void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* table, const float* verts,
                  const int32_t* faces, const float* colors, const WsPtrs& w, bool zero_dfv, hipStream_t s,
-                 bool timed = true) {
+                 bool timed = true, bool bwd_follows = false) {
   gmr_ctx* const th = timed ? h : nullptr;  // stage timing records events; untimed calls create none
   const KOpts ko = kopts(o);
   const Layout& L = p.L;
   if (small_build_fits(p.fv_total, p.tiles_total, L.capacity, o->sh_degree)) {  // one launch builds it all
     StageTimer t(th, s, kStBuildSmall);
-    const StatsInfo si{(uint32_t)p.items_total, (unsigned long long)L.statF, (unsigned long long)L.statB};
+    const StatsInfo si{(uint32_t)p.items_total, (unsigned long long)L.statF, (unsigned long long)L.statB,
+                       bwd_follows ? 1u : 0u};
     launch_build_small(table, verts, faces, colors, ko, w.rec, w.elA, w.hdr,
                        zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.ranges, 2 * p.tiles_total, w.keysF,
                        w.valsF, (uint32_t)L.capacity, si, s);
@@ -362,7 +363,8 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   const uint32_t inst_words = (uint32_t)L.parts_inst * 512u;
   {
     StageTimer t(th, s, kStProject);
-    const StatsInfo si{(uint32_t)p.items_total, (unsigned long long)L.statF, (unsigned long long)L.statB};
+    const StatsInfo si{(uint32_t)p.items_total, (unsigned long long)L.statF, (unsigned long long)L.statB,
+                       bwd_follows ? 1u : 0u};
     launch_project(table, p.f_total, verts, faces, colors, ko, w.rec, w.elA, w.hist,
                    zero_dfv ? reinterpret_cast<float4*>(w.dfv) : nullptr, w.hdr, w.descF0, fv_words, w.ranges,
                    2 * p.tiles_total, w.bdesc, L.scan_blocks, (uint32_t)L.capacity, si, p.max_views, s);
@@ -748,11 +750,14 @@ gmr_status gmr_render_bwd_l2(gmr_handle h, const gmr_batch* batch, const gmr_opt
                   saved, adj_off, adj_ent, recompute, d_verts, d_colors, loss_dev, 1, ws, ws_bytes, stream);
 }
 
-gmr_status gmr_render_step_l2(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
-                              const float* verts, const int32_t* faces, const float* colors, const float* target,
-                              float loss_weight, float* out_rgb, float* out_alpha, void* saved, const int32_t* adj_off,
-                              const int32_t* adj_ent, float* d_verts, float* d_colors, float* loss_dev, void* ws,
-                              size_t ws_bytes, void* stream) {
+namespace {
+// One step's rendering from a single list build (gmr_render_step_l2 / _recon): forward, then the
+// fused colour (and, with a mask, silhouette) backward.
+gmr_status step_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
+                     const float* verts, const int32_t* faces, const float* colors, const float* target,
+                     float color_weight, const float* mask, float sil_weight, float* out_rgb, float* out_alpha,
+                     void* saved, const int32_t* adj_off, const int32_t* adj_ent, float* d_verts, float* d_colors,
+                     float* losses_dev, int n_losses, void* ws, size_t ws_bytes, void* stream) {
   Plan p;
   gmr_status st = make_plan(batch, opt, true, p);
   if (st != GMR_OK) return st;
@@ -760,23 +765,22 @@ gmr_status gmr_render_step_l2(gmr_handle h, const gmr_batch* batch, const gmr_op
   if (st != GMR_OK) return st;
   if (!verts || !faces || !colors || !target || !out_rgb || !saved || !adj_off || !adj_ent || !d_verts || !d_colors)
     return fail(GMR_ERR_INVALID_ARG, "a required device pointer is NULL");
-  if (!std::isfinite(loss_weight)) return fail(GMR_ERR_INVALID_ARG, "loss_weight must be finite");
+  if (!std::isfinite(color_weight) || !std::isfinite(sil_weight))
+    return fail(GMR_ERR_INVALID_ARG, "loss weights must be finite");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const WsPtrs w = ws_ptrs(p.L, ws);
   const KOpts ko = kopts(opt);
-  build_lists(h, p, opt, table, verts, faces, colors, w, true, s);  // the projection also clears dfv
-  {
-    StageTimer t(h, s, kStFill);
-    launch_bwd_prologue(w.hdr, w.dfv, 0, s);
-  }
+  // the projection also clears dfv, and the build's prologue sets up the backward's counters
+  build_lists(h, p, opt, table, verts, faces, colors, w, true, s, true, true);
   float* saved_T = static_cast<float*>(saved);
   uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
   const double n3 = 3.0 * (double)p.p_total;
-  const float gs = (float)(2.0 * loss_weight / n3), ls = (float)(loss_weight / n3);
+  const float gs = (float)(2.0 * color_weight / n3), ls = (float)(color_weight / n3);
+  const float ss = (float)(sil_weight / (double)p.p_total);
   if (opt->px_per_lane == 1 && persistent_blocks(h, opt) == 0) {  // one launch composites and differentiates
     StageTimer t(h, s, kStRasterStep);
     launch_raster_step(table, p.items_total, opt->lane_lists != 0, w.ranges, w.sorted_vals, w.rec, ko, out_rgb,
-                       out_alpha, saved_T, saved_n, w.statF, target, gs, ls, w.dfv, w.statB, s);
+                       out_alpha, saved_T, saved_n, w.statF, target, gs, ls, mask, ss, w.dfv, w.statB, s);
   } else {
     {
       StageTimer t(h, s, kStRasterFwd);
@@ -786,13 +790,34 @@ gmr_status gmr_render_step_l2(gmr_handle h, const gmr_batch* batch, const gmr_op
     {
       StageTimer t(h, s, kStRasterBwd);
       launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals,
-                        w.rec, ko, saved_T, saved_n, nullptr, nullptr, out_rgb, target, gs, ls, nullptr, 0.f, w.dfv,
+                        w.rec, ko, saved_T, saved_n, nullptr, nullptr, out_rgb, target, gs, ls, mask, ss, w.dfv,
                         w.statB, s);
     }
   }
-  const LossRed red{w.statB, p.items_total, w.statR, w.hdr, loss_dev, 1, 0};
+  const LossRed red{w.statB, p.items_total, w.statR, w.hdr, losses_dev, n_losses, 0};
   bwd_tail(h, p, opt, table, verts, faces, colors, w, adj_off, adj_ent, d_verts, d_colors, &red, s);
   return check_launch();
+}
+}  // namespace
+
+gmr_status gmr_render_step_l2(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
+                              const float* verts, const int32_t* faces, const float* colors, const float* target,
+                              float loss_weight, float* out_rgb, float* out_alpha, void* saved, const int32_t* adj_off,
+                              const int32_t* adj_ent, float* d_verts, float* d_colors, float* loss_dev, void* ws,
+                              size_t ws_bytes, void* stream) {
+  return step_impl(h, batch, opt, table, verts, faces, colors, target, loss_weight, nullptr, 0.f, out_rgb, out_alpha,
+                   saved, adj_off, adj_ent, d_verts, d_colors, loss_dev, 1, ws, ws_bytes, stream);
+}
+
+gmr_status gmr_render_step_recon(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,
+                                 const float* verts, const int32_t* faces, const float* colors, const float* target,
+                                 float color_weight, const float* mask, float sil_weight, float* out_rgb,
+                                 float* out_alpha, void* saved, const int32_t* adj_off, const int32_t* adj_ent,
+                                 float* d_verts, float* d_colors, float* losses_dev, void* ws, size_t ws_bytes,
+                                 void* stream) {
+  if (!mask) return fail(GMR_ERR_INVALID_ARG, "mask must not be NULL");
+  return step_impl(h, batch, opt, table, verts, faces, colors, target, color_weight, mask, sil_weight, out_rgb,
+                   out_alpha, saved, adj_off, adj_ent, d_verts, d_colors, losses_dev, 2, ws, ws_bytes, stream);
 }
 
 gmr_status gmr_render_bwd_recon(gmr_handle h, const gmr_batch* batch, const gmr_options* opt, const void* table,

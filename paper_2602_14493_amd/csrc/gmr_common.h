@@ -125,6 +125,7 @@ struct KOpts {
 struct StatsInfo {
   uint32_t items;
   unsigned long long fwd_off, bwd_off;
+  uint32_t bwd;  // 1: a backward follows in the same call (its counters are set up with the lists)
 };
 
 // Blocks of the fixed-order loss sum (a multiple of nothing in particular; at most this many).

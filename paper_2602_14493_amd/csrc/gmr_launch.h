@@ -60,13 +60,15 @@ void launch_raster_fwd(const void* table, int items, int persistent_blocks, int 
                        const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
                        uint32_t* saved_n, unsigned long long* stats, hipStream_t s);
 
-// One step's compositing for the fused L2 loss (one pixel per lane, plain grid): per wavefront the
-// forward of its block (image, alpha, saved state, forward statistics), then that block's adjoint
-// (face-view sums into dfv, backward statistics).
+// One step's compositing for the fused colour loss, with the silhouette term when mask is given
+// (one pixel per lane, plain grid): per wavefront the forward of its block (image, alpha, saved
+// state, forward statistics), then that block's adjoint (face-view sums into dfv, backward
+// statistics).
 void launch_raster_step(const void* table, int items, bool lane_lists, const uint32_t* ranges, const uint32_t* vals,
                         const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
                         uint32_t* saved_n, unsigned long long* stats_fwd, const float* target, float l2_grad_scale,
-                        float l2_loss_scale, float* dfv, float4* stats_bwd, hipStream_t s);
+                        float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats_bwd,
+                        hipStream_t s);
 void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges, const uint32_t* vals,
                        const float4* rec, const KOpts& o, const float* saved_T, const uint32_t* saved_n,
                        const float* d_rgb, const float* d_alpha, const float* rgb, const float* target, float l2_grad_scale,

@@ -196,10 +196,14 @@ __global__ __launch_bounds__(256) void k_prologue(WsHdr* hdr, uint32_t* __restri
     hdr->overflow = 0u;
     hdr->capacity = cap;
     hdr->stats_items = si.items;
-    hdr->bwd_stats = 0u;
+    hdr->bwd_stats = si.bwd;
     hdr->stats_fwd_off = si.fwd_off;
     hdr->stats_bwd_off = si.bwd_off;
     hdr->red_ticket = 0u;
+    if (si.bwd) {
+      hdr->loss = 0.f;
+      hdr->loss_sil = 0.f;
+    }
     for (int c = 0; c < kKeyCopies; ++c) {
       hdr->key_hi_min[c] = 0xffffffffu;
       hdr->key_hi_max[c] = 0u;
@@ -234,10 +238,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(const void* __res
   if (tid == 0) {
     hdr->capacity = cap;
     hdr->stats_items = si.items;
-    hdr->bwd_stats = 0u;
+    hdr->bwd_stats = si.bwd;
     hdr->stats_fwd_off = si.fwd_off;
     hdr->stats_bwd_off = si.bwd_off;
     hdr->red_ticket = 0u;
+    if (si.bwd) {
+      hdr->loss = 0.f;
+      hdr->loss_sil = 0.f;
+    }
   }
   // 1. projection: records to the workspace, elements {depth bits, fv, first tile, nx | ny << 16}
   {

@@ -886,12 +886,13 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   }
 }
 
-// One training step's compositing for the fused L2 loss (one pixel per lane): each wavefront
+// One training step's compositing for the fused colour loss, with the silhouette term when a mask
+// is given (one pixel per lane): each wavefront
 // composites its 8 x 8 block front to back (per-lane or block-uniform walk, as k_raster_fwd),
 // writes the image, alpha and the saved per-pixel state, and then runs the same block's
-// reverse-order adjoint (as k_raster_bwd): the L2 upstream gradient of a pixel needs only that
-// pixel's colour, which each lane reads back from its own stores, so no grid-wide wait separates
-// the two and one list build serves both.  The two walks share the wavefront's LDS slots.
+// reverse-order adjoint (as k_raster_bwd): the upstream gradient of a pixel needs only that pixel's
+// colour and transmittance, which each lane reads back from its own stores, so no grid-wide wait
+// separates the two and one list build serves both.  The two walks share the wavefront's LDS slots.
 template <bool kLanes>
 __global__ __launch_bounds__(256) void k_raster_step(FwdArgs fa, BwdArgs ba) {
   __shared__ FwdLds<1, kLanes> s_f[256 / kWave];
@@ -912,11 +913,12 @@ __global__ __launch_bounds__(256) void k_raster_step(FwdArgs fa, BwdArgs ba) {
 void launch_raster_step(const void* table, int items, bool lane_lists, const uint32_t* ranges, const uint32_t* vals,
                         const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
                         uint32_t* saved_n, unsigned long long* stats_fwd, const float* target, float l2_grad_scale,
-                        float l2_loss_scale, float* dfv, float4* stats_bwd, hipStream_t s) {
+                        float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats_bwd,
+                        hipStream_t s) {
   if (items <= 0) return;
   const FwdArgs fa{table, ranges, vals, rec, o, out_rgb, out_alpha, saved_T, saved_n, stats_fwd};
-  const BwdArgs ba{table,  ranges,        vals,          rec,     o,   saved_T, saved_n, nullptr, nullptr,
-                   out_rgb, target, l2_grad_scale, l2_loss_scale, nullptr, 0.f, dfv, stats_bwd};
+  const BwdArgs ba{table,  ranges,        vals,          rec,  o,         saved_T, saved_n, nullptr, nullptr,
+                   out_rgb, target, l2_grad_scale, l2_loss_scale, mask, sil_scale, dfv,     stats_bwd};
   const dim3 grid((unsigned)((items + 3) / 4));
   if (lane_lists) hipLaunchKernelGGL((k_raster_step<true>), grid, dim3(256), 0, s, fa, ba);
   else hipLaunchKernelGGL((k_raster_step<false>), grid, dim3(256), 0, s, fa, ba);

@@ -233,6 +233,15 @@ class Renderer:
              _ptr(rgb), _ptr(alpha), _ptr(saved), _ptr(self.adj_off), _ptr(self.adj_ent), _ptr(d_verts),
              _ptr(d_colors), _ptr(loss), _ptr(ws), ws.numel(), _stream(self.device))
 
+    def step_recon_raw(self, verts, colors, target, color_weight, mask, sil_weight, rgb, alpha, saved, ws, d_verts,
+                       d_colors, losses=None):
+        """gmr_render_step_recon: forward + colour and silhouette backward from one list build."""
+        call("gmr_render_step_recon", self.handle.ptr, ctypes.byref(self.batch.c), ctypes.byref(self.opts),
+             _ptr(self.table), _ptr(verts), _ptr(self.faces), _ptr(colors), _ptr(target), float(color_weight),
+             _ptr(mask), float(sil_weight), _ptr(rgb), _ptr(alpha), _ptr(saved), _ptr(self.adj_off),
+             _ptr(self.adj_ent), _ptr(d_verts), _ptr(d_colors), _ptr(losses), _ptr(ws), ws.numel(),
+             _stream(self.device))
+
     def bwd_raw(self, verts, colors, d_rgb, d_alpha, saved, ws, recompute, d_verts, d_colors):
         call("gmr_render_bwd", self.handle.ptr, ctypes.byref(self.batch.c), ctypes.byref(self.opts), _ptr(self.table),
              _ptr(verts), _ptr(self.faces), _ptr(colors), _ptr(d_rgb), _ptr(d_alpha), _ptr(saved), _ptr(self.adj_off),
@@ -457,8 +466,9 @@ class ReconLoop:
 
     def __init__(self, renderer: Renderer, verts: torch.Tensor, colors: torch.Tensor, target: torch.Tensor,
                  mask: torch.Tensor, weights: ReconWeights | None = None, lr=1e-3, betas=(0.9, 0.999), eps=1e-8,
-                 recompute=True):
+                 recompute=True, fused=False):
         self.r = renderer
+        self.fused = fused  # render the step with gmr_render_step_recon (one list build)
         dev = renderer.device
         self.w = weights or ReconWeights()
         self.verts = verts.detach().clone().contiguous()
@@ -487,9 +497,13 @@ class ReconLoop:
 
     def _step_body(self):
         r, w = self.r, self.w
-        r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws)
-        r.bwd_recon_raw(self.verts, self.colors, self.rgb, self.target, w.color, self.mask, w.silhouette, self.saved,
-                        self.ws, 1 if self.recompute else 0, self.dV, self.dC, self.losses[0:2])
+        if self.fused:
+            r.step_recon_raw(self.verts, self.colors, self.target, w.color, self.mask, w.silhouette, self.rgb,
+                             self.alpha, self.saved, self.ws, self.dV, self.dC, self.losses[0:2])
+        else:
+            r.fwd_raw(self.verts, self.colors, self.rgb, self.alpha, self.saved, self.ws)
+            r.bwd_recon_raw(self.verts, self.colors, self.rgb, self.target, w.color, self.mask, w.silhouette,
+                            self.saved, self.ws, 1 if self.recompute else 0, self.dV, self.dC, self.losses[0:2])
         self.graph_mesh.regularizers_raw(self.verts, self.dV, self.losses[2:4], w.edge_length, w.edge, w.laplacian)
         vector_adam_step(self.verts, self.dV, self.m, self.v, self.step_count, self.lr, self.betas[0],
                          self.betas[1], self.eps)

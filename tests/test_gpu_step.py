@@ -81,3 +81,31 @@ def test_graph_adam_fused_step_matches_two_call_step(gpu):
     va, vb = to_np(a.verts).reshape(-1), to_np(b.verts).reshape(-1)
     assert np.allclose(vb[big], va[big], rtol=0, atol=1e-6)
     assert int(a.step_count) == int(b.step_count) == 1
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2-half", "cfg2-half-px2"])
+def test_step_recon_matches_fwd_then_bwd_recon(gpu, name):
+    """gmr_render_step_recon (colour + silhouette terms of Sec. 3.1) against gmr_render_fwd
+    followed by gmr_render_bwd_recon: outputs bit for bit, both losses, gradients up to atomic
+    order."""
+    import torch
+    say(f"fused reconstruction step vs forward + reconstruction backward: {name}")
+    W, r, verts, colors, target = _setup(name)
+    tv = torch.from_numpy(np.ascontiguousarray(W.target_verts, dtype=np.float32)).cuda()
+    _, t_alpha, _, _ = r.forward(tv, colors, check=True)
+    mask = (t_alpha > 0.5).to(torch.float32)
+    rgb, alpha, saved, ws = r.forward(verts, colors, check=True)
+    dV, dC, losses = r.backward_recon(verts, colors, rgb, target, mask, saved, ws, color_weight=1.0, sil_weight=0.1)
+    rgb2, alpha2, saved2 = r._alloc_outputs()
+    ws2 = r.new_workspace()
+    dV2, dC2 = torch.empty_like(dV), torch.empty_like(dC)
+    losses2 = torch.zeros((2,), dtype=torch.float32, device="cuda")
+    r.step_recon_raw(verts, colors, target, 1.0, mask, 0.1, rgb2, alpha2, saved2, ws2, dV2, dC2, losses2)
+    torch.cuda.synchronize()
+    assert not r.counters(ws2).overflow
+    assert torch.equal(rgb2, rgb) and torch.equal(alpha2, alpha) and torch.equal(saved2, saved)
+    l1, l2 = to_np(losses).astype(np.float64), to_np(losses2).astype(np.float64)
+    say(f"  losses {l1} / {l2}")
+    assert np.all(np.abs(l2 - l1) <= 1e-6 * np.abs(l1))
+    compare_grads(dV2, to_np(dV), f"{name} recon step dV", rel=1e-5)
+    compare_grads(dC2, to_np(dC), f"{name} recon step dC", rel=1e-5)
