@@ -228,6 +228,20 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   return GMR_OK;
 }
 
+// Raster-block masks in the instance keys: above the tile-id bits, where the tile's blocks fit.
+int32_t bm_shift1_of(const Plan& p) {
+  int tile_bits = 0;
+  while ((1ll << tile_bits) < p.tiles_total) ++tile_bits;
+  const int spt = p.sub_x * p.sub_y;
+  return (tile_bits <= 26 && spt <= 32 - tile_bits) ? tile_bits + 1 : 0;
+}
+
+// The tile-id bits of a sorted key.
+uint32_t key_tile_mask(const Plan& p) {
+  const int32_t b1 = bm_shift1_of(p);
+  return b1 > 0 ? (uint32_t)((1ull << (b1 - 1)) - 1ull) : 0xffffffffu;
+}
+
 void write_table(const Plan& p, void* dst) {
   char* base = static_cast<char*>(dst);
   TableHdr h{};
@@ -242,6 +256,7 @@ void write_table(const Plan& p, void* dst) {
   h.fv_total = p.fv_total;
   h.pixels_total = p.p_total;
   h.faces_total = p.f_total;
+  h.bm_shift1 = bm_shift1_of(p);
   h.views_off = sizeof(TableHdr);
   h.mesh_face_off = h.views_off + (int32_t)(sizeof(ViewDev) * p.nv);
   h.mesh_view_off = h.mesh_face_off + (int32_t)(sizeof(int32_t) * (p.nm + 1));
@@ -400,7 +415,7 @@ void build_lists(gmr_ctx* h, const Plan& p, const gmr_options* o, const void* ta
   }
   {
     StageTimer t(th, s, kStRanges);
-    launch_tile_ranges(w.keysF, w.hdr, w.ranges, hist_blocks(h), s);
+    launch_tile_ranges(w.keysF, key_tile_mask(p), w.hdr, w.ranges, hist_blocks(h), s);
   }
 }
 
@@ -465,8 +480,8 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   const double n3 = 3.0 * (double)p.p_total;
   {
     StageTimer t(h, s, kStRasterBwd);
-    launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals, w.rec, ko, saved_T,
-                      saved_n, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
+    launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals,
+                      w.keysF, w.rec, ko, saved_T, saved_n, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
                       mask, (float)(sil_weight / (double)p.p_total), w.dfv, w.statB, s);
   }
   // fused loss: fixed-order sum of the per-item slots into the header (and loss_dev), carried by
@@ -651,7 +666,7 @@ void fwd_impl(gmr_ctx* h, const Plan& p, const gmr_options* opt, const void* tab
   {
     StageTimer t(timed ? h : nullptr, s, kStRasterFwd);
     launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0, w.ranges,
-                      w.sorted_vals, w.rec, kopts(opt),
+                      w.sorted_vals, w.keysF, w.rec, kopts(opt),
                       out_rgb, out_alpha, saved_T, saved_n, w.statF, s);
   }
 }
@@ -779,18 +794,18 @@ gmr_status step_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* op
   const float ss = (float)(sil_weight / (double)p.p_total);
   if (opt->px_per_lane == 1 && persistent_blocks(h, opt) == 0) {  // one launch composites and differentiates
     StageTimer t(h, s, kStRasterStep);
-    launch_raster_step(table, p.items_total, opt->lane_lists != 0, w.ranges, w.sorted_vals, w.rec, ko, out_rgb,
-                       out_alpha, saved_T, saved_n, w.statF, target, gs, ls, mask, ss, w.dfv, w.statB, s);
+    launch_raster_step(table, p.items_total, opt->lane_lists != 0, w.ranges, w.sorted_vals, w.keysF, w.rec, ko,
+                       out_rgb, out_alpha, saved_T, saved_n, w.statF, target, gs, ls, mask, ss, w.dfv, w.statB, s);
   } else {
     {
       StageTimer t(h, s, kStRasterFwd);
       launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0,
-                        w.ranges, w.sorted_vals, w.rec, ko, out_rgb, out_alpha, saved_T, saved_n, w.statF, s);
+                        w.ranges, w.sorted_vals, w.keysF, w.rec, ko, out_rgb, out_alpha, saved_T, saved_n, w.statF, s);
     }
     {
       StageTimer t(h, s, kStRasterBwd);
       launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals,
-                        w.rec, ko, saved_T, saved_n, nullptr, nullptr, out_rgb, target, gs, ls, mask, ss, w.dfv,
+                        w.keysF, w.rec, ko, saved_T, saved_n, nullptr, nullptr, out_rgb, target, gs, ls, mask, ss, w.dfv,
                         w.statB, s);
     }
   }

@@ -46,7 +46,8 @@ struct TableHdr {          // 80 B
   int32_t tiles_total, sub_x, sub_y, items_total;   // sub_x/y: 8x8 blocks per tile; items = tiles*sub
   int64_t fv_total, pixels_total, faces_total;
   int32_t views_off, mesh_face_off, mesh_view_off, mesh_views_off;  // byte offsets in the table
-  int32_t pad[2];
+  int32_t bm_shift1;  // 1 + the key bit where an instance's raster-block mask starts; 0: no masks
+  int32_t pad;
 };
 struct ViewDev {           // 128 B
   float R[9], t[3];
@@ -65,6 +66,39 @@ __host__ __device__ inline const ViewDev* table_views(const void* t) {
 }
 __host__ __device__ inline const int32_t* table_i32(const void* t, int32_t off) {
   return reinterpret_cast<const int32_t*>(static_cast<const char*>(t) + off);
+}
+
+// Raster-block masks ------------------------------------------------------------------------------
+// A tile of tile_w x tile_h pixels is rastered as sub_x x sub_y blocks of kSub x (tile_h / sub_y)
+// pixels, block (sx, sy) being raster item sy * sub_x + sx of the tile.  When the table enables it
+// (bm_shift1 > 0: the tile ids leave at least sub_x * sub_y key bits free), every sorted instance
+// key carries, from bit bm_shift1 - 1 up, the mask of the tile's blocks that the instance's pixel
+// rectangle meets, and a raster item reads the face-view and record of only the list entries whose
+// bit it finds set (the same blocks its own rectangle test keeps).  The projection then packs,
+// into each face-view element, the block column of the rectangle's left edge in its first tile
+// column and of its right edge in its last, and likewise the block rows:
+//   el.z = first tile | chi << 26 | rhi << 29      el.w = nx | clo << 13 | ny << 16 | rlo << 29
+// (tile ids below 2^26, nx and ny below 2^13; without masks el.z is the first tile alone).
+constexpr uint32_t kElTileMask = (1u << 26) - 1u;
+__device__ inline uint32_t el_nx(uint32_t w) { return w & 0x1fffu; }
+__device__ inline uint32_t el_ny(uint32_t w) { return (w >> 16) & 0x1fffu; }
+
+// Blocks sx in [clo, chi], sy in [rlo, rhi] of a tile with sub_x block columns.
+__device__ inline uint32_t block_mask(uint32_t clo, uint32_t chi, uint32_t rlo, uint32_t rhi, uint32_t sub_x) {
+  const uint32_t cols = ((2u << chi) - 1u) & ~((1u << clo) - 1u);
+  uint32_t m = 0u;
+  for (uint32_t r = rlo; r <= rhi; ++r) m |= cols << (r * sub_x);
+  return m;
+}
+
+// The mask of the blocks of the tile with top-left pixel (X0, Y0) that the pixel rectangle
+// [ix0, ix1] x [iy0, iy1] (which meets the tile) meets.
+__device__ inline uint32_t rect_block_mask(int ix0, int ix1, int iy0, int iy1, int X0, int Y0, int tw,
+                                                    int tht, int sub_x, int sub_y) {
+  const int bh = tht / sub_y;
+  const int clo = max(ix0 - X0, 0) / kSub, chi = min(ix1 - X0, tw - 1) / kSub;
+  const int rlo = max(iy0 - Y0, 0) / bh, rhi = min(iy1 - Y0, tht - 1) / bh;
+  return block_mask((uint32_t)clo, (uint32_t)chi, (uint32_t)rlo, (uint32_t)rhi, (uint32_t)sub_x);
 }
 
 // Workspace header (device counters) ------------------------------------------------------------

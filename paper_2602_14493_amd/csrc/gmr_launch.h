@@ -35,7 +35,8 @@ void launch_sort_fv_pass(const uint4* in, uint4* out, uint32_t n, const uint32_t
 void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_t* out_v, const uint32_t* n_dev,
                            uint32_t cap, const uint32_t* hist, uint32_t* desc_cur, uint32_t* desc_next,
                            uint32_t next_words, uint32_t* ticket, int shift, uint32_t mask, int items, hipStream_t s);
-void launch_tile_ranges(const uint32_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int blocks, hipStream_t s);
+void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t tile_mask, const WsHdr* hdr, uint32_t* ranges, int blocks,
+                        hipStream_t s);
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float val, hipStream_t s);
@@ -56,7 +57,7 @@ struct LossRed {
 void launch_loss_reduce(const LossRed& r, hipStream_t s);
 
 void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists, const uint32_t* ranges,
-                       const uint32_t* vals,
+                       const uint32_t* vals, const uint32_t* keys,
                        const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
                        uint32_t* saved_n, unsigned long long* stats, hipStream_t s);
 
@@ -65,12 +66,12 @@ void launch_raster_fwd(const void* table, int items, int persistent_blocks, int 
 // state, forward statistics), then that block's adjoint (face-view sums into dfv, backward
 // statistics).
 void launch_raster_step(const void* table, int items, bool lane_lists, const uint32_t* ranges, const uint32_t* vals,
-                        const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
+                        const uint32_t* keys, const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
                         uint32_t* saved_n, unsigned long long* stats_fwd, const float* target, float l2_grad_scale,
                         float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats_bwd,
                         hipStream_t s);
 void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges, const uint32_t* vals,
-                       const float4* rec, const KOpts& o, const float* saved_T, const uint32_t* saved_n,
+                       const uint32_t* keys, const float4* rec, const KOpts& o, const float* saved_T, const uint32_t* saved_n,
                        const float* d_rgb, const float* d_alpha, const float* rgb, const float* target, float l2_grad_scale,
                        float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats,
                        hipStream_t s);

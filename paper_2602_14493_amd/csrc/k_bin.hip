@@ -1,5 +1,6 @@
 // Tile binning over the depth-sorted face-view elements: exclusive scan of tiles-touched, then
-// emission of one instance {tile, face-view} per (face-view, tile) in that order.  Emission order
+// emission of one instance {tile, face-view} per (face-view, tile) in that order (the key carrying,
+// above the tile id, the instance's raster-block mask when the table enables them).  Emission order
 // is (float32 depth, face-view), so a stable sort on the tile id alone completes the
 // (tile, depth, id) order.  The emitter also accumulates the histograms of the tile digits and
 // clears the first tile pass's descriptors.
@@ -19,12 +20,28 @@
 
 namespace gmr {
 
-// Instances of a face-view from its packed tile extent nx | ny << 16.
-__device__ inline uint32_t wh_count(uint32_t wh) { return (wh & 0xffffu) * (wh >> 16); }
+// Instances of a face-view from its packed tile extent (nx, ny fields of the element's last word).
+__device__ inline uint32_t wh_count(uint32_t wh) { return el_nx(wh) * el_ny(wh); }
+
+// The face-view's block columns / rows in its first and last tiles, and ny, packed for the emission:
+// clo | chi << 3 | rlo << 6 | rhi << 9 | ny << 16 (from the element's last two words).
+__device__ inline uint32_t emit_bits(uint32_t ez, uint32_t ew) {
+  return ((ew >> 13) & 7u) | (((ez >> 26) & 7u) << 3) | ((ew >> 29) << 6) | ((ez >> 29) << 9) | (el_ny(ew) << 16);
+}
+
+// Raster-block mask of the instance in tile column tx (of nx) and row ty of the face-view's range.
+__device__ inline uint32_t emit_mask(uint32_t bits, uint32_t tx, uint32_t ty, uint32_t nx, uint32_t sub_x,
+                                     uint32_t sub_y) {
+  const uint32_t ny = bits >> 16;
+  const uint32_t clo = tx == 0u ? (bits & 7u) : 0u, chi = tx + 1u == nx ? ((bits >> 3) & 7u) : sub_x - 1u;
+  const uint32_t rlo = ty == 0u ? ((bits >> 6) & 7u) : 0u, rhi = ty + 1u == ny ? ((bits >> 9) & 7u) : sub_y - 1u;
+  return block_mask(clo, chi, rlo, rhi, sub_x);
+}
 
 // Per-wavefront staging of one round's 64 face-views for the cooperative emission.
 struct EmitLds {
   uint32_t fv[kWave], t0[kWave], nxtx[kWave], ex[kWave];  // face-view, first tile, nx | tiles_x << 16, run start
+  uint32_t bits[kWave];                                    // emit_bits of the face-view
   int32_t mark[kWave];                                     // source lane of the run starting at a window slot
 };
 
@@ -87,6 +104,9 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
                                                      uint2* __restrict__ inst, uint32_t* __restrict__ hist, TilePasses tp,
                                                      uint32_t* __restrict__ desc0, uint32_t desc0_words) {
   const uint4* __restrict__ el = depth_keys_narrow(hdr) ? el_b : el_a;  // where the depth passes ended
+  const TableHdr* th = static_cast<const TableHdr*>(table);
+  const int bsh = th->bm_shift1 - 1;  // key bit of the raster-block masks (< 0: none)
+  const uint32_t sub_x = (uint32_t)th->sub_x, sub_y = (uint32_t)th->sub_y;
   __shared__ uint32_t s_w[kScanBlock / kWave];
   __shared__ uint32_t s_h[kMaxPasses - kTileRow0][kHistStride];
   __shared__ uint32_t s_b;
@@ -95,7 +115,7 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   if (threadIdx.x == 0) s_b = atomicAdd(&hdr->emit_ctr, 1u);
   const ViewDev* views = table_views(table);
-  const int nv = static_cast<const TableHdr*>(table)->num_views;
+  const int nv = th->num_views;
   for (int i = threadIdx.x; i < tp.n * kHistStride; i += kScanBlock) (&s_h[0][0])[i] = 0u;
   {  // this workgroup's slice of the first tile pass's descriptors
     const uint32_t chunk = (desc0_words + gridDim.x - 1) / gridDim.x;
@@ -152,13 +172,15 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
       uint64_t pos = off + inc - c;
       off += __shfl(inc, kWave - 1, kWave);
       if (c == 0u) continue;
-      const uint32_t nx = ew[i] & 0xffffu, ny = ew[i] >> 16;
+      const uint32_t nx = el_nx(ew[i]), ny = el_ny(ew[i]);
       const uint32_t tiles_x = (uint32_t)views[find_view_by_fv(views, nv, (int64_t)ef[i])].tiles_x;
+      const uint32_t bits = emit_bits(et[i], ew[i]), tile0 = bsh >= 0 ? et[i] & kElTileMask : et[i];
       for (uint32_t ty = 0; ty < ny; ++ty) {
         for (uint32_t tx = 0; tx < nx; ++tx, ++pos) {
           if (pos < cap) {
-            const uint32_t tile = et[i] + ty * tiles_x + tx;
-            inst[pos] = make_uint2(tile, ef[i]);
+            const uint32_t tile = tile0 + ty * tiles_x + tx;
+            const uint32_t key = bsh >= 0 ? tile | (emit_mask(bits, tx, ty, nx, sub_x, sub_y) << bsh) : tile;
+            inst[pos] = make_uint2(key, ef[i]);
             for (int q = 0; q < tp.n; ++q) atomicAdd(&s_h[q][(tile >> tp.shift[q]) & tp.mask[q]], 1u);
           }
         }
@@ -178,12 +200,13 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
       const uint32_t total = __shfl(inc, kWave - 1, kWave);
       if (total == 0u) continue;  // wave-uniform
       const uint32_t excl = inc - c;
-      const uint32_t nx = ew[i] & 0xffffu;
+      const uint32_t nx = el_nx(ew[i]);
       const uint32_t tiles_x = c ? (uint32_t)views[find_view_by_fv(views, nv, (int64_t)ef[i])].tiles_x : 0u;
       L.fv[lane] = ef[i];
-      L.t0[lane] = et[i];
+      L.t0[lane] = bsh >= 0 ? et[i] & kElTileMask : et[i];
       L.nxtx[lane] = nx | (tiles_x << 16);
       L.ex[lane] = excl;
+      L.bits[lane] = emit_bits(et[i], ew[i]);
       for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
         L.mark[lane] = -1;
         wave_lds_sync();
@@ -205,7 +228,9 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(const void* __restrict__ ta
           const uint64_t pos = off + j;
           if (pos < cap) {
             const uint32_t tile = L.t0[src] + ty * (nt >> 16) + (uint32_t)r;
-            inst[pos] = make_uint2(tile, L.fv[src]);
+            const uint32_t key =
+                bsh >= 0 ? tile | (emit_mask(L.bits[src], (uint32_t)r, ty, nxs, sub_x, sub_y) << bsh) : tile;
+            inst[pos] = make_uint2(key, L.fv[src]);
             for (int q = 0; q < tp.n; ++q) {
               const uint32_t dg = (tile >> tp.shift[q]) & tp.mask[q];
               if (q == 0) {  // the low digit of a run of neighbouring tiles: spread over the bins

@@ -6,7 +6,9 @@
 //                              {k l11, k l12, k l22, x-rect}  scaled Cholesky factor of the conic
 //                              {r, g, b, y-rect}              Eq. 16 colour; rects pack lo | hi << 16
 //   el[fv]   uint4 = 16 B      {float32 depth bits, fv, first tile, nx | ny << 16}: the element the
-//                              depth passes of the radix sort move (culled: nx = ny = 0)
+//                              depth passes of the radix sort move (culled: nx = ny = 0); with
+//                              raster-block masks, the spare bits of the last two words hold the
+//                              rectangle's block columns and rows in its first and last tiles
 // and adds each element's four 8-bit depth digits to the sort's histograms (LDS, then one global
 // atomic per bin and workgroup), and the range of the visible keys' high 16 bits to the workspace
 // header (per-thread, then one atomic pair per wavefront).
@@ -97,8 +99,13 @@ __device__ inline void project_face(const TableHdr* th, const void* __restrict__
         r[1] = make_float4((float)(kscale * l11), (float)(kscale * l12), (float)(kscale * l22),
                            u2f((uint32_t)ix0 | ((uint32_t)ix1 << 16)));
         r[2] = make_float4(col[0], col[1], col[2], u2f((uint32_t)iy0 | ((uint32_t)iy1 << 16)));
-        e = make_uint4(f2u((float)q.p[2]), (uint32_t)fv, (uint32_t)(V.tile_base + ty0 * V.tiles_x + tx0),
-                       (uint32_t)nx | ((uint32_t)ny << 16));
+        uint32_t ez = (uint32_t)(V.tile_base + ty0 * V.tiles_x + tx0), ew = (uint32_t)nx | ((uint32_t)ny << 16);
+        if (th->bm_shift1 > 0) {  // the rectangle's block columns / rows in its first and last tiles
+          const int bh = tht / th->sub_y;
+          ez |= ((uint32_t)((ix1 - tx1 * tw) / kSub) << 26) | ((uint32_t)((iy1 - ty1 * tht) / bh) << 29);
+          ew |= ((uint32_t)((ix0 - tx0 * tw) / kSub) << 13) | ((uint32_t)((iy0 - ty0 * tht) / bh) << 29);
+        }
+        e = make_uint4(f2u((float)q.p[2]), (uint32_t)fv, ez, ew);
         kmin = min(kmin, e.x >> 16);
         kmax = max(kmax, e.x >> 16);
       }
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(const void* __res
   for (int i = 0; i < kSmallPer; ++i) {
     const int64_t fv = (int64_t)tid * kSmallPer + i;
     e[i] = fv < nfv ? el[fv] : make_uint4(0xffffffffu, 0u, 0u, 0u);
-    cnt += (e[i].w & 0xffffu) * (e[i].w >> 16);
+    cnt += el_nx(e[i].w) * el_ny(e[i].w);
   }
   uint32_t inc = cnt;
 #pragma unroll
@@ -284,16 +291,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(const void* __res
   if (total > cap) return;  // uniform: the host grows the capacity and builds again
   // 3. keys
   const ViewDev* views = table_views(table);
+  const int bsh = th->bm_shift1 - 1;  // key bit of the raster-block masks (< 0: none)
 #pragma unroll
   for (int i = 0; i < kSmallPer; ++i) {
-    const uint32_t nx = e[i].w & 0xffffu, ny = e[i].w >> 16;
+    const uint32_t nx = el_nx(e[i].w), ny = el_ny(e[i].w);
     if (nx * ny == 0u) continue;
     const uint32_t fv = e[i].y;
     const uint32_t tiles_x = (uint32_t)views[find_view_by_fv(views, th->num_views, (int64_t)fv)].tiles_x;
+    const uint32_t tile0 = bsh >= 0 ? e[i].z & kElTileMask : e[i].z;
     const uint64_t low = ((uint64_t)e[i].x << kSmallFvBits) | fv;
     for (uint32_t ty = 0; ty < ny; ++ty)
       for (uint32_t tx = 0; tx < nx; ++tx)
-        s_key[base++] = ((uint64_t)(e[i].z + ty * tiles_x + tx) << (32 + kSmallFvBits)) | low;
+        s_key[base++] = ((uint64_t)(tile0 + ty * tiles_x + tx) << (32 + kSmallFvBits)) | low;
   }
   uint32_t n2 = 64;  // the network's width: the next power of two >= total
   while (n2 < total) n2 <<= 1;
@@ -319,12 +328,22 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(const void* __res
     }
   }
   __syncthreads();
-  // 5. keys, values and the tile ranges
+  // 5. keys (with the raster-block masks, from the record's pixel rectangle), values, tile ranges
   for (uint32_t i = tid; i < total; i += kSmallThreads) {
     const uint64_t key = s_key[i];
     const uint32_t tile = (uint32_t)(key >> (32 + kSmallFvBits));
-    keys_out[i] = tile;
-    vals_out[i] = (uint32_t)key & ((1u << kSmallFvBits) - 1u);
+    const uint32_t fv = (uint32_t)key & ((1u << kSmallFvBits) - 1u);
+    uint32_t kout = tile;
+    if (bsh >= 0) {
+      const ViewDev& V = views[find_view_by_tile(views, th->num_views, (int32_t)tile)];
+      const int lt = (int)tile - V.tile_base, tyi = lt / V.tiles_x, txi = lt - tyi * V.tiles_x;
+      const uint32_t rx = f2u(rec[kRecF4 * (size_t)fv + 1].w), ry = f2u(rec[kRecF4 * (size_t)fv + 2].w);
+      kout |= rect_block_mask((int)(rx & 0xffffu), (int)(rx >> 16), (int)(ry & 0xffffu), (int)(ry >> 16),
+                              txi * th->tile_w, tyi * th->tile_h, th->tile_w, th->tile_h, th->sub_x, th->sub_y)
+              << bsh;
+    }
+    keys_out[i] = kout;
+    vals_out[i] = fv;
     if (i == 0 || (uint32_t)(s_key[i - 1] >> (32 + kSmallFvBits)) != tile) ranges[2 * (size_t)tile] = i;
     if (i + 1 == total || (uint32_t)(s_key[i + 1] >> (32 + kSmallFvBits)) != tile) ranges[2 * (size_t)tile + 1] = i + 1;
   }

@@ -42,7 +42,7 @@ __device__ inline int xcd_remap(int b, int nb) {
 }
 
 struct ItemGeo {
-  int tile, x, bx0, by0, W, H;
+  int tile, sub, x, bx0, by0, W, H;  // sub: the block's index among its tile's raster items
   bool any;
   int64_t row0;  // pixel index of (0, by0 + ly) in the flat image
 };
@@ -53,6 +53,7 @@ __device__ inline ItemGeo item_geometry(const TableHdr* th, const ViewDev* views
   const int spt = th->sub_x * th->sub_y;
   g.tile = item / spt;
   const int sub = item - g.tile * spt;
+  g.sub = sub;
   const int vi = find_view_by_tile(views, th->num_views, g.tile);
   const ViewDev& V = views[vi];
   const int lt = g.tile - V.tile_base;
@@ -66,6 +67,12 @@ __device__ inline ItemGeo item_geometry(const TableHdr* th, const ViewDev* views
   g.x = g.bx0 + (lane & 7);
   g.row0 = V.pixel_offset + (int64_t)(g.by0 + (lane >> 3)) * V.W;
   return g;
+}
+
+// Key bit of this item's block in the instances' raster-block masks, or -1 without masks (then every
+// list entry is tested against the block's rectangle).
+__device__ inline int item_key_bit(const TableHdr* th, const ItemGeo& g) {
+  return th->bm_shift1 > 0 ? th->bm_shift1 - 1 + g.sub : -1;
 }
 
 __device__ inline bool rect_meets_block(uint32_t rx, uint32_t ry, int bx0, int by0, int bh) {
@@ -225,6 +232,7 @@ struct FwdArgs {
   const void* table;
   const uint32_t* ranges;
   const uint32_t* vals;
+  const uint32_t* keys;  // sorted keys: tile id and, above it, the raster-block mask
   const float4* rec;
   KOpts o;
   float* out_rgb;
@@ -233,6 +241,29 @@ struct FwdArgs {
   uint32_t* saved_n;
   unsigned long long* stats;  // [items] pairs evaluated per item (summed on the host when read)
 };
+
+// One list entry as a lane holds it: its key and face-view.  The raster loops load the next batch of
+// 64 entries while they work on the current one; a position outside the (non-empty) list [lo, hi)
+// reads its nearest entry instead, so that the loads need no branch (the caller ignores it) and the
+// compiler can wait for exactly the batch it uses.
+struct Entry {
+  uint32_t key, id;
+};
+__device__ __forceinline__ Entry load_entry(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                            int64_t pos, int64_t lo, int64_t hi) {
+  const int64_t q = pos < lo ? lo : (pos >= hi ? hi - 1 : pos);
+  return Entry{keys[q], vals[q]};
+}
+
+// Whether an entry may meet the item's block: with masks its key bit, else the rectangle test on
+// the record's two rectangle words.
+template <int PX>
+__device__ __forceinline__ bool entry_kept(const Entry& e, int kbit, const float4* __restrict__ rec,
+                                           const ItemGeo& g) {
+  if (kbit >= 0) return ((e.key >> kbit) & 1u) != 0u;
+  const float4* rp = rec + (size_t)kRecF4 * e.id;
+  return rect_meets_block(f2u(rp[1].w), f2u(rp[2].w), g.bx0, g.by0, kSub * PX);
+}
 
 // One record against a lane's PX pixels; `valid` = false makes it a no-op (predicated).  a = s[0][j],
 // b = s[1][j]; cov[k]: the record's pixel-rectangle coverage of row group k (bit = lane), uniform.
@@ -282,6 +313,7 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
   const float lxf = (float)(lane & 7), lyf = (float)ly;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
+  const int kbit = item_key_bit(th, g);
   float T[PX], C0[PX], C1[PX], C2[PX];
   uint32_t last[PX];
   bool done[PX];
@@ -294,20 +326,24 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
     done[k] = !(g.x < g.W && y[k] < g.H);
   }
   unsigned long long pairs = 0;
+  Entry cur{0u, 0u};
+  if (start < end) cur = load_entry(a.keys, a.vals, (int64_t)start + lane, start, end);  // (empty: no read)
   for (uint32_t cb = start; cb < end; cb += kWave) {
     bool live = false;
 #pragma unroll
     for (int k = 0; k < PX; ++k) live |= !done[k];
     if (__ballot(live) == 0ull) break;
     const uint32_t pos = cb + (uint32_t)lane;
+    const Entry nxt = load_entry(a.keys, a.vals, (int64_t)pos + kWave, start, end);
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
     bool ov = false;
-    if (pos < end) {
-      const uint32_t id = a.vals[pos];
-      const float4* rp = a.rec + (size_t)kRecF4 * id;
+    // with masks, an entry's key bit is the rectangle test: only the entries it keeps are read
+    if (pos < end && (kbit < 0 || ((cur.key >> kbit) & 1u) != 0u)) {
+      const float4* rp = a.rec + (size_t)kRecF4 * cur.id;
       r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
-      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX);
+      ov = kbit >= 0 || rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX);
     }
+    cur = nxt;
     uint64_t m = __ballot(ov);
     if (m == 0ull) continue;
     stage_record<PX>(s, lane, r0, r1, r2, g.bx0, g.by0);
@@ -428,20 +464,40 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
   }
 }
 
-// Forward with per-lane lists.  The tile's list is read 64 instances at a time; the Gaussians
-// whose rectangle meets the block are appended, in list order, to the wavefront's 64 LDS slots, and
-// each time the slots fill (and at the end of the list) they are walked with fwd_walk_lanes, so one
-// transpose serves 64 kept Gaussians however sparse they are in the list.
+// Stage the n queued entries (face-views s_qid[0, n), in list order) into the record slots and walk
+// them with per-lane lists.
+template <int PX>
+__device__ __forceinline__ void fwd_stage_walk(const FwdArgs& a, float4 (*s)[kWave], const uint32_t* s_pos,
+                                               const uint32_t* s_qid, uint2* s_rect, uint32_t n, const ItemGeo& g,
+                                               float lxf, float lyf, float amin, float amax, float teps,
+                                               float (&T)[PX], float (&C0)[PX], float (&C1)[PX], float (&C2)[PX],
+                                               uint32_t (&last)[PX], bool (&done)[PX], uint32_t& pairs, int lane) {
+  if ((uint32_t)lane < n) {
+    const float4* rp = a.rec + (size_t)kRecF4 * s_qid[lane];
+    const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
+    stage_record<PX>(s, lane, r0, r1, r2, g.bx0, g.by0);
+    s_rect[lane] = make_uint2(f2u(r1.w), f2u(r2.w));
+  }
+  wave_lds_sync();
+  fwd_walk_lanes<PX>(s, s_pos, s_rect, n, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
+}
+
+// Forward with per-lane lists.  The tile's list is read 64 entries at a time; the face-views of the
+// entries that meet the block (by their key's raster-block bit) are queued, in list order, in the
+// wavefront's 64 LDS slots, and each time the queue fills (and at the end of the list) their
+// records are read and walked with fwd_walk_lanes, so one record read and one transpose serve 64
+// kept Gaussians however sparse they are in the list.
 template <int PX>
 __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* th, const ViewDev* views,
                                                            int item, int lane, float4 (*s)[kWave], uint32_t* s_pos,
-                                                           uint2* s_rect) {
+                                                           uint32_t* s_qid, uint2* s_rect) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return 0ull;
   const int ly = lane >> 3;
   const float lxf = (float)(lane & 7), lyf = (float)ly;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
+  const int kbit = item_key_bit(th, g);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
   float T[PX], C0[PX], C1[PX], C2[PX];
   uint32_t last[PX];
@@ -455,51 +511,48 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
     done[k] = !(g.x < g.W && y[k] < g.H);
   }
   uint32_t pairs = 0;
-  uint32_t nk = 0;  // staged Gaussians (wave-uniform)
+  uint32_t nq = 0;  // queued entries (wave-uniform)
+  Entry cur{0u, 0u};
+  if (start < end) cur = load_entry(a.keys, a.vals, (int64_t)start + lane, start, end);  // (empty: no read)
   for (uint32_t cb = start; cb < end; cb += kWave) {
     bool live = false;
 #pragma unroll
     for (int k = 0; k < PX; ++k) live |= !done[k];
     if (__ballot(live) == 0ull) {
-      nk = 0;  // every pixel has stopped: what is staged no longer matters
+      nq = 0;  // every pixel has stopped: what is queued no longer matters
       break;
     }
     const uint32_t pos = cb + (uint32_t)lane;
-    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-    bool ov = false;
-    if (pos < end) {
-      const uint32_t id = a.vals[pos];
-      const float4* rp = a.rec + (size_t)kRecF4 * id;
-      r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
-      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX);
-    }
-    const uint64_t m = __ballot(ov);
+    const Entry nxt = load_entry(a.keys, a.vals, (int64_t)pos + kWave, start, end);
+    const uint32_t id = cur.id;
+    const bool kept = pos < end && entry_kept<PX>(cur, kbit, a.rec, g);
+    cur = nxt;
+    const uint64_t m = __ballot(kept);
     if (m == 0ull) continue;
-    const uint32_t cnt = (uint32_t)__popcll(m), slot = nk + (uint32_t)__popcll(m & below);
-    if (ov && slot < (uint32_t)kWave) {
-      stage_record<PX>(s, (int)slot, r0, r1, r2, g.bx0, g.by0);
+    const uint32_t cnt = (uint32_t)__popcll(m), slot = nq + (uint32_t)__popcll(m & below);
+    if (kept && slot < (uint32_t)kWave) {
+      s_qid[slot] = id;
       s_pos[slot] = pos - start + 1u;  // list position after this Gaussian
-      s_rect[slot] = make_uint2(f2u(r1.w), f2u(r2.w));
     }
-    if (nk + cnt < (uint32_t)kWave) {
-      nk += cnt;
+    if (nq + cnt < (uint32_t)kWave) {
+      nq += cnt;
       continue;
     }
     wave_lds_sync();
-    fwd_walk_lanes<PX>(s, s_pos, s_rect, (uint32_t)kWave, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done,
-                       pairs, lane);
+    fwd_stage_walk<PX>(a, s, s_pos, s_qid, s_rect, (uint32_t)kWave, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2,
+                       last, done, pairs, lane);
     wave_lds_sync();
-    if (ov && slot >= (uint32_t)kWave) {  // the overflow starts the next 64
+    if (kept && slot >= (uint32_t)kWave) {  // the overflow starts the next 64
       const uint32_t t = slot - (uint32_t)kWave;
-      stage_record<PX>(s, (int)t, r0, r1, r2, g.bx0, g.by0);
+      s_qid[t] = id;
       s_pos[t] = pos - start + 1u;
-      s_rect[t] = make_uint2(f2u(r1.w), f2u(r2.w));
     }
-    nk = nk + cnt - (uint32_t)kWave;
+    nq = nq + cnt - (uint32_t)kWave;
   }
-  if (nk > 0) {
+  if (nq > 0) {
     wave_lds_sync();
-    fwd_walk_lanes<PX>(s, s_pos, s_rect, nk, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
+    fwd_stage_walk<PX>(a, s, s_pos, s_qid, s_rect, nq, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done,
+                       pairs, lane);
   }
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
@@ -529,6 +582,7 @@ template <int PX, bool kLanes>
 struct FwdLds {
   float4 rec[PX > 1 ? 3 : 2][kWave];
   uint32_t pos[kLanes ? kWave : 1];
+  uint32_t qid[kLanes ? kWave : 1];  // queued face-views (per-lane lists)
   uint2 rect[kLanes ? kWave : 1];
   uint64_t cov[kLanes ? 1 : PX][kWave];
 };
@@ -537,7 +591,7 @@ template <int PX, bool kPersistent, bool kLanes>
 __device__ __forceinline__ void raster_fwd_any(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
                                                int lane, FwdLds<PX, kLanes>& L) {
   unsigned long long pairs;
-  if constexpr (kLanes) pairs = raster_fwd_item_lanes<PX>(a, th, views, item, lane, L.rec, L.pos, L.rect);
+  if constexpr (kLanes) pairs = raster_fwd_item_lanes<PX>(a, th, views, item, lane, L.rec, L.pos, L.qid, L.rect);
   else pairs = raster_fwd_item<PX>(a, th, views, item, lane, L.rec, L.cov);
   if (lane == 0) a.stats[item] = pairs;
 }
@@ -570,6 +624,7 @@ struct BwdArgs {
   const void* table;
   const uint32_t* ranges;
   const uint32_t* vals;
+  const uint32_t* keys;
   const float4* rec;
   KOpts o;
   const float* saved_T;
@@ -708,7 +763,8 @@ __device__ __forceinline__ void bwd_eval(const float4& a, const float4& b, const
 
 struct BwdLds {
   float4 (*rec)[kWave];   // [3][64] staged records (stage_record)
-  uint32_t* id;           // [64] their face-view ids
+  uint32_t* id;           // [64] their face-view ids (the queue of kept list entries)
+  uint32_t* pos;          // [64] their list positions, relative to the tile's start
   uint64_t (*cov)[kWave]; // [PX][64] their coverage of each row group of the block (bit = lane)
   float* red;             // [8 * 64] the gradient reduction's scratch
 };
@@ -716,8 +772,8 @@ struct BwdLds {
 // Block-uniform walk of one staged batch: every record is evaluated by the whole wavefront, two
 // per round, and its 8 partial sums are reduced across the wavefront.
 template <int PX>
-__device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds& L, uint64_t m, int64_t hi,
-                                                  uint32_t start, float lxf, float lyf, float amin, float amax,
+__device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds& L, uint64_t m,
+                                                  float lxf, float lyf, float amin, float amax,
                                                   const float (&gc0)[PX], const float (&gc1)[PX],
                                                   const float (&gc2)[PX], const float (&K)[PX],
                                                   const uint32_t (&last)[PX], float (&T)[PX], float (&S)[PX],
@@ -735,6 +791,7 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
     staged_oy<PX>(s, j1, a1, oy1);
     staged_oy<PX>(s, j2, a2, oy2);
     const uint32_t id1 = L.id[j1], id2 = L.id[j2];
+    const uint32_t p1 = L.pos[j1], p2 = L.pos[j2];
     uint64_t cv1[PX], cv2[PX];
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
@@ -748,11 +805,33 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
         if ((lane & 7) == 0) atomicAdd(a.dfv + 8 * (size_t)id + (lane >> 3), r);
       };
     };
-    bwd_eval<PX>(a1, b1, oy1, cv1, (uint32_t)(hi - 1 - j1 - (int64_t)start), lxf, lyf, amin, amax, gc0, gc1, gc2, K,
-                 last, T, S, pairs, emit(id1));
-    bwd_eval<PX>(a2, b2, oy2, cv2, (uint32_t)(hi - 1 - j2 - (int64_t)start), lxf, lyf, amin, amax, gc0, gc1, gc2, K,
-                 last, T, S, pairs, emit(id2));
+    bwd_eval<PX>(a1, b1, oy1, cv1, p1, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, emit(id1));
+    bwd_eval<PX>(a2, b2, oy2, cv2, p2, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, emit(id2));
   }
+}
+
+// Stage the n queued entries (face-views L.id[0, n), in reverse list order) and walk those whose
+// Gaussian can reach the alpha cutoff in the block.
+template <int PX>
+__device__ __forceinline__ void bwd_stage_walk(const BwdArgs& a, const BwdLds& L, uint32_t n, const ItemGeo& g,
+                                               float pmax, float lxf, float lyf, float amin, float amax,
+                                               const float (&gc0)[PX], const float (&gc1)[PX], const float (&gc2)[PX],
+                                               const float (&K)[PX], const uint32_t (&last)[PX], float (&T)[PX],
+                                               float (&S)[PX], unsigned long long& pairs, int lane) {
+  bool ov = false;
+  if ((uint32_t)lane < n) {
+    const float4* rp = a.rec + (size_t)kRecF4 * L.id[lane];
+    const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
+    ov = ellipse_meets_block(r0, r1, g.bx0, g.by0, kSub * PX, pmax);  // the rectangle meets it (queued)
+    stage_record<PX>(L.rec, lane, r0, r1, r2, g.bx0, g.by0);
+#pragma unroll
+    for (int k = 0; k < PX; ++k)
+      L.cov[k][lane] = ov ? block_coverage(f2u(r1.w), f2u(r2.w), g.bx0, g.by0 + kSub * k) : 0ull;
+  }
+  const uint64_t m = __ballot(ov);
+  if (m == 0ull) return;
+  wave_lds_sync();
+  bwd_batch_uniform<PX>(a, L, m, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
 }
 
 template <int PX, bool kL2>
@@ -831,27 +910,44 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   // power above which exp2(-power) < alpha_min, with a 2 % margin for rounding
   const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;
   unsigned long long pairs = 0;  // wave-uniform count
-  for (int64_t hi = (int64_t)start + mx; hi > (int64_t)start; hi -= kWave) {
+  const int kbit = item_key_bit(th, g);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
+  // walk the list back to front from the furthest position any pixel composited; the entries that
+  // meet the block are queued (reverse list order) and staged 64 at a time
+  uint32_t nq = 0;  // queued entries (wave-uniform)
+  const int64_t lo = start, hi0 = (int64_t)start + mx;  // mx >= 1: the window is not empty
+  Entry cur = load_entry(a.keys, a.vals, hi0 - 1 - lane, lo, hi0);
+  for (int64_t hi = hi0; hi > lo; hi -= kWave) {
     const int64_t pos = hi - 1 - lane;
-    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-    uint32_t id = 0;
-    bool ov = false;
-    if (pos >= (int64_t)start) {
-      id = a.vals[pos];
-      const float4* rp = a.rec + (size_t)kRecF4 * id;
-      r0 = rp[0]; r1 = rp[1]; r2 = rp[2];
-      ov = rect_meets_block(f2u(r1.w), f2u(r2.w), g.bx0, g.by0, kSub * PX) &&
-           ellipse_meets_block(r0, r1, g.bx0, g.by0, kSub * PX, pmax);
-    }
-    const uint64_t m = __ballot(ov);
+    const Entry nxt = load_entry(a.keys, a.vals, pos - kWave, lo, hi0);
+    const uint32_t id = cur.id;
+    const bool kept = pos >= (int64_t)start && entry_kept<PX>(cur, kbit, a.rec, g);
+    cur = nxt;
+    const uint64_t m = __ballot(kept);
     if (m == 0ull) continue;
-    stage_record<PX>(L.rec, lane, r0, r1, r2, g.bx0, g.by0);
-    L.id[lane] = id;
-#pragma unroll
-    for (int k = 0; k < PX; ++k)
-      L.cov[k][lane] = ov ? block_coverage(f2u(r1.w), f2u(r2.w), g.bx0, g.by0 + kSub * k) : 0ull;
+    const uint32_t cnt = (uint32_t)__popcll(m), slot = nq + (uint32_t)__popcll(m & below);
+    if (kept && slot < (uint32_t)kWave) {
+      L.id[slot] = id;
+      L.pos[slot] = (uint32_t)(pos - (int64_t)start);
+    }
+    if (nq + cnt < (uint32_t)kWave) {
+      nq += cnt;
+      continue;
+    }
     wave_lds_sync();
-    bwd_batch_uniform<PX>(a, L, m, hi, start, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
+    bwd_stage_walk<PX>(a, L, (uint32_t)kWave, g, pmax, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs,
+                       lane);
+    wave_lds_sync();
+    if (kept && slot >= (uint32_t)kWave) {  // the overflow starts the next 64
+      const uint32_t t = slot - (uint32_t)kWave;
+      L.id[t] = id;
+      L.pos[t] = (uint32_t)(pos - (int64_t)start);
+    }
+    nq = nq + cnt - (uint32_t)kWave;
+  }
+  if (nq > 0) {
+    wave_lds_sync();
+    bwd_stage_walk<PX>(a, L, nq, g, pmax, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
     wave_lds_sync();
   }
   return make_float4(loss, loss_sil, u2f((uint32_t)pairs), u2f((uint32_t)(pairs >> 32)));
@@ -861,12 +957,13 @@ template <int PX, bool kPersistent, bool kL2>
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   __shared__ float4 s_rec[256 / kWave][PX > 1 ? 3 : 2][kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
+  __shared__ uint32_t s_pos[256 / kWave][kWave];
   __shared__ uint64_t s_cov[256 / kWave][PX][kWave];
   __shared__ float s_red[256 / kWave][8 * kWave];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
   const ViewDev* views = table_views(a.table);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const BwdLds L{s_rec[w], s_id[w], s_cov[w], s_red[w]};
+  const BwdLds L{s_rec[w], s_id[w], s_pos[w], s_cov[w], s_red[w]};
   const int items = th->items_total;
   if (kPersistent) {
     const int groups = (items + 3) / 4;  // grid-stride, as in the forward
@@ -897,6 +994,7 @@ template <bool kLanes>
 __global__ __launch_bounds__(256) void k_raster_step(FwdArgs fa, BwdArgs ba) {
   __shared__ FwdLds<1, kLanes> s_f[256 / kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
+  __shared__ uint32_t s_pos[256 / kWave][kWave];
   __shared__ float s_red[256 / kWave][8 * kWave];
   const TableHdr* th = static_cast<const TableHdr*>(fa.table);
   const ViewDev* views = table_views(fa.table);
@@ -905,20 +1003,21 @@ __global__ __launch_bounds__(256) void k_raster_step(FwdArgs fa, BwdArgs ba) {
   if (item >= th->items_total) return;
   raster_fwd_any<1, false, kLanes>(fa, th, views, item, lane, s_f[w]);
   wave_lds_sync();  // the backward restages the slots
-  const BwdLds Lb{s_f[w].rec, s_id[w], s_f[w].cov, s_red[w]};
+  const BwdLds Lb{s_f[w].rec, s_id[w], s_pos[w], s_f[w].cov, s_red[w]};
   const float4 st = raster_bwd_item<1, true>(ba, th, views, item, lane, Lb);
   if (lane == 0) ba.stats[item] = st;
 }
 
 void launch_raster_step(const void* table, int items, bool lane_lists, const uint32_t* ranges, const uint32_t* vals,
-                        const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
+                        const uint32_t* keys, const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
                         uint32_t* saved_n, unsigned long long* stats_fwd, const float* target, float l2_grad_scale,
                         float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats_bwd,
                         hipStream_t s) {
   if (items <= 0) return;
-  const FwdArgs fa{table, ranges, vals, rec, o, out_rgb, out_alpha, saved_T, saved_n, stats_fwd};
-  const BwdArgs ba{table,  ranges,        vals,          rec,  o,         saved_T, saved_n, nullptr, nullptr,
-                   out_rgb, target, l2_grad_scale, l2_loss_scale, mask, sil_scale, dfv,     stats_bwd};
+  const FwdArgs fa{table, ranges, vals, keys, rec, o, out_rgb, out_alpha, saved_T, saved_n, stats_fwd};
+  const BwdArgs ba{table,  ranges,        vals,          keys, rec,       o,         saved_T, saved_n, nullptr,
+                   nullptr, out_rgb,      target,        l2_grad_scale,   l2_loss_scale, mask, sil_scale, dfv,
+                   stats_bwd};
   const dim3 grid((unsigned)((items + 3) / 4));
   if (lane_lists) hipLaunchKernelGGL((k_raster_step<true>), grid, dim3(256), 0, s, fa, ba);
   else hipLaunchKernelGGL((k_raster_step<false>), grid, dim3(256), 0, s, fa, ba);
@@ -945,10 +1044,10 @@ static void bwd_dispatch(const BwdArgs& a, bool l2, int items, int persistent_bl
 }
 
 void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists,
-                       const uint32_t* ranges, const uint32_t* vals, const float4* rec, const KOpts& o, float* out_rgb,
-                       float* out_alpha, float* saved_T, uint32_t* saved_n, unsigned long long* stats,
-                       hipStream_t s) {
-  FwdArgs a{table, ranges, vals, rec, o, out_rgb, out_alpha, saved_T, saved_n, stats};
+                       const uint32_t* ranges, const uint32_t* vals, const uint32_t* keys, const float4* rec,
+                       const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T, uint32_t* saved_n,
+                       unsigned long long* stats, hipStream_t s) {
+  FwdArgs a{table, ranges, vals, keys, rec, o, out_rgb, out_alpha, saved_T, saved_n, stats};
   if (items <= 0) return;
   if (lane_lists) {
     if (px == 4) fwd_dispatch<4, true>(a, items, persistent_blocks, s);
@@ -962,12 +1061,12 @@ void launch_raster_fwd(const void* table, int items, int persistent_blocks, int 
 }
 
 void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges,
-                       const uint32_t* vals, const float4* rec, const KOpts& o, const float* saved_T,
+                       const uint32_t* vals, const uint32_t* keys, const float4* rec, const KOpts& o, const float* saved_T,
                        const uint32_t* saved_n, const float* d_rgb, const float* d_alpha, const float* rgb,
                        const float* target, float l2_grad_scale, float l2_loss_scale, const float* mask,
                        float sil_scale, float* dfv, float4* stats, hipStream_t s) {
-  BwdArgs a{table,    ranges,        vals, rec,       o,   saved_T, saved_n, d_rgb, d_alpha, rgb, target,
-            l2_grad_scale, l2_loss_scale, mask, sil_scale, dfv, stats};
+  BwdArgs a{table, ranges, vals,          keys,          rec,  o,         saved_T, saved_n, d_rgb, d_alpha,
+            rgb,   target, l2_grad_scale, l2_loss_scale, mask, sil_scale, dfv,     stats};
   if (items <= 0) return;
   const bool l2 = target != nullptr;
   if (px == 4) bwd_dispatch<4>(a, l2, items, persistent_blocks, s);

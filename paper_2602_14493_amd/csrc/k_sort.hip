@@ -221,11 +221,12 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = val;
 }
 
-// Start / end of each tile's run in the sorted keys.  A thread takes 8 consecutive keys with two
-// 16-B loads plus its two neighbours, so the kernel streams the keys once at full width.
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ keys, const WsHdr* __restrict__ hdr,
-                                                     uint32_t* __restrict__ ranges) {
-  constexpr uint32_t kNone = 0xFFFFFFFFu;  // tile ids are < 2^30: never equal to a key
+// Start / end of each tile's run in the sorted keys (their tile-id bits: tmask; the bits above
+// carry the raster-block masks).  A thread takes 8 consecutive keys with two 16-B loads plus its two
+// neighbours, so the kernel streams the keys once at full width.
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t tmask,
+                                                     const WsHdr* __restrict__ hdr, uint32_t* __restrict__ ranges) {
+  constexpr uint32_t kNone = 0xFFFFFFFFu;  // tile ids are < 2^30: never equal to a masked key
   const uint32_t n = min(hdr->count, hdr->capacity);
   const uint32_t groups = (n + 7u) / 8u;
   for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < groups; gi += gridDim.x * blockDim.x) {
@@ -234,14 +235,14 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict_
     if (i0 + 8u <= n) {
       const uint4 a = reinterpret_cast<const uint4*>(keys + i0)[0];
       const uint4 b = reinterpret_cast<const uint4*>(keys + i0)[1];
-      k[1] = a.x; k[2] = a.y; k[3] = a.z; k[4] = a.w;
-      k[5] = b.x; k[6] = b.y; k[7] = b.z; k[8] = b.w;
+      k[1] = a.x & tmask; k[2] = a.y & tmask; k[3] = a.z & tmask; k[4] = a.w & tmask;
+      k[5] = b.x & tmask; k[6] = b.y & tmask; k[7] = b.z & tmask; k[8] = b.w & tmask;
     } else {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) k[1 + j] = i0 + j < n ? keys[i0 + j] : kNone;
+      for (int j = 0; j < 8; ++j) k[1 + j] = i0 + j < n ? keys[i0 + j] & tmask : kNone;
     }
-    k[0] = i0 > 0u ? keys[i0 - 1u] : kNone;
-    k[9] = i0 + 8u < n ? keys[i0 + 8u] : kNone;
+    k[0] = i0 > 0u ? keys[i0 - 1u] & tmask : kNone;
+    k[9] = i0 + 8u < n ? keys[i0 + 8u] & tmask : kNone;
 #pragma unroll
     for (int j = 1; j <= 8; ++j) {
       const uint32_t t = k[j];
@@ -313,8 +314,9 @@ void launch_sort_inst_pass(const uint2* in, uint2* out, uint32_t* out_k, uint32_
 }
 
 // ranges[] was zeroed by the list-building prologue (tiles without instances stay [0, 0)).
-void launch_tile_ranges(const uint32_t* sorted_keys, const WsHdr* hdr, uint32_t* ranges, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_ranges, dim3(blocks), dim3(256), 0, s, sorted_keys, hdr, ranges);
+void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t tile_mask, const WsHdr* hdr, uint32_t* ranges, int blocks,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_ranges, dim3(blocks), dim3(256), 0, s, sorted_keys, tile_mask, hdr, ranges);
 }
 
 }  // namespace gmr
