@@ -101,7 +101,9 @@ typedef struct gmr_counters {
   int64_t capacity;    /* capacity of the workspace                                           */
   int32_t overflow;    /* 1 if instances > capacity (outputs of that pass are incomplete)    */
   int32_t overflow_any;/* 1 if any list build since the previous read overflowed             */
-  int64_t pairs_fwd;   /* (pixel, Gaussian) pairs the last forward evaluated inside extents   */
+  int64_t pairs_fwd;   /* (pixel, Gaussian) pairs the last forward evaluated: pixel inside the
+                          Gaussian's 3-sigma rectangle and (with a margin) its 1/255 ellipse,
+                          up to the pixel's transmittance stop                                */
   int64_t pairs_bwd;   /* pairs the last backward differentiated (composited ones)           */
   float loss;          /* colour loss of the last fused backward (L2 or reconstruction)       */
   float loss_sil;      /* silhouette loss of the last gmr_render_bwd_recon (0 otherwise)      */
@@ -272,7 +274,10 @@ gmr_status gmr_render_step_recon(gmr_handle h, const gmr_batch* batch, const gmr
  * of the tile ranges (uint32 [tiles][2] = start, end into the sorted instances), the sorted
  * instance values (uint32 [instance_capacity] face-view indices, sorted by (tile, float32 depth,
  * face-view)), the projected records (float32 [face-views][12]) and the sorted instance keys
- * (uint32 [instance_capacity] global tile ids).  Tiles of view v are numbered from the sum of the
+ * (uint32 [instance_capacity]: the global tile id in the low b bits, b = ceil(log2(total tiles));
+ * when b <= 26 and the tile's (tile_w / 8) * (tile_h / (8 px_per_lane)) raster blocks fit in the
+ * 32 - b bits above, those bits hold the mask of the blocks that the instance's pixel rectangle
+ * meets, block (sx, sy) of 8 x (8 px_per_lane) pixels at bit b + sy * (tile_w / 8) + sx).  Tiles of view v are numbered from the sum of the
  * earlier views' tile counts, row-major.  Face-views of view v are numbered from the sum of the
  * earlier views' face counts, in face order.  Pure host arithmetic; the contents are valid after
  * gmr_render_fwd (or a recomputing gmr_render_bwd). */

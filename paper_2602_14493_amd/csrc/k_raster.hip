@@ -106,6 +106,31 @@ __device__ inline bool ellipse_meets_block(const float4& r0, const float4& r1, i
   return fminf(fminf(p1, p2), fminf(p3, p4)) <= pmax;
 }
 
+// Pixels of an 8 x 8 block (bit 8 * row + col) at whose centre the Gaussian's power is at most pmax:
+// pixel (c, r) takes dx = ox - c, dy = oy - r (offsets as staged), and the power is at most pmax
+// exactly where |l11 dx + l12 dy| <= sqrt(pmax - (l22 dy)^2), i.e. for c within
+// ox + (l12 dy -/+ sqrt(pmax - (l22 dy)^2)) / l11 (l11 > 0); the bounds are widened by 1e-3 px and a
+// NaN bound keeps the whole row.  With pmax carrying a margin over the power of the alpha cutoff,
+// every pixel at which the record reaches alpha_min is inside, so masking a walk with it changes no
+// image.
+__device__ inline uint64_t ellipse_rows(float ox, float oy, float l11, float l12, float l22, float pmax) {
+  const float il = __builtin_amdgcn_rcpf(l11);
+  uint64_t m = 0ull;
+#pragma unroll
+  for (int r = 0; r < kSub; ++r) {
+    const float dy = oy - (float)r;
+    const float w2 = l22 * dy;
+    const float t = pmax - w2 * w2;
+    const float hw = t != t ? __builtin_inff() : __builtin_sqrtf(fmaxf(t, 0.f)) * il;
+    const float c = fmaf(l12 * dy, il, ox);
+    const int ilo = max((int)ceilf(fmaxf(c - hw - 1e-3f, -1.f)), 0);
+    const int ihi = min((int)floorf(fminf(c + hw + 1e-3f, 8.f)), kSub - 1);
+    const uint32_t bits = (t >= 0.f || t != t) && ilo <= ihi ? (0xFFu << ilo) & (0xFFu >> (kSub - 1 - ihi)) : 0u;
+    m |= (uint64_t)bits << (kSub * r);
+  }
+  return m;
+}
+
 __device__ inline bool in_range(uint32_t r, int x) {
   const int lo = (int)(r & 0xffffu), hi = (int)(r >> 16);
   return (uint32_t)(x - lo) <= (uint32_t)(hi - lo);
@@ -313,6 +338,7 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
   const float lxf = (float)(lane & 7), lyf = (float)ly;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
+  const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;  // as in the per-lane walk
   const int kbit = item_key_bit(th, g);
   float T[PX], C0[PX], C1[PX], C2[PX];
   uint32_t last[PX];
@@ -347,8 +373,13 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
     uint64_t m = __ballot(ov);
     if (m == 0ull) continue;
     stage_record<PX>(s, lane, r0, r1, r2, g.bx0, g.by0);
+    // coverage: inside the pixel rectangle and the cutoff ellipse (the per-lane walk's pairs)
+    const float ox = block_off(r0.x, r0.z, g.bx0);
 #pragma unroll
-    for (int k = 0; k < PX; ++k) scov[k][lane] = ov ? block_coverage(f2u(r1.w), f2u(r2.w), g.bx0, g.by0 + kSub * k) : 0ull;
+    for (int k = 0; k < PX; ++k)
+      scov[k][lane] = ov ? block_coverage(f2u(r1.w), f2u(r2.w), g.bx0, g.by0 + kSub * k) &
+                               ellipse_rows(ox, block_off(r0.y, r0.w, g.by0 + kSub * k), r1.x, r1.y, r1.z, pmax)
+                         : 0ull;
     wave_lds_sync();
     // consume the kept records in list order, two per round: both broadcast reads are issued
     // before either is evaluated, and the second evaluation is predicated (not branched) when the
@@ -397,27 +428,22 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
   return pairs;
 }
 
-// Walk the n staged Gaussians (slots 0..n-1, in list order) with per-lane lists: lane j < n builds
-// its Gaussian's pixel-rectangle coverage of the block (one 64-bit row per row group), the rows are
-// transposed so that every lane holds the slots of the Gaussians that contain its pixel, and each
-// lane walks only those, in slot order.  Every (pixel, Gaussian) pair takes the same arithmetic as
-// in raster_fwd_item, so images are bit-identical.
+// Walk the n staged Gaussians (slots 0..n-1, in list order) with per-lane lists: lane j < n holds
+// in cov the pixels of each row group that its Gaussian may reach (one 64-bit row per row group:
+// inside its pixel rectangle and its cutoff ellipse), the rows are transposed so that every lane
+// holds the slots of the Gaussians that may reach its pixel, and each lane walks only those, in
+// slot order.  Every (pixel, Gaussian) pair left out has alpha below the cutoff there or lies
+// outside the rectangle, and every pair walked takes the same arithmetic as in raster_fwd_item, so
+// images are bit-identical.
 template <int PX>
-__device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const uint32_t* s_pos, const uint2* s_rect,
-                                               uint32_t n, const ItemGeo& g, float lxf, float lyf, float amin,
+__device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const uint32_t* s_pos,
+                                               const uint64_t (&cov)[PX], float lxf, float lyf, float amin,
                                                float amax, float teps, float (&T)[PX], float (&C0)[PX],
                                                float (&C1)[PX], float (&C2)[PX], uint32_t (&last)[PX],
                                                bool (&done)[PX], uint32_t& pairs, int lane) {
   uint64_t mine[PX];
-  {
-    const bool own = (uint32_t)lane < n;
-    const uint2 rr = own ? s_rect[lane] : make_uint2(0u, 0u);
 #pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      const uint64_t cov = own ? block_coverage(rr.x, rr.y, g.bx0, g.by0 + kSub * k) : 0ull;
-      mine[k] = transpose64(cov, lane);
-    }
-  }
+  for (int k = 0; k < PX; ++k) mine[k] = transpose64(cov[k], lane);
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     const uint64_t mk = done[k] ? 0ull : mine[k];
@@ -464,22 +490,29 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
   }
 }
 
-// Stage the n queued entries (face-views s_qid[0, n), in list order) into the record slots and walk
-// them with per-lane lists.
+// Stage the n queued entries (face-views s_qid[0, n), in list order) into the record slots, each
+// lane computing its record's coverage of the block, and walk them with per-lane lists.
 template <int PX>
 __device__ __forceinline__ void fwd_stage_walk(const FwdArgs& a, float4 (*s)[kWave], const uint32_t* s_pos,
-                                               const uint32_t* s_qid, uint2* s_rect, uint32_t n, const ItemGeo& g,
+                                               const uint32_t* s_qid, uint32_t n, const ItemGeo& g, float pmax,
                                                float lxf, float lyf, float amin, float amax, float teps,
                                                float (&T)[PX], float (&C0)[PX], float (&C1)[PX], float (&C2)[PX],
                                                uint32_t (&last)[PX], bool (&done)[PX], uint32_t& pairs, int lane) {
+  uint64_t cov[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) cov[k] = 0ull;
   if ((uint32_t)lane < n) {
     const float4* rp = a.rec + (size_t)kRecF4 * s_qid[lane];
     const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
     stage_record<PX>(s, lane, r0, r1, r2, g.bx0, g.by0);
-    s_rect[lane] = make_uint2(f2u(r1.w), f2u(r2.w));
+    const float ox = block_off(r0.x, r0.z, g.bx0);
+#pragma unroll
+    for (int k = 0; k < PX; ++k)
+      cov[k] = block_coverage(f2u(r1.w), f2u(r2.w), g.bx0, g.by0 + kSub * k) &
+               ellipse_rows(ox, block_off(r0.y, r0.w, g.by0 + kSub * k), r1.x, r1.y, r1.z, pmax);
   }
   wave_lds_sync();
-  fwd_walk_lanes<PX>(s, s_pos, s_rect, n, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
+  fwd_walk_lanes<PX>(s, s_pos, cov, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
 }
 
 // Forward with per-lane lists.  The tile's list is read 64 entries at a time; the face-views of the
@@ -490,13 +523,15 @@ __device__ __forceinline__ void fwd_stage_walk(const FwdArgs& a, float4 (*s)[kWa
 template <int PX>
 __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* th, const ViewDev* views,
                                                            int item, int lane, float4 (*s)[kWave], uint32_t* s_pos,
-                                                           uint32_t* s_qid, uint2* s_rect) {
+                                                           uint32_t* s_qid) {
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return 0ull;
   const int ly = lane >> 3;
   const float lxf = (float)(lane & 7), lyf = (float)ly;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
+  // power above which exp2(-power) < alpha_min, with a 2 % margin for rounding
+  const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;
   const int kbit = item_key_bit(th, g);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
   float T[PX], C0[PX], C1[PX], C2[PX];
@@ -539,7 +574,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
       continue;
     }
     wave_lds_sync();
-    fwd_stage_walk<PX>(a, s, s_pos, s_qid, s_rect, (uint32_t)kWave, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2,
+    fwd_stage_walk<PX>(a, s, s_pos, s_qid, (uint32_t)kWave, g, pmax, lxf, lyf, amin, amax, teps, T, C0, C1, C2,
                        last, done, pairs, lane);
     wave_lds_sync();
     if (kept && slot >= (uint32_t)kWave) {  // the overflow starts the next 64
@@ -551,7 +586,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
   }
   if (nq > 0) {
     wave_lds_sync();
-    fwd_stage_walk<PX>(a, s, s_pos, s_qid, s_rect, nq, g, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done,
+    fwd_stage_walk<PX>(a, s, s_pos, s_qid, nq, g, pmax, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done,
                        pairs, lane);
   }
 #pragma unroll
@@ -577,13 +612,12 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
 // Every item writes its own statistics slot (no atomics on a shared counter: one float or 64-bit
 // atomic per wavefront on one address serialises at the L2 and bounded these kernels).
 // LDS of one forward wavefront: the staged records, and per slot either its list position and
-// pixel rectangle (per-lane lists) or its coverage of each row group (block-uniform walk).
+// queued face-view (per-lane lists) or its coverage of each row group (block-uniform walk).
 template <int PX, bool kLanes>
 struct FwdLds {
   float4 rec[PX > 1 ? 3 : 2][kWave];
   uint32_t pos[kLanes ? kWave : 1];
   uint32_t qid[kLanes ? kWave : 1];  // queued face-views (per-lane lists)
-  uint2 rect[kLanes ? kWave : 1];
   uint64_t cov[kLanes ? 1 : PX][kWave];
 };
 
@@ -591,7 +625,7 @@ template <int PX, bool kPersistent, bool kLanes>
 __device__ __forceinline__ void raster_fwd_any(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
                                                int lane, FwdLds<PX, kLanes>& L) {
   unsigned long long pairs;
-  if constexpr (kLanes) pairs = raster_fwd_item_lanes<PX>(a, th, views, item, lane, L.rec, L.pos, L.qid, L.rect);
+  if constexpr (kLanes) pairs = raster_fwd_item_lanes<PX>(a, th, views, item, lane, L.rec, L.pos, L.qid);
   else pairs = raster_fwd_item<PX>(a, th, views, item, lane, L.rec, L.cov);
   if (lane == 0) a.stats[item] = pairs;
 }

@@ -239,6 +239,64 @@ def test_cfg5_view0_image_and_crop_grads_full_size(gpu):
 # tile lists
 # ------------------------------------------------------------------------------------------------
 
+@pytest.mark.parametrize("tw,th,px", [(32, 16, 1), (16, 32, 2), (64, 64, 1)])
+def test_instance_key_block_masks(gpu, tw, th, px):
+    """Every sorted instance key holds its tile id in the low b = ceil(log2(tiles)) bits and, when
+    the tile's raster blocks fit above them, the mask of the 8 x (8 px) blocks its record's pixel
+    rectangle meets (the rasters read only the entries whose bit is set); 64 x 64 tiles (64 blocks)
+    carry no mask.  The mask is recomputed here from the documented layout and the rectangles the
+    projection wrote; both build paths are covered (the one-workgroup build by config 1)."""
+    import ctypes
+    import paper_2602_14493_amd as gmr
+    for k in (2, 1):
+        say(f"key block masks cfg{k} tile {tw}x{th} px {px}")
+        W = wl.make_workload(k)
+        r, verts, colors = gpu_setup(W, tile_w=tw, tile_h=th, px_per_lane=px)
+        rgb, alpha, saved, ws = r.forward(verts, colors, check=True)
+        ro, vo, rc, ko = (ctypes.c_size_t() for _ in range(4))
+        gmr._lib.call("gmr_workspace_view", ctypes.byref(r.batch.c), ctypes.byref(r.opts), ctypes.byref(ro),
+                      ctypes.byref(vo), ctypes.byref(rc), ctypes.byref(ko))
+        w = ws.cpu().numpy()
+        n = r.counters(ws).instances
+        keys = w[ko.value:ko.value + 4 * n].view(np.uint32).astype(np.int64)
+        vals = w[vo.value:vo.value + 4 * n].view(np.uint32).astype(np.int64)
+        nfv = int(sum(W.face_offsets[int(W.view_mesh[v]) + 1] - W.face_offsets[int(W.view_mesh[v])]
+                      for v in range(W.num_views)))
+        rec = w[rc.value:rc.value + 48 * nfv].view(np.uint32).reshape(nfv, 12).astype(np.int64)
+        # tile geometry: view-major, row-major tile numbering
+        sizes = list(r.batch.sizes)
+        tx_n = np.array([(a + tw - 1) // tw for a, _ in sizes])
+        ty_n = np.array([(hh + th - 1) // th for _, hh in sizes])
+        base = np.concatenate([[0], np.cumsum(tx_n * ty_n)])
+        ntiles = int(base[-1])
+        b = 0
+        while (1 << b) < ntiles:
+            b += 1
+        sub_x, sub_y, bh = tw // 8, th // (8 * px), 8 * px
+        masks_on = b <= 26 and sub_x * sub_y <= 32 - b
+        tile = keys & ((1 << b) - 1)
+        # the tile ids are the sorted order's: ascending, each inside the table
+        assert (np.diff(tile) >= 0).all() and tile.max() < ntiles
+        v = np.searchsorted(base, tile, side="right") - 1
+        lt = tile - base[v]
+        X0, Y0 = (lt % tx_n[v]) * tw, (lt // tx_n[v]) * th
+        rx, ry = rec[vals, 7], rec[vals, 11]
+        ix0, ix1, iy0, iy1 = rx & 0xffff, rx >> 16, ry & 0xffff, ry >> 16
+        want = np.zeros(n, dtype=np.int64)
+        for sy in range(sub_y):
+            for sx in range(sub_x):
+                bx0, by0 = X0 + 8 * sx, Y0 + bh * sy
+                meet = (ix0 <= bx0 + 7) & (ix1 >= bx0) & (iy0 <= by0 + bh - 1) & (iy1 >= by0)
+                want |= meet.astype(np.int64) << (sy * sub_x + sx)
+        got = keys >> b
+        say(f"  {n} instances, {ntiles} tiles, b = {b}, masks {'on' if masks_on else 'off'}")
+        if masks_on:
+            assert (want != 0).all(), "an instance whose rectangle meets none of its tile's blocks"
+            assert np.array_equal(got, want)
+        else:
+            assert (got == 0).all()
+
+
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
 def test_tile_lists_bit_exact(gpu, tile):
     """Every tile's list (membership and order) equals the oracle's tile list built from per-pixel
