@@ -109,26 +109,27 @@ __device__ inline bool ellipse_meets_block(const float4& r0, const float4& r1, i
 // Pixels of an 8 x 8 block (bit 8 * row + col) at whose centre the Gaussian's power is at most pmax:
 // pixel (c, r) takes dx = ox - c, dy = oy - r (offsets as staged), and the power is at most pmax
 // exactly where |l11 dx + l12 dy| <= sqrt(pmax - (l22 dy)^2), i.e. for c within
-// ox + (l12 dy -/+ sqrt(pmax - (l22 dy)^2)) / l11 (l11 > 0); the bounds are widened by 1e-3 px and a
-// NaN bound keeps the whole row.  With pmax carrying a margin over the power of the alpha cutoff,
+// ox + (l12 dy -/+ sqrt(pmax - (l22 dy)^2)) / l11.  Records are finite with l11 > 0 (the projection
+// writes none other).  The half-width is widened by 1e-3 px, which covers the hardware square
+// root's and reciprocal's rounding; with pmax carrying a margin over the power of the alpha cutoff,
 // every pixel at which the record reaches alpha_min is inside, so masking a walk with it changes no
-// image.
+// image.  Each bound is clamped to the block before it is converted; an empty range gives no bits.
 __device__ inline uint64_t ellipse_rows(float ox, float oy, float l11, float l12, float l22, float pmax) {
   const float il = __builtin_amdgcn_rcpf(l11);
-  uint64_t m = 0ull;
+  const float w2o = l22 * oy, l12o = l12 * oy;
+  uint32_t m[2] = {0u, 0u};
 #pragma unroll
   for (int r = 0; r < kSub; ++r) {
-    const float dy = oy - (float)r;
-    const float w2 = l22 * dy;
-    const float t = pmax - w2 * w2;
-    const float hw = t != t ? __builtin_inff() : __builtin_sqrtf(fmaxf(t, 0.f)) * il;
-    const float c = fmaf(l12 * dy, il, ox);
-    const int ilo = max((int)ceilf(fmaxf(c - hw - 1e-3f, -1.f)), 0);
-    const int ihi = min((int)floorf(fminf(c + hw + 1e-3f, 8.f)), kSub - 1);
-    const uint32_t bits = (t >= 0.f || t != t) && ilo <= ihi ? (0xFFu << ilo) & (0xFFu >> (kSub - 1 - ihi)) : 0u;
-    m |= (uint64_t)bits << (kSub * r);
+    const float w2 = fmaf(-l22, (float)r, w2o);  // l22 dy
+    const float t = fmaf(-w2, w2, pmax);
+    const float hw = fmaf(__builtin_amdgcn_sqrtf(fmaxf(t, 0.f)), il, 1e-3f);
+    const float c = fmaf(fmaf(-l12, (float)r, l12o), il, ox);
+    const int ilo = (int)ceilf(__builtin_amdgcn_fmed3f(c - hw, 0.f, 8.f));    // 0 .. 8
+    const int ihi = (int)floorf(__builtin_amdgcn_fmed3f(c + hw, -1.f, 7.f));  // -1 .. 7
+    const uint32_t bits = (0xFFu << ilo) & (0xFFu >> (kSub - 1 - ihi));        // 0 when ilo > ihi
+    m[r >> 2] |= (t >= 0.f ? bits : 0u) << (kSub * (r & 3));
   }
-  return m;
+  return (uint64_t)m[0] | ((uint64_t)m[1] << 32);
 }
 
 __device__ inline bool in_range(uint32_t r, int x) {
@@ -193,9 +194,10 @@ __device__ __forceinline__ float add_dpp(float acc, float v) {
   return acc + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, true));
 }
 
-// The value lane ^ B holds, B in {1, 2, 4, 8, 16}.  All lanes must be active.
+// The value lane ^ B holds, B in {1, 2, 4, 8, 16}.  All lanes must be active.  up: all ones in the
+// lanes with (lane & B) set, else 0.
 template <int B>
-__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, uint32_t up) {
   if constexpr (B == 1) return __builtin_amdgcn_update_dpp(0u, v, kDppXor1, 0xF, 0xF, true);
   else if constexpr (B == 2) return __builtin_amdgcn_update_dpp(0u, v, kDppXor2, 0xF, 0xF, true);
   else if constexpr (B == 4) {
@@ -208,16 +210,22 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
     // swapping the odd rows of one copy with the even rows of another leaves row r's partner row
     // in the first copy for odd r and in the second for even r
     const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-    return (lane & 16) ? r[0] : r[1];
+    return (r[0] & up) | (r[1] & ~up);
   }
 }
 
 // One step of the 64 x 64 bit transpose on one 32-bit word: rows (lanes) r and r ^ B exchange the
-// off-diagonal B x B blocks; m selects the bit positions p with (p & B) == 0.
+// off-diagonal B x B blocks; m selects the bit positions p with (p & B) == 0.  A lane without B
+// keeps its m bits and takes the partner's m bits shifted up by B; a lane with B keeps its ~m bits
+// and takes the partner's ~m bits shifted down -- written with masks, not branches (every lane
+// runs the same instructions, as the lane exchanges need).
 template <int B>
-__device__ __forceinline__ uint32_t transpose_step(uint32_t w, int lane, uint32_t m) {
-  const uint32_t y = lane_xor<B>(w, lane);
-  return (lane & B) ? ((w & ~m) | ((y & ~m) >> B)) : ((w & m) | ((y & m) << B));
+__device__ __forceinline__ uint32_t transpose_step(uint32_t w, uint32_t m) {
+  const uint32_t up = 0u - ((__lane_id() >> __builtin_ctz(B)) & 1u);
+  const uint32_t y = lane_xor<B>(w, up);
+  const uint32_t sh = ((y >> B) & up) | ((y << B) & ~up);
+  const uint32_t keep = m ^ up;
+  return (w & keep) | (sh & ~keep);
 }
 
 // Lane r holds row r of a 64 x 64 bit matrix (bit c = entry (r, c)); returns column `lane`.
@@ -229,11 +237,11 @@ __device__ inline uint64_t transpose64(uint64_t x, int lane) {
   const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
   lo = r[0];
   hi = r[1];
-  lo = transpose_step<16>(lo, lane, 0x0000FFFFu); hi = transpose_step<16>(hi, lane, 0x0000FFFFu);
-  lo = transpose_step<8>(lo, lane, 0x00FF00FFu);  hi = transpose_step<8>(hi, lane, 0x00FF00FFu);
-  lo = transpose_step<4>(lo, lane, 0x0F0F0F0Fu);  hi = transpose_step<4>(hi, lane, 0x0F0F0F0Fu);
-  lo = transpose_step<2>(lo, lane, 0x33333333u);  hi = transpose_step<2>(hi, lane, 0x33333333u);
-  lo = transpose_step<1>(lo, lane, 0x55555555u);  hi = transpose_step<1>(hi, lane, 0x55555555u);
+  lo = transpose_step<16>(lo, 0x0000FFFFu); hi = transpose_step<16>(hi, 0x0000FFFFu);
+  lo = transpose_step<8>(lo, 0x00FF00FFu);  hi = transpose_step<8>(hi, 0x00FF00FFu);
+  lo = transpose_step<4>(lo, 0x0F0F0F0Fu);  hi = transpose_step<4>(hi, 0x0F0F0F0Fu);
+  lo = transpose_step<2>(lo, 0x33333333u);  hi = transpose_step<2>(hi, 0x33333333u);
+  lo = transpose_step<1>(lo, 0x55555555u);  hi = transpose_step<1>(hi, 0x55555555u);
   return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
@@ -631,7 +639,10 @@ __device__ __forceinline__ void raster_fwd_any(const FwdArgs& a, const TableHdr*
 }
 
 template <int PX, bool kPersistent, bool kLanes>
-__global__ __launch_bounds__(256) void k_raster_fwd(FwdArgs a) {
+// (one pixel per lane: 8 wavefronts per SIMD (7 persistent), which the register allocator meets
+// without spills; left alone the unrolled row extents of the staging code take ~90 VGPRs)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PX == 1 ? (kPersistent ? 7 : 8) : 1)))
+void k_raster_fwd(FwdArgs a) {
   __shared__ FwdLds<PX, kLanes> s_lds[256 / kWave];
   const TableHdr* th = static_cast<const TableHdr*>(a.table);
   const ViewDev* views = table_views(a.table);
@@ -1025,7 +1036,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
 // colour and transmittance, which each lane reads back from its own stores, so no grid-wide wait
 // separates the two and one list build serves both.  The two walks share the wavefront's LDS slots.
 template <bool kLanes>
-__global__ __launch_bounds__(256) void k_raster_step(FwdArgs fa, BwdArgs ba) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_raster_step(FwdArgs fa, BwdArgs ba) {
   __shared__ FwdLds<1, kLanes> s_f[256 / kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
   __shared__ uint32_t s_pos[256 / kWave][kWave];
