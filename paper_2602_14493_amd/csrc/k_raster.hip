@@ -719,13 +719,19 @@ __device__ inline float wave_reduce8_transpose(const float (&g)[8], int lane) {
 // The same sum through the wavefront's 8 x 64 LDS scratch: row i takes value i of every lane, lane l
 // adds the eight entries of row l >> 3 that lanes 8 (l & 7) .. 8 (l & 7) + 7 wrote, and three DPP
 // steps add the eight lanes of each row group: 8 stores, 2 loads and 10 adds where the exchanges
-// cost 7 lane swaps, 7 adds and 2 selects.
+// cost 7 lane swaps, 7 adds and 2 selects.  Inside each group of eight words the two halves are
+// swapped when h = (i ^ (group >> 2)) & 1 is set, and a reader loads half h first: the 16-byte
+// loads of one pass then cover every bank once (8 lanes of one row over 32 banks, or 16 lanes of
+// two rows over 64), where the plain layout had two lanes on each bank.
 __device__ inline float wave_reduce8_lds(const float (&g)[8], int lane, float* red) {
+  const int grp = lane & ~7, in = lane & 7, hj = (lane >> 5) & 1;
+  const int w_even = grp + (in ^ (4 * hj)), w_odd = grp + (in ^ (4 * (hj ^ 1)));
 #pragma unroll
-  for (int i = 0; i < 8; ++i) red[i * kWave + lane] = g[i];
+  for (int i = 0; i < 8; ++i) red[i * kWave + ((i & 1) ? w_odd : w_even)] = g[i];
   wave_lds_sync();
-  const float4* p = reinterpret_cast<const float4*>(red + (lane >> 3) * kWave + 8 * (lane & 7));
-  const float4 x = p[0], y = p[1];
+  const int row = lane >> 3, p = lane & 7, h = (row ^ (p >> 2)) & 1;
+  const float4* q = reinterpret_cast<const float4*>(red + row * kWave + 8 * p);
+  const float4 x = q[h], y = q[h ^ 1];
   wave_lds_sync();  // a later reduction's stores stay behind these loads
   float r = ((x.x + x.y) + (x.z + x.w)) + ((y.x + y.y) + (y.z + y.w));
   r = add_dpp<kDppXor1>(r, r);        // lane ^ 1
