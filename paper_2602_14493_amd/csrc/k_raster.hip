@@ -1042,7 +1042,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
 // colour and transmittance, which each lane reads back from its own stores, so no grid-wide wait
 // separates the two and one list build serves both.  The two walks share the wavefront's LDS slots.
 template <bool kLanes>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_raster_step(FwdArgs fa, BwdArgs ba) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_raster_step(FwdArgs fa, BwdArgs ba) {
   __shared__ FwdLds<1, kLanes> s_f[256 / kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
   __shared__ uint32_t s_pos[256 / kWave][kWave];
