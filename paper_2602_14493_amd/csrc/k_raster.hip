@@ -276,15 +276,16 @@ struct FwdArgs {
 };
 
 // One list entry as a lane holds it: its key and face-view.  The raster loops load the next batch of
-// 64 entries while they work on the current one; a position outside the (non-empty) list [lo, hi)
-// reads its nearest entry instead, so that the loads need no branch (the caller ignores it) and the
-// compiler can wait for exactly the batch it uses.
+// 64 entries while they work on the current one; positions are relative to the list's start (keys
+// and vals point there), and one outside the non-empty window [0, len) reads its nearest entry
+// instead, so that the loads need no branch (the caller ignores it) and the compiler can wait for
+// exactly the batch it uses.
 struct Entry {
   uint32_t key, id;
 };
 __device__ __forceinline__ Entry load_entry(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                                            int64_t pos, int64_t lo, int64_t hi) {
-  const int64_t q = pos < lo ? lo : (pos >= hi ? hi - 1 : pos);
+                                            int32_t r, int32_t len) {
+  const int32_t q = min(max(r, 0), len - 1);
   return Entry{keys[q], vals[q]};
 }
 
@@ -347,7 +348,10 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
   const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;  // as in the per-lane walk
-  const int kbit = item_key_bit(th, g);
+  const int kbit = __builtin_amdgcn_readfirstlane(item_key_bit(th, g));
+  const uint32_t* __restrict__ lkeys = a.keys + start;  // the tile's list
+  const uint32_t* __restrict__ lvals = a.vals + start;
+  const int32_t len = (int32_t)(end - start);
   float T[PX], C0[PX], C1[PX], C2[PX];
   uint32_t last[PX];
   bool done[PX];
@@ -361,14 +365,14 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
   }
   unsigned long long pairs = 0;
   Entry cur{0u, 0u};
-  if (start < end) cur = load_entry(a.keys, a.vals, (int64_t)start + lane, start, end);  // (empty: no read)
+  if (len > 0) cur = load_entry(lkeys, lvals, lane, len);  // (an empty list reads nothing)
   for (uint32_t cb = start; cb < end; cb += kWave) {
     bool live = false;
 #pragma unroll
     for (int k = 0; k < PX; ++k) live |= !done[k];
     if (__ballot(live) == 0ull) break;
     const uint32_t pos = cb + (uint32_t)lane;
-    const Entry nxt = load_entry(a.keys, a.vals, (int64_t)pos + kWave, start, end);
+    const Entry nxt = load_entry(lkeys, lvals, (int32_t)(pos - start) + kWave, len);
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
     bool ov = false;
     // with masks, an entry's key bit is the rectangle test: only the entries it keeps are read
@@ -540,7 +544,10 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
   const float amin = a.o.alpha_min, amax = a.o.alpha_max, teps = a.o.t_eps;
   // power above which exp2(-power) < alpha_min, with a 2 % margin for rounding
   const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;
-  const int kbit = item_key_bit(th, g);
+  const int kbit = __builtin_amdgcn_readfirstlane(item_key_bit(th, g));
+  const uint32_t* __restrict__ lkeys = a.keys + start;  // the tile's list
+  const uint32_t* __restrict__ lvals = a.vals + start;
+  const int32_t len = (int32_t)(end - start);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
   float T[PX], C0[PX], C1[PX], C2[PX];
   uint32_t last[PX];
@@ -556,7 +563,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
   uint32_t pairs = 0;
   uint32_t nq = 0;  // queued entries (wave-uniform)
   Entry cur{0u, 0u};
-  if (start < end) cur = load_entry(a.keys, a.vals, (int64_t)start + lane, start, end);  // (empty: no read)
+  if (len > 0) cur = load_entry(lkeys, lvals, lane, len);  // (an empty list reads nothing)
   for (uint32_t cb = start; cb < end; cb += kWave) {
     bool live = false;
 #pragma unroll
@@ -566,7 +573,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
       break;
     }
     const uint32_t pos = cb + (uint32_t)lane;
-    const Entry nxt = load_entry(a.keys, a.vals, (int64_t)pos + kWave, start, end);
+    const Entry nxt = load_entry(lkeys, lvals, (int32_t)(pos - start) + kWave, len);
     const uint32_t id = cur.id;
     const bool kept = pos < end && entry_kept<PX>(cur, kbit, a.rec, g);
     cur = nxt;
@@ -961,25 +968,28 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   // power above which exp2(-power) < alpha_min, with a 2 % margin for rounding
   const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;
   unsigned long long pairs = 0;  // wave-uniform count
-  const int kbit = item_key_bit(th, g);
+  const int kbit = __builtin_amdgcn_readfirstlane(item_key_bit(th, g));
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
-  // walk the list back to front from the furthest position any pixel composited; the entries that
-  // meet the block are queued (reverse list order) and staged 64 at a time
+  // walk the list back to front from the furthest position any pixel composited (window [0, mx) of
+  // the tile's list, mx >= 1); the entries that meet the block are queued (reverse list order) and
+  // staged 64 at a time
+  const uint32_t* __restrict__ lkeys = a.keys + start;
+  const uint32_t* __restrict__ lvals = a.vals + start;
+  const int32_t len = (int32_t)mx;
   uint32_t nq = 0;  // queued entries (wave-uniform)
-  const int64_t lo = start, hi0 = (int64_t)start + mx;  // mx >= 1: the window is not empty
-  Entry cur = load_entry(a.keys, a.vals, hi0 - 1 - lane, lo, hi0);
-  for (int64_t hi = hi0; hi > lo; hi -= kWave) {
-    const int64_t pos = hi - 1 - lane;
-    const Entry nxt = load_entry(a.keys, a.vals, pos - kWave, lo, hi0);
+  Entry cur = load_entry(lkeys, lvals, len - 1 - lane, len);
+  for (int32_t hi = len; hi > 0; hi -= kWave) {
+    const int32_t pos = hi - 1 - lane;  // relative to the list's start
+    const Entry nxt = load_entry(lkeys, lvals, pos - kWave, len);
     const uint32_t id = cur.id;
-    const bool kept = pos >= (int64_t)start && entry_kept<PX>(cur, kbit, a.rec, g);
+    const bool kept = pos >= 0 && entry_kept<PX>(cur, kbit, a.rec, g);
     cur = nxt;
     const uint64_t m = __ballot(kept);
     if (m == 0ull) continue;
     const uint32_t cnt = (uint32_t)__popcll(m), slot = nq + (uint32_t)__popcll(m & below);
     if (kept && slot < (uint32_t)kWave) {
       L.id[slot] = id;
-      L.pos[slot] = (uint32_t)(pos - (int64_t)start);
+      L.pos[slot] = (uint32_t)pos;
     }
     if (nq + cnt < (uint32_t)kWave) {
       nq += cnt;
@@ -992,7 +1002,7 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
     if (kept && slot >= (uint32_t)kWave) {  // the overflow starts the next 64
       const uint32_t t = slot - (uint32_t)kWave;
       L.id[t] = id;
-      L.pos[t] = (uint32_t)(pos - (int64_t)start);
+      L.pos[t] = (uint32_t)pos;
     }
     nq = nq + cnt - (uint32_t)kWave;
   }
