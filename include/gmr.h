@@ -144,7 +144,8 @@ gmr_status gmr_view_table_fill(const gmr_batch* batch, const gmr_options* opt, v
 /* Workspace bytes for one forward+backward of this batch at opt->instance_capacity.  The
  * workspace holds the per face-view projected records, the instance keys/values (double
  * buffered), the sort state, the tile ranges and the backward's gradient accumulators.
- * `saved_bytes` is the per-pixel state render_fwd leaves for render_bwd (8 bytes per pixel).
+ * `saved_bytes` is the state render_fwd leaves for render_bwd: 8 bytes per pixel, then 4096
+ * bytes per 8 x 8 raster block (the block's composited list, below).
  * The workspace needs no initialisation, except that zeroing its first 256 bytes once after
  * allocation arms the peak instance counter gmr_read_counters reports. */
 gmr_status gmr_workspace_size(const gmr_batch* batch, const gmr_options* opt, size_t* ws_bytes, size_t* saved_bytes);
@@ -166,8 +167,11 @@ gmr_status gmr_build_adjacency(const int32_t* faces_host, int64_t num_faces, int
  *   verts_dev  [V][3] f32, faces_dev [F][3] i32 (global), colors_dev [V][3] f32 ([V][K][3] with sh_degree)
  *   out_rgb_dev   [P][3] f32  composite + T_final * bg
  *   out_alpha_dev [P]    f32  1 - T_final (may be NULL)
- *   saved_dev     saved_bytes (T_final and the list position after the last composited
- *                 Gaussian, per pixel) -- input of gmr_render_bwd
+ *   saved_dev     saved_bytes: per pixel T_final and the list position after the last
+ *                 composited Gaussian; per raster block the count of the tile-list entries some
+ *                 pixel of the block composited and their positions, ascending (the first 1023;
+ *                 a larger count makes the backward test the block's whole list) -- input of
+ *                 gmr_render_bwd
  *   ws_dev/ws_bytes  workspace of gmr_workspace_size; after the call it holds the sorted
  *                 lists, which gmr_render_bwd may reuse (recompute_lists = 0).
  * If the instance count exceeds the capacity, writes are clamped, the overflow counter is set and

@@ -228,6 +228,10 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
   return GMR_OK;
 }
 
+// The saved buffer: per pixel T_final and the list position after its last composited Gaussian;
+// per raster item the block's composited list (kBlkWords words).
+size_t saved_size(const Plan& p) { return (size_t)p.p_total * 8 + (size_t)p.items_total * kBlkWords * 4; }
+
 // Raster-block masks in the instance keys: above the tile-id bits, where the tile's blocks fit.
 int32_t bm_shift1_of(const Plan& p) {
   int tile_bits = 0;
@@ -477,11 +481,12 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   }
   const float* saved_T = static_cast<const float*>(saved);
   const uint32_t* saved_n = reinterpret_cast<const uint32_t*>(saved_T + p.p_total);
+  const uint32_t* saved_blk = saved_n + p.p_total;
   const double n3 = 3.0 * (double)p.p_total;
   {
     StageTimer t(h, s, kStRasterBwd);
     launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals,
-                      w.keysF, w.rec, ko, saved_T, saved_n, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
+                      w.keysF, w.rec, ko, saved_T, saved_n, saved_blk, d_rgb, d_alpha, rgb, target, (float)(2.0 * loss_weight / n3), (float)(loss_weight / n3),
                       mask, (float)(sil_weight / (double)p.p_total), w.dfv, w.statB, s);
   }
   // fused loss: fixed-order sum of the per-item slots into the header (and loss_dev), carried by
@@ -634,7 +639,7 @@ gmr_status gmr_workspace_size(const gmr_batch* batch, const gmr_options* opt, si
   gmr_status st = make_plan(batch, opt, true, p);
   if (st != GMR_OK) return st;
   *ws_bytes = p.L.total;
-  *saved_bytes = (size_t)p.p_total * 8;
+  *saved_bytes = saved_size(p);
   return GMR_OK;
 }
 
@@ -663,11 +668,12 @@ void fwd_impl(gmr_ctx* h, const Plan& p, const gmr_options* opt, const void* tab
   build_lists(h, p, opt, table, verts, faces, colors, w, false, s, timed);
   float* saved_T = static_cast<float*>(saved);
   uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
+  uint32_t* saved_blk = saved_n + p.p_total;
   {
     StageTimer t(timed ? h : nullptr, s, kStRasterFwd);
     launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0, w.ranges,
                       w.sorted_vals, w.keysF, w.rec, kopts(opt),
-                      out_rgb, out_alpha, saved_T, saved_n, w.statF, s);
+                      out_rgb, out_alpha, saved_T, saved_n, saved_blk, w.statF, s);
   }
 }
 }  // namespace
@@ -789,23 +795,27 @@ gmr_status step_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* op
   build_lists(h, p, opt, table, verts, faces, colors, w, true, s, true, true);
   float* saved_T = static_cast<float*>(saved);
   uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
+  uint32_t* saved_blk = saved_n + p.p_total;
   const double n3 = 3.0 * (double)p.p_total;
   const float gs = (float)(2.0 * color_weight / n3), ls = (float)(color_weight / n3);
   const float ss = (float)(sil_weight / (double)p.p_total);
   if (opt->px_per_lane == 1 && persistent_blocks(h, opt) == 0) {  // one launch composites and differentiates
     StageTimer t(h, s, kStRasterStep);
     launch_raster_step(table, p.items_total, opt->lane_lists != 0, w.ranges, w.sorted_vals, w.keysF, w.rec, ko,
-                       out_rgb, out_alpha, saved_T, saved_n, w.statF, target, gs, ls, mask, ss, w.dfv, w.statB, s);
+                       out_rgb, out_alpha, saved_T, saved_n, saved_blk, w.statF, target, gs, ls, mask, ss, w.dfv,
+                       w.statB, s);
   } else {
     {
       StageTimer t(h, s, kStRasterFwd);
       launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0,
-                        w.ranges, w.sorted_vals, w.keysF, w.rec, ko, out_rgb, out_alpha, saved_T, saved_n, w.statF, s);
+                        w.ranges, w.sorted_vals, w.keysF, w.rec, ko, out_rgb, out_alpha, saved_T, saved_n, saved_blk,
+                        w.statF, s);
     }
     {
       StageTimer t(h, s, kStRasterBwd);
       launch_raster_bwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, w.ranges, w.sorted_vals,
-                        w.keysF, w.rec, ko, saved_T, saved_n, nullptr, nullptr, out_rgb, target, gs, ls, mask, ss, w.dfv,
+                        w.keysF, w.rec, ko, saved_T, saved_n, saved_blk, nullptr, nullptr, out_rgb, target, gs, ls, mask,
+                        ss, w.dfv,
                         w.statB, s);
     }
   }
@@ -1019,9 +1029,8 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
   float *&rgb = sc.rgb, *&dv = sc.dv, *&dc = sc.dc;
   void *&saved = sc.saved, *&ws = sc.ws, *&table = sc.table;
   hipEvent_t &e0 = sc.e0, &e1 = sc.e1;
-  size_t ws_cap = 0, table_cap = 0;
+  size_t ws_cap = 0, table_cap = 0, saved_cap = 0;  // grown per candidate (their raster items differ)
   GMR_CHECK_HIP(hipMalloc(&rgb, sizeof(float) * 3 * p0.p_total));
-  GMR_CHECK_HIP(hipMalloc(&saved, 8 * p0.p_total));
   GMR_CHECK_HIP(hipMalloc(&dv, sizeof(float) * 3 * p0.v_total));
   // colour gradients have the colours' layout: (sh_degree + 1)^2 coefficients per channel
   const size_t n_coef = (size_t)(b.sh_degree + 1) * (b.sh_degree + 1);
@@ -1053,6 +1062,12 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
         ws = nullptr;
         ws_cap = p.L.total;
         if (hipMalloc(&ws, ws_cap) != hipSuccess) return fail(GMR_ERR_HIP, "autotune: hipMalloc workspace");
+      }
+      if (saved_size(p) > saved_cap) {
+        if (saved) (void)hipFree(saved);
+        saved = nullptr;
+        saved_cap = saved_size(p);
+        if (hipMalloc(&saved, saved_cap) != hipSuccess) return fail(GMR_ERR_HIP, "autotune: hipMalloc saved");
       }
       if ((r = gmr_render_fwd(h, batch, &o, table, verts, faces, colors, rgb, nullptr, saved, ws, ws_cap, s)) != GMR_OK)
         return r;

@@ -101,6 +101,10 @@ __device__ inline uint32_t rect_block_mask(int ix0, int ix1, int iy0, int iy1, i
   return block_mask((uint32_t)clo, (uint32_t)chi, (uint32_t)rlo, (uint32_t)rhi, (uint32_t)sub_x);
 }
 
+// Per raster item in the saved buffer (after the per-pixel state): the count and the list positions
+// of the Gaussians its block composited, kBlkCap at most (a larger count: the list did not fit).
+constexpr int kBlkWords = 1024, kBlkCap = kBlkWords - 1;
+
 // Workspace header (device counters) ------------------------------------------------------------
 struct WsHdr {                 // 256 B at the start of the workspace
   uint32_t count;              // instances generated (may exceed capacity)

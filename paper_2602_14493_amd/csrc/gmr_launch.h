@@ -59,7 +59,7 @@ void launch_loss_reduce(const LossRed& r, hipStream_t s);
 void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists, const uint32_t* ranges,
                        const uint32_t* vals, const uint32_t* keys,
                        const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
-                       uint32_t* saved_n, unsigned long long* stats, hipStream_t s);
+                       uint32_t* saved_n, uint32_t* blk, unsigned long long* stats, hipStream_t s);
 
 // One step's compositing for the fused colour loss, with the silhouette term when mask is given
 // (one pixel per lane, plain grid): per wavefront the forward of its block (image, alpha, saved
@@ -67,12 +67,13 @@ void launch_raster_fwd(const void* table, int items, int persistent_blocks, int 
 // statistics).
 void launch_raster_step(const void* table, int items, bool lane_lists, const uint32_t* ranges, const uint32_t* vals,
                         const uint32_t* keys, const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
-                        uint32_t* saved_n, unsigned long long* stats_fwd, const float* target, float l2_grad_scale,
+                        uint32_t* saved_n, uint32_t* blk, unsigned long long* stats_fwd, const float* target,
+                        float l2_grad_scale,
                         float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats_bwd,
                         hipStream_t s);
 void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges, const uint32_t* vals,
                        const uint32_t* keys, const float4* rec, const KOpts& o, const float* saved_T, const uint32_t* saved_n,
-                       const float* d_rgb, const float* d_alpha, const float* rgb, const float* target, float l2_grad_scale,
+                       const uint32_t* blk, const float* d_rgb, const float* d_alpha, const float* rgb, const float* target, float l2_grad_scale,
                        float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats,
                        hipStream_t s);
 

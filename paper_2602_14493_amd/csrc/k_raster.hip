@@ -49,6 +49,7 @@ struct ItemGeo {
 
 template <int PX>
 __device__ inline ItemGeo item_geometry(const TableHdr* th, const ViewDev* views, int item, int lane) {
+  item = __builtin_amdgcn_readfirstlane(item);  // one item per wavefront: keep its geometry scalar
   ItemGeo g;
   const int spt = th->sub_x * th->sub_y;
   g.tile = item / spt;
@@ -272,6 +273,7 @@ struct FwdArgs {
   float* out_alpha;
   float* saved_T;
   uint32_t* saved_n;
+  uint32_t* blk;              // [items][kBlkWords] composited lists (see blk_append), or NULL
   unsigned long long* stats;  // [items] pairs evaluated per item (summed on the host when read)
 };
 
@@ -299,15 +301,32 @@ __device__ __forceinline__ bool entry_kept(const Entry& e, int kbit, const float
   return rect_meets_block(f2u(rp[1].w), f2u(rp[2].w), g.bx0, g.by0, kSub * PX);
 }
 
+// A block's composited list.  Per raster item the forward records, in list order, the list positions
+// (relative to the tile's list start) of the Gaussians that at least one of its pixels composited:
+// word 0 the count, words 1 .. kBlkCap the positions (those past the count undefined; a count above
+// kBlkCap means the list did not fit).  The backward walks only these -- a Gaussian no pixel of the
+// block composited adds nothing to the block's gradients -- instead of testing every entry of the
+// tile's list against the block.  Appends the staged slots set in the wave-uniform mask M (slot j
+// at list position pos_j), in slot order, to the item's list g.
+__device__ __forceinline__ void blk_append(uint32_t* g, uint64_t M, uint32_t pos_lane, uint32_t& cnt, int lane) {
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if ((M >> lane) & 1ull) {
+    const uint32_t idx = cnt + (uint32_t)__popcll(M & below);
+    if (idx < (uint32_t)kBlkCap) g[1 + idx] = pos_lane;
+  }
+  cnt += (uint32_t)__popcll(M);
+}
+
 // One record against a lane's PX pixels; `valid` = false makes it a no-op (predicated).  a = s[0][j],
 // b = s[1][j]; cov[k]: the record's pixel-rectangle coverage of row group k (bit = lane), uniform.
 template <int PX>
-__device__ __forceinline__ void fwd_eval(const float4& a, const float4& b, const float (&oy)[PX],
+__device__ __forceinline__ bool fwd_eval(const float4& a, const float4& b, const float (&oy)[PX],
                                          const uint64_t (&cov)[PX], bool valid, uint32_t pos_next, float lxf,
                                          float lyf, float amin, float amax, float teps, float (&T)[PX],
                                          float (&C0)[PX], float (&C1)[PX], float (&C2)[PX], uint32_t (&last)[PX],
                                          bool (&done)[PX], unsigned long long& pairs) {
   const float dx = a.x - lxf;
+  bool any = false;  // some pixel composited it
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     const bool act = valid && !done[k] && __builtin_amdgcn_inverse_ballot_w64(cov[k]);
@@ -320,6 +339,7 @@ __device__ __forceinline__ void fwd_eval(const float4& a, const float4& b, const
     const float Tn = T[k] * (1.f - al);
     const bool stop = ok && Tn < teps;
     const bool comp = ok && !(Tn < teps);
+    any = any || comp;
     pairs += (unsigned long long)__popcll(__ballot(act));  // wave-uniform, scalar unit
     done[k] = done[k] || stop;
     const float wt = al * T[k];
@@ -329,6 +349,7 @@ __device__ __forceinline__ void fwd_eval(const float4& a, const float4& b, const
     T[k] = comp ? Tn : T[k];
     last[k] = comp ? pos_next : last[k];
   }
+  return __ballot(any) != 0ull;  // wave-uniform
 }
 
 // A wave-uniform 64-bit value from LDS into scalar registers.
@@ -340,9 +361,14 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 // Returns the item's pair count (wave-uniform).
 template <int PX>
 __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const TableHdr* th, const ViewDev* views,
-                                                     int item, int lane, float4 (*s)[kWave], uint64_t (*scov)[kWave]) {
+                                                     int item, int lane, float4 (*s)[kWave], uint64_t (*scov)[kWave],
+                                                     uint32_t& bcnt) {
+  item = __builtin_amdgcn_readfirstlane(item);
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
-  if (!g.any) return 0ull;
+  if (!g.any) {  // a block past the image's edge composites nothing
+    if (a.blk && lane == 0) a.blk[(size_t)item * kBlkWords] = 0u;
+    return 0ull;
+  }
   const int ly = lane >> 3;
   const float lxf = (float)(lane & 7), lyf = (float)ly;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
@@ -364,6 +390,8 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
     done[k] = !(g.x < g.W && y[k] < g.H);
   }
   unsigned long long pairs = 0;
+  bcnt = 0;  // composited Gaussians (wave-uniform)
+  uint32_t* const bg = a.blk ? a.blk + (size_t)item * kBlkWords : nullptr;
   Entry cur{0u, 0u};
   if (len > 0) cur = load_entry(lkeys, lvals, lane, len);  // (an empty list reads nothing)
   for (uint32_t cb = start; cb < end; cb += kWave) {
@@ -413,10 +441,16 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
         cv1[k] = uniform64(scov[k][j1]);
         cv2[k] = uniform64(scov[k][j2]);
       }
-      fwd_eval<PX>(a0, a1, oy1, cv1, true, cb + (uint32_t)j1 - start + 1u, lxf, lyf, amin, amax, teps, T, C0, C1,
-                   C2, last, done, pairs);
-      fwd_eval<PX>(b0, b1, oy2, cv2, has2, cb + (uint32_t)j2 - start + 1u, lxf, lyf, amin, amax, teps, T, C0, C1,
-                   C2, last, done, pairs);
+      const bool c1 = fwd_eval<PX>(a0, a1, oy1, cv1, true, cb + (uint32_t)j1 - start + 1u, lxf, lyf, amin, amax,
+                                   teps, T, C0, C1, C2, last, done, pairs);
+      const bool c2 = fwd_eval<PX>(b0, b1, oy2, cv2, has2, cb + (uint32_t)j2 - start + 1u, lxf, lyf, amin, amax,
+                                   teps, T, C0, C1, C2, last, done, pairs);
+      if (bg && lane == 0) {  // list order: j1 before j2
+        const uint32_t i1 = bcnt, i2 = bcnt + (c1 ? 1u : 0u);
+        if (c1 && i1 < (uint32_t)kBlkCap) bg[1 + i1] = cb + (uint32_t)j1 - start;
+        if (c2 && i2 < (uint32_t)kBlkCap) bg[1 + i2] = cb + (uint32_t)j2 - start;
+      }
+      bcnt += (c1 ? 1u : 0u) + (c2 ? 1u : 0u);
       bool live2 = false;
 #pragma unroll
       for (int k = 0; k < PX; ++k) live2 |= !done[k];
@@ -437,6 +471,7 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
       a.saved_n[p] = last[k];
     }
   }
+  if (bg && lane == 0) bg[0] = bcnt;
   return pairs;
 }
 
@@ -452,7 +487,7 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
                                                const uint64_t (&cov)[PX], float lxf, float lyf, float amin,
                                                float amax, float teps, float (&T)[PX], float (&C0)[PX],
                                                float (&C1)[PX], float (&C2)[PX], uint32_t (&last)[PX],
-                                               bool (&done)[PX], uint32_t& pairs, int lane) {
+                                               bool (&done)[PX], uint32_t& pairs, uint32_t* s_comp, int lane) {
   uint64_t mine[PX];
 #pragma unroll
   for (int k = 0; k < PX; ++k) mine[k] = transpose64(cov[k], lane);
@@ -495,6 +530,7 @@ __device__ __forceinline__ void fwd_walk_lanes(const float4 (*s)[kWave], const u
             C2[k] = fmaf(b.w, wt, C2[k]);
             T[k] = Tn;
             last[k] = s_pos[j];
+            s_comp[j] = 1u;  // some pixel composited slot j
           }
         }
       }
@@ -509,7 +545,9 @@ __device__ __forceinline__ void fwd_stage_walk(const FwdArgs& a, float4 (*s)[kWa
                                                const uint32_t* s_qid, uint32_t n, const ItemGeo& g, float pmax,
                                                float lxf, float lyf, float amin, float amax, float teps,
                                                float (&T)[PX], float (&C0)[PX], float (&C1)[PX], float (&C2)[PX],
-                                               uint32_t (&last)[PX], bool (&done)[PX], uint32_t& pairs, int lane) {
+                                               uint32_t (&last)[PX], bool (&done)[PX], uint32_t& pairs,
+                                               uint32_t* s_comp, uint32_t* bg, uint32_t& bcnt,
+                                               int lane) {
   uint64_t cov[PX];
 #pragma unroll
   for (int k = 0; k < PX; ++k) cov[k] = 0ull;
@@ -523,8 +561,14 @@ __device__ __forceinline__ void fwd_stage_walk(const FwdArgs& a, float4 (*s)[kWa
       cov[k] = block_coverage(f2u(r1.w), f2u(r2.w), g.bx0, g.by0 + kSub * k) &
                ellipse_rows(ox, block_off(r0.y, r0.w, g.by0 + kSub * k), r1.x, r1.y, r1.z, pmax);
   }
+  s_comp[lane] = 0u;
   wave_lds_sync();
-  fwd_walk_lanes<PX>(s, s_pos, cov, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done, pairs, lane);
+  fwd_walk_lanes<PX>(s, s_pos, cov, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done, pairs, s_comp, lane);
+  if (bg) {
+    wave_lds_sync();
+    const uint64_t M = __ballot(s_comp[lane] != 0u);  // the slots some pixel composited
+    blk_append(bg, M, (uint32_t)lane < n ? s_pos[lane] - 1u : 0u, bcnt, lane);
+  }
 }
 
 // Forward with per-lane lists.  The tile's list is read 64 entries at a time; the face-views of the
@@ -535,9 +579,13 @@ __device__ __forceinline__ void fwd_stage_walk(const FwdArgs& a, float4 (*s)[kWa
 template <int PX>
 __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, const TableHdr* th, const ViewDev* views,
                                                            int item, int lane, float4 (*s)[kWave], uint32_t* s_pos,
-                                                           uint32_t* s_qid) {
+                                                           uint32_t* s_qid, uint32_t* s_comp, uint32_t& bcnt) {
+  item = __builtin_amdgcn_readfirstlane(item);
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
-  if (!g.any) return 0ull;
+  if (!g.any) {  // a block past the image's edge composites nothing
+    if (a.blk && lane == 0) a.blk[(size_t)item * kBlkWords] = 0u;
+    return 0ull;
+  }
   const int ly = lane >> 3;
   const float lxf = (float)(lane & 7), lyf = (float)ly;
   const uint32_t start = a.ranges[2 * (size_t)g.tile], end = a.ranges[2 * (size_t)g.tile + 1];
@@ -562,6 +610,8 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
   }
   uint32_t pairs = 0;
   uint32_t nq = 0;  // queued entries (wave-uniform)
+  bcnt = 0;         // composited Gaussians (wave-uniform)
+  uint32_t* const bg = a.blk ? a.blk + (size_t)item * kBlkWords : nullptr;
   Entry cur{0u, 0u};
   if (len > 0) cur = load_entry(lkeys, lvals, lane, len);  // (an empty list reads nothing)
   for (uint32_t cb = start; cb < end; cb += kWave) {
@@ -590,7 +640,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
     }
     wave_lds_sync();
     fwd_stage_walk<PX>(a, s, s_pos, s_qid, (uint32_t)kWave, g, pmax, lxf, lyf, amin, amax, teps, T, C0, C1, C2,
-                       last, done, pairs, lane);
+                       last, done, pairs, s_comp, bg, bcnt, lane);
     wave_lds_sync();
     if (kept && slot >= (uint32_t)kWave) {  // the overflow starts the next 64
       const uint32_t t = slot - (uint32_t)kWave;
@@ -602,7 +652,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
   if (nq > 0) {
     wave_lds_sync();
     fwd_stage_walk<PX>(a, s, s_pos, s_qid, nq, g, pmax, lxf, lyf, amin, amax, teps, T, C0, C1, C2, last, done,
-                       pairs, lane);
+                       pairs, s_comp, bg, bcnt, lane);
   }
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
@@ -617,6 +667,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
       a.saved_n[p] = last[k];
     }
   }
+  if (bg && lane == 0) bg[0] = bcnt;
   // wave sum of the per-lane pair counts
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) pairs += (uint32_t)__shfl_xor((int)pairs, d, kWave);
@@ -633,15 +684,19 @@ struct FwdLds {
   float4 rec[PX > 1 ? 3 : 2][kWave];
   uint32_t pos[kLanes ? kWave : 1];
   uint32_t qid[kLanes ? kWave : 1];  // queued face-views (per-lane lists)
+  uint32_t comp[kLanes ? kWave : 1]; // per staged slot: some pixel composited it (per-lane lists)
   uint64_t cov[kLanes ? 1 : PX][kWave];
 };
 
+// bcnt: the item's composited-list count (see blk_append).
 template <int PX, bool kPersistent, bool kLanes>
 __device__ __forceinline__ void raster_fwd_any(const FwdArgs& a, const TableHdr* th, const ViewDev* views, int item,
-                                               int lane, FwdLds<PX, kLanes>& L) {
+                                               int lane, FwdLds<PX, kLanes>& L, uint32_t& bcnt) {
   unsigned long long pairs;
-  if constexpr (kLanes) pairs = raster_fwd_item_lanes<PX>(a, th, views, item, lane, L.rec, L.pos, L.qid);
-  else pairs = raster_fwd_item<PX>(a, th, views, item, lane, L.rec, L.cov);
+  bcnt = 0;
+  if constexpr (kLanes)
+    pairs = raster_fwd_item_lanes<PX>(a, th, views, item, lane, L.rec, L.pos, L.qid, L.comp, bcnt);
+  else pairs = raster_fwd_item<PX>(a, th, views, item, lane, L.rec, L.cov, bcnt);
   if (lane == 0) a.stats[item] = pairs;
 }
 
@@ -661,11 +716,13 @@ void k_raster_fwd(FwdArgs a) {
     const int groups = (items + 3) / 4;
     for (int v = (int)blockIdx.x; v < groups; v += (int)gridDim.x) {
       const int item = xcd_remap(v, groups) * 4 + w;
-      if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_lds[w]);
+      uint32_t bcnt;
+      if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_lds[w], bcnt);
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
-    if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_lds[w]);
+    uint32_t bcnt;
+    if (item < items) raster_fwd_any<PX, kPersistent, kLanes>(a, th, views, item, lane, s_lds[w], bcnt);
   }
 }
 
@@ -681,6 +738,7 @@ struct BwdArgs {
   KOpts o;
   const float* saved_T;
   const uint32_t* saved_n;
+  const uint32_t* blk;    // [items][kBlkWords] the forward's composited lists, or NULL
   const float* d_rgb;     // explicit upstream (or NULL with the L2 form)
   const float* d_alpha;   // may be NULL
   const float* rgb;       // L2 form: forward output
@@ -870,17 +928,21 @@ __device__ __forceinline__ void bwd_batch_uniform(const BwdArgs& a, const BwdLds
 
 // Stage the n queued entries (face-views L.id[0, n), in reverse list order) and walk those whose
 // Gaussian can reach the alpha cutoff in the block.
+// own: this lane's slot holds an entry (slot = lane); composited: the entries are from the forward's
+// composited list, so they meet the block (no ellipse test).
 template <int PX>
-__device__ __forceinline__ void bwd_stage_walk(const BwdArgs& a, const BwdLds& L, uint32_t n, const ItemGeo& g,
-                                               float pmax, float lxf, float lyf, float amin, float amax,
-                                               const float (&gc0)[PX], const float (&gc1)[PX], const float (&gc2)[PX],
-                                               const float (&K)[PX], const uint32_t (&last)[PX], float (&T)[PX],
-                                               float (&S)[PX], unsigned long long& pairs, int lane) {
+__device__ __forceinline__ void bwd_stage_walk(const BwdArgs& a, const BwdLds& L, bool own, bool composited,
+                                               const ItemGeo& g, float pmax, float lxf, float lyf, float amin,
+                                               float amax, const float (&gc0)[PX], const float (&gc1)[PX],
+                                               const float (&gc2)[PX], const float (&K)[PX],
+                                               const uint32_t (&last)[PX], float (&T)[PX], float (&S)[PX],
+                                               unsigned long long& pairs, int lane) {
   bool ov = false;
-  if ((uint32_t)lane < n) {
+  if (own) {
     const float4* rp = a.rec + (size_t)kRecF4 * L.id[lane];
     const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
-    ov = ellipse_meets_block(r0, r1, g.bx0, g.by0, kSub * PX, pmax);  // the rectangle meets it (queued)
+    // the rectangle meets the block (queued by its key bit or rectangle test)
+    ov = composited || ellipse_meets_block(r0, r1, g.bx0, g.by0, kSub * PX, pmax);
     stage_record<PX>(L.rec, lane, r0, r1, r2, g.bx0, g.by0);
 #pragma unroll
     for (int k = 0; k < PX; ++k)
@@ -892,9 +954,12 @@ __device__ __forceinline__ void bwd_stage_walk(const BwdArgs& a, const BwdLds& L
   bwd_batch_uniform<PX>(a, L, m, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
 }
 
+// bl / bcnt: the forward's composited list of this item (positions from bl[0]) and its count; a NULL
+// list or a count above kBlkCap walks the tile's list instead.
 template <int PX, bool kL2>
 __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
-                                       const BwdLds& L) {
+                                       const BwdLds& L, const uint32_t* bl, uint32_t bcnt) {
+  item = __builtin_amdgcn_readfirstlane(item);
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return make_float4(0.f, 0.f, 0.f, 0.f);
   const int ly = lane >> 3;
@@ -968,6 +1033,20 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   // power above which exp2(-power) < alpha_min, with a 2 % margin for rounding
   const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;
   unsigned long long pairs = 0;  // wave-uniform count
+  if (bl && bcnt <= (uint32_t)kBlkCap) {
+    // the Gaussians some pixel of the block composited, latest first, 64 per round; a position past
+    // the pixels' furthest stop cannot come from a forward of these lists and is skipped
+    for (int32_t hi = (int32_t)bcnt; hi > 0; hi -= kWave) {
+      const int32_t i = hi - 1 - lane;
+      const uint32_t p = i >= 0 ? bl[i] : 0u;
+      const bool own = i >= 0 && p < mx;
+      L.id[lane] = own ? a.vals[start + p] : 0u;
+      L.pos[lane] = p;
+      bwd_stage_walk<PX>(a, L, own, true, g, pmax, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
+      wave_lds_sync();  // the next round restages the slots
+    }
+    return make_float4(loss, loss_sil, u2f((uint32_t)pairs), u2f((uint32_t)(pairs >> 32)));
+  }
   const int kbit = __builtin_amdgcn_readfirstlane(item_key_bit(th, g));
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes < this one
   // walk the list back to front from the furthest position any pixel composited (window [0, mx) of
@@ -996,8 +1075,7 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
       continue;
     }
     wave_lds_sync();
-    bwd_stage_walk<PX>(a, L, (uint32_t)kWave, g, pmax, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs,
-                       lane);
+    bwd_stage_walk<PX>(a, L, true, false, g, pmax, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
     wave_lds_sync();
     if (kept && slot >= (uint32_t)kWave) {  // the overflow starts the next 64
       const uint32_t t = slot - (uint32_t)kWave;
@@ -1008,7 +1086,8 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   }
   if (nq > 0) {
     wave_lds_sync();
-    bwd_stage_walk<PX>(a, L, nq, g, pmax, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S, pairs, lane);
+    bwd_stage_walk<PX>(a, L, (uint32_t)lane < nq, false, g, pmax, lxf, lyf, amin, amax, gc0, gc1, gc2, K, last, T, S,
+                       pairs, lane);
     wave_lds_sync();
   }
   return make_float4(loss, loss_sil, u2f((uint32_t)pairs), u2f((uint32_t)(pairs >> 32)));
@@ -1031,14 +1110,18 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     for (int v = (int)blockIdx.x; v < groups; v += (int)gridDim.x) {
       const int item = xcd_remap(v, groups) * 4 + w;
       if (item < items) {
-        const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
+        const uint32_t* bl = a.blk ? a.blk + (size_t)item * kBlkWords + 1 : nullptr;
+        const uint32_t bc = a.blk ? __builtin_amdgcn_readfirstlane(a.blk[(size_t)item * kBlkWords]) : ~0u;
+        const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L, bl, bc);
         if (lane == 0) a.stats[item] = st;
       }
     }
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
     if (item < items) {
-      const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L);
+      const uint32_t* bl = a.blk ? a.blk + (size_t)item * kBlkWords + 1 : nullptr;
+      const uint32_t bc = a.blk ? __builtin_amdgcn_readfirstlane(a.blk[(size_t)item * kBlkWords]) : ~0u;
+      const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L, bl, bc);
       if (lane == 0) a.stats[item] = st;
     }
   }
@@ -1052,7 +1135,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
 // colour and transmittance, which each lane reads back from its own stores, so no grid-wide wait
 // separates the two and one list build serves both.  The two walks share the wavefront's LDS slots.
 template <bool kLanes>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_raster_step(FwdArgs fa, BwdArgs ba) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_raster_step(FwdArgs fa, BwdArgs ba) {
   __shared__ FwdLds<1, kLanes> s_f[256 / kWave];
   __shared__ uint32_t s_id[256 / kWave][kWave];
   __shared__ uint32_t s_pos[256 / kWave][kWave];
@@ -1062,23 +1145,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
   if (item >= th->items_total) return;
-  raster_fwd_any<1, false, kLanes>(fa, th, views, item, lane, s_f[w]);
+  uint32_t bcnt;
+  raster_fwd_any<1, false, kLanes>(fa, th, views, item, lane, s_f[w], bcnt);
   wave_lds_sync();  // the backward restages the slots
+  // the composited list the forward stored is read back by other lanes of this wavefront
+  __threadfence_block();
   const BwdLds Lb{s_f[w].rec, s_id[w], s_pos[w], s_f[w].cov, s_red[w]};
-  const float4 st = raster_bwd_item<1, true>(ba, th, views, item, lane, Lb);
+  const uint32_t* bl = fa.blk ? fa.blk + (size_t)item * kBlkWords + 1 : nullptr;
+  const float4 st = raster_bwd_item<1, true>(ba, th, views, item, lane, Lb, bl, bcnt);
   if (lane == 0) ba.stats[item] = st;
 }
 
 void launch_raster_step(const void* table, int items, bool lane_lists, const uint32_t* ranges, const uint32_t* vals,
                         const uint32_t* keys, const float4* rec, const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T,
-                        uint32_t* saved_n, unsigned long long* stats_fwd, const float* target, float l2_grad_scale,
+                        uint32_t* saved_n, uint32_t* blk, unsigned long long* stats_fwd, const float* target, float l2_grad_scale,
                         float l2_loss_scale, const float* mask, float sil_scale, float* dfv, float4* stats_bwd,
                         hipStream_t s) {
   if (items <= 0) return;
-  const FwdArgs fa{table, ranges, vals, keys, rec, o, out_rgb, out_alpha, saved_T, saved_n, stats_fwd};
-  const BwdArgs ba{table,  ranges,        vals,          keys, rec,       o,         saved_T, saved_n, nullptr,
-                   nullptr, out_rgb,      target,        l2_grad_scale,   l2_loss_scale, mask, sil_scale, dfv,
-                   stats_bwd};
+  const FwdArgs fa{table, ranges, vals, keys, rec, o, out_rgb, out_alpha, saved_T, saved_n, blk, stats_fwd};
+  const BwdArgs ba{table,   ranges,  vals,   keys,          rec,           o,    saved_T,   saved_n, blk,
+                   nullptr, nullptr, out_rgb, target,       l2_grad_scale, l2_loss_scale, mask, sil_scale,
+                   dfv,     stats_bwd};
   const dim3 grid((unsigned)((items + 3) / 4));
   if (lane_lists) hipLaunchKernelGGL((k_raster_step<true>), grid, dim3(256), 0, s, fa, ba);
   else hipLaunchKernelGGL((k_raster_step<false>), grid, dim3(256), 0, s, fa, ba);
@@ -1107,8 +1194,8 @@ static void bwd_dispatch(const BwdArgs& a, bool l2, int items, int persistent_bl
 void launch_raster_fwd(const void* table, int items, int persistent_blocks, int px, bool lane_lists,
                        const uint32_t* ranges, const uint32_t* vals, const uint32_t* keys, const float4* rec,
                        const KOpts& o, float* out_rgb, float* out_alpha, float* saved_T, uint32_t* saved_n,
-                       unsigned long long* stats, hipStream_t s) {
-  FwdArgs a{table, ranges, vals, keys, rec, o, out_rgb, out_alpha, saved_T, saved_n, stats};
+                       uint32_t* blk, unsigned long long* stats, hipStream_t s) {
+  FwdArgs a{table, ranges, vals, keys, rec, o, out_rgb, out_alpha, saved_T, saved_n, blk, stats};
   if (items <= 0) return;
   if (lane_lists) {
     if (px == 4) fwd_dispatch<4, true>(a, items, persistent_blocks, s);
@@ -1123,11 +1210,11 @@ void launch_raster_fwd(const void* table, int items, int persistent_blocks, int 
 
 void launch_raster_bwd(const void* table, int items, int persistent_blocks, int px, const uint32_t* ranges,
                        const uint32_t* vals, const uint32_t* keys, const float4* rec, const KOpts& o, const float* saved_T,
-                       const uint32_t* saved_n, const float* d_rgb, const float* d_alpha, const float* rgb,
+                       const uint32_t* saved_n, const uint32_t* blk, const float* d_rgb, const float* d_alpha, const float* rgb,
                        const float* target, float l2_grad_scale, float l2_loss_scale, const float* mask,
                        float sil_scale, float* dfv, float4* stats, hipStream_t s) {
-  BwdArgs a{table, ranges, vals,          keys,          rec,  o,         saved_T, saved_n, d_rgb, d_alpha,
-            rgb,   target, l2_grad_scale, l2_loss_scale, mask, sil_scale, dfv,     stats};
+  BwdArgs a{table, ranges, vals,   keys,          rec,           o,    saved_T,   saved_n, blk, d_rgb,
+            d_alpha, rgb, target, l2_grad_scale, l2_loss_scale, mask, sil_scale, dfv, stats};
   if (items <= 0) return;
   const bool l2 = target != nullptr;
   if (px == 4) bwd_dispatch<4>(a, l2, items, persistent_blocks, s);

@@ -66,7 +66,8 @@ def test_view_table_and_workspace_sizes():
     assert buf[32:40].view(np.int64)[0] == fv_total
     ws, saved = ctypes.c_size_t(), ctypes.c_size_t()
     _lib.call("gmr_workspace_size", ctypes.byref(b.c), ctypes.byref(o), ctypes.byref(ws), ctypes.byref(saved))
-    assert saved.value == 8 * W.num_pixels
+    # per pixel T_final + list position; per raster item its composited list (1024 words)
+    assert saved.value == 8 * W.num_pixels + 1024 * 4 * hdr[7]
     assert ws.value >= (1 << 20) * 24 + fv_total * (48 + 16 + 4 + 32)
 
 

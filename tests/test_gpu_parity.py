@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gmr_testutil import (compare_grads, compare_images, fv_to_face, gpu_setup, to_np, workspace_lists)
+from gmr_testutil import (compare_grads, compare_images, fv_to_face, gpu_setup, saved_equal, to_np, workspace_lists)
 
 pytestmark = pytest.mark.gpu
 
@@ -377,8 +377,7 @@ def test_small_build_matches_radix_build(gpu, case):
     assert np.array_equal(ls[0], lb[0])
     n = cs.instances
     assert np.array_equal(ls[1][:n], lb[1][:n])
-    for x, y in zip(a[:3], b[:3]):
-        assert torch.equal(x, y)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and saved_equal(r_s, a[2], b[2])
     g = torch.randn_like(a[0])
     dV1, dC1 = r_s.backward(verts, colors, g, None, a[2], a[3], recompute=True)
     dV2, dC2 = r_b.backward(verts, colors, g, None, b[2], b[3], recompute=True)
@@ -439,7 +438,7 @@ def test_determinism_and_recompute_lists(gpu):
     r, verts, colors = gpu_setup(W)
     rgb1, a1, s1, ws1 = r.forward(verts, colors)
     rgb2, a2, s2, ws2 = r.forward(verts, colors)
-    assert torch.equal(rgb1, rgb2) and torch.equal(a1, a2) and torch.equal(s1, s2)
+    assert torch.equal(rgb1, rgb2) and torch.equal(a1, a2) and saved_equal(r, s1, s2)
     l1 = workspace_lists(r, ws1)
     l2 = workspace_lists(r, ws2)
     n = int(l1[0][:, 1].max())
@@ -643,6 +642,43 @@ def test_small_two_mesh_batch_images_and_grads(gpu):
     oV, oC = oracle.adjoint_workload(W, g)
     compare_grads(dV, oV, "two-mesh dV")
     compare_grads(dC, oC, "two-mesh dC")
+
+
+@pytest.mark.parametrize("cfg,kw", [(2, {}), (2, {"lane_lists": 0}), (2, {"px_per_lane": 2, "tile_w": 16, "tile_h": 16}),
+                                    (3, {"tile_w": 32, "tile_h": 16})])
+def test_backward_composited_lists_equal_full_walk(gpu, cfg, kw):
+    """The backward walks, per 8 x 8 block, only the Gaussians the forward recorded as composited by
+    one of its pixels (the saved buffer's per-item lists); with every list marked as not fitting it
+    walks the tile's whole list instead.  Both give the same pair count and the same gradients (up to
+    the order of the float atomics), lists saved or rebuilt; the lists hold ascending positions below
+    each block's furthest stop, at most 127 of them."""
+    import torch
+    from gmr_testutil import BLK_WORDS
+    say(f"composited lists vs full walk: cfg{cfg} {kw}")
+    W = wl.make_workload(cfg, scale=0.25 if cfg == 3 else 1.0)
+    r, verts, colors = gpu_setup(W, **kw)
+    rgb, alpha, saved, ws = r.forward(verts, colors, check=True)
+    P = W.num_pixels
+    blk = saved[8 * P:].view(torch.int32).view(-1, BLK_WORDS)
+    cnt = blk[:, 0].to(torch.int64) & 0xFFFFFFFF
+    say(f"  {blk.shape[0]} items, counts mean {float(cnt.float().mean()):.1f} max {int(cnt.max())}, "
+        f"{int((cnt > BLK_WORDS - 1).sum())} over the capacity")
+    fit = cnt <= BLK_WORDS - 1
+    ent = blk[:, 1:].to(torch.int64) & 0xFFFFFFFF
+    keep = torch.arange(BLK_WORDS - 1, device=saved.device)[None, :] < cnt.clamp(max=BLK_WORDS - 1)[:, None]
+    asc = (ent[:, 1:] > ent[:, :-1]) | ~keep[:, 1:]
+    assert bool(asc[fit].all()), "positions not ascending"
+    g = torch.randn_like(rgb)
+    for recompute in (False, True):
+        dV, dC = r.backward(verts, colors, g, None, saved, ws, recompute=recompute)
+        pairs = r.counters(ws).pairs_bwd
+        s2 = saved.clone()
+        b2 = s2[8 * P:].view(torch.int32).view(-1, BLK_WORDS)
+        b2[:, 0] = -1  # 0xffffffff: no list
+        dV2, dC2 = r.backward(verts, colors, g, None, s2, ws, recompute=recompute)
+        assert r.counters(ws).pairs_bwd == pairs
+        compare_grads(dV2, to_np(dV), f"cfg{cfg} lists vs full walk dV", rel=1e-5)
+        compare_grads(dC2, to_np(dC), f"cfg{cfg} lists vs full walk dC", rel=1e-5)
 
 
 def test_autograd_recompute_equals_saved(gpu):
