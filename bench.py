@@ -42,9 +42,9 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # counters were taken, and changed code reports null.
 TRAFFIC = {
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 8624714000, "write": 1799089089, "src": "a7a196b05ef9632f"},
+        {"fetch": 6005641469, "write": 1798039539, "src": "acec75aaa37c3ae3"},
     ("torus_2M_32x1920x1080", "raster_bwd", "32x32", 1, 0, 1):
-        {"fetch": 8838276883, "write": 1799106774, "src": "a7a196b05ef9632f"},
+        {"fetch": 5976967669, "write": 1797900365, "src": "acec75aaa37c3ae3"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
