@@ -25,7 +25,7 @@ class gmr_options(ctypes.Structure):
     _fields_ = [("cov_mode", c_int32), ("dilation", c_float), ("alpha_min", c_float), ("alpha_max", c_float),
                 ("t_eps", c_float), ("bg", c_float * 3), ("tile_w", c_int32), ("tile_h", c_int32),
                 ("raster_mode", c_int32), ("px_per_lane", c_int32), ("lane_lists", c_int32),
-                ("sh_degree", c_int32), ("instance_capacity", c_int64)]
+                ("sh_degree", c_int32), ("composited_lists", c_int32), ("instance_capacity", c_int64)]
 
 
 class gmr_batch(ctypes.Structure):

@@ -92,6 +92,8 @@ gmr_status validate_options(const gmr_options* o) {
   if (o->tile_h % (kSub * o->px_per_lane) != 0) return fail(GMR_ERR_INVALID_ARG, "tile_h must be a multiple of 8*px_per_lane");
   if (o->lane_lists != 0 && o->lane_lists != 1) return fail(GMR_ERR_INVALID_ARG, "lane_lists must be 0 or 1");
   if (o->sh_degree < 0 || o->sh_degree > 3) return fail(GMR_ERR_INVALID_ARG, "sh_degree must be in [0, 3]");
+  if (o->composited_lists < 0 || o->composited_lists > kMaxCompositedLists)
+    return fail(GMR_ERR_INVALID_ARG, "composited_lists must be in [0, 4095]");
   return GMR_OK;
 }
 
@@ -229,8 +231,11 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
 }
 
 // The saved buffer: per pixel T_final and the list position after its last composited Gaussian;
-// per raster item the block's composited list (kBlkWords words).
-size_t saved_size(const Plan& p) { return (size_t)p.p_total * 8 + (size_t)p.items_total * kBlkWords * 4; }
+// per raster item the block's composited list (blk_words words).
+uint32_t blk_words(const gmr_options* o) { return o->composited_lists > 0 ? (uint32_t)o->composited_lists + 1u : 0u; }
+size_t saved_size(const Plan& p, const gmr_options* o) {
+  return (size_t)p.p_total * 8 + (size_t)p.items_total * blk_words(o) * 4;
+}
 
 // Raster-block masks in the instance keys: above the tile-id bits, where the tile's blocks fit.
 int32_t bm_shift1_of(const Plan& p) {
@@ -283,6 +288,7 @@ KOpts kopts(const gmr_options* o) {
   k.bg1 = o->bg[1];
   k.bg2 = o->bg[2];
   k.sh_degree = o->sh_degree;
+  k.blk_words = blk_words(o);
   return k;
 }
 
@@ -481,7 +487,7 @@ gmr_status bwd_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* opt
   }
   const float* saved_T = static_cast<const float*>(saved);
   const uint32_t* saved_n = reinterpret_cast<const uint32_t*>(saved_T + p.p_total);
-  const uint32_t* saved_blk = saved_n + p.p_total;
+  const uint32_t* saved_blk = blk_words(opt) ? saved_n + p.p_total : nullptr;
   const double n3 = 3.0 * (double)p.p_total;
   {
     StageTimer t(h, s, kStRasterBwd);
@@ -559,6 +565,7 @@ gmr_options gmr_default_options(void) {
   o.px_per_lane = 1;
   o.lane_lists = 1;
   o.sh_degree = 0;
+  o.composited_lists = 1023;
   o.instance_capacity = 0;
   return o;
 }
@@ -639,7 +646,7 @@ gmr_status gmr_workspace_size(const gmr_batch* batch, const gmr_options* opt, si
   gmr_status st = make_plan(batch, opt, true, p);
   if (st != GMR_OK) return st;
   *ws_bytes = p.L.total;
-  *saved_bytes = saved_size(p);
+  *saved_bytes = saved_size(p, opt);
   return GMR_OK;
 }
 
@@ -668,7 +675,7 @@ void fwd_impl(gmr_ctx* h, const Plan& p, const gmr_options* opt, const void* tab
   build_lists(h, p, opt, table, verts, faces, colors, w, false, s, timed);
   float* saved_T = static_cast<float*>(saved);
   uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
-  uint32_t* saved_blk = saved_n + p.p_total;
+  uint32_t* saved_blk = blk_words(opt) ? saved_n + p.p_total : nullptr;
   {
     StageTimer t(timed ? h : nullptr, s, kStRasterFwd);
     launch_raster_fwd(table, p.items_total, persistent_blocks(h, opt), opt->px_per_lane, opt->lane_lists != 0, w.ranges,
@@ -795,7 +802,7 @@ gmr_status step_impl(gmr_handle h, const gmr_batch* batch, const gmr_options* op
   build_lists(h, p, opt, table, verts, faces, colors, w, true, s, true, true);
   float* saved_T = static_cast<float*>(saved);
   uint32_t* saved_n = reinterpret_cast<uint32_t*>(saved_T + p.p_total);
-  uint32_t* saved_blk = saved_n + p.p_total;
+  uint32_t* saved_blk = blk_words(opt) ? saved_n + p.p_total : nullptr;
   const double n3 = 3.0 * (double)p.p_total;
   const float gs = (float)(2.0 * color_weight / n3), ls = (float)(color_weight / n3);
   const float ss = (float)(sil_weight / (double)p.p_total);
@@ -1063,10 +1070,10 @@ gmr_status gmr_autotune(gmr_handle h, const gmr_batch* batch, const gmr_options*
         ws_cap = p.L.total;
         if (hipMalloc(&ws, ws_cap) != hipSuccess) return fail(GMR_ERR_HIP, "autotune: hipMalloc workspace");
       }
-      if (saved_size(p) > saved_cap) {
+      if (saved_size(p, &o) > saved_cap) {
         if (saved) (void)hipFree(saved);
         saved = nullptr;
-        saved_cap = saved_size(p);
+        saved_cap = saved_size(p, &o);
         if (hipMalloc(&saved, saved_cap) != hipSuccess) return fail(GMR_ERR_HIP, "autotune: hipMalloc saved");
       }
       if ((r = gmr_render_fwd(h, batch, &o, table, verts, faces, colors, rgb, nullptr, saved, ws, ws_cap, s)) != GMR_OK)

@@ -102,8 +102,9 @@ __device__ inline uint32_t rect_block_mask(int ix0, int ix1, int iy0, int iy1, i
 }
 
 // Per raster item in the saved buffer (after the per-pixel state): the count and the list positions
-// of the Gaussians its block composited, kBlkCap at most (a larger count: the list did not fit).
-constexpr int kBlkWords = 1024, kBlkCap = kBlkWords - 1;
+// of the Gaussians its block composited, at most blk_words - 1 of them (a larger count: the list did
+// not fit); blk_words = the composited_lists option + 1, or 0 when none are recorded.
+constexpr int kMaxCompositedLists = 4095;
 
 // Workspace header (device counters) ------------------------------------------------------------
 struct WsHdr {                 // 256 B at the start of the workspace
@@ -157,6 +158,7 @@ struct KOpts {
   float dilation, alpha_min, alpha_max, t_eps;
   float bg0, bg1, bg2;
   int32_t sh_degree;  // view-dependent colour degree (0: Eq. 16)
+  uint32_t blk_words; // words per raster item of the composited lists (0: none)
 };
 
 // Where the per-item raster statistics live (recorded in the header by the build prologue).

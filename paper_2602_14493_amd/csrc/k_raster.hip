@@ -273,7 +273,7 @@ struct FwdArgs {
   float* out_alpha;
   float* saved_T;
   uint32_t* saved_n;
-  uint32_t* blk;              // [items][kBlkWords] composited lists (see blk_append), or NULL
+  uint32_t* blk;              // [items][o.blk_words] composited lists (see blk_append), or NULL
   unsigned long long* stats;  // [items] pairs evaluated per item (summed on the host when read)
 };
 
@@ -303,16 +303,17 @@ __device__ __forceinline__ bool entry_kept(const Entry& e, int kbit, const float
 
 // A block's composited list.  Per raster item the forward records, in list order, the list positions
 // (relative to the tile's list start) of the Gaussians that at least one of its pixels composited:
-// word 0 the count, words 1 .. kBlkCap the positions (those past the count undefined; a count above
-// kBlkCap means the list did not fit).  The backward walks only these -- a Gaussian no pixel of the
+// word 0 the count, words 1 .. cap the positions, cap = o.blk_words - 1 (those past the count
+// undefined; a count above cap means the list did not fit).  The backward walks only these -- a Gaussian no pixel of the
 // block composited adds nothing to the block's gradients -- instead of testing every entry of the
 // tile's list against the block.  Appends the staged slots set in the wave-uniform mask M (slot j
 // at list position pos_j), in slot order, to the item's list g.
-__device__ __forceinline__ void blk_append(uint32_t* g, uint64_t M, uint32_t pos_lane, uint32_t& cnt, int lane) {
+__device__ __forceinline__ void blk_append(uint32_t* g, uint32_t cap, uint64_t M, uint32_t pos_lane, uint32_t& cnt,
+                                           int lane) {
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   if ((M >> lane) & 1ull) {
     const uint32_t idx = cnt + (uint32_t)__popcll(M & below);
-    if (idx < (uint32_t)kBlkCap) g[1 + idx] = pos_lane;
+    if (idx < cap) g[1 + idx] = pos_lane;
   }
   cnt += (uint32_t)__popcll(M);
 }
@@ -366,7 +367,7 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
   item = __builtin_amdgcn_readfirstlane(item);
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) {  // a block past the image's edge composites nothing
-    if (a.blk && lane == 0) a.blk[(size_t)item * kBlkWords] = 0u;
+    if (a.blk && lane == 0) a.blk[(size_t)item * a.o.blk_words] = 0u;
     return 0ull;
   }
   const int ly = lane >> 3;
@@ -391,7 +392,7 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
   }
   unsigned long long pairs = 0;
   bcnt = 0;  // composited Gaussians (wave-uniform)
-  uint32_t* const bg = a.blk ? a.blk + (size_t)item * kBlkWords : nullptr;
+  uint32_t* const bg = a.blk ? a.blk + (size_t)item * a.o.blk_words : nullptr;
   Entry cur{0u, 0u};
   if (len > 0) cur = load_entry(lkeys, lvals, lane, len);  // (an empty list reads nothing)
   for (uint32_t cb = start; cb < end; cb += kWave) {
@@ -447,8 +448,9 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
                                    teps, T, C0, C1, C2, last, done, pairs);
       if (bg && lane == 0) {  // list order: j1 before j2
         const uint32_t i1 = bcnt, i2 = bcnt + (c1 ? 1u : 0u);
-        if (c1 && i1 < (uint32_t)kBlkCap) bg[1 + i1] = cb + (uint32_t)j1 - start;
-        if (c2 && i2 < (uint32_t)kBlkCap) bg[1 + i2] = cb + (uint32_t)j2 - start;
+        const uint32_t cap = a.o.blk_words - 1u;
+        if (c1 && i1 < cap) bg[1 + i1] = cb + (uint32_t)j1 - start;
+        if (c2 && i2 < cap) bg[1 + i2] = cb + (uint32_t)j2 - start;
       }
       bcnt += (c1 ? 1u : 0u) + (c2 ? 1u : 0u);
       bool live2 = false;
@@ -567,7 +569,7 @@ __device__ __forceinline__ void fwd_stage_walk(const FwdArgs& a, float4 (*s)[kWa
   if (bg) {
     wave_lds_sync();
     const uint64_t M = __ballot(s_comp[lane] != 0u);  // the slots some pixel composited
-    blk_append(bg, M, (uint32_t)lane < n ? s_pos[lane] - 1u : 0u, bcnt, lane);
+    blk_append(bg, a.o.blk_words - 1u, M, (uint32_t)lane < n ? s_pos[lane] - 1u : 0u, bcnt, lane);
   }
 }
 
@@ -583,7 +585,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
   item = __builtin_amdgcn_readfirstlane(item);
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) {  // a block past the image's edge composites nothing
-    if (a.blk && lane == 0) a.blk[(size_t)item * kBlkWords] = 0u;
+    if (a.blk && lane == 0) a.blk[(size_t)item * a.o.blk_words] = 0u;
     return 0ull;
   }
   const int ly = lane >> 3;
@@ -611,7 +613,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
   uint32_t pairs = 0;
   uint32_t nq = 0;  // queued entries (wave-uniform)
   bcnt = 0;         // composited Gaussians (wave-uniform)
-  uint32_t* const bg = a.blk ? a.blk + (size_t)item * kBlkWords : nullptr;
+  uint32_t* const bg = a.blk ? a.blk + (size_t)item * a.o.blk_words : nullptr;
   Entry cur{0u, 0u};
   if (len > 0) cur = load_entry(lkeys, lvals, lane, len);  // (an empty list reads nothing)
   for (uint32_t cb = start; cb < end; cb += kWave) {
@@ -738,7 +740,7 @@ struct BwdArgs {
   KOpts o;
   const float* saved_T;
   const uint32_t* saved_n;
-  const uint32_t* blk;    // [items][kBlkWords] the forward's composited lists, or NULL
+  const uint32_t* blk;    // [items][o.blk_words] the forward's composited lists, or NULL
   const float* d_rgb;     // explicit upstream (or NULL with the L2 form)
   const float* d_alpha;   // may be NULL
   const float* rgb;       // L2 form: forward output
@@ -955,7 +957,7 @@ __device__ __forceinline__ void bwd_stage_walk(const BwdArgs& a, const BwdLds& L
 }
 
 // bl / bcnt: the forward's composited list of this item (positions from bl[0]) and its count; a NULL
-// list or a count above kBlkCap walks the tile's list instead.
+// list or a count above o.blk_words - 1 walks the tile's list instead.
 template <int PX, bool kL2>
 __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
                                        const BwdLds& L, const uint32_t* bl, uint32_t bcnt) {
@@ -1033,7 +1035,7 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   // power above which exp2(-power) < alpha_min, with a 2 % margin for rounding
   const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;
   unsigned long long pairs = 0;  // wave-uniform count
-  if (bl && bcnt <= (uint32_t)kBlkCap) {
+  if (bl && bcnt < a.o.blk_words) {
     // the Gaussians some pixel of the block composited, latest first, 64 per round; a position past
     // the pixels' furthest stop cannot come from a forward of these lists and is skipped
     for (int32_t hi = (int32_t)bcnt; hi > 0; hi -= kWave) {
@@ -1110,8 +1112,8 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     for (int v = (int)blockIdx.x; v < groups; v += (int)gridDim.x) {
       const int item = xcd_remap(v, groups) * 4 + w;
       if (item < items) {
-        const uint32_t* bl = a.blk ? a.blk + (size_t)item * kBlkWords + 1 : nullptr;
-        const uint32_t bc = a.blk ? __builtin_amdgcn_readfirstlane(a.blk[(size_t)item * kBlkWords]) : ~0u;
+        const uint32_t* bl = a.blk ? a.blk + (size_t)item * a.o.blk_words + 1 : nullptr;
+        const uint32_t bc = a.blk ? __builtin_amdgcn_readfirstlane(a.blk[(size_t)item * a.o.blk_words]) : ~0u;
         const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L, bl, bc);
         if (lane == 0) a.stats[item] = st;
       }
@@ -1119,8 +1121,8 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
     if (item < items) {
-      const uint32_t* bl = a.blk ? a.blk + (size_t)item * kBlkWords + 1 : nullptr;
-      const uint32_t bc = a.blk ? __builtin_amdgcn_readfirstlane(a.blk[(size_t)item * kBlkWords]) : ~0u;
+      const uint32_t* bl = a.blk ? a.blk + (size_t)item * a.o.blk_words + 1 : nullptr;
+      const uint32_t bc = a.blk ? __builtin_amdgcn_readfirstlane(a.blk[(size_t)item * a.o.blk_words]) : ~0u;
       const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L, bl, bc);
       if (lane == 0) a.stats[item] = st;
     }
@@ -1151,7 +1153,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
   // the composited list the forward stored is read back by other lanes of this wavefront
   __threadfence_block();
   const BwdLds Lb{s_f[w].rec, s_id[w], s_pos[w], s_f[w].cov, s_red[w]};
-  const uint32_t* bl = fa.blk ? fa.blk + (size_t)item * kBlkWords + 1 : nullptr;
+  const uint32_t* bl = fa.blk ? fa.blk + (size_t)item * fa.o.blk_words + 1 : nullptr;
   const float4 st = raster_bwd_item<1, true>(ba, th, views, item, lane, Lb, bl, bcnt);
   if (lane == 0) ba.stats[item] = st;
 }

@@ -82,23 +82,30 @@ def workspace_lists(r, ws):
     return ranges, vals
 
 
-BLK_WORDS = 1024  # per raster item in the saved buffer: count, then up to 1023 list positions
+def blk_words(r):
+    """Words per raster item of the saved composited lists: the count, then up to composited_lists
+    positions (0: none recorded)."""
+    c = int(r.opts.composited_lists)
+    return c + 1 if c > 0 else 0
 
 
 def saved_equal(r, a, b):
     """Saved states equal where they are defined: T_final and list positions per pixel, and per
-    raster item the composited-list count and its first min(count, 1023) positions (the rest of an
+    raster item the composited-list count and its first min(count, composited_lists) positions (the rest of an
     item's words is left as it was)."""
     import torch
     P = r.batch.num_pixels
     if a.numel() != b.numel() or not torch.equal(a[:8 * P], b[:8 * P]):
         return False
-    ta = a[8 * P:].view(torch.int32).view(-1, BLK_WORDS)
-    tb = b[8 * P:].view(torch.int32).view(-1, BLK_WORDS)
+    nw = blk_words(r)
+    if nw == 0:
+        return True
+    ta = a[8 * P:].view(torch.int32).view(-1, nw)
+    tb = b[8 * P:].view(torch.int32).view(-1, nw)
     if not torch.equal(ta[:, 0], tb[:, 0]):
         return False
     n = ta[:, 0].to(torch.int64) & 0xFFFFFFFF  # the counts, unsigned
-    keep = torch.arange(BLK_WORDS - 1, device=a.device)[None, :] < n.clamp(max=BLK_WORDS - 1)[:, None]
+    keep = torch.arange(nw - 1, device=a.device)[None, :] < n.clamp(max=nw - 1)[:, None]
     return torch.equal(ta[:, 1:][keep], tb[:, 1:][keep])
 
 

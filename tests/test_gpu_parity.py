@@ -645,20 +645,21 @@ def test_small_two_mesh_batch_images_and_grads(gpu):
 
 
 @pytest.mark.parametrize("cfg,kw", [(2, {}), (2, {"lane_lists": 0}), (2, {"px_per_lane": 2, "tile_w": 16, "tile_h": 16}),
-                                    (3, {"tile_w": 32, "tile_h": 16})])
+                                    (2, {"composited_lists": 7}), (3, {"tile_w": 32, "tile_h": 16})])
 def test_backward_composited_lists_equal_full_walk(gpu, cfg, kw):
     """The backward walks, per 8 x 8 block, only the Gaussians the forward recorded as composited by
     one of its pixels (the saved buffer's per-item lists); with every list marked as not fitting it
     walks the tile's whole list instead.  Both give the same pair count and the same gradients (up to
     the order of the float atomics), lists saved or rebuilt; the lists hold ascending positions below
-    each block's furthest stop, at most 127 of them."""
+    each block's furthest stop, at most composited_lists of them."""
     import torch
-    from gmr_testutil import BLK_WORDS
+    from gmr_testutil import blk_words
     say(f"composited lists vs full walk: cfg{cfg} {kw}")
     W = wl.make_workload(cfg, scale=0.25 if cfg == 3 else 1.0)
     r, verts, colors = gpu_setup(W, **kw)
     rgb, alpha, saved, ws = r.forward(verts, colors, check=True)
     P = W.num_pixels
+    BLK_WORDS = blk_words(r)
     blk = saved[8 * P:].view(torch.int32).view(-1, BLK_WORDS)
     cnt = blk[:, 0].to(torch.int64) & 0xFFFFFFFF
     say(f"  {blk.shape[0]} items, counts mean {float(cnt.float().mean()):.1f} max {int(cnt.max())}, "
@@ -679,6 +680,30 @@ def test_backward_composited_lists_equal_full_walk(gpu, cfg, kw):
         assert r.counters(ws).pairs_bwd == pairs
         compare_grads(dV2, to_np(dV), f"cfg{cfg} lists vs full walk dV", rel=1e-5)
         compare_grads(dC2, to_np(dC), f"cfg{cfg} lists vs full walk dC", rel=1e-5)
+
+
+def test_composited_lists_off_equals_default(gpu):
+    """composited_lists = 0 records no lists (the saved state is the 8 bytes per pixel) and the
+    backward walks every tile's whole list: images, per-pixel saved state, pair counts and
+    gradients (up to atomic order) equal those of the default options."""
+    import torch
+    say("composited lists off vs default: cfg2")
+    W = wl.make_workload(2)
+    outs = []
+    for kw in ({}, {"composited_lists": 0}):
+        r, verts, colors = gpu_setup(W, **kw)
+        rgb, alpha, saved, ws = r.forward(verts, colors, check=True)
+        g = torch.randn(rgb.shape, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+        dV, dC = r.backward(verts, colors, g, None, saved, ws)
+        c = r.counters(ws)
+        outs.append((rgb, alpha, saved, dV, dC, c.pairs_fwd, c.pairs_bwd))
+    a, b = outs
+    P = W.num_pixels
+    assert b[2].numel() == 8 * P
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2][:8 * P], b[2])
+    assert a[5:] == b[5:]
+    compare_grads(b[3], to_np(a[3]), "lists off dV", rel=1e-5)
+    compare_grads(b[4], to_np(a[4]), "lists off dC", rel=1e-5)
 
 
 def test_autograd_recompute_equals_saved(gpu):
