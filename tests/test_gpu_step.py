@@ -21,6 +21,8 @@ CASES = {
     "cfg2-half": (2, 0.5, {}),
     "cfg2-half-block-uniform": (2, 0.5, {"lane_lists": 0}),
     "cfg2-half-px2": (2, 0.5, {"px_per_lane": 2, "tile_w": 16, "tile_h": 16}),
+    "cfg2-half-lists-off": (2, 0.5, {"composited_lists": 0}),
+    "cfg2-half-lists-7": (2, 0.5, {"composited_lists": 7}),
     "cfg3-quarter": (3, 0.25, {"tile_w": 16, "tile_h": 16}),
 }
 
