@@ -646,6 +646,7 @@ def test_small_two_mesh_batch_images_and_grads(gpu):
 
 @pytest.mark.parametrize("cfg,kw", [(2, {}), (2, {"lane_lists": 0}), (2, {"px_per_lane": 2, "tile_w": 16, "tile_h": 16}),
                                     (2, {"px_per_lane": 4, "tile_w": 32, "tile_h": 32}), (2, {"raster_mode": 1}),
+                                    (2, {"px_per_lane": 2, "tile_w": 16, "tile_h": 16, "lane_lists": 0}),
                                     (2, {"composited_lists": 7}), (3, {"tile_w": 32, "tile_h": 16})])
 def test_backward_composited_lists_equal_full_walk(gpu, cfg, kw):
     """The backward walks, per 8 x 8 block, only the Gaussians the forward recorded as composited by
