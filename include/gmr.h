@@ -79,12 +79,14 @@ typedef struct gmr_options {
                                 direction from the camera centre to the face's mean, Y_k the real
                                 spherical harmonics (3DGS sign convention); d_colors_dev has the
                                 same layout                                                          */
-  int32_t composited_lists;  /* [1023] per 8 x 8 raster block, how many list positions of the Gaussians
+  int32_t composited_lists;  /* [2046] per 8 x 8 raster block, how many list positions of the Gaussians
                                 some pixel of the block composited the forward records in the saved
-                                state (0 to 4095): the backward then visits only those, and a block
-                                with more walks its tile's whole list.  The saved state takes
-                                4 (composited_lists + 1) bytes per block beyond its 8 bytes per
-                                pixel; 0 records none.  Results are the same for every value.    */
+                                state (0 to 8190): the backward then visits only those, and a block
+                                with more (or in a tile whose list exceeds 65536 entries) walks its
+                                tile's whole list.  The saved state takes 4 (1 + ceil(
+                                composited_lists / 2)) bytes per block beyond its 8 bytes per pixel
+                                (4 KB at the default); 0 records none.  Results are the same for
+                                every value.                                                       */
   int64_t instance_capacity; /* [0] (Gaussian, tile) instances the workspace holds; must be > 0
                                 when sizing a workspace or rendering                               */
 } gmr_options;
@@ -151,8 +153,8 @@ gmr_status gmr_view_table_fill(const gmr_batch* batch, const gmr_options* opt, v
  * workspace holds the per face-view projected records, the instance keys/values (double
  * buffered), the sort state, the tile ranges and the backward's gradient accumulators.
  * `saved_bytes` is the state render_fwd leaves for render_bwd: 8 bytes per pixel, then
- * 4 (opt->composited_lists + 1) bytes per 8 x 8 raster block when composited_lists > 0 (the
- * block's composited list, below).
+ * 4 (1 + ceil(opt->composited_lists / 2)) bytes per 8 x 8 raster block when composited_lists > 0
+ * (the block's composited list, below).
  * The workspace needs no initialisation, except that zeroing its first 256 bytes once after
  * allocation arms the peak instance counter gmr_read_counters reports. */
 gmr_status gmr_workspace_size(const gmr_batch* batch, const gmr_options* opt, size_t* ws_bytes, size_t* saved_bytes);
@@ -175,10 +177,11 @@ gmr_status gmr_build_adjacency(const int32_t* faces_host, int64_t num_faces, int
  *   out_rgb_dev   [P][3] f32  composite + T_final * bg
  *   out_alpha_dev [P]    f32  1 - T_final (may be NULL)
  *   saved_dev     saved_bytes: per pixel T_final and the list position after the last
- *                 composited Gaussian; per raster block the count of the tile-list entries some
- *                 pixel of the block composited and their positions, ascending (the first
- *                 opt->composited_lists; a larger count makes the backward walk the block's whole
- *                 list) -- input of
+ *                 composited Gaussian; per raster block a uint32 count of the tile-list entries
+ *                 some pixel of the block composited, then their positions in the tile's list as
+ *                 uint16, ascending (the first opt->composited_lists; a larger count, or
+ *                 0xffffffff for a tile list too long for 16-bit positions, makes the backward
+ *                 walk the block's whole list) -- input of
  *                 gmr_render_bwd
  *   ws_dev/ws_bytes  workspace of gmr_workspace_size; after the call it holds the sorted
  *                 lists, which gmr_render_bwd may reuse (recompute_lists = 0).

@@ -93,7 +93,7 @@ gmr_status validate_options(const gmr_options* o) {
   if (o->lane_lists != 0 && o->lane_lists != 1) return fail(GMR_ERR_INVALID_ARG, "lane_lists must be 0 or 1");
   if (o->sh_degree < 0 || o->sh_degree > 3) return fail(GMR_ERR_INVALID_ARG, "sh_degree must be in [0, 3]");
   if (o->composited_lists < 0 || o->composited_lists > kMaxCompositedLists)
-    return fail(GMR_ERR_INVALID_ARG, "composited_lists must be in [0, 4095]");
+    return fail(GMR_ERR_INVALID_ARG, "composited_lists must be in [0, 8190]");
   return GMR_OK;
 }
 
@@ -231,8 +231,10 @@ gmr_status make_plan(const gmr_batch* b, const gmr_options* o, bool need_capacit
 }
 
 // The saved buffer: per pixel T_final and the list position after its last composited Gaussian;
-// per raster item the block's composited list (blk_words words).
-uint32_t blk_words(const gmr_options* o) { return o->composited_lists > 0 ? (uint32_t)o->composited_lists + 1u : 0u; }
+// per raster item the block's composited list: a count word, then 16-bit positions.
+uint32_t blk_words(const gmr_options* o) {
+  return o->composited_lists > 0 ? 1u + ((uint32_t)o->composited_lists + 1u) / 2u : 0u;
+}
 size_t saved_size(const Plan& p, const gmr_options* o) {
   return (size_t)p.p_total * 8 + (size_t)p.items_total * blk_words(o) * 4;
 }
@@ -289,6 +291,7 @@ KOpts kopts(const gmr_options* o) {
   k.bg2 = o->bg[2];
   k.sh_degree = o->sh_degree;
   k.blk_words = blk_words(o);
+  k.blk_cap = (uint32_t)o->composited_lists;
   return k;
 }
 
@@ -565,7 +568,7 @@ gmr_options gmr_default_options(void) {
   o.px_per_lane = 1;
   o.lane_lists = 1;
   o.sh_degree = 0;
-  o.composited_lists = 1023;
+  o.composited_lists = 2046;
   o.instance_capacity = 0;
   return o;
 }

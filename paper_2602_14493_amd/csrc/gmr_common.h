@@ -102,9 +102,10 @@ __device__ inline uint32_t rect_block_mask(int ix0, int ix1, int iy0, int iy1, i
 }
 
 // Per raster item in the saved buffer (after the per-pixel state): the count and the list positions
-// of the Gaussians its block composited, at most blk_words - 1 of them (a larger count: the list did
-// not fit); blk_words = the composited_lists option + 1, or 0 when none are recorded.
-constexpr int kMaxCompositedLists = 4095;
+// (16 bits each, relative to the tile's list) of the Gaussians its block composited, at most blk_cap
+// = the composited_lists option of them (a larger count: the list did not fit); blk_words = 1 +
+// ceil(blk_cap / 2), or 0 when none are recorded.
+constexpr int kMaxCompositedLists = 8190;
 
 // Workspace header (device counters) ------------------------------------------------------------
 struct WsHdr {                 // 256 B at the start of the workspace
@@ -159,6 +160,7 @@ struct KOpts {
   float bg0, bg1, bg2;
   int32_t sh_degree;  // view-dependent colour degree (0: Eq. 16)
   uint32_t blk_words; // words per raster item of the composited lists (0: none)
+  uint32_t blk_cap;   // list positions per raster item
 };
 
 // Where the per-item raster statistics live (recorded in the header by the build prologue).

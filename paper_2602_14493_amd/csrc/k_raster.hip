@@ -301,19 +301,30 @@ __device__ __forceinline__ bool entry_kept(const Entry& e, int kbit, const float
   return rect_meets_block(f2u(rp[1].w), f2u(rp[2].w), g.bx0, g.by0, kSub * PX);
 }
 
+// The item's composited list in the saved buffer, or NULL when none is recorded: no buffer, or a tile
+// list longer than 16-bit positions reach (its count is then set to 0xffffffff, "did not fit").
+__device__ __forceinline__ uint32_t* blk_of(const FwdArgs& a, int item, uint32_t len, int lane) {
+  if (!a.blk) return nullptr;
+  uint32_t* const g = a.blk + (size_t)item * a.o.blk_words;
+  if (len <= 65536u) return g;
+  if (lane == 0) g[0] = ~0u;
+  return nullptr;
+}
+
 // A block's composited list.  Per raster item the forward records, in list order, the list positions
 // (relative to the tile's list start) of the Gaussians that at least one of its pixels composited:
-// word 0 the count, words 1 .. cap the positions, cap = o.blk_words - 1 (those past the count
-// undefined; a count above cap means the list did not fit).  The backward walks only these -- a Gaussian no pixel of the
-// block composited adds nothing to the block's gradients -- instead of testing every entry of the
-// tile's list against the block.  Appends the staged slots set in the wave-uniform mask M (slot j
+// word 0 the count, then the positions as 16-bit values, o.blk_cap of them at most (those past the
+// count undefined; a count above the cap means the list did not fit, and a tile list longer than
+// 65536 entries records no list: count 0xffffffff).  The backward walks only these -- a Gaussian
+// no pixel of the block composited adds nothing to the block's gradients -- instead of testing
+// every entry of the tile's list against the block.  Appends the staged slots set in the wave-uniform mask M (slot j
 // at list position pos_j), in slot order, to the item's list g.
 __device__ __forceinline__ void blk_append(uint32_t* g, uint32_t cap, uint64_t M, uint32_t pos_lane, uint32_t& cnt,
                                            int lane) {
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   if ((M >> lane) & 1ull) {
     const uint32_t idx = cnt + (uint32_t)__popcll(M & below);
-    if (idx < cap) g[1 + idx] = pos_lane;
+    if (idx < cap) reinterpret_cast<uint16_t*>(g + 1)[idx] = (uint16_t)pos_lane;
   }
   cnt += (uint32_t)__popcll(M);
 }
@@ -392,7 +403,7 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
   }
   unsigned long long pairs = 0;
   bcnt = 0;  // composited Gaussians (wave-uniform)
-  uint32_t* const bg = a.blk ? a.blk + (size_t)item * a.o.blk_words : nullptr;
+  uint32_t* const bg = blk_of(a, item, end - start, lane);
   Entry cur{0u, 0u};
   if (len > 0) cur = load_entry(lkeys, lvals, lane, len);  // (an empty list reads nothing)
   for (uint32_t cb = start; cb < end; cb += kWave) {
@@ -448,9 +459,9 @@ __device__ inline unsigned long long raster_fwd_item(const FwdArgs& a, const Tab
                                    teps, T, C0, C1, C2, last, done, pairs);
       if (bg && lane == 0) {  // list order: j1 before j2
         const uint32_t i1 = bcnt, i2 = bcnt + (c1 ? 1u : 0u);
-        const uint32_t cap = a.o.blk_words - 1u;
-        if (c1 && i1 < cap) bg[1 + i1] = cb + (uint32_t)j1 - start;
-        if (c2 && i2 < cap) bg[1 + i2] = cb + (uint32_t)j2 - start;
+        uint16_t* const be = reinterpret_cast<uint16_t*>(bg + 1);
+        if (c1 && i1 < a.o.blk_cap) be[i1] = (uint16_t)(cb + (uint32_t)j1 - start);
+        if (c2 && i2 < a.o.blk_cap) be[i2] = (uint16_t)(cb + (uint32_t)j2 - start);
       }
       bcnt += (c1 ? 1u : 0u) + (c2 ? 1u : 0u);
       bool live2 = false;
@@ -569,7 +580,7 @@ __device__ __forceinline__ void fwd_stage_walk(const FwdArgs& a, float4 (*s)[kWa
   if (bg) {
     wave_lds_sync();
     const uint64_t M = __ballot(s_comp[lane] != 0u);  // the slots some pixel composited
-    blk_append(bg, a.o.blk_words - 1u, M, (uint32_t)lane < n ? s_pos[lane] - 1u : 0u, bcnt, lane);
+    blk_append(bg, a.o.blk_cap, M, (uint32_t)lane < n ? s_pos[lane] - 1u : 0u, bcnt, lane);
   }
 }
 
@@ -613,7 +624,7 @@ __device__ inline unsigned long long raster_fwd_item_lanes(const FwdArgs& a, con
   uint32_t pairs = 0;
   uint32_t nq = 0;  // queued entries (wave-uniform)
   bcnt = 0;         // composited Gaussians (wave-uniform)
-  uint32_t* const bg = a.blk ? a.blk + (size_t)item * a.o.blk_words : nullptr;
+  uint32_t* const bg = blk_of(a, item, end - start, lane);
   Entry cur{0u, 0u};
   if (len > 0) cur = load_entry(lkeys, lvals, lane, len);  // (an empty list reads nothing)
   for (uint32_t cb = start; cb < end; cb += kWave) {
@@ -960,7 +971,7 @@ __device__ __forceinline__ void bwd_stage_walk(const BwdArgs& a, const BwdLds& L
 // list or a count above o.blk_words - 1 walks the tile's list instead.
 template <int PX, bool kL2>
 __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, const ViewDev* views, int item, int lane,
-                                       const BwdLds& L, const uint32_t* bl, uint32_t bcnt) {
+                                       const BwdLds& L, const uint16_t* bl, uint32_t bcnt) {
   item = __builtin_amdgcn_readfirstlane(item);
   const ItemGeo g = item_geometry<PX>(th, views, item, lane);
   if (!g.any) return make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1035,7 +1046,7 @@ __device__ inline float4 raster_bwd_item(const BwdArgs& a, const TableHdr* th, c
   // power above which exp2(-power) < alpha_min, with a 2 % margin for rounding
   const float pmax = -__builtin_amdgcn_logf(amin) * 1.02f;
   unsigned long long pairs = 0;  // wave-uniform count
-  if (bl && bcnt < a.o.blk_words) {
+  if (bl && bcnt <= a.o.blk_cap) {
     // the Gaussians some pixel of the block composited, latest first, 64 per round; a position past
     // the pixels' furthest stop cannot come from a forward of these lists and is skipped
     for (int32_t hi = (int32_t)bcnt; hi > 0; hi -= kWave) {
@@ -1112,7 +1123,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     for (int v = (int)blockIdx.x; v < groups; v += (int)gridDim.x) {
       const int item = xcd_remap(v, groups) * 4 + w;
       if (item < items) {
-        const uint32_t* bl = a.blk ? a.blk + (size_t)item * a.o.blk_words + 1 : nullptr;
+        const uint16_t* bl = a.blk ? reinterpret_cast<const uint16_t*>(a.blk + (size_t)item * a.o.blk_words + 1) : nullptr;
         const uint32_t bc = a.blk ? __builtin_amdgcn_readfirstlane(a.blk[(size_t)item * a.o.blk_words]) : ~0u;
         const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L, bl, bc);
         if (lane == 0) a.stats[item] = st;
@@ -1121,7 +1132,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
   } else {
     const int item = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (256 / kWave) + w;
     if (item < items) {
-      const uint32_t* bl = a.blk ? a.blk + (size_t)item * a.o.blk_words + 1 : nullptr;
+      const uint16_t* bl = a.blk ? reinterpret_cast<const uint16_t*>(a.blk + (size_t)item * a.o.blk_words + 1) : nullptr;
       const uint32_t bc = a.blk ? __builtin_amdgcn_readfirstlane(a.blk[(size_t)item * a.o.blk_words]) : ~0u;
       const float4 st = raster_bwd_item<PX, kL2>(a, th, views, item, lane, L, bl, bc);
       if (lane == 0) a.stats[item] = st;
@@ -1153,7 +1164,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
   // the composited list the forward stored is read back by other lanes of this wavefront
   __threadfence_block();
   const BwdLds Lb{s_f[w].rec, s_id[w], s_pos[w], s_f[w].cov, s_red[w]};
-  const uint32_t* bl = fa.blk ? fa.blk + (size_t)item * fa.o.blk_words + 1 : nullptr;
+  const uint16_t* bl = fa.blk ? reinterpret_cast<const uint16_t*>(fa.blk + (size_t)item * fa.o.blk_words + 1) : nullptr;
   const float4 st = raster_bwd_item<1, true>(ba, th, views, item, lane, Lb, bl, bcnt);
   if (lane == 0) ba.stats[item] = st;
 }

@@ -84,29 +84,38 @@ def workspace_lists(r, ws):
 
 def blk_words(r):
     """Words per raster item of the saved composited lists: the count, then up to composited_lists
-    positions (0: none recorded)."""
+    16-bit positions, two to a word (0: none recorded)."""
     c = int(r.opts.composited_lists)
-    return c + 1 if c > 0 else 0
+    return 1 + (c + 1) // 2 if c > 0 else 0
+
+
+def blk_lists(r, saved):
+    """(counts, positions, kept) of the saved composited lists: counts [items] int64 (unsigned),
+    positions [items, composited_lists] int64, kept = position index < min(count, cap)."""
+    import torch
+    P, nw, cap = r.batch.num_pixels, blk_words(r), int(r.opts.composited_lists)
+    t = saved[8 * P:].view(torch.int32).view(-1, nw)
+    cnt = t[:, 0].to(torch.int64) & 0xFFFFFFFF
+    pos = t[:, 1:].contiguous().view(torch.int16)[:, :cap].to(torch.int64) & 0xFFFF
+    kept = torch.arange(cap, device=saved.device)[None, :] < cnt.clamp(max=cap)[:, None]
+    return cnt, pos, kept
 
 
 def saved_equal(r, a, b):
     """Saved states equal where they are defined: T_final and list positions per pixel, and per
-    raster item the composited-list count and its first min(count, composited_lists) positions (the rest of an
-    item's words is left as it was)."""
+    raster item the composited-list count and its first min(count, composited_lists) positions (the
+    rest of an item's words is left as it was)."""
     import torch
     P = r.batch.num_pixels
     if a.numel() != b.numel() or not torch.equal(a[:8 * P], b[:8 * P]):
         return False
-    nw = blk_words(r)
-    if nw == 0:
+    if blk_words(r) == 0:
         return True
-    ta = a[8 * P:].view(torch.int32).view(-1, nw)
-    tb = b[8 * P:].view(torch.int32).view(-1, nw)
-    if not torch.equal(ta[:, 0], tb[:, 0]):
+    na, pa, keep = blk_lists(r, a)
+    nb, pb, _ = blk_lists(r, b)
+    if not torch.equal(na, nb):
         return False
-    n = ta[:, 0].to(torch.int64) & 0xFFFFFFFF  # the counts, unsigned
-    keep = torch.arange(nw - 1, device=a.device)[None, :] < n.clamp(max=nw - 1)[:, None]
-    return torch.equal(ta[:, 1:][keep], tb[:, 1:][keep])
+    return torch.equal(pa[keep], pb[keep])
 
 
 def table_tiles(r):

@@ -41,7 +41,7 @@ def test_default_options():
     import paper_2602_14493_amd as gmr
     o = gmr.default_options()
     assert o.cov_mode == 0 and o.tile_w == 16 and o.tile_h == 16 and o.raster_mode == 0 and o.px_per_lane == 1
-    assert o.lane_lists == 1 and o.sh_degree == 0 and o.composited_lists == 1023
+    assert o.lane_lists == 1 and o.sh_degree == 0 and o.composited_lists == 2046
     assert ctypes.sizeof(o) == 72 and type(o).instance_capacity.offset == 64
     assert o.alpha_min == np.float32(1 / 255) and o.alpha_max == np.float32(0.99) and o.t_eps == np.float32(1e-4)
     assert o.dilation == np.float32(0.3) and tuple(o.bg) == (0.0, 0.0, 0.0)
@@ -66,19 +66,20 @@ def test_view_table_and_workspace_sizes():
     assert buf[32:40].view(np.int64)[0] == fv_total
     ws, saved = ctypes.c_size_t(), ctypes.c_size_t()
     _lib.call("gmr_workspace_size", ctypes.byref(b.c), ctypes.byref(o), ctypes.byref(ws), ctypes.byref(saved))
-    # per pixel T_final + list position; per raster item its composited list (count + 1023 positions)
+    # per pixel T_final + list position; per raster item its composited list (a count word, then
+    # 2046 16-bit positions: 1024 words)
     assert saved.value == 8 * W.num_pixels + 1024 * 4 * hdr[7]
-    for cap in (0, 7):
+    for cap, words in ((0, 0), (1, 2), (7, 5), (8, 5), (8190, 4096)):
         o.composited_lists = cap
         _lib.call("gmr_workspace_size", ctypes.byref(b.c), ctypes.byref(o), ctypes.byref(ws), ctypes.byref(saved))
-        assert saved.value == 8 * W.num_pixels + (cap + 1 if cap else 0) * 4 * hdr[7]
+        assert saved.value == 8 * W.num_pixels + words * 4 * hdr[7]
     assert ws.value >= (1 << 20) * 24 + fv_total * (48 + 16 + 4 + 32)
 
 
 @pytest.mark.parametrize("field,value", [("cov_mode", 3), ("tile_w", 12), ("tile_h", 72), ("alpha_min", 0.0),
                                          ("t_eps", 1.5), ("raster_mode", 3), ("px_per_lane", 3),
                                          ("lane_lists", 2), ("lane_lists", -1), ("sh_degree", 4), ("sh_degree", -1),
-                                         ("composited_lists", -1), ("composited_lists", 4096),
+                                         ("composited_lists", -1), ("composited_lists", 8191),
                                          ("instance_capacity", 0), ("instance_capacity", 1 << 30)])
 def test_invalid_options_rejected(field, value):
     import paper_2602_14493_amd as gmr

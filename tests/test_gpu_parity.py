@@ -655,20 +655,17 @@ def test_backward_composited_lists_equal_full_walk(gpu, cfg, kw):
     the order of the float atomics), lists saved or rebuilt; the lists hold ascending positions below
     each block's furthest stop, at most composited_lists of them."""
     import torch
-    from gmr_testutil import blk_words
+    from gmr_testutil import blk_lists, blk_words
     say(f"composited lists vs full walk: cfg{cfg} {kw}")
     W = wl.make_workload(cfg, scale=0.25 if cfg == 3 else 1.0)
     r, verts, colors = gpu_setup(W, **kw)
     rgb, alpha, saved, ws = r.forward(verts, colors, check=True)
     P = W.num_pixels
-    BLK_WORDS = blk_words(r)
-    blk = saved[8 * P:].view(torch.int32).view(-1, BLK_WORDS)
-    cnt = blk[:, 0].to(torch.int64) & 0xFFFFFFFF
-    say(f"  {blk.shape[0]} items, counts mean {float(cnt.float().mean()):.1f} max {int(cnt.max())}, "
-        f"{int((cnt > BLK_WORDS - 1).sum())} over the capacity")
-    fit = cnt <= BLK_WORDS - 1
-    ent = blk[:, 1:].to(torch.int64) & 0xFFFFFFFF
-    keep = torch.arange(BLK_WORDS - 1, device=saved.device)[None, :] < cnt.clamp(max=BLK_WORDS - 1)[:, None]
+    cap = int(r.opts.composited_lists)
+    cnt, ent, keep = blk_lists(r, saved)
+    say(f"  {cnt.shape[0]} items, counts mean {float(cnt.float().mean()):.1f} max {int(cnt.max())}, "
+        f"{int((cnt > cap).sum())} over the capacity")
+    fit = cnt <= cap
     asc = (ent[:, 1:] > ent[:, :-1]) | ~keep[:, 1:]
     assert bool(asc[fit].all()), "positions not ascending"
     g = torch.randn_like(rgb)
@@ -676,7 +673,7 @@ def test_backward_composited_lists_equal_full_walk(gpu, cfg, kw):
         dV, dC = r.backward(verts, colors, g, None, saved, ws, recompute=recompute)
         pairs = r.counters(ws).pairs_bwd
         s2 = saved.clone()
-        b2 = s2[8 * P:].view(torch.int32).view(-1, BLK_WORDS)
+        b2 = s2[8 * P:].view(torch.int32).view(-1, blk_words(r))
         b2[:, 0] = -1  # 0xffffffff: no list
         dV2, dC2 = r.backward(verts, colors, g, None, s2, ws, recompute=recompute)
         assert r.counters(ws).pairs_bwd == pairs
