@@ -42,9 +42,9 @@ FLOPS_PER_PAIR = {"raster_fwd": 25, "raster_bwd": 52}
 # counters were taken, and changed code reports null.
 TRAFFIC = {
     ("torus_2M_32x1920x1080", "raster_bwd", "32x16", 1, 0, 1):
-        {"fetch": 5998609052, "write": 1798054992, "src": "8effe59903d80b89"},
+        {"fetch": 5748517158, "write": 1797968330, "src": "6ff199d478dfb5b8"},
     ("torus_2M_32x1920x1080", "raster_bwd", "32x32", 1, 0, 1):
-        {"fetch": 5969846918, "write": 1797916409, "src": "8effe59903d80b89"},
+        {"fetch": 5703783343, "write": 1797835751, "src": "6ff199d478dfb5b8"},
 }
 STAGE_SOURCE = {"raster_fwd": "k_raster.hip", "raster_bwd": "k_raster.hip", "sort_fv_pass": "k_sort.hip",
                 "sort_pass": "k_sort.hip", "tile_ranges": "k_sort.hip",
