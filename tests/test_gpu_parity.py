@@ -705,6 +705,36 @@ def test_composited_lists_off_equals_default(gpu):
     compare_grads(b[4], to_np(a[4]), "lists off dC", rel=1e-5)
 
 
+def test_composited_lists_long_tile_lists(gpu):
+    """A tile list longer than 16-bit positions reach records no composited list (count
+    0xffffffff) and its blocks walk the whole list: the uv sphere's 400,000 faces in 64 x 64 views
+    of one 64 x 64 tile each.  Images, per-pixel saved state, pair counts and gradients equal those
+    with the lists off."""
+    import torch
+    from gmr_testutil import blk_lists
+    say("composited lists, tile lists over 65536 entries: uvsphere 4 x 64^2, one tile per view")
+    W = wl.make_workload(3, scale=1 / 16)
+    outs = []
+    for kw in ({}, {"composited_lists": 0}):
+        r, verts, colors = gpu_setup(W, tile_w=64, tile_h=64, **kw)
+        rgb, alpha, saved, ws = r.forward(verts, colors, check=True)
+        if kw == {}:
+            cnt, _, _ = blk_lists(r, saved)
+            say(f"  {r.counters(ws).instances} instances over {W.num_views} tiles")
+            assert r.counters(ws).instances > 65536 * W.num_views
+            assert bool((cnt == 0xFFFFFFFF).all())
+        g = torch.randn(rgb.shape, device="cuda", generator=torch.Generator("cuda").manual_seed(9))
+        dV, dC = r.backward(verts, colors, g, None, saved, ws)
+        c = r.counters(ws)
+        outs.append((rgb, alpha, saved, dV, dC, c.pairs_fwd, c.pairs_bwd))
+    a, b = outs
+    P = W.num_pixels
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2][:8 * P], b[2])
+    assert a[5:] == b[5:]
+    compare_grads(b[3], to_np(a[3]), "long lists dV", rel=1e-5)
+    compare_grads(b[4], to_np(a[4]), "long lists dC", rel=1e-5)
+
+
 def test_autograd_recompute_equals_saved(gpu):
     import torch
     import paper_2602_14493_amd as gmr
